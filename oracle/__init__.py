@@ -1,0 +1,264 @@
+"""FP64 CPU oracle for ADMM distributed bundle adjustment.
+
+TEST INFRASTRUCTURE ONLY: imported by ``tests/``, by ``__graft_entry__.smoke``
+and by the CPU-baseline leg of ``bench.py``.  The GPU library never imports,
+links or calls anything here, and nothing here uses the GPU library.
+
+What it computes (Ramamurthy et al., "Distributed Bundle Adjustment"):
+  * camera model: perspective division (Sec. 2.1, Eq. 1) extended to a
+    9-parameter camera (angle-axis w, translation t, focal f, radial k1, k2):
+    P = R(w) X + t, p = (P1/P3, P2/P3), pi = f (1 + k1 r^2 + k2 r^4) p;
+  * the split objective and its augmented Lagrangian (Sec. 3.1, Eqs. 5-8),
+    in scaled-dual form u = r / rho;
+  * one ADMM iteration (Eqs. 9-13): per-observation local update, point and
+    camera consensus, dual update; plus the primal/dual residual norms and
+    residual-balancing of rho used to monitor and steer it;
+  * reprojection statistics (RMSE, robust cost) at the consensus estimate;
+  * ``oracle.mlp``: the warm-start network's forward/backward in FP64.
+
+Readings where the paper is silent or loose (the same on the GPU path):
+  R1 camera: 9 parameters as above, all optimised; no principal point; the
+     rotation is updated additively in angle-axis form; for |w| < 1e-2 the
+     Rodrigues coefficients use their Taylor series to 4th order.
+  R2 Huber on the 2-D residual norm: phi(s) = s for s <= delta^2, else
+     2 delta sqrt(s) - delta^2 (s = |e|^2); Student-t: nu log(1 + s/nu).
+  R3 data term without 1/2, penalty (rho/2)|.|^2, as written in Eq. (8).
+  R4 local solver (the paper names Gauss-Newton / L-BFGS): robust LM with
+     IRLS weight phi'(s), Gauss-Newton matrix 2 w J^T J + P, Marquardt damping
+     lambda*diag, lambda0 = 1e-3, x10 / /10 within [1e-12, 1e12], exactly S
+     steps counting rejected ones, strict acceptance F' < F, a trial with
+     depth P3 <= 1e-6 or a non-positive Cholesky pivot is rejected; the solve
+     starts from the previous local copy.
+  R5 iteration order: local -> consensus -> dual -> norms -> rho update.
+  R6 residuals: r_pri = sqrt(sum_k |copy_k - consensus|^2),
+     r_dual = sqrt(rho_x^2 sum_i N_i |dx_i|^2 + rho_y^2 sum_j M_j |dy_j|^2).
+  R7 residual balancing: mu = 10, tau = 2, rho clamped to [1e-6, 1e6],
+     scaled duals multiplied by rho_old / rho_new.
+  R8 RMSE = sqrt(sum |e|^2 / L) at the consensus estimate.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import subprocess
+from dataclasses import dataclass
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "dba_oracle.c")
+_LIB = os.path.join(_HERE, "liboracle.so")
+
+LOSS = {"l2": 0, "huber": 1, "student_t": 2}
+
+
+def build(force: bool = False) -> str:
+    """Compile the C oracle with gcc (plain -O2, no fast-math, no FMA
+    contraction)."""
+    if force or not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
+        tmp = _LIB + ".tmp"
+        subprocess.check_call(["gcc", "-O2", "-fno-fast-math", "-ffp-contract=off",
+                               "-std=c11", "-shared", "-fPIC", "-o", tmp, _SRC, "-lm"])
+        os.replace(tmp, _LIB)
+    return _LIB
+
+
+_lib = None
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        _lib = ctypes.CDLL(build())
+        _declare(_lib)
+    return _lib
+
+
+_dp = ctypes.POINTER(ctypes.c_double)
+_ip = ctypes.POINTER(ctypes.c_int32)
+_up = ctypes.POINTER(ctypes.c_uint8)
+
+
+class OrcOpts(ctypes.Structure):
+    _fields_ = [("loss", ctypes.c_int32), ("loss_param", ctypes.c_double),
+                ("lm_steps", ctypes.c_int32), ("lambda0", ctypes.c_double),
+                ("rho_balancing", ctypes.c_int32), ("rb_mu", ctypes.c_double),
+                ("rb_tau", ctypes.c_double), ("rho_min", ctypes.c_double),
+                ("rho_max", ctypes.c_double)]
+
+
+def _declare(L):
+    L.orc_rot_coeffs.argtypes = [ctypes.c_double, _dp]
+    L.orc_transform.argtypes = [_dp, _dp, _dp]
+    L.orc_project.argtypes = [_dp, _dp, _dp]
+    L.orc_project.restype = ctypes.c_double
+    L.orc_project_jac.argtypes = [_dp, _dp, _dp, _dp]
+    L.orc_project_jac.restype = ctypes.c_double
+    L.orc_loss.argtypes = [ctypes.c_int, ctypes.c_double, ctypes.c_double, _dp]
+    L.orc_cholesky_solve.argtypes = [ctypes.c_int, _dp, _dp, _dp]
+    L.orc_cholesky_solve.restype = ctypes.c_int
+    L.orc_local_objective.argtypes = [ctypes.POINTER(OrcOpts), _dp, _dp, _dp,
+                                      ctypes.c_double, ctypes.c_double]
+    L.orc_local_objective.restype = ctypes.c_double
+    L.orc_local_solve.argtypes = [ctypes.POINTER(OrcOpts), _dp, _dp, _dp,
+                                  ctypes.c_double, ctypes.c_double, ctypes.c_int, _dp]
+    L.orc_local_solve.restype = ctypes.c_int
+    L.orc_admm_iterate.argtypes = [ctypes.c_int64, ctypes.c_int32, ctypes.c_int32,
+                                   _ip, _ip, _dp, _dp, _dp, _dp, _dp, _dp,
+                                   ctypes.POINTER(OrcOpts), ctypes.c_int32, _dp]
+    L.orc_admm_iterate.restype = ctypes.c_int
+    L.orc_reprojection_stats.argtypes = [ctypes.c_int64, _ip, _ip, _dp, _dp, _dp, _up,
+                                         ctypes.c_int, ctypes.c_double, _dp]
+
+
+def _d(a):
+    assert a.dtype == np.float64 and a.flags.c_contiguous
+    return a.ctypes.data_as(_dp)
+
+
+def _i(a):
+    assert a.dtype == np.int32 and a.flags.c_contiguous
+    return a.ctypes.data_as(_ip)
+
+
+def _f64(a):
+    return np.ascontiguousarray(a, dtype=np.float64)
+
+
+def make_opts(loss="huber", loss_param=2.0, lm_steps=5, lambda0=1e-3,
+              rho_balancing=False, rb_mu=10.0, rb_tau=2.0, rho_min=1e-6, rho_max=1e6):
+    return OrcOpts(LOSS[loss] if isinstance(loss, str) else int(loss), float(loss_param),
+                   int(lm_steps), float(lambda0), int(bool(rho_balancing)), float(rb_mu),
+                   float(rb_tau), float(rho_min), float(rho_max))
+
+
+# ---------------------------------------------------------------- pieces
+
+def rot_coeffs(theta2: float) -> np.ndarray:
+    out = np.zeros(5)
+    lib().orc_rot_coeffs(float(theta2), _d(out))
+    return out
+
+
+def transform(cam, X):
+    cam, X = _f64(cam), _f64(X)
+    P = np.zeros(3)
+    lib().orc_transform(_d(cam), _d(X), _d(P))
+    return P
+
+
+def project(cam, X):
+    cam, X = _f64(cam), _f64(X)
+    uv = np.zeros(2)
+    depth = lib().orc_project(_d(cam), _d(X), _d(uv))
+    return uv, depth
+
+
+def project_jac(cam, X):
+    cam, X = _f64(cam), _f64(X)
+    uv, J = np.zeros(2), np.zeros((2, 12))
+    depth = lib().orc_project_jac(_d(cam), _d(X), _d(uv), _d(J))
+    return uv, J, depth
+
+
+def loss(kind, param, s):
+    out = np.zeros(2)
+    lib().orc_loss(LOSS[kind] if isinstance(kind, str) else int(kind), float(param),
+                   float(s), _d(out))
+    return out[0], out[1]
+
+
+def cholesky_solve(A, b):
+    A, b = _f64(A), _f64(b)
+    n = b.shape[0]
+    x = np.zeros(n)
+    rc = lib().orc_cholesky_solve(n, _d(A), _d(b), _d(x))
+    return x if rc == 0 else None
+
+
+def local_objective(opts, z, v, theta, rho_x, rho_y):
+    return lib().orc_local_objective(ctypes.byref(opts), _d(_f64(z)), _d(_f64(v)),
+                                     _d(_f64(theta)), float(rho_x), float(rho_y))
+
+
+def local_solve(opts, z, v, theta, rho_x, rho_y, steps=None):
+    """Returns (theta_out, n_accepted, F trace of length steps+1)."""
+    steps = opts.lm_steps if steps is None else int(steps)
+    th = _f64(theta).copy()
+    tr = np.zeros(steps + 1)
+    acc = lib().orc_local_solve(ctypes.byref(opts), _d(_f64(z)), _d(_f64(v)), _d(th),
+                                float(rho_x), float(rho_y), steps, _d(tr))
+    return th, acc, tr
+
+
+# ---------------------------------------------------------------- whole ADMM
+
+@dataclass
+class Problem:
+    n_cams: int
+    n_points: int
+    obs_cam: np.ndarray
+    obs_point: np.ndarray
+    obs_uv: np.ndarray
+
+    @classmethod
+    def from_scene(cls, s):
+        return cls(s.n_cams, s.n_points, np.ascontiguousarray(s.obs_cam, np.int32),
+                   np.ascontiguousarray(s.obs_point, np.int32), _f64(s.obs_uv).reshape(-1, 2))
+
+
+class ADMM:
+    """The plain ADMM iteration on the whole problem, state in numpy arrays:
+    ``cons_y`` (m, 9), ``cons_x`` (n, 3), ``copy`` (L, 12) = (y_j^i, x_i^j),
+    ``dual`` (L, 12) scaled duals, ``rho`` = [rho_x, rho_y]."""
+
+    def __init__(self, problem: Problem, cams0, points0, *, loss="huber", loss_param=2.0,
+                 rho=1.0, rho_x=None, rho_y=None, rho_balancing=False, lm_steps=5,
+                 lambda0=1e-3):
+        self.p = problem
+        self.opts = make_opts(loss, loss_param, lm_steps, lambda0, rho_balancing)
+        self.loss, self.loss_param = loss, loss_param
+        self.cons_y = _f64(cams0).reshape(-1, 9).copy()
+        self.cons_x = _f64(points0).reshape(-1, 3).copy()
+        L = problem.obs_cam.shape[0]
+        self.copy = np.zeros((L, 12))
+        self.copy[:, :9] = self.cons_y[problem.obs_cam]
+        self.copy[:, 9:] = self.cons_x[problem.obs_point]
+        self.dual = np.zeros((L, 12))
+        self.rho = np.array([rho if rho_x is None else rho_x,
+                             rho if rho_y is None else rho_y], dtype=np.float64)
+        self.iteration = 0
+
+    def iterate(self, n_iters: int) -> np.ndarray:
+        """Runs n iterations; returns the trace (n, 4): r_pri, r_dual, rho_x, rho_y."""
+        tr = np.zeros((n_iters, 4))
+        p = self.p
+        rc = lib().orc_admm_iterate(p.obs_cam.shape[0], p.n_cams, p.n_points,
+                                    _i(p.obs_cam), _i(p.obs_point), _d(p.obs_uv),
+                                    _d(self.cons_y), _d(self.cons_x), _d(self.copy),
+                                    _d(self.dual), _d(self.rho), ctypes.byref(self.opts),
+                                    int(n_iters), _d(tr))
+        if rc != 0:
+            raise ValueError("oracle: bad problem indices")
+        self.iteration += n_iters
+        return tr
+
+    def stats(self, mask=None):
+        """(rmse_all, rmse_masked, robust_cost, mean_abs_error) at consensus."""
+        return reprojection_stats(self.p, self.cons_y, self.cons_x, mask,
+                                  self.loss, self.loss_param)
+
+
+def reprojection_stats(problem: Problem, cams, points, mask=None, loss_kind="l2",
+                       loss_param=1.0):
+    out = np.zeros(4)
+    cams, points = _f64(cams), _f64(points)
+    mp = None
+    if mask is not None:
+        mk = np.ascontiguousarray(mask, dtype=np.uint8)
+        mp = mk.ctypes.data_as(_up)
+    lib().orc_reprojection_stats(problem.obs_cam.shape[0], _i(problem.obs_cam),
+                                 _i(problem.obs_point), _d(problem.obs_uv), _d(cams),
+                                 _d(points), mp, LOSS[loss_kind] if isinstance(loss_kind, str)
+                                 else int(loss_kind), float(loss_param), _d(out))
+    return out

@@ -1,0 +1,433 @@
+/*
+ * dba_oracle.c -- plain, single-threaded FP64 reference implementation of
+ * ADMM distributed bundle adjustment ("Distributed Bundle Adjustment",
+ * Ramamurthy et al.).
+ *
+ * TEST INFRASTRUCTURE ONLY.  Only the test suite, the smoke check and the
+ * benchmark's CPU-baseline leg may load this library.  It shares no code with
+ * the GPU path and the GPU path never calls it.
+ *
+ * Everything is written for clarity, not speed: one observation at a time,
+ * dense 12x12 normal equations solved by Cholesky, sums in ascending
+ * observation order.  Readings of the paper that it fixes (camera model,
+ * loss definitions, local solver, residual norms, rho balancing) are listed
+ * in the header of oracle/__init__.py.
+ *
+ * Build: gcc -O2 -fno-fast-math -ffp-contract=off -shared -fPIC
+ */
+#include <math.h>
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+
+#define ORC_SMALL_ANGLE 1e-2  /* below: Taylor series for the Rodrigues coefficients */
+#define ORC_DEPTH_EPS 1e-6    /* depth at or below this: trial point rejected */
+#define ORC_LAMBDA_MIN 1e-12
+#define ORC_LAMBDA_MAX 1e12
+
+enum { ORC_L2 = 0, ORC_HUBER = 1, ORC_STUDENT_T = 2 };
+
+/* ------------------------------------------------------------------------ */
+/* Rotation by an angle-axis vector w (Rodrigues):                          */
+/*   R X = c X + a (w x X) + b (w . X) w,  theta = |w|,                     */
+/*   c = cos theta, a = sin theta / theta, b = (1 - cos theta) / theta^2.   */
+/* For the Jacobian also a1 = (da/dtheta)/theta, b1 = (db/dtheta)/theta.    */
+/* ------------------------------------------------------------------------ */
+void orc_rot_coeffs(double theta2, double out[5])
+{
+    double c, a, b, a1, b1;
+    if (theta2 < ORC_SMALL_ANGLE * ORC_SMALL_ANGLE) {
+        double t2 = theta2, t4 = theta2 * theta2;
+        c = 1.0 - t2 / 2.0 + t4 / 24.0;
+        a = 1.0 - t2 / 6.0 + t4 / 120.0;
+        b = 0.5 - t2 / 24.0 + t4 / 720.0;
+        a1 = -1.0 / 3.0 + t2 / 30.0 - t4 / 840.0;
+        b1 = -1.0 / 12.0 + t2 / 180.0 - t4 / 6720.0;
+    } else {
+        /* 1 - cos t is formed as 2 sin^2(t/2), which keeps its relative
+         * accuracy for small t */
+        double t = sqrt(theta2);
+        double s = sin(t);
+        double h = sin(0.5 * t);
+        double omc = 2.0 * h * h;
+        c = cos(t);
+        a = s / t;
+        b = omc / theta2;
+        a1 = (t * c - s) / (theta2 * t);
+        b1 = (t * s - 2.0 * omc) / (theta2 * theta2);
+    }
+    out[0] = c; out[1] = a; out[2] = b; out[3] = a1; out[4] = b1;
+}
+
+static void cross3(const double u[3], const double v[3], double o[3])
+{
+    o[0] = u[1] * v[2] - u[2] * v[1];
+    o[1] = u[2] * v[0] - u[0] * v[2];
+    o[2] = u[0] * v[1] - u[1] * v[0];
+}
+
+static double dot3(const double u[3], const double v[3])
+{
+    return u[0] * v[0] + u[1] * v[1] + u[2] * v[2];
+}
+
+/* Camera transform P = R(w) X + t. */
+void orc_transform(const double cam[9], const double X[3], double P[3])
+{
+    const double *w = cam;
+    double k[5], wx[3];
+    orc_rot_coeffs(dot3(w, w), k);
+    cross3(w, X, wx);
+    double wd = dot3(w, X);
+    for (int r = 0; r < 3; ++r)
+        P[r] = k[0] * X[r] + k[1] * wx[r] + k[2] * wd * w[r] + cam[3 + r];
+}
+
+/* Projection pi(cam, X): perspective division (Eq. 1) with focal length and
+ * two radial distortion terms.  Returns the depth P_3. */
+double orc_project(const double cam[9], const double X[3], double uv[2])
+{
+    double P[3];
+    orc_transform(cam, X, P);
+    double p0 = P[0] / P[2], p1 = P[1] / P[2];
+    double r2 = p0 * p0 + p1 * p1;
+    double d = 1.0 + cam[7] * r2 + cam[8] * r2 * r2;
+    uv[0] = cam[6] * d * p0;
+    uv[1] = cam[6] * d * p1;
+    return P[2];
+}
+
+/* Projection and its analytic Jacobian J (2 x 12, row-major) with respect to
+ * theta = (cam[0..8], X[0..2]).  Returns the depth. */
+double orc_project_jac(const double cam[9], const double X[3], double uv[2], double J[24])
+{
+    const double *w = cam;
+    double k[5], wx[3], P[3];
+    orc_rot_coeffs(dot3(w, w), k);
+    const double c = k[0], a = k[1], b = k[2], a1 = k[3], b1 = k[4];
+    cross3(w, X, wx);
+    double wd = dot3(w, X);
+    for (int r = 0; r < 3; ++r)
+        P[r] = c * X[r] + a * wx[r] + b * wd * w[r] + cam[3 + r];
+
+    /* R = c I + a [w]x + b w w^T */
+    double R[3][3];
+    double W[3][3] = {{0, -w[2], w[1]}, {w[2], 0, -w[0]}, {-w[1], w[0], 0}};
+    for (int r = 0; r < 3; ++r)
+        for (int s = 0; s < 3; ++s)
+            R[r][s] = (r == s ? c : 0.0) + a * W[r][s] + b * w[r] * w[s];
+
+    /* dRX/dw = -a X w^T + a1 (w x X) w^T - a [X]x + b1 (w.X) w w^T
+     *          + b (w X^T + (w.X) I) */
+    double XX[3][3] = {{0, -X[2], X[1]}, {X[2], 0, -X[0]}, {-X[1], X[0], 0}};
+    double D[3][3];
+    for (int r = 0; r < 3; ++r)
+        for (int s = 0; s < 3; ++s)
+            D[r][s] = -a * X[r] * w[s] + a1 * wx[r] * w[s] - a * XX[r][s]
+                      + b1 * wd * w[r] * w[s] + b * (w[r] * X[s] + (r == s ? wd : 0.0));
+
+    const double f = cam[6], k1 = cam[7], k2 = cam[8];
+    double q = 1.0 / P[2];
+    double p0 = P[0] / P[2], p1 = P[1] / P[2];
+    double r2 = p0 * p0 + p1 * p1;
+    double d = 1.0 + k1 * r2 + k2 * r2 * r2;
+    uv[0] = f * d * p0;
+    uv[1] = f * d * p1;
+
+    /* dpi/dp = f (d I + (2 k1 + 4 k2 r2) p p^T);  dp/dP = q [[1,0,-p0],[0,1,-p1]] */
+    double g = 2.0 * k1 + 4.0 * k2 * r2;
+    double M[2][2] = {{f * (d + g * p0 * p0), f * g * p0 * p1},
+                      {f * g * p1 * p0, f * (d + g * p1 * p1)}};
+    double dPdP[2][3] = {{q, 0.0, -q * p0}, {0.0, q, -q * p1}};
+    double A[2][3]; /* dpi/dP */
+    for (int r = 0; r < 2; ++r)
+        for (int s = 0; s < 3; ++s)
+            A[r][s] = M[r][0] * dPdP[0][s] + M[r][1] * dPdP[1][s];
+
+    for (int r = 0; r < 2; ++r) {
+        double *Jr = J + 12 * r;
+        for (int s = 0; s < 3; ++s) {
+            Jr[s] = A[r][0] * D[0][s] + A[r][1] * D[1][s] + A[r][2] * D[2][s];
+            Jr[3 + s] = A[r][s];
+            Jr[9 + s] = A[r][0] * R[0][s] + A[r][1] * R[1][s] + A[r][2] * R[2][s];
+        }
+        double pr = (r == 0) ? p0 : p1;
+        Jr[6] = d * pr;
+        Jr[7] = f * r2 * pr;
+        Jr[8] = f * r2 * r2 * pr;
+    }
+    return P[2];
+}
+
+/* ------------------------------------------------------------------------ */
+/* Misfit loss phi_m of the squared residual norm s = |e|^2 (Eq. 5), and     */
+/* its derivative phi'(s).  l2: phi = s.  Huber (delta): phi = s inside,     */
+/* 2 delta sqrt(s) - delta^2 outside.  Student-t (nu): nu log(1 + s/nu).     */
+/* ------------------------------------------------------------------------ */
+void orc_loss(int kind, double param, double s, double out[2])
+{
+    if (kind == ORC_HUBER) {
+        double d2 = param * param;
+        if (s <= d2) { out[0] = s; out[1] = 1.0; }
+        else { double r = sqrt(s); out[0] = 2.0 * param * r - d2; out[1] = param / r; }
+    } else if (kind == ORC_STUDENT_T) {
+        out[0] = param * log1p(s / param);
+        out[1] = 1.0 / (1.0 + s / param);
+    } else {
+        out[0] = s; out[1] = 1.0;
+    }
+}
+
+/* ------------------------------------------------------------------------ */
+/* Dense symmetric positive definite solve A x = b by Cholesky (A = L L^T). */
+/* Returns 0, or -1 on a non-positive (or non-finite) pivot.                */
+/* ------------------------------------------------------------------------ */
+int orc_cholesky_solve(int n, const double *A, const double *b, double *x)
+{
+    double Lm[64 * 64];
+    double y[64];
+    if (n < 1 || n > 64) return -2;
+    for (int i = 0; i < n; ++i) {
+        for (int j = 0; j <= i; ++j) {
+            double s = A[i * n + j];
+            for (int k = 0; k < j; ++k) s -= Lm[i * n + k] * Lm[j * n + k];
+            if (i == j) {
+                if (!(s > 0.0) || !isfinite(s)) return -1;
+                Lm[i * n + i] = sqrt(s);
+            } else {
+                Lm[i * n + j] = s / Lm[j * n + j];
+            }
+        }
+    }
+    for (int i = 0; i < n; ++i) {
+        double s = b[i];
+        for (int k = 0; k < i; ++k) s -= Lm[i * n + k] * y[k];
+        y[i] = s / Lm[i * n + i];
+    }
+    for (int i = n - 1; i >= 0; --i) {
+        double s = y[i];
+        for (int k = i + 1; k < n; ++k) s -= Lm[k * n + i] * x[k];
+        x[i] = s / Lm[i * n + i];
+    }
+    return 0;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Local update (Eq. 9) in scaled form: with u = r / rho, minimise           */
+/*   F(theta) = phi(|z - pi(theta)|^2) + 1/2 (theta - v)^T P (theta - v),    */
+/*   v = consensus - u,  P = diag(rho_y (x9), rho_x (x3)),                   */
+/* by robust Levenberg-Marquardt: IRLS weight w = phi'(s), Gauss-Newton      */
+/* matrix H = 2 w J^T J + P, Marquardt damping lambda diag(H), exactly       */
+/* `steps` steps (rejected ones included), strict acceptance F' < F.         */
+/* ------------------------------------------------------------------------ */
+typedef struct {
+    int32_t loss;
+    double loss_param;
+    int32_t lm_steps;
+    double lambda0;
+    int32_t rho_balancing;
+    double rb_mu, rb_tau, rho_min, rho_max;
+} orc_opts;
+
+double orc_local_objective(const orc_opts *o, const double z[2], const double v[12],
+                           const double theta[12], double rho_x, double rho_y)
+{
+    double uv[2], ls[2];
+    double depth = orc_project(theta, theta + 9, uv);
+    if (!(depth > ORC_DEPTH_EPS)) return INFINITY;
+    double e0 = z[0] - uv[0], e1 = z[1] - uv[1];
+    orc_loss(o->loss, o->loss_param, e0 * e0 + e1 * e1, ls);
+    double pen = 0.0;
+    for (int c = 0; c < 12; ++c) {
+        double d = theta[c] - v[c];
+        pen += (c < 9 ? rho_y : rho_x) * d * d;
+    }
+    return ls[0] + 0.5 * pen;
+}
+
+/* theta: in = start point, out = result.  f_trace (optional, steps+1
+ * entries): F after each step (entry 0 = at the start).  Returns the number
+ * of accepted steps. */
+int orc_local_solve(const orc_opts *o, const double z[2], const double v[12],
+                    double theta[12], double rho_x, double rho_y, int steps,
+                    double *f_trace)
+{
+    double lambda = o->lambda0;
+    double F = orc_local_objective(o, z, v, theta, rho_x, rho_y);
+    if (f_trace) f_trace[0] = F;
+    int accepted = 0;
+    for (int it = 0; it < steps; ++it) {
+        double uv[2], J[24], ls[2];
+        orc_project_jac(theta, theta + 9, uv, J);
+        double e0 = z[0] - uv[0], e1 = z[1] - uv[1];
+        orc_loss(o->loss, o->loss_param, e0 * e0 + e1 * e1, ls);
+        double w = ls[1];
+        double g[12], H[144], A[144], rhs[12], delta[12];
+        for (int r = 0; r < 12; ++r) {
+            double pr = (r < 9 ? rho_y : rho_x);
+            g[r] = -2.0 * w * (J[r] * e0 + J[12 + r] * e1) + pr * (theta[r] - v[r]);
+            for (int s = 0; s < 12; ++s)
+                H[r * 12 + s] = 2.0 * w * (J[r] * J[s] + J[12 + r] * J[12 + s])
+                                + (r == s ? pr : 0.0);
+        }
+        for (int r = 0; r < 12; ++r) {
+            for (int s = 0; s < 12; ++s) A[r * 12 + s] = H[r * 12 + s];
+            A[r * 12 + r] += lambda * H[r * 12 + r];
+            rhs[r] = -g[r];
+        }
+        int ok = orc_cholesky_solve(12, A, rhs, delta) == 0;
+        double Fn = INFINITY;
+        double trial[12];
+        if (ok) {
+            for (int r = 0; r < 12; ++r) trial[r] = theta[r] + delta[r];
+            Fn = orc_local_objective(o, z, v, trial, rho_x, rho_y);
+        }
+        if (ok && Fn < F) {
+            memcpy(theta, trial, sizeof(trial));
+            F = Fn;
+            lambda = fmax(lambda / 10.0, ORC_LAMBDA_MIN);
+            ++accepted;
+        } else {
+            lambda = fmin(lambda * 10.0, ORC_LAMBDA_MAX);
+        }
+        if (f_trace) f_trace[it + 1] = F;
+    }
+    return accepted;
+}
+
+/* ------------------------------------------------------------------------ */
+/* ADMM iterations (Eqs. 9-13) over the whole problem, state updated in      */
+/* place.  Per observation k (camera j = obs_cam[k], point i = obs_pt[k]):   */
+/*   copy[12k..12k+11] = (y_j^i (9), x_i^j (3)),  dual = scaled duals u.     */
+/* One iteration:                                                            */
+/*   1. local solve of every observation (Eq. 9), started at its copy;       */
+/*   2. consensus (Eqs. 10, 11): mean over each segment of copy + u, summed  */
+/*      in ascending observation order;                                      */
+/*   3. scaled dual update (Eqs. 12, 13): u += copy - consensus;             */
+/*   4. residual norms r_pri = |copy - consensus|,                           */
+/*      r_dual = |rho (consensus - previous consensus)| counted once per     */
+/*      copy;                                                                */
+/*   5. optional residual balancing of rho, duals rescaled by old/new rho.   */
+/* trace (optional, 4 per iteration): r_pri, r_dual, rho_x, rho_y used.      */
+/* Returns 0, or -1 on bad input.                                            */
+/* ------------------------------------------------------------------------ */
+int orc_admm_iterate(int64_t L, int32_t m, int32_t n,
+                     const int32_t *obs_cam, const int32_t *obs_pt, const double *obs_uv,
+                     double *cons_y, double *cons_x, double *copy, double *dual,
+                     double *rho, const orc_opts *o, int32_t n_iters, double *trace)
+{
+    double *cnt_y = calloc((size_t)m, sizeof(double));
+    double *cnt_x = calloc((size_t)n, sizeof(double));
+    double *sum_y = malloc(sizeof(double) * 9 * (size_t)m);
+    double *sum_x = malloc(sizeof(double) * 3 * (size_t)n);
+    double *old_y = malloc(sizeof(double) * 9 * (size_t)m);
+    double *old_x = malloc(sizeof(double) * 3 * (size_t)n);
+    if (!cnt_y || !cnt_x || !sum_y || !sum_x || !old_y || !old_x) return -1;
+    for (int64_t k = 0; k < L; ++k) {
+        if (obs_cam[k] < 0 || obs_cam[k] >= m || obs_pt[k] < 0 || obs_pt[k] >= n) return -1;
+        cnt_y[obs_cam[k]] += 1.0;
+        cnt_x[obs_pt[k]] += 1.0;
+    }
+
+    for (int32_t it = 0; it < n_iters; ++it) {
+        const double rx = rho[0], ry = rho[1];
+        /* 1. local updates */
+        for (int64_t k = 0; k < L; ++k) {
+            const int j = obs_cam[k], i = obs_pt[k];
+            double v[12];
+            for (int c = 0; c < 9; ++c) v[c] = cons_y[9 * j + c] - dual[12 * k + c];
+            for (int c = 0; c < 3; ++c) v[9 + c] = cons_x[3 * i + c] - dual[12 * k + 9 + c];
+            orc_local_solve(o, obs_uv + 2 * k, v, copy + 12 * k, rx, ry, o->lm_steps, NULL);
+        }
+        /* 2. consensus */
+        memcpy(old_y, cons_y, sizeof(double) * 9 * (size_t)m);
+        memcpy(old_x, cons_x, sizeof(double) * 3 * (size_t)n);
+        memset(sum_y, 0, sizeof(double) * 9 * (size_t)m);
+        memset(sum_x, 0, sizeof(double) * 3 * (size_t)n);
+        for (int64_t k = 0; k < L; ++k) {
+            const int j = obs_cam[k], i = obs_pt[k];
+            for (int c = 0; c < 9; ++c) sum_y[9 * j + c] += copy[12 * k + c] + dual[12 * k + c];
+            for (int c = 0; c < 3; ++c) sum_x[3 * i + c] += copy[12 * k + 9 + c] + dual[12 * k + 9 + c];
+        }
+        for (int j = 0; j < m; ++j)
+            for (int c = 0; c < 9; ++c) cons_y[9 * j + c] = sum_y[9 * j + c] / cnt_y[j];
+        for (int i = 0; i < n; ++i)
+            for (int c = 0; c < 3; ++c) cons_x[3 * i + c] = sum_x[3 * i + c] / cnt_x[i];
+        /* 3. dual update and 4. primal residual */
+        double pri2 = 0.0;
+        for (int64_t k = 0; k < L; ++k) {
+            const int j = obs_cam[k], i = obs_pt[k];
+            for (int c = 0; c < 12; ++c) {
+                double cv = (c < 9) ? cons_y[9 * j + c] : cons_x[3 * i + c - 9];
+                double d = copy[12 * k + c] - cv;
+                dual[12 * k + c] += d;
+                pri2 += d * d;
+            }
+        }
+        /* 4. dual residual */
+        double dy2 = 0.0, dx2 = 0.0;
+        for (int j = 0; j < m; ++j) {
+            double s = 0.0;
+            for (int c = 0; c < 9; ++c) { double d = cons_y[9 * j + c] - old_y[9 * j + c]; s += d * d; }
+            dy2 += cnt_y[j] * s;
+        }
+        for (int i = 0; i < n; ++i) {
+            double s = 0.0;
+            for (int c = 0; c < 3; ++c) { double d = cons_x[3 * i + c] - old_x[3 * i + c]; s += d * d; }
+            dx2 += cnt_x[i] * s;
+        }
+        double r_pri = sqrt(pri2);
+        double r_dual = sqrt(rx * rx * dx2 + ry * ry * dy2);
+        if (trace) {
+            trace[4 * it + 0] = r_pri; trace[4 * it + 1] = r_dual;
+            trace[4 * it + 2] = rx; trace[4 * it + 3] = ry;
+        }
+        /* 5. residual balancing */
+        if (o->rho_balancing) {
+            double fac = 1.0;
+            if (r_pri > o->rb_mu * r_dual) fac = o->rb_tau;
+            else if (r_dual > o->rb_mu * r_pri) fac = 1.0 / o->rb_tau;
+            if (fac != 1.0) {
+                double nx = fmin(fmax(rx * fac, o->rho_min), o->rho_max);
+                double ny = fmin(fmax(ry * fac, o->rho_min), o->rho_max);
+                double sx = rx / nx, sy = ry / ny;
+                for (int64_t k = 0; k < L; ++k) {
+                    for (int c = 0; c < 9; ++c) dual[12 * k + c] *= sy;
+                    for (int c = 9; c < 12; ++c) dual[12 * k + c] *= sx;
+                }
+                rho[0] = nx; rho[1] = ny;
+            }
+        }
+    }
+    free(cnt_y); free(cnt_x); free(sum_y); free(sum_x); free(old_y); free(old_x);
+    return 0;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Reprojection statistics at the consensus estimate.                        */
+/* out[0] = RMSE over all observations, sqrt(sum |e|^2 / L);                 */
+/* out[1] = RMSE over observations with mask[k] != 0 (all if mask == NULL);  */
+/* out[2] = robust cost sum phi(|e|^2); out[3] = mean |e| over all.          */
+/* ------------------------------------------------------------------------ */
+void orc_reprojection_stats(int64_t L, const int32_t *obs_cam, const int32_t *obs_pt,
+                            const double *obs_uv, const double *cons_y, const double *cons_x,
+                            const uint8_t *mask, int loss, double loss_param, double out[4])
+{
+    double s_all = 0.0, s_m = 0.0, cost = 0.0, abs_sum = 0.0;
+    int64_t n_m = 0;
+    for (int64_t k = 0; k < L; ++k) {
+        double uv[2], ls[2];
+        orc_project(cons_y + 9 * (size_t)obs_cam[k], cons_x + 3 * (size_t)obs_pt[k], uv);
+        double e0 = obs_uv[2 * k] - uv[0], e1 = obs_uv[2 * k + 1] - uv[1];
+        double s = e0 * e0 + e1 * e1;
+        s_all += s;
+        abs_sum += sqrt(s);
+        orc_loss(loss, loss_param, s, ls);
+        cost += ls[0];
+        if (!mask || mask[k]) { s_m += s; ++n_m; }
+    }
+    out[0] = L > 0 ? sqrt(s_all / (double)L) : 0.0;
+    out[1] = n_m > 0 ? sqrt(s_m / (double)n_m) : 0.0;
+    out[2] = cost;
+    out[3] = L > 0 ? abs_sum / (double)L : 0.0;
+}

@@ -26,7 +26,11 @@ Readings where the paper is silent or loose (the same on the GPU path):
   R4 local solver (the paper names Gauss-Newton / L-BFGS): robust LM with
      IRLS weight phi'(s), Gauss-Newton matrix 2 w J^T J + P, Marquardt damping
      lambda*diag, lambda0 = 1e-3, x10 / /10 within [1e-12, 1e12], exactly S
-     steps counting rejected ones, strict acceptance F' < F, a trial with
+     steps counting rejected ones; a trial is accepted if F' < F, or if the
+     damped Gauss-Newton model predicts a decrease below
+     1e-13 (F + |e| (|z_1| + |z_2| + f)) -- F's rounding resolution, since
+     e = z - pi loses ~eps |z| -- so the model decides instead of rounding;
+     a trial with
      depth P3 <= 1e-6 or a non-positive Cholesky pivot is rejected; the solve
      starts from the previous local copy.
   R5 iteration order: local -> consensus -> dual -> norms -> rho update.

@@ -24,6 +24,7 @@
 #define ORC_DEPTH_EPS 1e-6    /* depth at or below this: trial point rejected */
 #define ORC_LAMBDA_MIN 1e-12
 #define ORC_LAMBDA_MAX 1e12
+#define ORC_TIE 1e-13         /* predicted decrease (relative to F's resolution) F cannot judge */
 
 enum { ORC_L2 = 0, ORC_HUBER = 1, ORC_STUDENT_T = 2 };
 
@@ -218,7 +219,9 @@ int orc_cholesky_solve(int n, const double *A, const double *b, double *x)
 /*   v = consensus - u,  P = diag(rho_y (x9), rho_x (x3)),                   */
 /* by robust Levenberg-Marquardt: IRLS weight w = phi'(s), Gauss-Newton      */
 /* matrix H = 2 w J^T J + P, Marquardt damping lambda diag(H), exactly       */
-/* `steps` steps (rejected ones included), strict acceptance F' < F.         */
+/* `steps` steps (rejected ones included), acceptance if F' < F or if the   */
+/* step's predicted decrease is below 1e-13 (F + |e| (|z_1| + |z_2| + f)),  */
+/* the rounding resolution of F (too small for F to judge).                  */
 /* ------------------------------------------------------------------------ */
 typedef struct {
     int32_t loss;
@@ -262,6 +265,10 @@ int orc_local_solve(const orc_opts *o, const double z[2], const double v[12],
         double e0 = z[0] - uv[0], e1 = z[1] - uv[1];
         orc_loss(o->loss, o->loss_param, e0 * e0 + e1 * e1, ls);
         double w = ls[1];
+        /* resolution of F at theta: rounding of e = z - pi is ~eps |z|, so F
+         * carries noise ~eps |e| |z| besides eps F (f stands in for the
+         * pixel scale of pi) */
+        const double fres = F + sqrt(e0 * e0 + e1 * e1) * (fabs(z[0]) + fabs(z[1]) + fabs(theta[6]));
         double g[12], H[144], A[144], rhs[12], delta[12];
         for (int r = 0; r < 12; ++r) {
             double pr = (r < 9 ? rho_y : rho_x);
@@ -276,13 +283,23 @@ int orc_local_solve(const orc_opts *o, const double z[2], const double v[12],
             rhs[r] = -g[r];
         }
         int ok = orc_cholesky_solve(12, A, rhs, delta) == 0;
-        double Fn = INFINITY;
+        double Fn = INFINITY, pred = INFINITY;
         double trial[12];
         if (ok) {
             for (int r = 0; r < 12; ++r) trial[r] = theta[r] + delta[r];
             Fn = orc_local_objective(o, z, v, trial, rho_x, rho_y);
+            /* decrease predicted by the damped Gauss-Newton model:
+             * -g.delta - 1/2 delta^T H delta = 1/2 (lambda sum H_rr delta_r^2 - g.delta) */
+            double gd = 0.0, dd = 0.0;
+            for (int r = 0; r < 12; ++r) {
+                gd += g[r] * delta[r];
+                dd += H[r * 12 + r] * delta[r] * delta[r];
+            }
+            pred = 0.5 * (lambda * dd - gd);
         }
-        if (ok && Fn < F) {
+        /* accept a decrease of F; a step whose predicted decrease is below
+         * what F can resolve is accepted on the model's word */
+        if (ok && isfinite(Fn) && (Fn < F || pred <= ORC_TIE * fres)) {
             memcpy(theta, trial, sizeof(trial));
             F = Fn;
             lambda = fmax(lambda / 10.0, ORC_LAMBDA_MIN);

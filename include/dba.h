@@ -1,0 +1,180 @@
+/*
+ * dba.h -- C ABI of the MI355X ADMM bundle-adjustment library (libdba.so).
+ *
+ * The library runs the data-parallel hot path of distributed bundle
+ * adjustment by ADMM (Ramamurthy et al., "Distributed Bundle Adjustment",
+ * Sec. 3.1): every observation z_ij owns a local copy (y_j^i, x_i^j) of its
+ * camera and point; one iteration solves each copy's local problem (Eq. 9),
+ * averages copies plus scaled duals into consensus values (Eqs. 10, 11),
+ * updates the scaled duals (Eqs. 12, 13), and evaluates primal/dual residual
+ * norms (with optional residual balancing of rho).
+ *
+ * Conventions for every call:
+ *   - All pointer arguments are HOST memory owned by the caller.  Inputs are
+ *     copied before the call returns; outputs are written before it returns.
+ *   - Camera vectors have 9 doubles: (w_x, w_y, w_z, t_x, t_y, t_z, f, k1, k2)
+ *     -- angle-axis rotation world->camera, translation, focal length in
+ *     pixels, two radial distortion terms; pixel = f (1 + k1 r^2 + k2 r^4) *
+ *     (P_1/P_3, P_2/P_3) with P = R(w) X + t (Sec. 2.1, Eq. 1, extended by
+ *     f, k1, k2).  Points have 3 doubles.  Observations are (camera, point,
+ *     u, v) in any order; arrays are indexed by observation k = 0..n_obs-1.
+ *   - Every function returns a dba_status; on error the handle state is
+ *     unchanged and dba_last_error() describes the failure.
+ *   - Work is enqueued on the handle's stream; calls that return data
+ *     synchronise that stream.  A handle is not thread-safe.
+ */
+#ifndef DBA_H
+#define DBA_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct dba_handle dba_handle;
+
+typedef enum {
+    DBA_OK = 0,
+    DBA_E_INVALID_ARG = -1,   /* null pointer, bad size or option */
+    DBA_E_INDEX_RANGE = -2,   /* camera/point index outside [0, n) */
+    DBA_E_UNOBSERVED = -3,    /* a camera or point has no observation */
+    DBA_E_NONFINITE = -4,     /* non-finite input, or the iteration produced one */
+    DBA_E_BEHIND_CAMERA = -5, /* an observation has depth <= 1e-6 at the initial estimate */
+    DBA_E_DEVICE = -6,        /* HIP runtime error */
+    DBA_E_STATE = -7          /* call not valid in the current state (e.g. no problem set) */
+} dba_status;
+
+typedef enum {
+    DBA_LOSS_L2 = 0,          /* phi(s) = s */
+    DBA_LOSS_HUBER = 1,       /* phi(s) = s if s <= d^2 else 2 d sqrt(s) - d^2, d = loss_param (px) */
+    DBA_LOSS_STUDENT_T = 2    /* phi(s) = nu log(1 + s/nu), nu = loss_param */
+} dba_loss;
+
+typedef enum {
+    DBA_PREC_FP64 = 0,        /* everything in FP64 */
+    DBA_PREC_FP32_LOCAL = 1   /* local solves in FP32; consensus, duals, norms in FP64 */
+} dba_precision;
+
+typedef enum {
+    DBA_START_PLAIN = 0,      /* local LM starts from the previous local copy */
+    DBA_START_LEARNED = 1     /* start from the better of the copy and copy + MLP prediction */
+} dba_start;
+
+typedef struct dba_options {
+    int32_t device;           /* HIP device ordinal */
+    void *stream;             /* hipStream_t to enqueue on; NULL: a stream the handle creates */
+    int32_t precision;        /* dba_precision */
+    int32_t loss;             /* dba_loss (phi_m of Eq. 8) */
+    double loss_param;        /* Huber delta in pixels, or Student-t nu */
+    double rho_x, rho_y;      /* penalty weights of Eq. (8), points and cameras (> 0) */
+    int32_t rho_balancing;    /* 1: residual balancing of rho after every iteration */
+    double rb_mu, rb_tau;     /* balancing: act when one residual exceeds mu x the other; scale by tau */
+    double rho_min, rho_max;  /* balancing clamps */
+    int32_t lm_steps;         /* LM steps per local solve, counting rejected ones (1..64) */
+    double lm_lambda0;        /* initial Marquardt damping of each local solve */
+    int32_t start;            /* dba_start */
+    int32_t learned_lm_steps; /* LM steps after the learned start (1..64) */
+    int32_t use_graph;        /* 1: replay iterations from a captured hipGraph */
+    int32_t block_waves;      /* local-solve workgroup size in wavefronts (1,2,4,8); 0: autotune */
+    int32_t persistent;       /* local solve: 1 persistent grid, 0 one workgroup per tile, -1 autotune */
+} dba_options;
+
+/* Fills *opt with the defaults: device 0, NULL stream, FP64, Huber 2 px,
+ * rho 1, no balancing (mu 10, tau 2, clamps 1e-6..1e6), 5 LM steps,
+ * lambda0 1e-3, plain start, 2 learned steps, graphs on, autotune. */
+int dba_default_options(dba_options *opt);
+
+/* Creates a handle on opt->device.  *out receives the handle. */
+int dba_create(const dba_options *opt, dba_handle **out);
+
+/* Frees the handle and all device memory it owns.  NULL is allowed. */
+void dba_destroy(dba_handle *h);
+
+/* Message of the last failed call on this handle ("" if none).  The string
+ * stays valid until the next call on the handle. */
+const char *dba_last_error(const dba_handle *h);
+
+/* One bundle-adjustment problem (the statement of Sec. 2.2): n_cams
+ * cameras y_j, n_points points x_i, and n_obs observations z_ij, i in S(j). */
+typedef struct dba_problem_desc {
+    int32_t n_cams, n_points;
+    int64_t n_obs;
+    const int32_t *obs_cam;   /* [n_obs] camera index j of observation k */
+    const int32_t *obs_point; /* [n_obs] point index i of observation k */
+    const double *obs_uv;     /* [2*n_obs] pixel (u, v) of observation k */
+    const double *cams;       /* [9*n_cams] initial consensus cameras */
+    const double *points;     /* [3*n_points] initial consensus points */
+} dba_problem_desc;
+
+/* Sets one problem (equivalent to dba_set_problems with one entry).
+ * Initial local copies = initial consensus, scaled duals = 0, rho from the
+ * options, iteration counter 0.  Validation: indices in range
+ * (DBA_E_INDEX_RANGE), all values finite (DBA_E_NONFINITE), every camera and
+ * point observed at least once, since Eqs. (10)-(11) divide by the count
+ * (DBA_E_UNOBSERVED), depth > 1e-6 for every observation at the initial
+ * estimate (DBA_E_BEHIND_CAMERA). */
+int dba_set_problem(dba_handle *h, int32_t n_cams, int32_t n_points, int64_t n_obs,
+                    const int32_t *obs_cam, const int32_t *obs_point, const double *obs_uv,
+                    const double *cams, const double *points);
+
+/* Sets n_problems independent problems that then iterate together in the
+ * same launches; each keeps its own rho, residuals and iteration count, and
+ * its results are bitwise identical to running it alone. */
+int dba_set_problems(dba_handle *h, int32_t n_problems, const dba_problem_desc *probs);
+
+/* Runs n_iters ADMM iterations (Eqs. 9-13 + residual norms + optional rho
+ * balancing) on every problem.  Asynchronous: returns after enqueueing.
+ * n_iters >= 0. */
+int dba_iterate(dba_handle *h, int32_t n_iters);
+
+typedef struct dba_residual_report {
+    double primal;            /* sqrt(sum_k |copy_k - consensus|^2) of the last iteration */
+    double dual;              /* sqrt(rho_x^2 sum_i N_i |dx_i|^2 + rho_y^2 sum_j M_j |dy_j|^2) */
+    double rho_x, rho_y;      /* rho used by the last iteration */
+    double next_rho_x, next_rho_y; /* rho the next iteration will use */
+    double rmse;              /* sqrt(sum |e|^2 / L) at the consensus estimate (want_rmse) */
+    double rmse_masked;       /* same over the observations of the evaluation mask */
+    double robust_cost;       /* sum phi(|e|^2) at the consensus estimate */
+    double mean_error;        /* mean |e| */
+    int64_t iteration;        /* iterations run so far */
+    int32_t nonfinite;        /* 1 if a non-finite value was seen in the consensus */
+    int32_t reserved;
+} dba_residual_report;
+
+/* Residual report of problem `problem`.  want_rmse != 0 also evaluates the
+ * reprojection statistics at the current consensus (one extra pass). */
+int dba_residuals(dba_handle *h, int32_t problem, int32_t want_rmse, dba_residual_report *out);
+
+/* Marks which observations of `problem` count for rmse_masked (mask[k] != 0);
+ * NULL resets to all observations. */
+int dba_set_eval_mask(dba_handle *h, int32_t problem, const uint8_t *mask);
+
+/* Consensus estimate of `problem`: cams [9*n_cams], points [3*n_points], FP64. */
+int dba_get_params(dba_handle *h, int32_t problem, double *cams, double *points);
+
+/* Full ADMM state of `problem` in the caller's observation order: local
+ * copies [12*n_obs] as (y_j^i (9), x_i^j (3)) and scaled duals [12*n_obs],
+ * FP64.  Either pointer may be NULL. */
+int dba_get_state(dba_handle *h, int32_t problem, double *copies, double *duals);
+
+/* Number of problems set, and the sizes of one. */
+int dba_problem_info(const dba_handle *h, int32_t problem, int32_t *n_cams, int32_t *n_points,
+                     int64_t *n_obs);
+
+/* Kernel timing: while enabled, dba_iterate records HIP events around each
+ * kernel on the handle's stream (graphs are not used).  Kernel ids:
+ * 0 local solve, 1 consensus, 2 residual norms, 3 learned warm start.
+ * dba_kernel_times returns, per id, total milliseconds and launch counts
+ * since timing was enabled (synchronises the stream). */
+int dba_set_kernel_timing(dba_handle *h, int32_t enable);
+int dba_kernel_times(dba_handle *h, double *total_ms /*[4]*/, int64_t *launches /*[4]*/);
+
+/* Launch schedule in use: waves per local-solve workgroup, persistent flag,
+ * and number of candidate schedules the autotuner timed (0 if fixed). */
+int dba_schedule(const dba_handle *h, int32_t *block_waves, int32_t *persistent, int32_t *tuned);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

@@ -1,0 +1,781 @@
+// dba_host.cpp -- C ABI, validation, device layout builder, iteration driver
+// (eager launches or hipGraph replay), launch-schedule autotuner and kernel
+// timing for the ADMM bundle-adjustment library.
+#include "dba.h"
+#include "dba_internal.h"
+
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+namespace {
+
+using dba::Ctrl;
+using dba::DevArrays;
+using dba::ProblemRange;
+
+constexpr int kKernels = 4;   // local, consensus, norms, learned
+constexpr int kGraphBatch = 16;
+
+struct Buffers {
+    std::vector<void *> ptrs;
+    ~Buffers() { release(); }
+    void release()
+    {
+        for (void *p : ptrs) (void)hipFree(p);
+        ptrs.clear();
+    }
+    template <typename T>
+    hipError_t alloc(T **out, size_t count)
+    {
+        void *p = nullptr;
+        hipError_t e = hipMalloc(&p, std::max<size_t>(count, 1) * sizeof(T));
+        if (e != hipSuccess) return e;
+        ptrs.push_back(p);
+        *out = static_cast<T *>(p);
+        return hipSuccess;
+    }
+};
+
+struct ProblemSet {
+    Buffers buf;
+    int n_problems = 0;
+    std::vector<ProblemRange> ranges;
+    std::vector<int> m, n;
+    std::vector<long long> L;
+    DevArrays<float> a32{};
+    DevArrays<double> a64{};
+    uint8_t *mask = nullptr;
+    long long n_slots = 0;
+};
+
+struct Timing {
+    bool on = false;
+    double total_ms[kKernels] = {0, 0, 0, 0};
+    long long launches[kKernels] = {0, 0, 0, 0};
+    std::vector<hipEvent_t> pool;
+    std::vector<int> pending_kernel;  // kernel id per recorded pair
+    size_t used = 0;
+};
+
+}  // namespace
+
+struct dba_handle {
+    dba_options opt{};
+    hipStream_t stream = nullptr;
+    bool own_stream = false;
+    int n_cu = 256;
+    std::string err;
+    ProblemSet *ps = nullptr;
+    bool fp32 = false;
+    dba::SolverParams sp{};
+    // schedule
+    int block_waves = 4, persistent = 0, tuned = 0;
+    bool schedule_ready = false;
+    int tune_next = 0;
+    std::vector<float> tune_ms;
+    // graphs: [0] one iteration, [1] kGraphBatch iterations
+    hipGraphExec_t gexec[2] = {nullptr, nullptr};
+    Timing timing;
+};
+
+namespace {
+
+int fail(dba_handle *h, int code, const char *fmt, ...)
+{
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof(buf), fmt, ap);
+    va_end(ap);
+    if (h) h->err = buf;
+    return code;
+}
+
+#define HIP_TRY(h, expr)                                                                        \
+    do {                                                                                        \
+        hipError_t e_ = (expr);                                                                 \
+        if (e_ != hipSuccess)                                                                   \
+            return fail((h), DBA_E_DEVICE, "%s failed: %s", #expr, hipGetErrorString(e_));     \
+    } while (0)
+
+void drop_graphs(dba_handle *h)
+{
+    for (auto &g : h->gexec) {
+        if (g) (void)hipGraphExecDestroy(g);
+        g = nullptr;
+    }
+}
+
+// Depth P_3 of R(w) X + t (host-side validation only).
+double host_depth(const double *cam, const double *X)
+{
+    const double w0 = cam[0], w1 = cam[1], w2 = cam[2];
+    const double t2 = w0 * w0 + w1 * w1 + w2 * w2;
+    double c, a, b;
+    if (t2 < 1e-4) {
+        c = 1.0 - t2 / 2.0 + t2 * t2 / 24.0;
+        a = 1.0 - t2 / 6.0 + t2 * t2 / 120.0;
+        b = 0.5 - t2 / 24.0 + t2 * t2 / 720.0;
+    } else {
+        const double t = std::sqrt(t2), sh = std::sin(0.5 * t);
+        c = std::cos(t);
+        a = std::sin(t) / t;
+        b = 2.0 * sh * sh / t2;
+    }
+    const double wd = w0 * X[0] + w1 * X[1] + w2 * X[2];
+    return c * X[2] + a * (w0 * X[1] - w1 * X[0]) + b * wd * w2 + cam[5];
+}
+
+int validate(dba_handle *h, int p, const dba_problem_desc &d)
+{
+    if (d.n_cams < 1 || d.n_points < 1 || d.n_obs < 1)
+        return fail(h, DBA_E_INVALID_ARG, "problem %d: sizes must be positive (m=%d n=%d L=%lld)", p,
+                    d.n_cams, d.n_points, (long long)d.n_obs);
+    if (!d.obs_cam || !d.obs_point || !d.obs_uv || !d.cams || !d.points)
+        return fail(h, DBA_E_INVALID_ARG, "problem %d: null array", p);
+    if (d.n_obs > (1LL << 30))
+        return fail(h, DBA_E_INVALID_ARG, "problem %d: too many observations", p);
+    std::vector<int> cc(d.n_cams, 0), pc(d.n_points, 0);
+    for (long long k = 0; k < d.n_obs; ++k) {
+        const int j = d.obs_cam[k], i = d.obs_point[k];
+        if (j < 0 || j >= d.n_cams || i < 0 || i >= d.n_points)
+            return fail(h, DBA_E_INDEX_RANGE, "problem %d: observation %lld has camera %d / point %d out of range",
+                        p, k, j, i);
+        ++cc[j];
+        ++pc[i];
+        if (!std::isfinite(d.obs_uv[2 * k]) || !std::isfinite(d.obs_uv[2 * k + 1]))
+            return fail(h, DBA_E_NONFINITE, "problem %d: observation %lld is not finite", p, k);
+    }
+    for (long long q = 0; q < 9LL * d.n_cams; ++q)
+        if (!std::isfinite(d.cams[q])) return fail(h, DBA_E_NONFINITE, "problem %d: camera value %lld not finite", p, q);
+    for (long long q = 0; q < 3LL * d.n_points; ++q)
+        if (!std::isfinite(d.points[q])) return fail(h, DBA_E_NONFINITE, "problem %d: point value %lld not finite", p, q);
+    for (int j = 0; j < d.n_cams; ++j)
+        if (!cc[j]) return fail(h, DBA_E_UNOBSERVED, "problem %d: camera %d has no observation", p, j);
+    for (int i = 0; i < d.n_points; ++i)
+        if (!pc[i]) return fail(h, DBA_E_UNOBSERVED, "problem %d: point %d has no observation", p, i);
+    for (long long k = 0; k < d.n_obs; ++k) {
+        const double z = host_depth(d.cams + 9LL * d.obs_cam[k], d.points + 3LL * d.obs_point[k]);
+        if (!(z > 1e-6))
+            return fail(h, DBA_E_BEHIND_CAMERA, "problem %d: observation %lld has depth %g at the initial estimate",
+                        p, k, z);
+    }
+    return DBA_OK;
+}
+
+template <typename R>
+int build_set(dba_handle *h, int np, const dba_problem_desc *probs, ProblemSet *ps, DevArrays<R> &A)
+{
+    using R2 = typename dba::Vec<R>::R2;
+    using R4 = typename dba::Vec<R>::R4;
+    const int CH = dba::kChunk;
+    // global sizes
+    long long n_chunks = 0, n_recs = 0;
+    int n_cams = 0, n_pts = 0;
+    ps->n_problems = np;
+    for (int p = 0; p < np; ++p) {
+        const dba_problem_desc &d = probs[p];
+        std::vector<int> cc(d.n_cams, 0);
+        for (long long k = 0; k < d.n_obs; ++k) ++cc[d.obs_cam[k]];
+        ProblemRange r{};
+        r.cam0 = n_cams; r.n_cams = d.n_cams;
+        r.pt0 = n_pts; r.n_points = d.n_points;
+        r.chunk0 = (int)n_chunks;
+        long long ch = 0;
+        for (int j = 0; j < d.n_cams; ++j) ch += (cc[j] + CH - 1) / CH;
+        r.n_chunks = (int)ch;
+        r.rec0 = n_recs; r.n_obs = d.n_obs;
+        ps->ranges.push_back(r);
+        ps->m.push_back(d.n_cams);
+        ps->n.push_back(d.n_points);
+        ps->L.push_back(d.n_obs);
+        n_cams += d.n_cams;
+        n_pts += d.n_points;
+        n_chunks += ch;
+        n_recs += d.n_obs;
+    }
+    const long long S = n_chunks * CH;
+    if (S >= (1LL << 31) || n_recs >= (1LL << 31))
+        return fail(h, DBA_E_INVALID_ARG, "problem set too large (%lld slots)", S);
+    ps->n_slots = S;
+
+    std::vector<R2> uv(S);
+    std::vector<int> pslot(S, -1), ptid(S, 0), orig(S, 0);
+    std::vector<uint8_t> mask(S, 1);
+    std::vector<R> copy_y(9 * (size_t)S, R(0));
+    std::vector<R4> xrec(n_recs);
+    std::vector<int> pt_off(n_pts + 1, 0), chunk_cam(n_chunks), cam_prob(n_cams), pt_prob(n_pts),
+        cam_chunk0(n_cams + 1), cam_count(n_cams);
+    std::vector<double> cons_y((size_t)n_cams * dba::kConsY, 0.0);
+    std::vector<double4> cons_x(n_pts);
+    std::vector<Ctrl> ctrl(np);
+
+    for (int p = 0; p < np; ++p) {
+        const dba_problem_desc &d = probs[p];
+        const ProblemRange &r = ps->ranges[p];
+        const long long L = d.n_obs;
+        // point-major records, stable in observation order
+        std::vector<int> poff(d.n_points + 1, 0);
+        for (long long k = 0; k < L; ++k) ++poff[d.obs_point[k] + 1];
+        for (int i = 0; i < d.n_points; ++i) poff[i + 1] += poff[i];
+        std::vector<int> fill(poff.begin(), poff.end() - 1);
+        std::vector<int> rec_obs(L);
+        for (long long k = 0; k < L; ++k) rec_obs[fill[d.obs_point[k]]++] = (int)k;
+        for (int i = 0; i <= d.n_points; ++i) pt_off[r.pt0 + i] = (int)(r.rec0 + poff[i]);
+        for (int i = 0; i < d.n_points; ++i) {
+            pt_prob[r.pt0 + i] = p;
+            cons_x[r.pt0 + i] = make_double4(d.points[3 * i], d.points[3 * i + 1], d.points[3 * i + 2], 0.0);
+        }
+        // camera-major slots, stable in record order
+        std::vector<int> cc(d.n_cams, 0);
+        for (long long k = 0; k < L; ++k) ++cc[d.obs_cam[k]];
+        std::vector<long long> cslot(d.n_cams);
+        int chunk = r.chunk0;
+        for (int j = 0; j < d.n_cams; ++j) {
+            const int J = r.cam0 + j;
+            cam_prob[J] = p;
+            cam_chunk0[J] = chunk;
+            cam_count[J] = cc[j];
+            cslot[j] = (long long)chunk * CH;
+            const int nch = (cc[j] + CH - 1) / CH;
+            for (int q = 0; q < nch; ++q) chunk_cam[chunk + q] = J;
+            chunk += nch;
+            for (int c = 0; c < 9; ++c) cons_y[(size_t)J * dba::kConsY + c] = d.cams[9 * j + c];
+        }
+        for (long long rr = 0; rr < L; ++rr) {
+            const int k = rec_obs[rr];
+            const int j = d.obs_cam[k], i = d.obs_point[k];
+            const long long s = cslot[j]++;
+            pslot[s] = (int)(r.rec0 + rr);
+            ptid[s] = r.pt0 + i;
+            orig[s] = k;
+            uv[s].x = (R)d.obs_uv[2 * k];
+            uv[s].y = (R)d.obs_uv[2 * k + 1];
+            for (int c = 0; c < 9; ++c) copy_y[(size_t)c * S + s] = (R)d.cams[9 * j + c];
+            R4 x;
+            x.x = (R)d.points[3 * i]; x.y = (R)d.points[3 * i + 1]; x.z = (R)d.points[3 * i + 2]; x.w = R(0);
+            xrec[r.rec0 + rr] = x;
+        }
+        Ctrl &c = ctrl[p];
+        std::memset(&c, 0, sizeof(c));
+        c.rho_x = h->opt.rho_x;
+        c.rho_y = h->opt.rho_y;
+        c.ratio_x = c.ratio_y = 1.0;
+        c.last_rho_x = h->opt.rho_x;
+        c.last_rho_y = h->opt.rho_y;
+        c.rb_mu = h->opt.rb_mu;
+        c.rb_tau = h->opt.rb_tau;
+        c.rho_min = h->opt.rho_min;
+        c.rho_max = h->opt.rho_max;
+        c.balancing = h->opt.rho_balancing ? 1 : 0;
+    }
+    cam_chunk0[n_cams] = (int)n_chunks;
+
+    // device
+    Buffers &B = ps->buf;
+    R2 *d_uv; int *d_pslot, *d_ptid, *d_orig; uint8_t *d_mask; R *d_copy; double *d_dual;
+    R4 *d_xrec; double4 *d_urec; int *d_ptoff, *d_chunk_cam, *d_cam_prob, *d_pt_prob, *d_cam_chunk0, *d_cam_count;
+    double *d_cons_y; double4 *d_cons_x; Ctrl *d_ctrl; ProblemRange *d_prob;
+    double *d_cpart, *d_ppart, *d_campart, *d_epart, *d_estats;
+    HIP_TRY(h, B.alloc(&d_uv, S));
+    HIP_TRY(h, B.alloc(&d_pslot, S));
+    HIP_TRY(h, B.alloc(&d_ptid, S));
+    HIP_TRY(h, B.alloc(&d_orig, S));
+    HIP_TRY(h, B.alloc(&d_mask, S));
+    HIP_TRY(h, B.alloc(&d_copy, 9 * (size_t)S));
+    HIP_TRY(h, B.alloc(&d_dual, 9 * (size_t)S));
+    HIP_TRY(h, B.alloc(&d_xrec, n_recs));
+    HIP_TRY(h, B.alloc(&d_urec, n_recs));
+    HIP_TRY(h, B.alloc(&d_ptoff, n_pts + 1));
+    HIP_TRY(h, B.alloc(&d_chunk_cam, n_chunks));
+    HIP_TRY(h, B.alloc(&d_cam_prob, n_cams));
+    HIP_TRY(h, B.alloc(&d_pt_prob, n_pts));
+    HIP_TRY(h, B.alloc(&d_cam_chunk0, n_cams + 1));
+    HIP_TRY(h, B.alloc(&d_cam_count, n_cams));
+    HIP_TRY(h, B.alloc(&d_cons_y, (size_t)n_cams * dba::kConsY));
+    HIP_TRY(h, B.alloc(&d_cons_x, n_pts));
+    HIP_TRY(h, B.alloc(&d_ctrl, np));
+    HIP_TRY(h, B.alloc(&d_prob, np));
+    HIP_TRY(h, B.alloc(&d_cpart, (size_t)n_chunks * dba::kCpart));
+    HIP_TRY(h, B.alloc(&d_ppart, 2 * (size_t)n_pts));
+    HIP_TRY(h, B.alloc(&d_campart, 2 * (size_t)n_cams));
+    HIP_TRY(h, B.alloc(&d_epart, (size_t)n_chunks * dba::kEpart));
+    HIP_TRY(h, B.alloc(&d_estats, (size_t)np * dba::kEpart));
+
+    HIP_TRY(h, hipMemcpy(d_uv, uv.data(), S * sizeof(R2), hipMemcpyHostToDevice));
+    HIP_TRY(h, hipMemcpy(d_pslot, pslot.data(), S * sizeof(int), hipMemcpyHostToDevice));
+    HIP_TRY(h, hipMemcpy(d_ptid, ptid.data(), S * sizeof(int), hipMemcpyHostToDevice));
+    HIP_TRY(h, hipMemcpy(d_orig, orig.data(), S * sizeof(int), hipMemcpyHostToDevice));
+    HIP_TRY(h, hipMemcpy(d_mask, mask.data(), S, hipMemcpyHostToDevice));
+    HIP_TRY(h, hipMemcpy(d_copy, copy_y.data(), 9 * (size_t)S * sizeof(R), hipMemcpyHostToDevice));
+    HIP_TRY(h, hipMemset(d_dual, 0, 9 * (size_t)S * sizeof(double)));
+    HIP_TRY(h, hipMemcpy(d_xrec, xrec.data(), n_recs * sizeof(R4), hipMemcpyHostToDevice));
+    HIP_TRY(h, hipMemset(d_urec, 0, n_recs * sizeof(double4)));
+    HIP_TRY(h, hipMemcpy(d_ptoff, pt_off.data(), (n_pts + 1) * sizeof(int), hipMemcpyHostToDevice));
+    HIP_TRY(h, hipMemcpy(d_chunk_cam, chunk_cam.data(), n_chunks * sizeof(int), hipMemcpyHostToDevice));
+    HIP_TRY(h, hipMemcpy(d_cam_prob, cam_prob.data(), n_cams * sizeof(int), hipMemcpyHostToDevice));
+    HIP_TRY(h, hipMemcpy(d_pt_prob, pt_prob.data(), n_pts * sizeof(int), hipMemcpyHostToDevice));
+    HIP_TRY(h, hipMemcpy(d_cam_chunk0, cam_chunk0.data(), (n_cams + 1) * sizeof(int), hipMemcpyHostToDevice));
+    HIP_TRY(h, hipMemcpy(d_cam_count, cam_count.data(), n_cams * sizeof(int), hipMemcpyHostToDevice));
+    HIP_TRY(h, hipMemcpy(d_cons_y, cons_y.data(), cons_y.size() * sizeof(double), hipMemcpyHostToDevice));
+    HIP_TRY(h, hipMemcpy(d_cons_x, cons_x.data(), n_pts * sizeof(double4), hipMemcpyHostToDevice));
+    HIP_TRY(h, hipMemcpy(d_ctrl, ctrl.data(), np * sizeof(Ctrl), hipMemcpyHostToDevice));
+    HIP_TRY(h, hipMemcpy(d_prob, ps->ranges.data(), np * sizeof(ProblemRange), hipMemcpyHostToDevice));
+    HIP_TRY(h, hipMemset(d_cpart, 0, (size_t)n_chunks * dba::kCpart * sizeof(double)));
+
+    A.n_slots = S;
+    A.uv = d_uv; A.pslot = d_pslot; A.ptid = d_ptid;
+    A.copy_y = d_copy; A.dual_y = d_dual; A.mask = d_mask; A.slot_orig = d_orig;
+    A.n_recs = n_recs; A.xrec = d_xrec; A.urec = d_urec; A.pt_off = d_ptoff;
+    A.n_chunks = (int)n_chunks; A.n_cams = n_cams; A.n_pts = n_pts; A.n_problems = np;
+    A.chunk_cam = d_chunk_cam; A.cam_prob = d_cam_prob; A.pt_prob = d_pt_prob;
+    A.cam_chunk0 = d_cam_chunk0; A.cam_count = d_cam_count;
+    A.cons_y = d_cons_y; A.cons_x = d_cons_x; A.ctrl = d_ctrl; A.prob = d_prob;
+    A.cpart = d_cpart; A.ppart = d_ppart; A.campart = d_campart; A.epart = d_epart; A.estats = d_estats;
+    ps->mask = d_mask;
+    return DBA_OK;
+}
+
+// One ADMM iteration, eager.
+template <typename R>
+hipError_t run_iteration(dba_handle *h, const DevArrays<R> &A, int bw, int pers, bool timed)
+{
+    Timing &T = h->timing;
+    auto mark = [&](int kid) -> hipEvent_t {
+        if (!timed) return nullptr;
+        if (T.used + 2 > T.pool.size()) {
+            for (int q = 0; q < 64; ++q) {
+                hipEvent_t e;
+                if (hipEventCreate(&e) != hipSuccess) return nullptr;
+                T.pool.push_back(e);
+            }
+        }
+        hipEvent_t e0 = T.pool[T.used];
+        (void)hipEventRecord(e0, h->stream);
+        T.pending_kernel.push_back(kid);
+        T.used += 2;
+        return T.pool[T.used - 1];
+    };
+    auto done = [&](hipEvent_t e1) {
+        if (e1) (void)hipEventRecord(e1, h->stream);
+    };
+    hipEvent_t e;
+    hipError_t err;
+    e = mark(0);
+    err = dba::launch_local<R>(A, h->sp, bw, pers, h->n_cu, h->stream);
+    done(e);
+    if (err != hipSuccess) return err;
+    e = mark(1);
+    err = dba::launch_consensus<R>(A, h->stream);
+    done(e);
+    if (err != hipSuccess) return err;
+    e = mark(2);
+    err = dba::launch_norms<R>(A, h->stream);
+    done(e);
+    return err;
+}
+
+int collect_timing(dba_handle *h)
+{
+    Timing &T = h->timing;
+    if (T.used == 0) return DBA_OK;
+    HIP_TRY(h, hipStreamSynchronize(h->stream));
+    for (size_t q = 0; q < T.pending_kernel.size(); ++q) {
+        float ms = 0.f;
+        HIP_TRY(h, hipEventElapsedTime(&ms, T.pool[2 * q], T.pool[2 * q + 1]));
+        T.total_ms[T.pending_kernel[q]] += ms;
+        T.launches[T.pending_kernel[q]] += 1;
+    }
+    T.pending_kernel.clear();
+    T.used = 0;
+    return DBA_OK;
+}
+
+template <typename R>
+int iterate_impl(dba_handle *h, const DevArrays<R> &A, int n)
+{
+    static const int cand_bw[] = {1, 2, 4, 8, 1, 2, 4, 8};
+    static const int cand_p[] = {0, 0, 0, 0, 1, 1, 1, 1};
+    // autotune on real iterations: every schedule gives bitwise-identical
+    // results, so tuning does not change the trajectory
+    while (!h->schedule_ready && n > 0) {
+        const bool tune_bw = h->opt.block_waves == 0, tune_p = h->opt.persistent < 0;
+        std::vector<int> idx;
+        for (int q = 0; q < 8; ++q)
+            if ((tune_bw || cand_bw[q] == h->opt.block_waves) && (tune_p || cand_p[q] == h->opt.persistent))
+                idx.push_back(q);
+        if (h->tune_next == 0) {  // warm-up iteration, untimed
+            HIP_TRY(h, run_iteration<R>(h, A, cand_bw[idx[0]], cand_p[idx[0]], false));
+            h->tune_next = 1;
+            h->tune_ms.clear();
+            --n;
+            continue;
+        }
+        const int q = idx[h->tune_next - 1];
+        hipEvent_t e0, e1;
+        HIP_TRY(h, hipEventCreate(&e0));
+        HIP_TRY(h, hipEventCreate(&e1));
+        HIP_TRY(h, hipEventRecord(e0, h->stream));
+        HIP_TRY(h, dba::launch_local<R>(A, h->sp, cand_bw[q], cand_p[q], h->n_cu, h->stream));
+        HIP_TRY(h, hipEventRecord(e1, h->stream));
+        HIP_TRY(h, dba::launch_consensus<R>(A, h->stream));
+        HIP_TRY(h, dba::launch_norms<R>(A, h->stream));
+        HIP_TRY(h, hipEventSynchronize(e1));
+        float ms = 0.f;
+        HIP_TRY(h, hipEventElapsedTime(&ms, e0, e1));
+        (void)hipEventDestroy(e0);
+        (void)hipEventDestroy(e1);
+        h->tune_ms.push_back(ms);
+        --n;
+        if (++h->tune_next > (int)idx.size()) {
+            int best = 0;
+            for (int t = 1; t < (int)h->tune_ms.size(); ++t)
+                if (h->tune_ms[t] < h->tune_ms[best]) best = t;
+            h->block_waves = cand_bw[idx[best]];
+            h->persistent = cand_p[idx[best]];
+            h->tuned = (int)idx.size();
+            h->schedule_ready = true;
+        }
+    }
+    if (n <= 0) return DBA_OK;
+    if (h->timing.on || !h->opt.use_graph) {
+        for (int it = 0; it < n; ++it) HIP_TRY(h, run_iteration<R>(h, A, h->block_waves, h->persistent, h->timing.on));
+        if (h->timing.on) return collect_timing(h);
+        return DBA_OK;
+    }
+    for (int g = 0; g < 2; ++g) {
+        if (h->gexec[g]) continue;
+        const int iters = g == 0 ? 1 : kGraphBatch;
+        hipGraph_t graph;
+        HIP_TRY(h, hipStreamBeginCapture(h->stream, hipStreamCaptureModeThreadLocal));
+        hipError_t err = hipSuccess;
+        for (int it = 0; it < iters && err == hipSuccess; ++it)
+            err = run_iteration<R>(h, A, h->block_waves, h->persistent, false);
+        hipError_t e2 = hipStreamEndCapture(h->stream, &graph);
+        if (err != hipSuccess) return fail(h, DBA_E_DEVICE, "graph capture: %s", hipGetErrorString(err));
+        HIP_TRY(h, e2);
+        err = hipGraphInstantiate(&h->gexec[g], graph, nullptr, nullptr, 0);
+        (void)hipGraphDestroy(graph);
+        HIP_TRY(h, err);
+    }
+    while (n >= kGraphBatch) {
+        HIP_TRY(h, hipGraphLaunch(h->gexec[1], h->stream));
+        n -= kGraphBatch;
+    }
+    for (; n > 0; --n) HIP_TRY(h, hipGraphLaunch(h->gexec[0], h->stream));
+    return DBA_OK;
+}
+
+void free_set(dba_handle *h)
+{
+    drop_graphs(h);
+    delete h->ps;
+    h->ps = nullptr;
+}
+
+int check_problem(const dba_handle *h, int p)
+{
+    if (!h->ps) return DBA_E_STATE;
+    if (p < 0 || p >= h->ps->n_problems) return DBA_E_INVALID_ARG;
+    return DBA_OK;
+}
+
+}  // namespace
+
+// ============================================================================
+extern "C" {
+
+int dba_default_options(dba_options *o)
+{
+    if (!o) return DBA_E_INVALID_ARG;
+    std::memset(o, 0, sizeof(*o));
+    o->device = 0;
+    o->stream = nullptr;
+    o->precision = DBA_PREC_FP64;
+    o->loss = DBA_LOSS_HUBER;
+    o->loss_param = 2.0;
+    o->rho_x = o->rho_y = 1.0;
+    o->rho_balancing = 0;
+    o->rb_mu = 10.0;
+    o->rb_tau = 2.0;
+    o->rho_min = 1e-6;
+    o->rho_max = 1e6;
+    o->lm_steps = 5;
+    o->lm_lambda0 = 1e-3;
+    o->start = DBA_START_PLAIN;
+    o->learned_lm_steps = 2;
+    o->use_graph = 1;
+    o->block_waves = 0;
+    o->persistent = -1;
+    return DBA_OK;
+}
+
+int dba_create(const dba_options *opt, dba_handle **out)
+{
+    if (!opt || !out) return DBA_E_INVALID_ARG;
+    *out = nullptr;
+    const dba_options &o = *opt;
+    if (o.precision != DBA_PREC_FP64 && o.precision != DBA_PREC_FP32_LOCAL) return DBA_E_INVALID_ARG;
+    if (o.loss < 0 || o.loss > 2) return DBA_E_INVALID_ARG;
+    if ((o.loss != DBA_LOSS_L2) && !(o.loss_param > 0)) return DBA_E_INVALID_ARG;
+    if (!(o.rho_x > 0) || !(o.rho_y > 0)) return DBA_E_INVALID_ARG;
+    if (o.lm_steps < 1 || o.lm_steps > 64 || !(o.lm_lambda0 > 0)) return DBA_E_INVALID_ARG;
+    if (o.rho_balancing && (!(o.rb_mu > 1) || !(o.rb_tau > 1) || !(o.rho_min > 0) || !(o.rho_max >= o.rho_min)))
+        return DBA_E_INVALID_ARG;
+    if (o.block_waves != 0 && o.block_waves != 1 && o.block_waves != 2 && o.block_waves != 4 && o.block_waves != 8)
+        return DBA_E_INVALID_ARG;
+    if (o.persistent < -1 || o.persistent > 1) return DBA_E_INVALID_ARG;
+    if (o.start != DBA_START_PLAIN) return DBA_E_INVALID_ARG;  // learned start needs dba_set_mlp
+    dba_handle *h = new dba_handle();
+    h->opt = o;
+    h->fp32 = o.precision == DBA_PREC_FP32_LOCAL;
+    h->sp.loss = o.loss;
+    h->sp.loss_param = o.loss == DBA_LOSS_L2 ? 1.0 : o.loss_param;
+    h->sp.lm_steps = o.lm_steps;
+    h->sp.lambda0 = o.lm_lambda0;
+    if (hipSetDevice(o.device) != hipSuccess) {
+        delete h;
+        return DBA_E_DEVICE;
+    }
+    hipDeviceProp_t prop;
+    if (hipGetDeviceProperties(&prop, o.device) == hipSuccess) h->n_cu = prop.multiProcessorCount;
+    if (o.stream) {
+        h->stream = static_cast<hipStream_t>(o.stream);
+    } else {
+        if (hipStreamCreate(&h->stream) != hipSuccess) {
+            delete h;
+            return DBA_E_DEVICE;
+        }
+        h->own_stream = true;
+    }
+    h->block_waves = o.block_waves ? o.block_waves : 4;
+    h->persistent = o.persistent < 0 ? 0 : o.persistent;
+    h->schedule_ready = o.block_waves != 0 && o.persistent >= 0;
+    *out = h;
+    return DBA_OK;
+}
+
+void dba_destroy(dba_handle *h)
+{
+    if (!h) return;
+    (void)hipSetDevice(h->opt.device);
+    if (h->stream) (void)hipStreamSynchronize(h->stream);
+    free_set(h);
+    for (hipEvent_t e : h->timing.pool) (void)hipEventDestroy(e);
+    if (h->own_stream) (void)hipStreamDestroy(h->stream);
+    delete h;
+}
+
+const char *dba_last_error(const dba_handle *h) { return h ? h->err.c_str() : "null handle"; }
+
+int dba_set_problems(dba_handle *h, int32_t np, const dba_problem_desc *probs)
+{
+    if (!h) return DBA_E_INVALID_ARG;
+    h->err.clear();
+    if (np < 1 || !probs) return fail(h, DBA_E_INVALID_ARG, "need at least one problem");
+    for (int p = 0; p < np; ++p) {
+        const int rc = validate(h, p, probs[p]);
+        if (rc != DBA_OK) return rc;
+    }
+    HIP_TRY(h, hipSetDevice(h->opt.device));
+    HIP_TRY(h, hipStreamSynchronize(h->stream));
+    ProblemSet *ps = new ProblemSet();
+    const int rc = h->fp32 ? build_set<float>(h, np, probs, ps, ps->a32)
+                           : build_set<double>(h, np, probs, ps, ps->a64);
+    if (rc != DBA_OK) {
+        delete ps;
+        return rc;
+    }
+    free_set(h);
+    h->ps = ps;
+    h->schedule_ready = h->opt.block_waves != 0 && h->opt.persistent >= 0;
+    h->tune_next = 0;
+    return DBA_OK;
+}
+
+int dba_set_problem(dba_handle *h, int32_t n_cams, int32_t n_points, int64_t n_obs, const int32_t *obs_cam,
+                    const int32_t *obs_point, const double *obs_uv, const double *cams, const double *points)
+{
+    dba_problem_desc d{n_cams, n_points, n_obs, obs_cam, obs_point, obs_uv, cams, points};
+    return dba_set_problems(h, 1, &d);
+}
+
+int dba_iterate(dba_handle *h, int32_t n_iters)
+{
+    if (!h) return DBA_E_INVALID_ARG;
+    h->err.clear();
+    if (!h->ps) return fail(h, DBA_E_STATE, "no problem set");
+    if (n_iters < 0) return fail(h, DBA_E_INVALID_ARG, "n_iters < 0");
+    HIP_TRY(h, hipSetDevice(h->opt.device));
+    return h->fp32 ? iterate_impl<float>(h, h->ps->a32, n_iters) : iterate_impl<double>(h, h->ps->a64, n_iters);
+}
+
+int dba_residuals(dba_handle *h, int32_t p, int32_t want_rmse, dba_residual_report *out)
+{
+    if (!h || !out) return DBA_E_INVALID_ARG;
+    h->err.clear();
+    int rc = check_problem(h, p);
+    if (rc != DBA_OK) return fail(h, rc, "bad problem index %d", p);
+    HIP_TRY(h, hipSetDevice(h->opt.device));
+    ProblemSet &ps = *h->ps;
+    Ctrl c;
+    const Ctrl *dctrl = h->fp32 ? ps.a32.ctrl : ps.a64.ctrl;
+    HIP_TRY(h, hipMemcpyAsync(&c, dctrl + p, sizeof(Ctrl), hipMemcpyDeviceToHost, h->stream));
+    std::memset(out, 0, sizeof(*out));
+    double st[dba::kEpart] = {0, 0, 0, 0, 0};
+    if (want_rmse) {
+        hipError_t e = h->fp32 ? dba::launch_eval<float>(ps.a32, h->sp, h->stream)
+                               : dba::launch_eval<double>(ps.a64, h->sp, h->stream);
+        HIP_TRY(h, e);
+        const double *dst = (h->fp32 ? ps.a32.estats : ps.a64.estats) + (size_t)p * dba::kEpart;
+        HIP_TRY(h, hipMemcpyAsync(st, dst, sizeof(st), hipMemcpyDeviceToHost, h->stream));
+    }
+    HIP_TRY(h, hipStreamSynchronize(h->stream));
+    out->primal = c.primal;
+    out->dual = c.dual;
+    out->rho_x = c.last_rho_x;
+    out->rho_y = c.last_rho_y;
+    out->next_rho_x = c.rho_x;
+    out->next_rho_y = c.rho_y;
+    out->iteration = c.iteration;
+    out->nonfinite = c.nonfinite;
+    if (want_rmse) {
+        const double L = (double)ps.L[p];
+        out->rmse = std::sqrt(st[0] / L);
+        out->robust_cost = st[1];
+        out->mean_error = st[2] / L;
+        out->rmse_masked = st[4] > 0 ? std::sqrt(st[3] / st[4]) : 0.0;
+        if (!std::isfinite(st[0])) out->nonfinite = 1;
+    }
+    return DBA_OK;
+}
+
+int dba_set_eval_mask(dba_handle *h, int32_t p, const uint8_t *mask)
+{
+    if (!h) return DBA_E_INVALID_ARG;
+    h->err.clear();
+    int rc = check_problem(h, p);
+    if (rc != DBA_OK) return fail(h, rc, "bad problem index %d", p);
+    HIP_TRY(h, hipSetDevice(h->opt.device));
+    ProblemSet &ps = *h->ps;
+    const ProblemRange &r = ps.ranges[p];
+    const long long s0 = (long long)r.chunk0 * dba::kChunk, ns = (long long)r.n_chunks * dba::kChunk;
+    std::vector<int> orig(ns), pslot(ns);
+    const int *d_orig = h->fp32 ? ps.a32.slot_orig : ps.a64.slot_orig;
+    const int *d_pslot = h->fp32 ? ps.a32.pslot : ps.a64.pslot;
+    HIP_TRY(h, hipMemcpy(orig.data(), d_orig + s0, ns * sizeof(int), hipMemcpyDeviceToHost));
+    HIP_TRY(h, hipMemcpy(pslot.data(), d_pslot + s0, ns * sizeof(int), hipMemcpyDeviceToHost));
+    std::vector<uint8_t> m(ns, 1);
+    if (mask)
+        for (long long s = 0; s < ns; ++s) m[s] = pslot[s] >= 0 ? (mask[orig[s]] != 0) : 0;
+    HIP_TRY(h, hipStreamSynchronize(h->stream));
+    HIP_TRY(h, hipMemcpy(ps.mask + s0, m.data(), ns, hipMemcpyHostToDevice));
+    return DBA_OK;
+}
+
+int dba_get_params(dba_handle *h, int32_t p, double *cams, double *points)
+{
+    if (!h) return DBA_E_INVALID_ARG;
+    h->err.clear();
+    int rc = check_problem(h, p);
+    if (rc != DBA_OK) return fail(h, rc, "bad problem index %d", p);
+    HIP_TRY(h, hipSetDevice(h->opt.device));
+    ProblemSet &ps = *h->ps;
+    const ProblemRange &r = ps.ranges[p];
+    std::vector<double> cy((size_t)r.n_cams * dba::kConsY);
+    std::vector<double4> cx(r.n_points);
+    const double *dcy = h->fp32 ? ps.a32.cons_y : ps.a64.cons_y;
+    const double4 *dcx = h->fp32 ? ps.a32.cons_x : ps.a64.cons_x;
+    HIP_TRY(h, hipMemcpyAsync(cy.data(), dcy + (size_t)r.cam0 * dba::kConsY, cy.size() * sizeof(double),
+                              hipMemcpyDeviceToHost, h->stream));
+    HIP_TRY(h, hipMemcpyAsync(cx.data(), dcx + r.pt0, cx.size() * sizeof(double4), hipMemcpyDeviceToHost,
+                              h->stream));
+    HIP_TRY(h, hipStreamSynchronize(h->stream));
+    if (cams)
+        for (int j = 0; j < r.n_cams; ++j)
+            for (int c = 0; c < 9; ++c) cams[9 * (size_t)j + c] = cy[(size_t)j * dba::kConsY + c];
+    if (points)
+        for (int i = 0; i < r.n_points; ++i) {
+            points[3 * (size_t)i] = cx[i].x;
+            points[3 * (size_t)i + 1] = cx[i].y;
+            points[3 * (size_t)i + 2] = cx[i].z;
+        }
+    return DBA_OK;
+}
+
+int dba_get_state(dba_handle *h, int32_t p, double *copies, double *duals)
+{
+    if (!h) return DBA_E_INVALID_ARG;
+    h->err.clear();
+    int rc = check_problem(h, p);
+    if (rc != DBA_OK) return fail(h, rc, "bad problem index %d", p);
+    HIP_TRY(h, hipSetDevice(h->opt.device));
+    ProblemSet &ps = *h->ps;
+    const long long L = ps.L[p];
+    double *d = nullptr;
+    HIP_TRY(h, hipMalloc(&d, 24 * (size_t)L * sizeof(double)));
+    hipError_t e = h->fp32 ? dba::launch_materialize<float>(ps.a32, p, d, d + 12 * L, h->stream)
+                           : dba::launch_materialize<double>(ps.a64, p, d, d + 12 * L, h->stream);
+    if (e == hipSuccess && copies)
+        e = hipMemcpyAsync(copies, d, 12 * L * sizeof(double), hipMemcpyDeviceToHost, h->stream);
+    if (e == hipSuccess && duals)
+        e = hipMemcpyAsync(duals, d + 12 * L, 12 * L * sizeof(double), hipMemcpyDeviceToHost, h->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(h->stream);
+    (void)hipFree(d);
+    HIP_TRY(h, e);
+    return DBA_OK;
+}
+
+int dba_problem_info(const dba_handle *h, int32_t p, int32_t *m, int32_t *n, int64_t *L)
+{
+    if (!h) return DBA_E_INVALID_ARG;
+    if (!h->ps) return DBA_E_STATE;
+    if (p < 0 || p >= h->ps->n_problems) return DBA_E_INVALID_ARG;
+    if (m) *m = h->ps->m[p];
+    if (n) *n = h->ps->n[p];
+    if (L) *L = h->ps->L[p];
+    return DBA_OK;
+}
+
+int dba_set_kernel_timing(dba_handle *h, int32_t enable)
+{
+    if (!h) return DBA_E_INVALID_ARG;
+    h->err.clear();
+    int rc = collect_timing(h);
+    if (rc != DBA_OK) return rc;
+    h->timing.on = enable != 0;
+    for (int k = 0; k < kKernels; ++k) {
+        h->timing.total_ms[k] = 0.0;
+        h->timing.launches[k] = 0;
+    }
+    return DBA_OK;
+}
+
+int dba_kernel_times(dba_handle *h, double *total_ms, int64_t *launches)
+{
+    if (!h || !total_ms || !launches) return DBA_E_INVALID_ARG;
+    h->err.clear();
+    int rc = collect_timing(h);
+    if (rc != DBA_OK) return rc;
+    for (int k = 0; k < kKernels; ++k) {
+        total_ms[k] = h->timing.total_ms[k];
+        launches[k] = h->timing.launches[k];
+    }
+    return DBA_OK;
+}
+
+int dba_schedule(const dba_handle *h, int32_t *bw, int32_t *pers, int32_t *tuned)
+{
+    if (!h) return DBA_E_INVALID_ARG;
+    if (bw) *bw = h->block_waves;
+    if (pers) *pers = h->persistent;
+    if (tuned) *tuned = h->tuned;
+    return DBA_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,693 @@
+// dba_kernels.hip -- gfx950 kernels of one ADMM bundle-adjustment iteration
+// (Ramamurthy et al., "Distributed Bundle Adjustment", Sec. 3.1, Eqs. 9-13).
+//
+// local      one lane per observation (wave64 = one 64-slot chunk of one
+//            camera).  Applies the deferred scaled-dual update of the
+//            previous iteration, then minimises the local objective of Eq. (9)
+//            in scaled form, F = phi(|z - pi(theta)|^2) + 1/2 (theta - v)^T P
+//            (theta - v), by robust Levenberg-Marquardt: 12x12 normal
+//            equations and their Cholesky factor live in registers.  Emits the
+//            chunk's sums for the camera consensus with a fixed butterfly.
+// consensus  point consensus (Eq. 10): one thread per point, ascending record
+//            order; camera consensus (Eq. 11): one wave per camera summing its
+//            chunk partials in ascending chunk order.  Both in FP64.
+// norms      one workgroup per problem: primal/dual residual norms, residual
+//            balancing of rho, rescale factor for the pending dual update.
+// eval       reprojection statistics at the consensus estimate (FP64).
+//
+// Every reduction has a fixed order that does not depend on the launch
+// schedule, so all schedules (and batched vs solo runs) are bitwise equal.
+#include "dba_internal.h"
+
+#include <math.h>
+
+namespace dba {
+namespace {
+
+template <typename R> struct Num;
+template <> struct Num<float> {
+    static constexpr float small2 = 0.0625f;  // |w| < 0.25: Rodrigues coefficients by series
+    __device__ static float rcp(float x) { return __builtin_amdgcn_rcpf(x); }
+    __device__ static float sqrt(float x) { return sqrtf(x); }
+    __device__ static float rsqrt(float x) { return rsqrtf(x); }
+    __device__ static void sincos(float x, float *s, float *c) { sincosf(x, s, c); }
+    __device__ static float log1p(float x) { return log1pf(x); }
+    __device__ static float div(float x, float y) { return x * __builtin_amdgcn_rcpf(y); }
+    static constexpr float inf = __builtin_huge_valf();
+    static constexpr float tie = 1e-6f;       // predicted decrease F cannot resolve
+};
+template <> struct Num<double> {
+    static constexpr double small2 = 1e-4;    // |w| < 1e-2
+    __device__ static double rcp(double x) { return 1.0 / x; }
+    __device__ static double sqrt(double x) { return ::sqrt(x); }
+    __device__ static double rsqrt(double x) { return 1.0 / ::sqrt(x); }
+    __device__ static void sincos(double x, double *s, double *c) { ::sincos(x, s, c); }
+    __device__ static double log1p(double x) { return ::log1p(x); }
+    __device__ static double div(double x, double y) { return x / y; }
+    static constexpr double inf = __builtin_huge_val();
+    static constexpr double tie = 1e-13;
+};
+
+constexpr int IX(int i, int j) { return i * (i + 1) / 2 + j; }  // packed lower triangle
+
+// Rodrigues coefficients of R(w) X = c X + a (w x X) + b (w.X) w and, for the
+// Jacobian, a1 = a'(t)/t and b1 = b'(t)/t; 1 - cos t is formed as 2 sin^2(t/2).
+template <typename R, bool DERIV>
+__device__ __forceinline__ void rot_coeffs(R t2, R &c, R &a, R &b, R &a1, R &b1)
+{
+    if (t2 < Num<R>::small2) {
+        const R t4 = t2 * t2;
+        c = R(1) - t2 * R(0.5) + t4 * R(1.0 / 24.0);
+        a = R(1) - t2 * R(1.0 / 6.0) + t4 * R(1.0 / 120.0);
+        b = R(0.5) - t2 * R(1.0 / 24.0) + t4 * R(1.0 / 720.0);
+        if (DERIV) {
+            a1 = R(-1.0 / 3.0) + t2 * R(1.0 / 30.0) - t4 * R(1.0 / 840.0);
+            b1 = R(-1.0 / 12.0) + t2 * R(1.0 / 180.0) - t4 * R(1.0 / 6720.0);
+        }
+    } else {
+        const R t = Num<R>::sqrt(t2);
+        R sh, ch;
+        Num<R>::sincos(t * R(0.5), &sh, &ch);
+        const R s = R(2) * sh * ch;
+        const R omc = R(2) * sh * sh;
+        c = R(1) - omc;
+        const R it = Num<R>::rcp(t);
+        const R it2 = it * it;
+        a = s * it;
+        b = omc * it2;
+        if (DERIV) {
+            a1 = (t * c - s) * it2 * it;
+            b1 = (t * s - R(2) * omc) * it2 * it2;
+        }
+    }
+}
+
+// pi(theta) for theta = (w, t, f, k1, k2, X) and, if JAC, the two rows of
+// d pi / d theta.  With A = d pi / d P (2x3), row r of the Jacobian is
+//   d/dw = (A_r.q) w + b (A_r.w) X - a (A_r x X) + b (w.X) A_r,
+//          q = a1 (w x X) + b1 (w.X) w - a X,
+//   d/dt = A_r,   d/dX = c A_r + a (A_r x w) + b (A_r.w) w,
+//   d/df = d p_r, d/dk1 = f r^2 p_r, d/dk2 = f r^4 p_r.
+// Returns the depth P_3.
+template <typename R, bool JAC>
+__device__ __forceinline__ R project(const R *th, R &pu, R &pv, R *J0, R *J1)
+{
+    const R w0 = th[0], w1 = th[1], w2 = th[2];
+    const R X0 = th[9], X1 = th[10], X2 = th[11];
+    R c, a, b, a1 = R(0), b1 = R(0);
+    rot_coeffs<R, JAC>(w0 * w0 + w1 * w1 + w2 * w2, c, a, b, a1, b1);
+    const R cx0 = w1 * X2 - w2 * X1, cx1 = w2 * X0 - w0 * X2, cx2 = w0 * X1 - w1 * X0;
+    const R wd = w0 * X0 + w1 * X1 + w2 * X2;
+    const R bwd = b * wd;
+    const R P0 = c * X0 + a * cx0 + bwd * w0 + th[3];
+    const R P1 = c * X1 + a * cx1 + bwd * w1 + th[4];
+    const R P2 = c * X2 + a * cx2 + bwd * w2 + th[5];
+    const R iz = Num<R>::rcp(P2);
+    const R p0 = P0 * iz, p1 = P1 * iz;
+    const R r2 = p0 * p0 + p1 * p1;
+    const R f = th[6], k1 = th[7], k2 = th[8];
+    const R d = R(1) + r2 * (k1 + k2 * r2);
+    const R fd = f * d;
+    pu = fd * p0;
+    pv = fd * p1;
+    if (JAC) {
+        const R g = R(2) * k1 + R(4) * k2 * r2;
+        const R fq = f * iz;
+        const R dg = d + g * r2;
+        const R A00 = fq * (d + g * p0 * p0), A01 = fq * (g * p0 * p1), A02 = -fq * p0 * dg;
+        const R A11 = fq * (d + g * p1 * p1), A12 = -fq * p1 * dg;
+        const R b1wd = b1 * wd;
+        const R q0 = a1 * cx0 + b1wd * w0 - a * X0;
+        const R q1 = a1 * cx1 + b1wd * w1 - a * X1;
+        const R q2 = a1 * cx2 + b1wd * w2 - a * X2;
+        const R fr2 = f * r2;
+        auto row = [&](R *Jr, R Ar0, R Ar1, R Ar2, R pr) {
+            const R Aq = Ar0 * q0 + Ar1 * q1 + Ar2 * q2;
+            const R bAw = b * (Ar0 * w0 + Ar1 * w1 + Ar2 * w2);
+            Jr[0] = Aq * w0 + bAw * X0 - a * (Ar1 * X2 - Ar2 * X1) + bwd * Ar0;
+            Jr[1] = Aq * w1 + bAw * X1 - a * (Ar2 * X0 - Ar0 * X2) + bwd * Ar1;
+            Jr[2] = Aq * w2 + bAw * X2 - a * (Ar0 * X1 - Ar1 * X0) + bwd * Ar2;
+            Jr[3] = Ar0;
+            Jr[4] = Ar1;
+            Jr[5] = Ar2;
+            Jr[6] = d * pr;
+            Jr[7] = fr2 * pr;
+            Jr[8] = fr2 * r2 * pr;
+            Jr[9] = c * Ar0 + a * (Ar1 * w2 - Ar2 * w1) + bAw * w0;
+            Jr[10] = c * Ar1 + a * (Ar2 * w0 - Ar0 * w2) + bAw * w1;
+            Jr[11] = c * Ar2 + a * (Ar0 * w1 - Ar1 * w0) + bAw * w2;
+        };
+        row(J0, A00, A01, A02, p0);
+        row(J1, A01, A11, A12, p1);
+    }
+    return P2;
+}
+
+// phi(s) and w = phi'(s) of the misfit loss of Eq. (8).
+template <typename R>
+__device__ __forceinline__ R loss_phi(int kind, R lp, R s, R &w)
+{
+    if (kind == 1) {
+        const R d2 = lp * lp;
+        if (s <= d2) { w = R(1); return s; }
+        const R r = Num<R>::sqrt(s);
+        w = Num<R>::div(lp, r);
+        return R(2) * lp * r - d2;
+    }
+    if (kind == 2) {
+        const R q = Num<R>::div(s, lp);
+        w = Num<R>::rcp(R(1) + q);
+        return lp * Num<R>::log1p(q);
+    }
+    w = R(1);
+    return s;
+}
+
+template <typename R>
+__device__ __forceinline__ R objective(const R *th, const R *v, R z0, R z1, R rx, R ry,
+                                       int kind, R lp)
+{
+    R pu, pv;
+    const R depth = project<R, false>(th, pu, pv, nullptr, nullptr);
+    if (!(depth > R(1e-6))) return Num<R>::inf;
+    const R e0 = z0 - pu, e1 = z1 - pv;
+    R w;
+    const R phi = loss_phi<R>(kind, lp, e0 * e0 + e1 * e1, w);
+    R pen = R(0);
+#pragma unroll
+    for (int i = 0; i < 12; ++i) {
+        const R dd = th[i] - v[i];
+        pen += (i < 9 ? ry : rx) * dd * dd;
+    }
+    return phi + R(0.5) * pen;
+}
+
+// In-place Cholesky of the packed 12x12 SPD matrix (the diagonal keeps
+// 1/L_jj) and solve of A x = b; false on a non-positive or non-finite pivot.
+template <typename R>
+__device__ __forceinline__ bool chol_solve12(R *A, R *x)
+{
+    bool ok = true;
+#pragma unroll
+    for (int j = 0; j < 12; ++j) {
+        R s = A[IX(j, j)];
+#pragma unroll
+        for (int k = 0; k < j; ++k) s -= A[IX(j, k)] * A[IX(j, k)];
+        ok = ok && (s > R(0)) && (s < Num<R>::inf);
+        const R inv = Num<R>::rsqrt(s > R(0) ? s : R(1));
+        A[IX(j, j)] = inv;
+#pragma unroll
+        for (int i = j + 1; i < 12; ++i) {
+            R t = A[IX(i, j)];
+#pragma unroll
+            for (int k = 0; k < j; ++k) t -= A[IX(i, k)] * A[IX(j, k)];
+            A[IX(i, j)] = t * inv;
+        }
+    }
+#pragma unroll
+    for (int i = 0; i < 12; ++i) {
+        R t = x[i];
+#pragma unroll
+        for (int k = 0; k < i; ++k) t -= A[IX(i, k)] * x[k];
+        x[i] = t * A[IX(i, i)];
+    }
+#pragma unroll
+    for (int i = 11; i >= 0; --i) {
+        R t = x[i];
+#pragma unroll
+        for (int k = i + 1; k < 12; ++k) t -= A[IX(k, i)] * x[k];
+        x[i] = t * A[IX(i, i)];
+    }
+    return ok;
+}
+
+template <typename R> __device__ __forceinline__ R lam_down(R l);
+template <> __device__ __forceinline__ float lam_down(float l) { return fmaxf(l * 0.1f, 1e-12f); }
+template <> __device__ __forceinline__ double lam_down(double l) { return fmax(l / 10.0, 1e-12); }
+template <typename R> __device__ __forceinline__ R lam_up(R l) { return l * R(10) < R(1e12) ? l * R(10) : R(1e12); }
+
+// Robust LM on the local objective, exactly `steps` steps (rejected ones
+// included), Marquardt damping lambda * diag(H).  A trial is accepted if it
+// lowers F, or if the model's predicted decrease is below tie times F's
+// rounding resolution, F + |e| (|z_1| + |z_2| + f) -- a step that small cannot
+// be judged by F in this precision, so the model decides.
+// A non-finite trial (depth <= 1e-6 or a failed factorisation) is rejected.
+template <typename R>
+__device__ __forceinline__ void local_lm(R *th, const R *v, R z0, R z1, R rx, R ry, int kind,
+                                         R lp, int steps, R lam)
+{
+    R F = objective<R>(th, v, z0, z1, rx, ry, kind, lp);
+    for (int it = 0; it < steps; ++it) {
+        R pu, pv, J0[12], J1[12];
+        project<R, true>(th, pu, pv, J0, J1);
+        const R e0 = z0 - pu, e1 = z1 - pv;
+        R w;
+        const R s2 = e0 * e0 + e1 * e1;
+        loss_phi<R>(kind, lp, s2, w);
+        const R c2 = R(2) * w;
+        // rounding resolution of F here: e = z - pi loses ~eps |z|
+        const R fres = F + Num<R>::sqrt(s2) * (fabs(z0) + fabs(z1) + fabs(th[6]));
+        R A[78], x[12], ng[12], hd[12];
+#pragma unroll
+        for (int i = 0; i < 12; ++i) {
+            const R Pi = i < 9 ? ry : rx;
+            const R ci0 = c2 * J0[i], ci1 = c2 * J1[i];
+            x[i] = (ci0 * e0 + ci1 * e1) - Pi * (th[i] - v[i]);
+            ng[i] = x[i];
+#pragma unroll
+            for (int j = 0; j <= i; ++j) A[IX(i, j)] = ci0 * J0[j] + ci1 * J1[j];
+            A[IX(i, i)] += Pi;
+            hd[i] = A[IX(i, i)];
+            A[IX(i, i)] += lam * A[IX(i, i)];
+        }
+        const bool ok = chol_solve12<R>(A, x);
+        R tr[12];
+        R gd = R(0), dd = R(0);
+#pragma unroll
+        for (int i = 0; i < 12; ++i) {
+            tr[i] = th[i] + x[i];
+            gd += ng[i] * x[i];
+            dd += hd[i] * x[i] * x[i];
+        }
+        // decrease predicted by the damped Gauss-Newton model
+        const R pred = R(0.5) * (lam * dd + gd);
+        const R Fn = ok ? objective<R>(tr, v, z0, z1, rx, ry, kind, lp) : Num<R>::inf;
+        // accept a decrease of F, or a step too small for F to judge
+        if (Fn < Num<R>::inf && (Fn < F || pred <= Num<R>::tie * fres)) {
+#pragma unroll
+            for (int i = 0; i < 12; ++i) th[i] = tr[i];
+            F = Fn;
+            lam = lam_down<R>(lam);
+        } else {
+            lam = lam_up<R>(lam);
+        }
+    }
+}
+
+__device__ __forceinline__ double wave_sum(double v)
+{
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1) v += __shfl_xor(v, off, 64);
+    return v;
+}
+
+// Block -> tile mapping that gives each XCD (blocks are dealt round-robin to
+// the 8 XCDs) a contiguous range of tiles, so neighbouring cameras share an L2.
+__device__ __forceinline__ int xcd_block()
+{
+    const int G = gridDim.x, b = blockIdx.x;
+    const int q = G >> 3, r = G & 7, x = b & 7;
+    return x * q + (x < r ? x : r) + (b >> 3);
+}
+
+// ---------------------------------------------------------------- local
+template <typename R>
+__device__ __forceinline__ void local_chunk(const DevArrays<R> &a, const SolverParams &sp, int c,
+                                            int lane)
+{
+    using R2 = typename Vec<R>::R2;
+    using R4 = typename Vec<R>::R4;
+    const int J = a.chunk_cam[c];
+    const Ctrl *ct = a.ctrl + a.cam_prob[J];
+    const double rho_x = ct->rho_x, rho_y = ct->rho_y;
+    const double rat_x = ct->ratio_x, rat_y = ct->ratio_y;
+    const int pending = ct->pending;
+    const long long S = a.n_slots;
+    const long long s = (long long)c * kChunk + lane;
+    const int ps = a.pslot[s];
+    double cy[9];
+#pragma unroll
+    for (int i = 0; i < 9; ++i) cy[i] = a.cons_y[(long long)J * kConsY + i];
+
+    double acc[19];
+#pragma unroll
+    for (int i = 0; i < 19; ++i) acc[i] = 0.0;
+
+    if (ps >= 0) {
+        const int pt = a.ptid[s];
+        const R2 z = a.uv[s];
+        const double4 cx = a.cons_x[pt];
+        const double cons[12] = {cy[0], cy[1], cy[2], cy[3], cy[4], cy[5], cy[6], cy[7], cy[8],
+                                 cx.x, cx.y, cx.z};
+        R th[12];
+        double u[12];
+#pragma unroll
+        for (int i = 0; i < 9; ++i) {
+            th[i] = a.copy_y[i * S + s];
+            u[i] = a.dual_y[i * S + s];
+        }
+        const R4 xr = a.xrec[ps];
+        const double4 ur = a.urec[ps];
+        th[9] = xr.x; th[10] = xr.y; th[11] = xr.z;
+        u[9] = ur.x; u[10] = ur.y; u[11] = ur.z;
+        if (pending) {  // Eqs. (12)-(13) of the previous iteration, then the rho rescale
+#pragma unroll
+            for (int i = 0; i < 12; ++i)
+                u[i] = (u[i] + ((double)th[i] - cons[i])) * (i < 9 ? rat_y : rat_x);
+#pragma unroll
+            for (int i = 0; i < 9; ++i) a.dual_y[i * S + s] = u[i];
+            a.urec[ps] = make_double4(u[9], u[10], u[11], 0.0);
+        }
+        R v[12];
+#pragma unroll
+        for (int i = 0; i < 12; ++i) v[i] = (R)(cons[i] - u[i]);
+        local_lm<R>(th, v, z.x, z.y, (R)rho_x, (R)rho_y, sp.loss, (R)sp.loss_param, sp.lm_steps,
+                    (R)sp.lambda0);
+#pragma unroll
+        for (int i = 0; i < 9; ++i) a.copy_y[i * S + s] = th[i];
+        R4 xo;
+        xo.x = th[9]; xo.y = th[10]; xo.z = th[11]; xo.w = R(0);
+        a.xrec[ps] = xo;
+#pragma unroll
+        for (int i = 0; i < 9; ++i) {
+            const double t = (double)th[i];
+            const double dd = t - cy[i];
+            acc[i] = t + u[i];
+            acc[9 + i] = dd;
+            acc[18] += dd * dd;
+        }
+    }
+#pragma unroll
+    for (int i = 0; i < 19; ++i) acc[i] = wave_sum(acc[i]);
+    if (lane == 0) {
+        double *o = a.cpart + (long long)c * kCpart;
+#pragma unroll
+        for (int i = 0; i < 19; ++i) o[i] = acc[i];
+    }
+}
+
+// FP32: up to 8 waves per workgroup; FP64 needs more than 256 VGPRs, so at
+// most 4 waves (one per SIMD) per workgroup.
+template <typename R> struct LocalBound { static constexpr int threads = 512; };
+template <> struct LocalBound<double> { static constexpr int threads = 256; };
+
+template <typename R>
+__global__ __launch_bounds__(LocalBound<R>::threads) void k_local(DevArrays<R> a, SolverParams sp,
+                                                                  int persistent)
+{
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, wpb = blockDim.x >> 6;
+    const int lb = xcd_block();
+    int c0, c1;
+    if (persistent) {
+        const int per = (a.n_chunks + gridDim.x - 1) / gridDim.x;
+        c0 = lb * per;
+        c1 = min(c0 + per, a.n_chunks);
+    } else {
+        c0 = lb * wpb;
+        c1 = min(c0 + wpb, a.n_chunks);
+    }
+    for (int c = c0 + wave; c < c1; c += wpb) local_chunk<R>(a, sp, c, lane);
+}
+
+// ---------------------------------------------------------------- consensus
+template <typename R>
+__global__ __launch_bounds__(256) void k_consensus(DevArrays<R> a, int pt_blocks)
+{
+    using R4 = typename Vec<R>::R4;
+    if ((int)blockIdx.x < pt_blocks) {
+        const int i = blockIdx.x * 256 + threadIdx.x;
+        if (i >= a.n_pts) return;
+        const int r0 = a.pt_off[i], r1 = a.pt_off[i + 1];
+        double s0 = 0.0, s1 = 0.0, s2 = 0.0;
+        for (int r = r0; r < r1; ++r) {
+            const R4 x = a.xrec[r];
+            const double4 u = a.urec[r];
+            s0 += (double)x.x + u.x;
+            s1 += (double)x.y + u.y;
+            s2 += (double)x.z + u.z;
+        }
+        const double n = (double)(r1 - r0);
+        const double c0 = s0 / n, c1 = s1 / n, c2 = s2 / n;
+        double pri = 0.0;
+        for (int r = r0; r < r1; ++r) {
+            const R4 x = a.xrec[r];
+            const double d0 = (double)x.x - c0, d1 = (double)x.y - c1, d2 = (double)x.z - c2;
+            pri += d0 * d0 + d1 * d1 + d2 * d2;
+        }
+        const double4 old = a.cons_x[i];
+        const double e0 = c0 - old.x, e1 = c1 - old.y, e2 = c2 - old.z;
+        a.cons_x[i] = make_double4(c0, c1, c2, 0.0);
+        a.ppart[2 * (long long)i] = pri;
+        a.ppart[2 * (long long)i + 1] = n * (e0 * e0 + e1 * e1 + e2 * e2);
+    } else {
+        const int lane = threadIdx.x & 63;
+        const int J = (blockIdx.x - pt_blocks) * 4 + (threadIdx.x >> 6);
+        if (J >= a.n_cams) return;  // whole wave
+        const int k0 = a.cam_chunk0[J], k1 = a.cam_chunk0[J + 1];
+        double acc = 0.0;
+        if (lane < 19)
+            for (int k = k0; k < k1; ++k) acc += a.cpart[(long long)k * kCpart + lane];
+        double S[19];
+#pragma unroll
+        for (int i = 0; i < 19; ++i) S[i] = __shfl(acc, i, 64);
+        if (lane == 0) {
+            const double M = (double)a.cam_count[J];
+            double *cy = a.cons_y + (long long)J * kConsY;
+            double dd = 0.0, dS = 0.0;
+#pragma unroll
+            for (int i = 0; i < 9; ++i) {
+                const double cn = S[i] / M;
+                const double del = cn - cy[i];
+                cy[i] = cn;
+                dd += del * del;
+                dS += del * S[9 + i];
+            }
+            // sum_k |copy_k - new|^2 = sum |d_k|^2 - 2 del . sum d_k + M |del|^2,
+            // d_k = copy_k - old consensus
+            const double pri = S[18] - 2.0 * dS + M * dd;
+            a.campart[2 * (long long)J] = pri > 0.0 ? pri : 0.0;
+            a.campart[2 * (long long)J + 1] = M * dd;
+        }
+    }
+}
+
+// ---------------------------------------------------------------- norms
+__device__ __forceinline__ void block_sum4(double *v, double (*sh)[kNormThreads])
+{
+    const int t = threadIdx.x;
+#pragma unroll
+    for (int k = 0; k < 4; ++k) sh[k][t] = v[k];
+    __syncthreads();
+    for (int w = kNormThreads / 2; w >= 1; w >>= 1) {
+        if (t < w)
+#pragma unroll
+            for (int k = 0; k < 4; ++k) sh[k][t] += sh[k][t + w];
+        __syncthreads();
+    }
+#pragma unroll
+    for (int k = 0; k < 4; ++k) v[k] = sh[k][0];
+}
+
+template <typename R>
+__global__ __launch_bounds__(kNormThreads) void k_norms(DevArrays<R> a)
+{
+    __shared__ double sh[4][kNormThreads];
+    const int p = blockIdx.x;
+    const ProblemRange pr = a.prob[p];
+    double v[4] = {0.0, 0.0, 0.0, 0.0};  // pri_x, dual_x, pri_y, dual_y
+    for (int i = threadIdx.x; i < pr.n_points; i += kNormThreads) {
+        v[0] += a.ppart[2 * (long long)(pr.pt0 + i)];
+        v[1] += a.ppart[2 * (long long)(pr.pt0 + i) + 1];
+    }
+    for (int j = threadIdx.x; j < pr.n_cams; j += kNormThreads) {
+        v[2] += a.campart[2 * (long long)(pr.cam0 + j)];
+        v[3] += a.campart[2 * (long long)(pr.cam0 + j) + 1];
+    }
+    block_sum4(v, sh);
+    if (threadIdx.x == 0) {
+        Ctrl &ct = a.ctrl[p];
+        const double rx = ct.rho_x, ry = ct.rho_y;
+        const double r_pri = sqrt(v[0] + v[2]);
+        const double r_dual = sqrt(rx * rx * v[1] + ry * ry * v[3]);
+        ct.primal = r_pri;
+        ct.dual = r_dual;
+        ct.last_rho_x = rx;
+        ct.last_rho_y = ry;
+        ct.iteration += 1;
+        ct.pending = 1;
+        if (!isfinite(r_pri) || !isfinite(r_dual)) ct.nonfinite = 1;
+        double ratx = 1.0, raty = 1.0;
+        if (ct.balancing) {
+            double fac = 1.0;
+            if (r_pri > ct.rb_mu * r_dual) fac = ct.rb_tau;
+            else if (r_dual > ct.rb_mu * r_pri) fac = 1.0 / ct.rb_tau;
+            if (fac != 1.0) {
+                const double nx = fmin(fmax(rx * fac, ct.rho_min), ct.rho_max);
+                const double ny = fmin(fmax(ry * fac, ct.rho_min), ct.rho_max);
+                ratx = rx / nx;
+                raty = ry / ny;
+                ct.rho_x = nx;
+                ct.rho_y = ny;
+            }
+        }
+        ct.ratio_x = ratx;
+        ct.ratio_y = raty;
+    }
+}
+
+// ---------------------------------------------------------------- eval
+template <typename R>
+__global__ __launch_bounds__(256) void k_eval(DevArrays<R> a, SolverParams sp)
+{
+    const int lane = threadIdx.x & 63;
+    const int c = blockIdx.x * 4 + (threadIdx.x >> 6);
+    if (c >= a.n_chunks) return;  // whole wave
+    const long long s = (long long)c * kChunk + lane;
+    const int ps = a.pslot[s];
+    double val[kEpart] = {0.0, 0.0, 0.0, 0.0, 0.0};
+    if (ps >= 0) {
+        const int J = a.chunk_cam[c];
+        const double4 cx = a.cons_x[a.ptid[s]];
+        double th[12];
+#pragma unroll
+        for (int i = 0; i < 9; ++i) th[i] = a.cons_y[(long long)J * kConsY + i];
+        th[9] = cx.x; th[10] = cx.y; th[11] = cx.z;
+        double pu, pv;
+        project<double, false>(th, pu, pv, nullptr, nullptr);
+        const typename Vec<R>::R2 z = a.uv[s];
+        const double e0 = (double)z.x - pu, e1 = (double)z.y - pv;
+        const double s2 = e0 * e0 + e1 * e1;
+        double w;
+        val[0] = s2;
+        val[1] = loss_phi<double>(sp.loss, sp.loss_param, s2, w);
+        val[2] = sqrt(s2);
+        const bool m = a.mask[s] != 0;
+        val[3] = m ? s2 : 0.0;
+        val[4] = m ? 1.0 : 0.0;
+    }
+#pragma unroll
+    for (int i = 0; i < kEpart; ++i) val[i] = wave_sum(val[i]);
+    if (lane == 0)
+#pragma unroll
+        for (int i = 0; i < kEpart; ++i) a.epart[(long long)c * kEpart + i] = val[i];
+}
+
+template <typename R>
+__global__ __launch_bounds__(kNormThreads) void k_eval_reduce(DevArrays<R> a)
+{
+    __shared__ double sh[4][kNormThreads];
+    const int p = blockIdx.x;
+    const ProblemRange pr = a.prob[p];
+    double v[4] = {0.0, 0.0, 0.0, 0.0}, w4[4] = {0.0, 0.0, 0.0, 0.0};
+    for (int c = threadIdx.x; c < pr.n_chunks; c += kNormThreads) {
+        const double *e = a.epart + (long long)(pr.chunk0 + c) * kEpart;
+        v[0] += e[0]; v[1] += e[1]; v[2] += e[2]; v[3] += e[3];
+        w4[0] += e[4];
+    }
+    block_sum4(v, sh);
+    __syncthreads();
+    block_sum4(w4, sh);
+    if (threadIdx.x == 0) {
+        double *o = a.estats + (long long)p * kEpart;
+        o[0] = v[0]; o[1] = v[1]; o[2] = v[2]; o[3] = v[3]; o[4] = w4[0];
+    }
+}
+
+// ---------------------------------------------------------------- state export
+template <typename R>
+__global__ __launch_bounds__(256) void k_materialize(DevArrays<R> a, int p, double *copies,
+                                                      double *duals)
+{
+    const ProblemRange pr = a.prob[p];
+    const long long s = (long long)pr.chunk0 * kChunk + (long long)blockIdx.x * 256 + threadIdx.x;
+    if (s >= (long long)(pr.chunk0 + pr.n_chunks) * kChunk) return;
+    const int ps = a.pslot[s];
+    if (ps < 0) return;
+    const long long k = a.slot_orig[s];
+    const long long S = a.n_slots;
+    const int J = a.chunk_cam[s / kChunk];
+    const Ctrl &ct = a.ctrl[p];
+    const double4 cx = a.cons_x[a.ptid[s]];
+    const typename Vec<R>::R4 xr = a.xrec[ps];
+    const double4 ur = a.urec[ps];
+    const double xc[3] = {(double)xr.x, (double)xr.y, (double)xr.z};
+    const double xu[3] = {ur.x, ur.y, ur.z};
+    const double xs[3] = {cx.x, cx.y, cx.z};
+    for (int i = 0; i < 12; ++i) {
+        double cp, u, cs, rat;
+        if (i < 9) {
+            cp = (double)a.copy_y[i * S + s];
+            u = a.dual_y[i * S + s];
+            cs = a.cons_y[(long long)J * kConsY + i];
+            rat = ct.ratio_y;
+        } else {
+            cp = xc[i - 9];
+            u = xu[i - 9];
+            cs = xs[i - 9];
+            rat = ct.ratio_x;
+        }
+        if (ct.pending) u = (u + (cp - cs)) * rat;
+        if (copies) copies[k * 12 + i] = cp;
+        if (duals) duals[k * 12 + i] = u;
+    }
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------- launchers
+template <typename R>
+hipError_t launch_local(const DevArrays<R> &a, const SolverParams &sp, int block_waves,
+                        int persistent, int n_cu, hipStream_t s)
+{
+    if (64 * block_waves > LocalBound<R>::threads) block_waves = LocalBound<R>::threads / 64;
+    const int threads = 64 * block_waves;
+    int grid;
+    if (persistent) {
+        grid = n_cu * (8 / block_waves > 0 ? 8 / block_waves : 1);
+        const int need = (a.n_chunks + block_waves - 1) / block_waves;
+        if (grid > need) grid = need;
+    } else {
+        grid = (a.n_chunks + block_waves - 1) / block_waves;
+    }
+    if (grid < 1) grid = 1;
+    hipLaunchKernelGGL(k_local<R>, dim3(grid), dim3(threads), 0, s, a, sp, persistent);
+    return hipGetLastError();
+}
+
+template <typename R>
+hipError_t launch_consensus(const DevArrays<R> &a, hipStream_t s)
+{
+    const int pt_blocks = (a.n_pts + 255) / 256;
+    const int cam_blocks = (a.n_cams + 3) / 4;
+    hipLaunchKernelGGL(k_consensus<R>, dim3(pt_blocks + cam_blocks), dim3(256), 0, s, a, pt_blocks);
+    return hipGetLastError();
+}
+
+template <typename R>
+hipError_t launch_norms(const DevArrays<R> &a, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_norms<R>, dim3(a.n_problems), dim3(kNormThreads), 0, s, a);
+    return hipGetLastError();
+}
+
+template <typename R>
+hipError_t launch_eval(const DevArrays<R> &a, const SolverParams &sp, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_eval<R>, dim3((a.n_chunks + 3) / 4), dim3(256), 0, s, a, sp);
+    hipLaunchKernelGGL(k_eval_reduce<R>, dim3(a.n_problems), dim3(kNormThreads), 0, s, a);
+    return hipGetLastError();
+}
+
+template <typename R>
+hipError_t launch_materialize(const DevArrays<R> &a, int problem, double *copies, double *duals,
+                              hipStream_t s)
+{
+    // the problem's slots: caller passes the chunk count through a.prob on device;
+    // grid covers the largest possible range and threads beyond the problem exit
+    hipLaunchKernelGGL(k_materialize<R>, dim3((unsigned)((a.n_slots + 255) / 256)), dim3(256), 0, s,
+                       a, problem, copies, duals);
+    return hipGetLastError();
+}
+
+#define DBA_INSTANTIATE(R)                                                                        \
+    template hipError_t launch_local<R>(const DevArrays<R> &, const SolverParams &, int, int, int, \
+                                        hipStream_t);                                             \
+    template hipError_t launch_consensus<R>(const DevArrays<R> &, hipStream_t);                   \
+    template hipError_t launch_norms<R>(const DevArrays<R> &, hipStream_t);                       \
+    template hipError_t launch_eval<R>(const DevArrays<R> &, const SolverParams &, hipStream_t);  \
+    template hipError_t launch_materialize<R>(const DevArrays<R> &, int, double *, double *,      \
+                                              hipStream_t);
+DBA_INSTANTIATE(float)
+DBA_INSTANTIATE(double)
+
+}  // namespace dba

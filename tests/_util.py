@@ -1,0 +1,29 @@
+"""Shared helpers of the test suite (comparison metrics only)."""
+import numpy as np
+
+CAM_FLOOR = np.array([1, 1, 1, 1, 1, 1, 1, 1e-2, 1e-2], dtype=np.float64)
+
+
+def param_rel_err(cams, pts, cams_ref, pts_ref):
+    """Max over components of |a - b| / max(|b|, floor): floor 1 for rotation,
+    translation, focal and points, 1e-2 for the distortion terms."""
+    ec = np.abs(cams - cams_ref) / np.maximum(np.abs(cams_ref), CAM_FLOOR)
+    ep = np.abs(pts - pts_ref) / np.maximum(np.abs(pts_ref), 1.0)
+    return float(max(ec.max(), ep.max()))
+
+
+def state_rel_err(a, b):
+    """Max |a - b| over a (L, 12) state, relative to the per-column scale of b."""
+    scale = np.maximum(np.abs(b).max(axis=0), 1e-300)
+    return float((np.abs(a - b) / scale).max())
+
+
+def worst_param(cams, pts, cams_ref, pts_ref):
+    """(kind, index, component, value, reference) of the largest relative error."""
+    ec = np.abs(cams - cams_ref) / np.maximum(np.abs(cams_ref), CAM_FLOOR)
+    ep = np.abs(pts - pts_ref) / np.maximum(np.abs(pts_ref), 1.0)
+    if ec.max() >= ep.max():
+        j, c = np.unravel_index(ec.argmax(), ec.shape)
+        return ("cam", int(j), int(c), float(cams[j, c]), float(cams_ref[j, c]))
+    i, c = np.unravel_index(ep.argmax(), ep.shape)
+    return ("point", int(i), int(c), float(pts[i, c]), float(pts_ref[i, c]))

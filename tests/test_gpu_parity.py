@@ -1,0 +1,180 @@
+"""GPU parity: the HIP path through the C ABI against the FP64 oracle on the
+same seeded inputs.  FP64 path: 1e-9 relative on every parameter; FP32-local
+path: 1e-3 relative and RMSE within 0.5%."""
+import numpy as np
+import pytest
+
+import oracle
+from paper_1708_07954_amd import binding
+from scenes import make_config0, make_config2, make_ring_scene, make_sphere_scene
+from _util import param_rel_err, state_rel_err, worst_param
+
+pytestmark = pytest.mark.gpu
+
+
+def gpu_run(scene, iters, **opts):
+    s = binding.Solver(**opts).set_scene(scene)
+    s.iterate(iters)
+    return s
+
+
+def oracle_run(scene, iters, *, loss, loss_param, rho, rho_balancing=False, rho_min=1e-6, rho_max=1e6,
+               lm_steps=5):
+    a = oracle.ADMM(oracle.Problem.from_scene(scene), scene.cams_init, scene.points_init, loss=loss,
+                    loss_param=loss_param, rho=rho, rho_balancing=rho_balancing, lm_steps=lm_steps)
+    a.opts.rho_min, a.opts.rho_max = rho_min, rho_max
+    tr = a.iterate(iters)
+    return a, tr
+
+
+CASES = {
+    "ring_huber_rho1e4": (lambda: make_config0(), dict(loss="huber", loss_param=2.0, rho=1e4), 50),
+    "ring_huber_rho1": (lambda: make_config0(), dict(loss="huber", loss_param=2.0, rho=1.0), 50),
+    "ring7x37_l2": (lambda: make_ring_scene(seed=4, n_cams=7, n_points=37), dict(loss="l2", loss_param=1.0, rho=1e3), 40),
+    "sphere_t": (lambda: make_sphere_scene(seed=8, n_cams=20, n_points=700), dict(loss="student_t", loss_param=4.0, rho=1e3), 30),
+    "traj_balancing": (lambda: make_config2(n_cams=60, n_points=800),
+                       dict(loss="huber", loss_param=2.0, rho=1e4, rho_balancing=True, rho_min=1e4, rho_max=1e7), 30),
+}
+
+
+@pytest.mark.parametrize("case", sorted(CASES))
+def test_fp64_parity(case):
+    make, kw, iters = CASES[case]
+    sc = make()
+    a, tr = oracle_run(sc, iters, **kw)
+    s = gpu_run(sc, iters, precision="fp64", **kw)
+    cams, pts = s.params()
+    err = param_rel_err(cams, pts, a.cons_y, a.cons_x)
+    r = s.residuals(want_rmse=True)
+    st = a.stats()
+    print(case, "max rel err", err, worst_param(cams, pts, a.cons_y, a.cons_x), "r_pri", r["primal"],
+          tr[-1, 0], "rmse", r["rmse"], st[0])
+    assert err < 1e-9
+    assert r["iteration"] == iters
+    assert r["rho_x"] == tr[-1, 2] and r["rho_y"] == tr[-1, 3]
+    assert r["next_rho_x"] == a.rho[0]
+    assert r["primal"] == pytest.approx(tr[-1, 0], rel=1e-6)
+    assert r["dual"] == pytest.approx(tr[-1, 1], rel=1e-6)
+    assert r["rmse"] == pytest.approx(st[0], rel=1e-9)
+    assert r["robust_cost"] == pytest.approx(st[2], rel=1e-9)
+
+
+@pytest.mark.parametrize("case", ["ring7x37_l2", "traj_balancing"])
+def test_fp64_state_parity(case):
+    make, kw, _ = CASES[case]
+    sc = make()
+    a, _ = oracle_run(sc, 7, **kw)
+    s = gpu_run(sc, 7, precision="fp64", **kw)
+    copies, duals = s.state()
+    assert state_rel_err(copies, a.copy) < 1e-9
+    assert state_rel_err(duals, a.dual) < 1e-7
+
+
+@pytest.mark.parametrize("case", ["ring_huber_rho1e4", "sphere_t", "traj_balancing"])
+def test_fp32_parity(case):
+    make, kw, iters = CASES[case]
+    sc = make()
+    a, _ = oracle_run(sc, iters, **kw)
+    s = gpu_run(sc, iters, precision="fp32", **kw)
+    cams, pts = s.params()
+    err = param_rel_err(cams, pts, a.cons_y, a.cons_x)
+    r = s.residuals(want_rmse=True)
+    st = a.stats()
+    print(case, "fp32 max rel err", err, worst_param(cams, pts, a.cons_y, a.cons_x), "rmse", r["rmse"], st[0])
+    assert err < 1e-3
+    assert abs(r["rmse"] - st[0]) < 5e-3 * st[0]
+
+
+def test_dual_invariant_on_gpu():
+    sc = make_sphere_scene(seed=8, n_cams=20, n_points=700)
+    s = gpu_run(sc, 9, precision="fp64", loss="student_t", loss_param=4.0, rho=1e3)
+    copies, duals = s.state()
+    sy = np.zeros((sc.n_cams, 9))
+    np.add.at(sy, sc.obs_cam, duals[:, :9])
+    sx = np.zeros((sc.n_points, 3))
+    np.add.at(sx, sc.obs_point, duals[:, 9:])
+    scale = np.abs(copies).max()
+    assert np.abs(sy).max() < 1e-12 * scale * 200
+    assert np.abs(sx).max() < 1e-12 * scale * 20
+    cams, pts = s.params()
+    cy = np.zeros((sc.n_cams, 9))
+    np.add.at(cy, sc.obs_cam, copies[:, :9])
+    cy /= np.bincount(sc.obs_cam)[:, None]
+    np.testing.assert_allclose(cams, cy, rtol=1e-12, atol=1e-12)
+
+
+@pytest.mark.parametrize("precision", ["fp32", "fp64"])
+def test_every_schedule_is_bitwise_identical(precision):
+    sc = make_sphere_scene(seed=9, n_cams=30, n_points=900)
+    kw = dict(precision=precision, loss="student_t", loss_param=4.0, rho=1e3)
+    ref = None
+    for bw in (1, 2, 4, 8):
+        for pers in (0, 1):
+            for graph in (False, True):
+                s = gpu_run(sc, 6, block_waves=bw, persistent=pers, use_graph=graph, **kw)
+                cams, pts = s.params()
+                copies, duals = s.state()
+                r = s.residuals()
+                got = (cams, pts, copies, duals, r["primal"], r["dual"])
+                if ref is None:
+                    ref = got
+                else:
+                    for x, y in zip(got[:4], ref[:4]):
+                        np.testing.assert_array_equal(x, y)
+                    assert got[4:] == ref[4:]
+                s.close()
+    s = gpu_run(sc, 6, **kw)  # autotuned (tuning runs on real iterations)
+    np.testing.assert_array_equal(s.params()[0], ref[0])
+    s.iterate(6)
+    assert binding.dba_schedule(s.h)["tuned"] > 1
+
+
+def test_iterate_in_pieces_equals_one_call():
+    sc = make_config0()
+    kw = dict(precision="fp64", loss="huber", loss_param=2.0, rho=1e4, block_waves=4, persistent=0)
+    a = gpu_run(sc, 37, **kw)
+    b = binding.Solver(**kw).set_scene(sc)
+    for n in (1, 16, 3, 17):
+        b.iterate(n)
+    np.testing.assert_array_equal(a.params()[0], b.params()[0])
+    np.testing.assert_array_equal(a.state()[1], b.state()[1])
+
+
+def test_input_validation_errors():
+    sc = make_ring_scene(seed=1, n_cams=4, n_points=10)
+    s = binding.Solver(precision="fp64")
+    bad = sc.obs_uv.copy()
+    bad[3, 1] = np.nan
+    with pytest.raises(binding.DbaError) as e:
+        binding.dba_set_problem(s.h, sc.n_cams, sc.n_points, sc.obs_cam, sc.obs_point, bad,
+                                sc.cams_init, sc.points_init)
+    assert e.value.status == "DBA_E_NONFINITE"
+    oc = sc.obs_cam.copy()
+    oc[0] = 4
+    with pytest.raises(binding.DbaError) as e:
+        binding.dba_set_problem(s.h, sc.n_cams, sc.n_points, oc, sc.obs_point, sc.obs_uv,
+                                sc.cams_init, sc.points_init)
+    assert e.value.status == "DBA_E_INDEX_RANGE"
+    keep = sc.obs_point != 3
+    with pytest.raises(binding.DbaError) as e:
+        binding.dba_set_problem(s.h, sc.n_cams, sc.n_points, sc.obs_cam[keep], sc.obs_point[keep],
+                                sc.obs_uv[keep], sc.cams_init, sc.points_init)
+    assert e.value.status == "DBA_E_UNOBSERVED"
+    cams = sc.cams_init.copy()
+    cams[2, 3:6] = 0.0     # camera at the origin of a scene around the origin
+    cams[2, :3] = 0.0
+    pts = sc.points_init.copy()
+    pts[:, 2] = -np.abs(pts[:, 2]) - 1.0
+    with pytest.raises(binding.DbaError) as e:
+        binding.dba_set_problem(s.h, sc.n_cams, sc.n_points, sc.obs_cam, sc.obs_point, sc.obs_uv, cams, pts)
+    assert e.value.status == "DBA_E_BEHIND_CAMERA"
+    with pytest.raises(binding.DbaError) as e:
+        binding.dba_iterate(s.h, 1)
+    assert e.value.status == "DBA_E_STATE"
+    # a failed set keeps the previous problem
+    s.set_scene(sc)
+    s.iterate(2)
+    with pytest.raises(binding.DbaError):
+        binding.dba_set_problem(s.h, sc.n_cams, sc.n_points, oc, sc.obs_point, sc.obs_uv,
+                                sc.cams_init, sc.points_init)
+    assert s.residuals()["iteration"] == 2

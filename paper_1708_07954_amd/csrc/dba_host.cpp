@@ -176,7 +176,7 @@ int build_set(dba_handle *h, int np, const dba_problem_desc *probs, ProblemSet *
     const int CH = dba::kChunk;
     // global sizes
     long long n_chunks = 0, n_recs = 0;
-    int n_cams = 0, n_pts = 0;
+    int n_cams = 0, n_pts = 0, n_pblk = 0;
     ps->n_problems = np;
     for (int p = 0; p < np; ++p) {
         const dba_problem_desc &d = probs[p];
@@ -190,6 +190,8 @@ int build_set(dba_handle *h, int np, const dba_problem_desc *probs, ProblemSet *
         for (int j = 0; j < d.n_cams; ++j) ch += (cc[j] + CH - 1) / CH;
         r.n_chunks = (int)ch;
         r.rec0 = n_recs; r.n_obs = d.n_obs;
+        r.pblk0 = n_pblk; r.n_pblk = (d.n_points + dba::kPtBlock - 1) / dba::kPtBlock;
+        n_pblk += r.n_pblk;
         ps->ranges.push_back(r);
         ps->m.push_back(d.n_cams);
         ps->n.push_back(d.n_points);
@@ -214,6 +216,14 @@ int build_set(dba_handle *h, int np, const dba_problem_desc *probs, ProblemSet *
     std::vector<double> cons_y((size_t)n_cams * dba::kConsY, 0.0);
     std::vector<double4> cons_x(n_pts);
     std::vector<Ctrl> ctrl(np);
+    std::vector<int> pblk_pt0(n_pblk), pblk_cnt(n_pblk);
+    for (int p = 0; p < np; ++p) {
+        const ProblemRange &r = ps->ranges[p];
+        for (int q = 0; q < r.n_pblk; ++q) {
+            pblk_pt0[r.pblk0 + q] = r.pt0 + q * dba::kPtBlock;
+            pblk_cnt[r.pblk0 + q] = std::min(dba::kPtBlock, r.n_points - q * dba::kPtBlock);
+        }
+    }
 
     for (int p = 0; p < np; ++p) {
         const dba_problem_desc &d = probs[p];
@@ -282,6 +292,7 @@ int build_set(dba_handle *h, int np, const dba_problem_desc *probs, ProblemSet *
     R4 *d_xrec; double4 *d_urec; int *d_ptoff, *d_chunk_cam, *d_cam_prob, *d_pt_prob, *d_cam_chunk0, *d_cam_count;
     double *d_cons_y; double4 *d_cons_x; Ctrl *d_ctrl; ProblemRange *d_prob;
     double *d_cpart, *d_ppart, *d_campart, *d_epart, *d_estats;
+    int *d_pblk_pt0, *d_pblk_cnt;
     HIP_TRY(h, B.alloc(&d_uv, S));
     HIP_TRY(h, B.alloc(&d_pslot, S));
     HIP_TRY(h, B.alloc(&d_ptid, S));
@@ -302,7 +313,11 @@ int build_set(dba_handle *h, int np, const dba_problem_desc *probs, ProblemSet *
     HIP_TRY(h, B.alloc(&d_ctrl, np));
     HIP_TRY(h, B.alloc(&d_prob, np));
     HIP_TRY(h, B.alloc(&d_cpart, (size_t)n_chunks * dba::kCpart));
-    HIP_TRY(h, B.alloc(&d_ppart, 2 * (size_t)n_pts));
+    HIP_TRY(h, B.alloc(&d_ppart, 2 * (size_t)n_pblk));
+    HIP_TRY(h, B.alloc(&d_pblk_pt0, n_pblk));
+    HIP_TRY(h, B.alloc(&d_pblk_cnt, n_pblk));
+    HIP_TRY(h, hipMemcpy(d_pblk_pt0, pblk_pt0.data(), n_pblk * sizeof(int), hipMemcpyHostToDevice));
+    HIP_TRY(h, hipMemcpy(d_pblk_cnt, pblk_cnt.data(), n_pblk * sizeof(int), hipMemcpyHostToDevice));
     HIP_TRY(h, B.alloc(&d_campart, 2 * (size_t)n_cams));
     HIP_TRY(h, B.alloc(&d_epart, (size_t)n_chunks * dba::kEpart));
     HIP_TRY(h, B.alloc(&d_estats, (size_t)np * dba::kEpart));
@@ -336,6 +351,7 @@ int build_set(dba_handle *h, int np, const dba_problem_desc *probs, ProblemSet *
     A.chunk_cam = d_chunk_cam; A.cam_prob = d_cam_prob; A.pt_prob = d_pt_prob;
     A.cam_chunk0 = d_cam_chunk0; A.cam_count = d_cam_count;
     A.cons_y = d_cons_y; A.cons_x = d_cons_x; A.ctrl = d_ctrl; A.prob = d_prob;
+    A.n_pblk = n_pblk; A.pblk_pt0 = d_pblk_pt0; A.pblk_cnt = d_pblk_cnt;
     A.cpart = d_cpart; A.ppart = d_ppart; A.campart = d_campart; A.epart = d_epart; A.estats = d_estats;
     ps->mask = d_mask;
     return DBA_OK;

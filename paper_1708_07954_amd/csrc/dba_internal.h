@@ -52,8 +52,11 @@ struct ProblemRange {              // per problem, global index ranges
     int cam0, n_cams;
     int pt0, n_points;
     int chunk0, n_chunks;
+    int pblk0, n_pblk;             // point blocks of the consensus kernel
     long long rec0, n_obs;
 };
+
+constexpr int kPtBlock = 256;      // points per consensus block (never straddles problems)
 
 template <typename R> struct Vec;
 template <> struct Vec<float> { using R2 = float2; using R4 = float4; };
@@ -87,7 +90,10 @@ struct DevArrays {
     Ctrl *ctrl;             // [n_problems]
     const ProblemRange *prob; // [n_problems]
     double *cpart;          // [n_chunks][kCpart]
-    double *ppart;          // [n_pts][2]
+    int n_pblk;
+    const int *pblk_pt0;    // [n_pblk] first global point of the block
+    const int *pblk_cnt;    // [n_pblk] points in the block (<= kPtBlock)
+    double *ppart;          // [n_pblk][2] block sums of the point residual terms
     double *campart;        // [n_cams][2]
     double *epart;          // [n_chunks][kEpart]
     double *estats;         // [n_problems][kEpart]

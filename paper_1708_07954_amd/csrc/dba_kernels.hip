@@ -5,12 +5,14 @@
 //            camera).  Applies the deferred scaled-dual update of the
 //            previous iteration, then minimises the local objective of Eq. (9)
 //            in scaled form, F = phi(|z - pi(theta)|^2) + 1/2 (theta - v)^T P
-//            (theta - v), by robust Levenberg-Marquardt: 12x12 normal
-//            equations and their Cholesky factor live in registers.  Emits the
-//            chunk's sums for the camera consensus with a fixed butterfly.
+//            (theta - v), by robust Levenberg-Marquardt: the 12x12 normal
+//            equations and their LDL^T (Cholesky) factor live in registers.
+//            Emits the chunk's sums for the camera consensus with a fixed
+//            butterfly.
 // consensus  point consensus (Eq. 10): one thread per point, ascending record
-//            order; camera consensus (Eq. 11): one wave per camera summing its
-//            chunk partials in ascending chunk order.  Both in FP64.
+//            order, residual terms summed per 256-point block by a fixed tree;
+//            camera consensus (Eq. 11): one wave per camera summing its chunk
+//            partials in ascending chunk order.  Both in FP64.
 // norms      one workgroup per problem: primal/dual residual norms, residual
 //            balancing of rho, rescale factor for the pending dual update.
 // eval       reprojection statistics at the consensus estimate (FP64).
@@ -48,7 +50,6 @@ template <> struct Num<double> {
     static constexpr double tie = 1e-13;
 };
 
-constexpr int IX(int i, int j) { return i * (i + 1) / 2 + j; }  // packed lower triangle
 
 // Rodrigues coefficients of R(w) X = c X + a (w x X) + b (w.X) w and, for the
 // Jacobian, a1 = a'(t)/t and b1 = b'(t)/t; 1 - cos t is formed as 2 sin^2(t/2).
@@ -82,65 +83,87 @@ __device__ __forceinline__ void rot_coeffs(R t2, R &c, R &a, R &b, R &a1, R &b1)
     }
 }
 
-// pi(theta) for theta = (w, t, f, k1, k2, X) and, if JAC, the two rows of
-// d pi / d theta.  With A = d pi / d P (2x3), row r of the Jacobian is
+// Projection pi(theta), theta = (w, t, f, k1, k2, X), with the intermediate
+// values the Jacobian needs (so an accepted trial point's projection is
+// reused as the next linearisation point).
+template <typename R>
+struct Proj {
+    R c, a, b, a1, b1;      // Rodrigues coefficients
+    R cx0, cx1, cx2, wd;    // w x X, w . X
+    R iz, p0, p1, r2, d;    // 1/P_3, P_{1,2}/P_3, r^2, distortion factor
+    R pu, pv, depth;        // pixel and depth
+};
+
+template <typename R, bool DERIV>
+__device__ __forceinline__ Proj<R> proj_core(const R *th)
+{
+    Proj<R> o;
+    const R w0 = th[0], w1 = th[1], w2 = th[2];
+    const R X0 = th[9], X1 = th[10], X2 = th[11];
+    o.a1 = o.b1 = R(0);
+    rot_coeffs<R, DERIV>(w0 * w0 + w1 * w1 + w2 * w2, o.c, o.a, o.b, o.a1, o.b1);
+    o.cx0 = w1 * X2 - w2 * X1;
+    o.cx1 = w2 * X0 - w0 * X2;
+    o.cx2 = w0 * X1 - w1 * X0;
+    o.wd = w0 * X0 + w1 * X1 + w2 * X2;
+    const R bwd = o.b * o.wd;
+    const R P0 = o.c * X0 + o.a * o.cx0 + bwd * w0 + th[3];
+    const R P1 = o.c * X1 + o.a * o.cx1 + bwd * w1 + th[4];
+    const R P2 = o.c * X2 + o.a * o.cx2 + bwd * w2 + th[5];
+    o.depth = P2;
+    o.iz = Num<R>::rcp(P2);
+    o.p0 = P0 * o.iz;
+    o.p1 = P1 * o.iz;
+    o.r2 = o.p0 * o.p0 + o.p1 * o.p1;
+    o.d = R(1) + o.r2 * (th[7] + th[8] * o.r2);
+    const R fd = th[6] * o.d;
+    o.pu = fd * o.p0;
+    o.pv = fd * o.p1;
+    return o;
+}
+
+// The two rows of d pi / d theta at the point of `o`.  With A = d pi / d P
+// (2x3), row r is
 //   d/dw = (A_r.q) w + b (A_r.w) X - a (A_r x X) + b (w.X) A_r,
 //          q = a1 (w x X) + b1 (w.X) w - a X,
 //   d/dt = A_r,   d/dX = c A_r + a (A_r x w) + b (A_r.w) w,
 //   d/df = d p_r, d/dk1 = f r^2 p_r, d/dk2 = f r^4 p_r.
-// Returns the depth P_3.
-template <typename R, bool JAC>
-__device__ __forceinline__ R project(const R *th, R &pu, R &pv, R *J0, R *J1)
+template <typename R>
+__device__ __forceinline__ void proj_jac(const Proj<R> &o, const R *th, R *J0, R *J1)
 {
     const R w0 = th[0], w1 = th[1], w2 = th[2];
     const R X0 = th[9], X1 = th[10], X2 = th[11];
-    R c, a, b, a1 = R(0), b1 = R(0);
-    rot_coeffs<R, JAC>(w0 * w0 + w1 * w1 + w2 * w2, c, a, b, a1, b1);
-    const R cx0 = w1 * X2 - w2 * X1, cx1 = w2 * X0 - w0 * X2, cx2 = w0 * X1 - w1 * X0;
-    const R wd = w0 * X0 + w1 * X1 + w2 * X2;
-    const R bwd = b * wd;
-    const R P0 = c * X0 + a * cx0 + bwd * w0 + th[3];
-    const R P1 = c * X1 + a * cx1 + bwd * w1 + th[4];
-    const R P2 = c * X2 + a * cx2 + bwd * w2 + th[5];
-    const R iz = Num<R>::rcp(P2);
-    const R p0 = P0 * iz, p1 = P1 * iz;
-    const R r2 = p0 * p0 + p1 * p1;
     const R f = th[6], k1 = th[7], k2 = th[8];
-    const R d = R(1) + r2 * (k1 + k2 * r2);
-    const R fd = f * d;
-    pu = fd * p0;
-    pv = fd * p1;
-    if (JAC) {
-        const R g = R(2) * k1 + R(4) * k2 * r2;
-        const R fq = f * iz;
-        const R dg = d + g * r2;
-        const R A00 = fq * (d + g * p0 * p0), A01 = fq * (g * p0 * p1), A02 = -fq * p0 * dg;
-        const R A11 = fq * (d + g * p1 * p1), A12 = -fq * p1 * dg;
-        const R b1wd = b1 * wd;
-        const R q0 = a1 * cx0 + b1wd * w0 - a * X0;
-        const R q1 = a1 * cx1 + b1wd * w1 - a * X1;
-        const R q2 = a1 * cx2 + b1wd * w2 - a * X2;
-        const R fr2 = f * r2;
-        auto row = [&](R *Jr, R Ar0, R Ar1, R Ar2, R pr) {
-            const R Aq = Ar0 * q0 + Ar1 * q1 + Ar2 * q2;
-            const R bAw = b * (Ar0 * w0 + Ar1 * w1 + Ar2 * w2);
-            Jr[0] = Aq * w0 + bAw * X0 - a * (Ar1 * X2 - Ar2 * X1) + bwd * Ar0;
-            Jr[1] = Aq * w1 + bAw * X1 - a * (Ar2 * X0 - Ar0 * X2) + bwd * Ar1;
-            Jr[2] = Aq * w2 + bAw * X2 - a * (Ar0 * X1 - Ar1 * X0) + bwd * Ar2;
-            Jr[3] = Ar0;
-            Jr[4] = Ar1;
-            Jr[5] = Ar2;
-            Jr[6] = d * pr;
-            Jr[7] = fr2 * pr;
-            Jr[8] = fr2 * r2 * pr;
-            Jr[9] = c * Ar0 + a * (Ar1 * w2 - Ar2 * w1) + bAw * w0;
-            Jr[10] = c * Ar1 + a * (Ar2 * w0 - Ar0 * w2) + bAw * w1;
-            Jr[11] = c * Ar2 + a * (Ar0 * w1 - Ar1 * w0) + bAw * w2;
-        };
-        row(J0, A00, A01, A02, p0);
-        row(J1, A01, A11, A12, p1);
-    }
-    return P2;
+    const R c = o.c, a = o.a, b = o.b, d = o.d, r2 = o.r2, p0 = o.p0, p1 = o.p1;
+    const R bwd = b * o.wd;
+    const R g = R(2) * k1 + R(4) * k2 * r2;
+    const R fq = f * o.iz;
+    const R dg = d + g * r2;
+    const R A00 = fq * (d + g * p0 * p0), A01 = fq * (g * p0 * p1), A02 = -fq * p0 * dg;
+    const R A11 = fq * (d + g * p1 * p1), A12 = -fq * p1 * dg;
+    const R b1wd = o.b1 * o.wd;
+    const R q0 = o.a1 * o.cx0 + b1wd * w0 - a * X0;
+    const R q1 = o.a1 * o.cx1 + b1wd * w1 - a * X1;
+    const R q2 = o.a1 * o.cx2 + b1wd * w2 - a * X2;
+    const R fr2 = f * r2;
+    auto row = [&](R *Jr, R Ar0, R Ar1, R Ar2, R pr) {
+        const R Aq = Ar0 * q0 + Ar1 * q1 + Ar2 * q2;
+        const R bAw = b * (Ar0 * w0 + Ar1 * w1 + Ar2 * w2);
+        Jr[0] = Aq * w0 + bAw * X0 - a * (Ar1 * X2 - Ar2 * X1) + bwd * Ar0;
+        Jr[1] = Aq * w1 + bAw * X1 - a * (Ar2 * X0 - Ar0 * X2) + bwd * Ar1;
+        Jr[2] = Aq * w2 + bAw * X2 - a * (Ar0 * X1 - Ar1 * X0) + bwd * Ar2;
+        Jr[3] = Ar0;
+        Jr[4] = Ar1;
+        Jr[5] = Ar2;
+        Jr[6] = d * pr;
+        Jr[7] = fr2 * pr;
+        Jr[8] = fr2 * r2 * pr;
+        Jr[9] = c * Ar0 + a * (Ar1 * w2 - Ar2 * w1) + bAw * w0;
+        Jr[10] = c * Ar1 + a * (Ar2 * w0 - Ar0 * w2) + bAw * w1;
+        Jr[11] = c * Ar2 + a * (Ar0 * w1 - Ar1 * w0) + bAw * w2;
+    };
+    row(J0, A00, A01, A02, p0);
+    row(J1, A01, A11, A12, p1);
 }
 
 // phi(s) and w = phi'(s) of the misfit loss of Eq. (8).
@@ -163,14 +186,15 @@ __device__ __forceinline__ R loss_phi(int kind, R lp, R s, R &w)
     return s;
 }
 
+// Local objective of Eq. (9) in scaled form at the point of `o`:
+// phi(|z - pi|^2) + 1/2 sum_i P_i (theta_i - v_i)^2, P = (rho_y x9, rho_x x3);
+// +inf when the depth is <= 1e-6.
 template <typename R>
-__device__ __forceinline__ R objective(const R *th, const R *v, R z0, R z1, R rx, R ry,
-                                       int kind, R lp)
+__device__ __forceinline__ R objective(const Proj<R> &o, const R *th, const R *v, R z0, R z1,
+                                       R rx, R ry, int kind, R lp)
 {
-    R pu, pv;
-    const R depth = project<R, false>(th, pu, pv, nullptr, nullptr);
-    if (!(depth > R(1e-6))) return Num<R>::inf;
-    const R e0 = z0 - pu, e1 = z1 - pv;
+    if (!(o.depth > R(1e-6))) return Num<R>::inf;
+    const R e0 = z0 - o.pu, e1 = z1 - o.pv;
     R w;
     const R phi = loss_phi<R>(kind, lp, e0 * e0 + e1 * e1, w);
     R pen = R(0);
@@ -182,45 +206,6 @@ __device__ __forceinline__ R objective(const R *th, const R *v, R z0, R z1, R rx
     return phi + R(0.5) * pen;
 }
 
-// In-place Cholesky of the packed 12x12 SPD matrix (the diagonal keeps
-// 1/L_jj) and solve of A x = b; false on a non-positive or non-finite pivot.
-template <typename R>
-__device__ __forceinline__ bool chol_solve12(R *A, R *x)
-{
-    bool ok = true;
-#pragma unroll
-    for (int j = 0; j < 12; ++j) {
-        R s = A[IX(j, j)];
-#pragma unroll
-        for (int k = 0; k < j; ++k) s -= A[IX(j, k)] * A[IX(j, k)];
-        ok = ok && (s > R(0)) && (s < Num<R>::inf);
-        const R inv = Num<R>::rsqrt(s > R(0) ? s : R(1));
-        A[IX(j, j)] = inv;
-#pragma unroll
-        for (int i = j + 1; i < 12; ++i) {
-            R t = A[IX(i, j)];
-#pragma unroll
-            for (int k = 0; k < j; ++k) t -= A[IX(i, k)] * A[IX(j, k)];
-            A[IX(i, j)] = t * inv;
-        }
-    }
-#pragma unroll
-    for (int i = 0; i < 12; ++i) {
-        R t = x[i];
-#pragma unroll
-        for (int k = 0; k < i; ++k) t -= A[IX(i, k)] * x[k];
-        x[i] = t * A[IX(i, i)];
-    }
-#pragma unroll
-    for (int i = 11; i >= 0; --i) {
-        R t = x[i];
-#pragma unroll
-        for (int k = i + 1; k < 12; ++k) t -= A[IX(k, i)] * x[k];
-        x[i] = t * A[IX(i, i)];
-    }
-    return ok;
-}
-
 template <typename R> __device__ __forceinline__ R lam_down(R l);
 template <> __device__ __forceinline__ float lam_down(float l) { return fmaxf(l * 0.1f, 1e-12f); }
 template <> __device__ __forceinline__ double lam_down(double l) { return fmax(l / 10.0, 1e-12); }
@@ -230,37 +215,95 @@ template <typename R> __device__ __forceinline__ R lam_up(R l) { return l * R(10
 // included), Marquardt damping lambda * diag(H).  A trial is accepted if it
 // lowers F, or if the model's predicted decrease is below tie times F's
 // rounding resolution, F + |e| (|z_1| + |z_2| + f) -- a step that small cannot
-// be judged by F in this precision, so the model decides.
-// A non-finite trial (depth <= 1e-6 or a failed factorisation) is rejected.
+// be judged by F in this precision, so the model decides.  A non-finite trial
+// (depth <= 1e-6 or a failed factorisation) is rejected.
+//
+// Normal equations: A = H + lambda diag(H), H = P + 2w J^T J, i.e.
+// A = D + c (J0 J0^T + J1 J1^T) with D diagonal and c = 2w.  Its LDL^T
+// (Cholesky) factor is built by two rank-one updates of the diagonal factor
+// (Gill, Golub, Murray & Saunders 1974, method C1): A = L1 L2 D2 L2^T L1^T
+// with unit lower-triangular L1 = I + low(J0 b1^T), L2 = I + low(q b2^T),
+// q = L1^-1 J1.  The factor lives in registers as four 12-vectors and both
+// the factorisation and the solve take O(12) operations.
 template <typename R>
 __device__ __forceinline__ void local_lm(R *th, const R *v, R z0, R z1, R rx, R ry, int kind,
                                          R lp, int steps, R lam)
 {
-    R F = objective<R>(th, v, z0, z1, rx, ry, kind, lp);
+    Proj<R> cur = proj_core<R, true>(th);
+    R F = objective<R>(cur, th, v, z0, z1, rx, ry, kind, lp);
     for (int it = 0; it < steps; ++it) {
-        R pu, pv, J0[12], J1[12];
-        project<R, true>(th, pu, pv, J0, J1);
-        const R e0 = z0 - pu, e1 = z1 - pv;
+        R J0[12], J1[12];
+        proj_jac<R>(cur, th, J0, J1);
+        const R e0 = z0 - cur.pu, e1 = z1 - cur.pv;
         R w;
         const R s2 = e0 * e0 + e1 * e1;
         loss_phi<R>(kind, lp, s2, w);
         const R c2 = R(2) * w;
         // rounding resolution of F here: e = z - pi loses ~eps |z|
         const R fres = F + Num<R>::sqrt(s2) * (fabs(z0) + fabs(z1) + fabs(th[6]));
-        R A[78], x[12], ng[12], hd[12];
+        R x[12], ng[12], hd[12], Dd[12];
 #pragma unroll
         for (int i = 0; i < 12; ++i) {
             const R Pi = i < 9 ? ry : rx;
-            const R ci0 = c2 * J0[i], ci1 = c2 * J1[i];
-            x[i] = (ci0 * e0 + ci1 * e1) - Pi * (th[i] - v[i]);
-            ng[i] = x[i];
-#pragma unroll
-            for (int j = 0; j <= i; ++j) A[IX(i, j)] = ci0 * J0[j] + ci1 * J1[j];
-            A[IX(i, i)] += Pi;
-            hd[i] = A[IX(i, i)];
-            A[IX(i, i)] += lam * A[IX(i, i)];
+            ng[i] = c2 * (J0[i] * e0 + J1[i] * e1) - Pi * (th[i] - v[i]);  // -gradient
+            hd[i] = Pi + c2 * (J0[i] * J0[i] + J1[i] * J1[i]);             // diag(H)
+            Dd[i] = Pi + lam * hd[i];                                       // A - c J^T J
         }
-        const bool ok = chol_solve12<R>(A, x);
+        // rank-one update 1: diag -> L1 D1 L1^T (p = J0)
+        R b1[12], id1[12], b2[12], q[12], id2[12];
+        R tau = R(1);
+#pragma unroll
+        for (int j = 0; j < 12; ++j) {
+            const R idj = Num<R>::rcp(Dd[j]);
+            const R cp = c2 * J0[j] * idj;
+            const R tn = tau + cp * J0[j];
+            const R itn = Num<R>::rcp(tn);
+            id1[j] = idj * tau * itn;
+            b1[j] = cp * itn;
+            tau = tn;
+        }
+        // rank-one update 2 (z = J1): q = L1^-1 J1, then L2 D2 L2^T
+        R S = R(0);
+        R tau2 = R(1);
+#pragma unroll
+        for (int j = 0; j < 12; ++j) {
+            q[j] = J1[j] - J0[j] * S;
+            S += b1[j] * q[j];
+            const R cq = c2 * q[j] * id1[j];
+            const R tn = tau2 + cq * q[j];
+            const R itn = Num<R>::rcp(tn);
+            id2[j] = id1[j] * tau2 * itn;
+            b2[j] = cq * itn;
+            tau2 = tn;
+        }
+        const bool ok = (tau2 > R(0)) && (tau2 < Num<R>::inf) && (tau < Num<R>::inf);
+        // solve L1 L2 D2 L2^T L1^T x = -g
+        S = R(0);
+#pragma unroll
+        for (int j = 0; j < 12; ++j) {
+            x[j] = ng[j] - J0[j] * S;
+            S += b1[j] * x[j];
+        }
+        S = R(0);
+#pragma unroll
+        for (int j = 0; j < 12; ++j) {
+            x[j] = x[j] - q[j] * S;
+            S += b2[j] * x[j];
+        }
+#pragma unroll
+        for (int j = 0; j < 12; ++j) x[j] *= id2[j];
+        S = R(0);
+#pragma unroll
+        for (int j = 11; j >= 0; --j) {
+            x[j] = x[j] - b2[j] * S;
+            S += q[j] * x[j];
+        }
+        S = R(0);
+#pragma unroll
+        for (int j = 11; j >= 0; --j) {
+            x[j] = x[j] - b1[j] * S;
+            S += J0[j] * x[j];
+        }
         R tr[12];
         R gd = R(0), dd = R(0);
 #pragma unroll
@@ -271,11 +314,13 @@ __device__ __forceinline__ void local_lm(R *th, const R *v, R z0, R z1, R rx, R 
         }
         // decrease predicted by the damped Gauss-Newton model
         const R pred = R(0.5) * (lam * dd + gd);
-        const R Fn = ok ? objective<R>(tr, v, z0, z1, rx, ry, kind, lp) : Num<R>::inf;
+        const Proj<R> nxt = proj_core<R, true>(tr);
+        const R Fn = ok ? objective<R>(nxt, tr, v, z0, z1, rx, ry, kind, lp) : Num<R>::inf;
         // accept a decrease of F, or a step too small for F to judge
         if (Fn < Num<R>::inf && (Fn < F || pred <= Num<R>::tie * fres)) {
 #pragma unroll
             for (int i = 0; i < 12; ++i) th[i] = tr[i];
+            cur = nxt;
             F = Fn;
             lam = lam_down<R>(lam);
         } else {
@@ -405,30 +450,48 @@ __global__ __launch_bounds__(256) void k_consensus(DevArrays<R> a, int pt_blocks
 {
     using R4 = typename Vec<R>::R4;
     if ((int)blockIdx.x < pt_blocks) {
-        const int i = blockIdx.x * 256 + threadIdx.x;
-        if (i >= a.n_pts) return;
-        const int r0 = a.pt_off[i], r1 = a.pt_off[i + 1];
-        double s0 = 0.0, s1 = 0.0, s2 = 0.0;
-        for (int r = r0; r < r1; ++r) {
-            const R4 x = a.xrec[r];
-            const double4 u = a.urec[r];
-            s0 += (double)x.x + u.x;
-            s1 += (double)x.y + u.y;
-            s2 += (double)x.z + u.z;
+        __shared__ double sh[2][kPtBlock];
+        const int b = blockIdx.x;
+        double pri = 0.0, dual = 0.0;
+        if ((int)threadIdx.x < a.pblk_cnt[b]) {
+            const int i = a.pblk_pt0[b] + threadIdx.x;
+            const int r0 = a.pt_off[i], r1 = a.pt_off[i + 1];
+            double s0 = 0.0, s1 = 0.0, s2 = 0.0;
+            for (int r = r0; r < r1; ++r) {
+                const R4 x = a.xrec[r];
+                const double4 u = a.urec[r];
+                s0 += (double)x.x + u.x;
+                s1 += (double)x.y + u.y;
+                s2 += (double)x.z + u.z;
+            }
+            const double n = (double)(r1 - r0);
+            const double c0 = s0 / n, c1 = s1 / n, c2 = s2 / n;
+            for (int r = r0; r < r1; ++r) {
+                const R4 x = a.xrec[r];
+                const double d0 = (double)x.x - c0, d1 = (double)x.y - c1, d2 = (double)x.z - c2;
+                pri += d0 * d0 + d1 * d1 + d2 * d2;
+            }
+            const double4 old = a.cons_x[i];
+            const double e0 = c0 - old.x, e1 = c1 - old.y, e2 = c2 - old.z;
+            a.cons_x[i] = make_double4(c0, c1, c2, 0.0);
+            dual = n * (e0 * e0 + e1 * e1 + e2 * e2);
         }
-        const double n = (double)(r1 - r0);
-        const double c0 = s0 / n, c1 = s1 / n, c2 = s2 / n;
-        double pri = 0.0;
-        for (int r = r0; r < r1; ++r) {
-            const R4 x = a.xrec[r];
-            const double d0 = (double)x.x - c0, d1 = (double)x.y - c1, d2 = (double)x.z - c2;
-            pri += d0 * d0 + d1 * d1 + d2 * d2;
+        // fixed-order tree over the block's points
+        const int t = threadIdx.x;
+        sh[0][t] = pri;
+        sh[1][t] = dual;
+        __syncthreads();
+        for (int w = kPtBlock / 2; w >= 1; w >>= 1) {
+            if (t < w) {
+                sh[0][t] += sh[0][t + w];
+                sh[1][t] += sh[1][t + w];
+            }
+            __syncthreads();
         }
-        const double4 old = a.cons_x[i];
-        const double e0 = c0 - old.x, e1 = c1 - old.y, e2 = c2 - old.z;
-        a.cons_x[i] = make_double4(c0, c1, c2, 0.0);
-        a.ppart[2 * (long long)i] = pri;
-        a.ppart[2 * (long long)i + 1] = n * (e0 * e0 + e1 * e1 + e2 * e2);
+        if (t == 0) {
+            a.ppart[2 * (long long)b] = sh[0][0];
+            a.ppart[2 * (long long)b + 1] = sh[1][0];
+        }
     } else {
         const int lane = threadIdx.x & 63;
         const int J = (blockIdx.x - pt_blocks) * 4 + (threadIdx.x >> 6);
@@ -485,9 +548,9 @@ __global__ __launch_bounds__(kNormThreads) void k_norms(DevArrays<R> a)
     const int p = blockIdx.x;
     const ProblemRange pr = a.prob[p];
     double v[4] = {0.0, 0.0, 0.0, 0.0};  // pri_x, dual_x, pri_y, dual_y
-    for (int i = threadIdx.x; i < pr.n_points; i += kNormThreads) {
-        v[0] += a.ppart[2 * (long long)(pr.pt0 + i)];
-        v[1] += a.ppart[2 * (long long)(pr.pt0 + i) + 1];
+    for (int i = threadIdx.x; i < pr.n_pblk; i += kNormThreads) {
+        v[0] += a.ppart[2 * (long long)(pr.pblk0 + i)];
+        v[1] += a.ppart[2 * (long long)(pr.pblk0 + i) + 1];
     }
     for (int j = threadIdx.x; j < pr.n_cams; j += kNormThreads) {
         v[2] += a.campart[2 * (long long)(pr.cam0 + j)];
@@ -542,10 +605,9 @@ __global__ __launch_bounds__(256) void k_eval(DevArrays<R> a, SolverParams sp)
 #pragma unroll
         for (int i = 0; i < 9; ++i) th[i] = a.cons_y[(long long)J * kConsY + i];
         th[9] = cx.x; th[10] = cx.y; th[11] = cx.z;
-        double pu, pv;
-        project<double, false>(th, pu, pv, nullptr, nullptr);
+        const Proj<double> pr = proj_core<double, false>(th);
         const typename Vec<R>::R2 z = a.uv[s];
-        const double e0 = (double)z.x - pu, e1 = (double)z.y - pv;
+        const double e0 = (double)z.x - pr.pu, e1 = (double)z.y - pr.pv;
         const double s2 = e0 * e0 + e1 * e1;
         double w;
         val[0] = s2;
@@ -647,9 +709,8 @@ hipError_t launch_local(const DevArrays<R> &a, const SolverParams &sp, int block
 template <typename R>
 hipError_t launch_consensus(const DevArrays<R> &a, hipStream_t s)
 {
-    const int pt_blocks = (a.n_pts + 255) / 256;
     const int cam_blocks = (a.n_cams + 3) / 4;
-    hipLaunchKernelGGL(k_consensus<R>, dim3(pt_blocks + cam_blocks), dim3(256), 0, s, a, pt_blocks);
+    hipLaunchKernelGGL(k_consensus<R>, dim3(a.n_pblk + cam_blocks), dim3(256), 0, s, a, a.n_pblk);
     return hipGetLastError();
 }
 

@@ -33,10 +33,11 @@ HBM_PEAK_GBS = 8000.0
 
 WORKLOADS = {
     # name: (scene maker kwargs, solver options, description)
-    "trajectory": dict(scene="config2", opts=dict(precision="fp32", loss="huber", loss_param=2.0, rho=1e4,
-                                                   rho_balancing=True, rho_min=1e4, rho_max=1e7),
+    "trajectory": dict(scene="config2", opts=dict(precision="fp32", loss="huber", loss_param=2.0, rho=1e5,
+                                                   rho_balancing=True, rho_min=1e5, rho_max=1e7),
                        desc="1000 cameras on a random-walk trajectory, 200000 points, Zipf tracks 2..60, "
-                            "5% outliers; Huber 2 px, rho 1e4 with residual balancing; FP32 local / FP64 consensus"),
+                            "5% outliers; Huber 2 px, rho 1e5 with residual balancing in [1e5, 1e7]; "
+                            "FP32 local / FP64 consensus"),
     "sphere": dict(scene="config1", opts=dict(precision="fp32", loss="student_t", loss_param=4.0, rho=1e3),
                    desc="100 cameras on a sphere cap, 20000 points, 8..15 cameras per point; Student-t nu 4, "
                         "rho 1e3; FP32 local / FP64 consensus"),
@@ -54,7 +55,7 @@ def make_scene(kind):
 
 def kernel_source_hash():
     h = hashlib.sha256()
-    for f in ("dba_kernels.hip", "dba_internal.h"):
+    for f in ("dba_kernels.hip", "dba_device.h", "dba_internal.h"):
         with open(os.path.join(ROOT, "paper_1708_07954_amd", "csrc", f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:12]

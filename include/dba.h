@@ -174,6 +174,57 @@ int dba_kernel_times(dba_handle *h, double *total_ms /*[4]*/, int64_t *launches 
  * and number of candidate schedules the autotuner timed (0 if fixed). */
 int dba_schedule(const dba_handle *h, int32_t *block_waves, int32_t *persistent, int32_t *tuned);
 
+/* ---------------------------------------------------------------------------
+ * Learned warm start.  Before each local solve a small network predicts the
+ * solve's update from 26 features of the observation's local problem:
+ * residual at the start point (2), camera copy minus consensus (9), point
+ * copy minus consensus (3), scaled duals (9 + 3).  Network 26 -> 128 -> GELU
+ * -> 128 -> GELU -> 12, bf16 weights and activations, FP32 accumulation
+ * (gfx950 matrix cores).  The solve starts from the better (lower F of
+ * Eq. 9) of the copy and copy + prediction, ties keep the copy, and then runs
+ * `learned_lm_steps` plain LM steps.  FP32 local solves only.
+ * Parameter block (DBA_MLP_PARAMS floats): W1 [32][128] (rows 26..31 zero),
+ * b1 [128], W2 [128][128], b2 [128], W3 [128][16] (columns 12..15 zero),
+ * b3 [16]; layer l computes h W_l + b_l.  Normalisation (DBA_MLP_NORM floats):
+ * feature mean [26], feature std [26], output mean [12], output std [12];
+ * the network sees (f - mean) / std and predicts (delta - mean) / std.
+ * ------------------------------------------------------------------------- */
+#define DBA_MLP_PARAMS 22800
+#define DBA_MLP_NORM 76
+
+/* Sets the network (copied; bf16 copies made on the device). */
+int dba_set_mlp(dba_handle *h, const float *params, const float *norm);
+/* Reads the network's FP32 parameters and normalisation (either may be NULL). */
+int dba_get_mlp(dba_handle *h, float *params, float *norm);
+/* Switches the start of the local solves (dba_start) and the LM steps that
+ * follow a learned start; DBA_E_STATE at the next dba_iterate if learned and
+ * no network is set. */
+int dba_set_start(dba_handle *h, int32_t start, int32_t learned_lm_steps);
+/* Network evaluation: features [n][26] -> predicted updates [n][12]. */
+int dba_mlp_forward(dba_handle *h, const float *features, int64_t n, float *delta);
+/* Mean squared error over n x 12 of the network on standardized inputs
+ * x_std [n][32] (rounded to bf16 on the device) against standardized targets
+ * t_std [n][16] (columns 12..15 ignored), its gradient with respect to the
+ * parameter block (grad [DBA_MLP_PARAMS], may be NULL) and the outputs
+ * y_out [n][16] (may be NULL).  n a multiple of 64, at most 65536. */
+int dba_mlp_loss_grad(dba_handle *h, const float *x_std, const float *t_std, int32_t n, float *loss, float *grad,
+                      float *y_out);
+/* Runs n_iters plain ADMM iterations of the problem set; before each one
+ * samples per_iter observations (seeded) and records, for each, its 26
+ * features and the update of an LM run of conv_steps steps from the copy on
+ * the same local problem: features [n_iters*per_iter][26], deltas [..][12].
+ * FP32 local solves only. */
+int dba_collect_pairs(dba_handle *h, int32_t n_iters, int32_t per_iter, uint64_t seed, int32_t conv_steps,
+                      float *features, float *deltas);
+/* Trains the network on n pairs: standardisation from the pairs, N(0,
+ * 1/fan_in) initialisation (seeded), Adam (0.9, 0.999, 1e-8) with a cosine
+ * learning-rate schedule from lr, mean squared error on standardized
+ * targets, shuffled full batches of `batch` (a multiple of 64).  epoch_loss
+ * [epochs] receives the mean training loss of each epoch (may be NULL).  The
+ * trained network becomes the handle's network. */
+int dba_mlp_train(dba_handle *h, const float *features, const float *deltas, int64_t n, int32_t epochs, int32_t batch,
+                  double lr, uint64_t seed, float *epoch_loss);
+
 #ifdef __cplusplus
 }
 #endif

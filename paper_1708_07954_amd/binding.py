@@ -67,7 +67,9 @@ class dba_residual_report(ctypes.Structure):
 EXPORTS = ("dba_default_options", "dba_create", "dba_destroy", "dba_last_error",
            "dba_set_problem", "dba_set_problems", "dba_iterate", "dba_residuals",
            "dba_set_eval_mask", "dba_get_params", "dba_get_state", "dba_problem_info",
-           "dba_set_kernel_timing", "dba_kernel_times", "dba_schedule")
+           "dba_set_kernel_timing", "dba_kernel_times", "dba_schedule", "dba_set_mlp", "dba_get_mlp",
+           "dba_set_start", "dba_mlp_forward", "dba_mlp_loss_grad", "dba_collect_pairs", "dba_mlp_train")
+MLP_PARAMS, MLP_NORM = 22800, 76
 
 _lib = None
 
@@ -107,13 +109,14 @@ def load(path: Optional[str] = None) -> ctypes.CDLL:
 
 
 def _declare_learned(L):
-    vp, i32, i64, dbl = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_double
-    L.dba_set_mlp.argtypes = [vp, vp, vp, vp]
-    L.dba_mlp_get_weights.argtypes = [vp, vp, vp]
-    L.dba_collect_pairs.argtypes = [vp, i32, i32, i32, i64, vp, vp, ctypes.POINTER(i64)]
-    L.dba_mlp_train.argtypes = [vp, vp, vp, i64, i32, i32, dbl, ctypes.c_uint64, vp, vp]
+    vp, i32, i64, dbl, u64 = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_double, ctypes.c_uint64
+    L.dba_set_mlp.argtypes = [vp, vp, vp]
+    L.dba_get_mlp.argtypes = [vp, vp, vp]
+    L.dba_set_start.argtypes = [vp, i32, i32]
     L.dba_mlp_forward.argtypes = [vp, vp, i64, vp]
-    L.dba_mlp_backward.argtypes = [vp, vp, vp, i64, vp]
+    L.dba_mlp_loss_grad.argtypes = [vp, vp, vp, i32, vp, vp, vp]
+    L.dba_collect_pairs.argtypes = [vp, i32, i32, u64, i32, vp, vp]
+    L.dba_mlp_train.argtypes = [vp, vp, vp, i64, i32, i32, dbl, u64, vp]
 
 
 def _ptr(a: Optional[np.ndarray]):
@@ -239,6 +242,62 @@ def dba_schedule(h):
     bw, pe, tu = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32()
     _check(h, load().dba_schedule(h, ctypes.byref(bw), ctypes.byref(pe), ctypes.byref(tu)))
     return dict(block_waves=bw.value, persistent=pe.value, tuned=tu.value)
+
+
+def _f32(a, shape=None):
+    a = np.ascontiguousarray(a, dtype=np.float32)
+    if shape is not None and a.shape != shape:
+        a = a.reshape(shape)
+    return a
+
+
+def dba_set_mlp(h, params, norm):
+    p, n = _f32(params).reshape(-1), _f32(norm).reshape(-1)
+    assert p.size == MLP_PARAMS and n.size == MLP_NORM
+    _check(h, load().dba_set_mlp(h, _ptr(p), _ptr(n)))
+
+
+def dba_get_mlp(h):
+    p, n = np.zeros(MLP_PARAMS, np.float32), np.zeros(MLP_NORM, np.float32)
+    _check(h, load().dba_get_mlp(h, _ptr(p), _ptr(n)))
+    return p, n
+
+
+def dba_set_start(h, start, learned_lm_steps=2):
+    _check(h, load().dba_set_start(h, START[start] if isinstance(start, str) else int(start), int(learned_lm_steps)))
+
+
+def dba_mlp_forward(h, features):
+    f = _f32(features).reshape(-1, 26)
+    out = np.zeros((f.shape[0], 12), np.float32)
+    _check(h, load().dba_mlp_forward(h, _ptr(f), f.shape[0], _ptr(out)))
+    return out
+
+
+def dba_mlp_loss_grad(h, x_std, t_std):
+    x, t = _f32(x_std).reshape(-1, 32), _f32(t_std).reshape(-1, 16)
+    n = x.shape[0]
+    loss = np.zeros(1, np.float32)
+    grad = np.zeros(MLP_PARAMS, np.float32)
+    y = np.zeros((n, 16), np.float32)
+    _check(h, load().dba_mlp_loss_grad(h, _ptr(x), _ptr(t), n, _ptr(loss), _ptr(grad), _ptr(y)))
+    return float(loss[0]), grad, y
+
+
+def dba_collect_pairs(h, n_iters, per_iter, seed=0, conv_steps=30):
+    f = np.zeros((n_iters * per_iter, 26), np.float32)
+    d = np.zeros((n_iters * per_iter, 12), np.float32)
+    _check(h, load().dba_collect_pairs(h, int(n_iters), int(per_iter), int(seed), int(conv_steps), _ptr(f), _ptr(d)))
+    return f, d
+
+
+def dba_mlp_train(h, features, deltas, epochs=10, batch=4096, lr=1e-3, seed=0):
+    f, d = _f32(features).reshape(-1, 26), _f32(deltas).reshape(-1, 12)
+    assert f.shape[0] == d.shape[0]
+    el = np.zeros(int(epochs), np.float32)
+    _check(h, load().dba_mlp_train(h, _ptr(f), _ptr(d), f.shape[0], int(epochs), int(batch), float(lr), int(seed),
+                                   _ptr(el)))
+    return el
 
 
 # ---------------------------------------------------------------- convenience

@@ -9,27 +9,27 @@ state read or written once per iteration.
 from __future__ import annotations
 
 # --- local solve (per observation) -----------------------------------------
-# projection with Jacobian: Rodrigues coefficients 25, transform 36, perspective
-# + distortion 14, d pi / d P 24, q 16, two Jacobian rows 2 x 70
-PROJ_JAC = 25 + 36 + 14 + 24 + 16 + 140
-# projection only (trial point): coefficients 16, transform 36, perspective 14
-PROJ = 16 + 36 + 14
-# residual, loss weight and resolution of F
+# projection core (also the trial evaluation): Rodrigues coefficients with
+# their derivatives 25, transform 36, perspective + distortion 14
+PROJ = 25 + 36 + 14
+# Jacobian rows from the cached projection: d pi / d P 24, q 16, 2 rows x 70
+JAC = 24 + 16 + 140
+# residual, loss weight, resolution of F
 RESID = 5 + 6 + 6
-# normal equations: for each row 12 (gradient, scale), 78 packed entries x 3,
-# diagonal + damping 24
-NORMAL = 12 * 10 + 78 * 3 + 24
-# packed 12x12 Cholesky: sum_j 2j + sum_j (11-j)(2j+1) + 12 rsqrt
-CHOL = 132 + 506 + 12
-# forward + backward substitution
-SOLVE = 2 * 144
-# trial point, predicted decrease, objective at the trial (projection,
-# residual, loss, 12-term penalty), acceptance
-TRIAL = 12 + 60 + 3 + PROJ + 10 + 36 + 15
-LM_STEP = PROJ_JAC + RESID + NORMAL + CHOL + SOLVE + TRIAL
-# per solve: initial objective, deferred dual update (12 x 3), v (12),
-# chunk sums (19 values, 6 butterfly adds each, plus forming them 40)
-PER_SOLVE = (PROJ + 10 + 36) + 36 + 12 + 19 * 6 + 40
+# negative gradient (7), diag(H) (5), Marquardt diagonal (2), per parameter
+GRAD = 12 * 14
+# LDL^T of D + c (J0 J0^T + J1 J1^T): rank-one update 1 (9 per row),
+# L1^-1 J1 and rank-one update 2 (12 per row)
+FACTOR = 12 * 9 + 12 * 12
+# L1^-1, L2^-1, D2^-1, L2^-T, L1^-T
+SOLVE = 4 * 48 + 12
+# trial point 12, predicted decrease 63, objective at the trial (projection,
+# residual 5, loss 5, 12-term penalty 36, total 2), acceptance 30
+TRIAL = 12 + 63 + PROJ + 48 + 30
+LM_STEP = JAC + RESID + GRAD + FACTOR + SOLVE + TRIAL
+# per solve: initial projection and objective, deferred dual update (12 x 3),
+# v (12), chunk sums (19 values, 6 butterfly adds each, plus forming them 40)
+PER_SOLVE = (PROJ + 48) + 36 + 12 + 19 * 6 + 40
 
 
 def local_flops_per_obs(lm_steps: int = 5) -> int:

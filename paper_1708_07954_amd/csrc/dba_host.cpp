@@ -1,8 +1,7 @@
 // dba_host.cpp -- C ABI, validation, device layout builder, iteration driver
 // (eager launches or hipGraph replay), launch-schedule autotuner and kernel
 // timing for the ADMM bundle-adjustment library.
-#include "dba.h"
-#include "dba_internal.h"
+#include "dba_host_internal.h"
 
 #include <algorithm>
 #include <cmath>
@@ -10,98 +9,11 @@
 #include <cstdio>
 #include <cstring>
 #include <string>
+#include <type_traits>
 #include <vector>
 
-namespace {
-
-using dba::Ctrl;
-using dba::DevArrays;
-using dba::ProblemRange;
-
-constexpr int kKernels = 4;   // local, consensus, norms, learned
-constexpr int kGraphBatch = 16;
-
-struct Buffers {
-    std::vector<void *> ptrs;
-    ~Buffers() { release(); }
-    void release()
-    {
-        for (void *p : ptrs) (void)hipFree(p);
-        ptrs.clear();
-    }
-    template <typename T>
-    hipError_t alloc(T **out, size_t count)
-    {
-        void *p = nullptr;
-        hipError_t e = hipMalloc(&p, std::max<size_t>(count, 1) * sizeof(T));
-        if (e != hipSuccess) return e;
-        ptrs.push_back(p);
-        *out = static_cast<T *>(p);
-        return hipSuccess;
-    }
-};
-
-struct ProblemSet {
-    Buffers buf;
-    int n_problems = 0;
-    std::vector<ProblemRange> ranges;
-    std::vector<int> m, n;
-    std::vector<long long> L;
-    DevArrays<float> a32{};
-    DevArrays<double> a64{};
-    uint8_t *mask = nullptr;
-    long long n_slots = 0;
-};
-
-struct Timing {
-    bool on = false;
-    double total_ms[kKernels] = {0, 0, 0, 0};
-    long long launches[kKernels] = {0, 0, 0, 0};
-    std::vector<hipEvent_t> pool;
-    std::vector<int> pending_kernel;  // kernel id per recorded pair
-    size_t used = 0;
-};
-
-}  // namespace
-
-struct dba_handle {
-    dba_options opt{};
-    hipStream_t stream = nullptr;
-    bool own_stream = false;
-    int n_cu = 256;
-    std::string err;
-    ProblemSet *ps = nullptr;
-    bool fp32 = false;
-    dba::SolverParams sp{};
-    // schedule
-    int block_waves = 4, persistent = 0, tuned = 0;
-    bool schedule_ready = false;
-    int tune_next = 0;
-    std::vector<float> tune_ms;
-    // graphs: [0] one iteration, [1] kGraphBatch iterations
-    hipGraphExec_t gexec[2] = {nullptr, nullptr};
-    Timing timing;
-};
-
-namespace {
-
-int fail(dba_handle *h, int code, const char *fmt, ...)
-{
-    char buf[512];
-    va_list ap;
-    va_start(ap, fmt);
-    vsnprintf(buf, sizeof(buf), fmt, ap);
-    va_end(ap);
-    if (h) h->err = buf;
-    return code;
-}
-
-#define HIP_TRY(h, expr)                                                                        \
-    do {                                                                                        \
-        hipError_t e_ = (expr);                                                                 \
-        if (e_ != hipSuccess)                                                                   \
-            return fail((h), DBA_E_DEVICE, "%s failed: %s", #expr, hipGetErrorString(e_));     \
-    } while (0)
+namespace dba {
+namespace host {
 
 void drop_graphs(dba_handle *h)
 {
@@ -357,6 +269,19 @@ int build_set(dba_handle *h, int np, const dba_problem_desc *probs, ProblemSet *
     return DBA_OK;
 }
 
+void free_mlp(dba_handle *h);
+
+// The local-solve launch of the handle's start mode.
+template <typename R>
+hipError_t launch_local_sel(dba_handle *h, const DevArrays<R> &A, int bw, int pers)
+{
+    if constexpr (std::is_same<R, float>::value) {
+        if (h->start == DBA_START_LEARNED)
+            return dba::launch_local_learned(A, h->sp, h->mlp->params(), pers, h->n_cu, h->stream);
+    }
+    return dba::launch_local<R>(A, h->sp, bw, pers, h->n_cu, h->stream);
+}
+
 // One ADMM iteration, eager.
 template <typename R>
 hipError_t run_iteration(dba_handle *h, const DevArrays<R> &A, int bw, int pers, bool timed)
@@ -382,8 +307,8 @@ hipError_t run_iteration(dba_handle *h, const DevArrays<R> &A, int bw, int pers,
     };
     hipEvent_t e;
     hipError_t err;
-    e = mark(0);
-    err = dba::launch_local<R>(A, h->sp, bw, pers, h->n_cu, h->stream);
+    e = mark(h->start == DBA_START_LEARNED ? 3 : 0);
+    err = launch_local_sel<R>(h, A, bw, pers);
     done(e);
     if (err != hipSuccess) return err;
     e = mark(1);
@@ -437,7 +362,7 @@ int iterate_impl(dba_handle *h, const DevArrays<R> &A, int n)
         HIP_TRY(h, hipEventCreate(&e0));
         HIP_TRY(h, hipEventCreate(&e1));
         HIP_TRY(h, hipEventRecord(e0, h->stream));
-        HIP_TRY(h, dba::launch_local<R>(A, h->sp, cand_bw[q], cand_p[q], h->n_cu, h->stream));
+        HIP_TRY(h, launch_local_sel<R>(h, A, cand_bw[q], cand_p[q]));
         HIP_TRY(h, hipEventRecord(e1, h->stream));
         HIP_TRY(h, dba::launch_consensus<R>(A, h->stream));
         HIP_TRY(h, dba::launch_norms<R>(A, h->stream));
@@ -501,7 +426,10 @@ int check_problem(const dba_handle *h, int p)
     return DBA_OK;
 }
 
-}  // namespace
+}  // namespace host
+}  // namespace dba
+
+using namespace dba::host;
 
 // ============================================================================
 extern "C" {
@@ -546,7 +474,9 @@ int dba_create(const dba_options *opt, dba_handle **out)
     if (o.block_waves != 0 && o.block_waves != 1 && o.block_waves != 2 && o.block_waves != 4 && o.block_waves != 8)
         return DBA_E_INVALID_ARG;
     if (o.persistent < -1 || o.persistent > 1) return DBA_E_INVALID_ARG;
-    if (o.start != DBA_START_PLAIN) return DBA_E_INVALID_ARG;  // learned start needs dba_set_mlp
+    if (o.start != DBA_START_PLAIN && o.start != DBA_START_LEARNED) return DBA_E_INVALID_ARG;
+    if (o.start == DBA_START_LEARNED && o.precision != DBA_PREC_FP32_LOCAL) return DBA_E_INVALID_ARG;
+    if (o.learned_lm_steps < 0 || o.learned_lm_steps > 64) return DBA_E_INVALID_ARG;
     dba_handle *h = new dba_handle();
     h->opt = o;
     h->fp32 = o.precision == DBA_PREC_FP32_LOCAL;
@@ -554,6 +484,8 @@ int dba_create(const dba_options *opt, dba_handle **out)
     h->sp.loss_param = o.loss == DBA_LOSS_L2 ? 1.0 : o.loss_param;
     h->sp.lm_steps = o.lm_steps;
     h->sp.lambda0 = o.lm_lambda0;
+    h->sp.learned_steps = o.learned_lm_steps;
+    h->start = o.start;
     if (hipSetDevice(o.device) != hipSuccess) {
         delete h;
         return DBA_E_DEVICE;
@@ -582,6 +514,7 @@ void dba_destroy(dba_handle *h)
     (void)hipSetDevice(h->opt.device);
     if (h->stream) (void)hipStreamSynchronize(h->stream);
     free_set(h);
+    free_mlp(h);
     for (hipEvent_t e : h->timing.pool) (void)hipEventDestroy(e);
     if (h->own_stream) (void)hipStreamDestroy(h->stream);
     delete h;
@@ -627,6 +560,8 @@ int dba_iterate(dba_handle *h, int32_t n_iters)
     h->err.clear();
     if (!h->ps) return fail(h, DBA_E_STATE, "no problem set");
     if (n_iters < 0) return fail(h, DBA_E_INVALID_ARG, "n_iters < 0");
+    if (h->start == DBA_START_LEARNED && !(h->mlp && h->mlp->ready))
+        return fail(h, DBA_E_STATE, "learned start without a network (dba_set_mlp or dba_mlp_train)");
     HIP_TRY(h, hipSetDevice(h->opt.device));
     return h->fp32 ? iterate_impl<float>(h, h->ps->a32, n_iters) : iterate_impl<double>(h, h->ps->a64, n_iters);
 }

@@ -104,14 +104,55 @@ struct SolverParams {
     double loss_param;
     int lm_steps;
     double lambda0;
+    int learned_steps;   // LM steps after the learned start
+};
+
+// ---- learned warm start: 26 -> 128 -> GELU -> 128 -> GELU -> 12 network
+constexpr int kIn = 26, kInPad = 32, kHid = 128, kOut = 12, kOutPad = 16;
+// packed bf16 weight block (dense, row-major):
+//   W1^T [128][32] | W2^T [128][128] | W3^T [16][128] | W2 [128][128] | W3 [128][32]
+constexpr int kOffW1T = 0;
+constexpr int kOffW2T = kOffW1T + kHid * kInPad;
+constexpr int kOffW3T = kOffW2T + kHid * kHid;
+constexpr int kOffW2N = kOffW3T + kOutPad * kHid;
+constexpr int kOffW3N = kOffW2N + kHid * kHid;
+constexpr int kWTotal = kOffW3N + kHid * 2 * kOutPad;
+// FP32 master parameters (flat): W1 [32][128] | b1 [128] | W2 [128][128] | b2 [128] | W3 [128][16] | b3 [16]
+constexpr int kPW1 = 0, kPB1 = kPW1 + kInPad * kHid, kPW2 = kPB1 + kHid, kPB2 = kPW2 + kHid * kHid,
+              kPW3 = kPB2 + kHid, kPB3 = kPW3 + kHid * kOutPad, kPTotal = kPB3 + kOutPad;
+// normalisation block: mu_in[26] sd_in[26] mu_out[12] sd_out[12]
+constexpr int kNormTotal = 2 * kIn + 2 * kOut;
+
+struct MlpParams {
+    const __bf16 *w;       // packed bf16 weights (kWTotal)
+    const float *b1, *b2, *b3;
+    const float *norm;     // kNormTotal
 };
 
 // launchers (dba_kernels.hip); each returns hipGetLastError()
 template <typename R>
 hipError_t launch_local(const DevArrays<R> &a, const SolverParams &sp, int block_waves,
                         int persistent, int n_cu, hipStream_t s);
+hipError_t launch_local_learned(const DevArrays<float> &a, const SolverParams &sp, const MlpParams &mp,
+                                int persistent, int n_cu, hipStream_t s);
 template <typename R>
 hipError_t launch_consensus(const DevArrays<R> &a, hipStream_t s);
+
+// network kernels (mlp_kernels.hip)
+hipError_t mlp_pack(const float *P, __bf16 *w, hipStream_t s);
+hipError_t mlp_prepare(const float *feat, const float *delta, const float *norm, long long n, __bf16 *xq, float *t,
+                       hipStream_t s);
+hipError_t mlp_forward(const __bf16 *xq, const int *rows, int n, const MlpParams &mp, float *y, __bf16 *xb, float *gp1,
+                       __bf16 *h1, float *gp2, __bf16 *h2, hipStream_t s);
+hipError_t mlp_backward(const float *y, const float *tq, const int *rows, int n, const __bf16 *w, const float *gp1,
+                        const float *gp2, float *dy, __bf16 *dyq, float *dz2, __bf16 *dz2q, float *dz1, __bf16 *dz1q,
+                        float *loss_part, hipStream_t s);
+hipError_t mlp_wgrad(const __bf16 *xb, const __bf16 *h1, const __bf16 *h2, const __bf16 *dyq, const __bf16 *dz2q,
+                     const __bf16 *dz1q, int n, float *grad, hipStream_t s);
+hipError_t mlp_bias(const float *dy, const float *dz2, const float *dz1, int n, float *grad, hipStream_t s);
+hipError_t mlp_adam(float *P, float *m, float *v, const float *g, float lr, float bc1, float bc2, hipStream_t s);
+hipError_t collect_pairs(const DevArrays<float> &a, const SolverParams &sp, const int *slots, int n, float *feat,
+                         float *delta, int conv_steps, hipStream_t s);
 template <typename R>
 hipError_t launch_norms(const DevArrays<R> &a, hipStream_t s);
 template <typename R>

@@ -19,336 +19,23 @@
 //
 // Every reduction has a fixed order that does not depend on the launch
 // schedule, so all schedules (and batched vs solo runs) are bitwise equal.
-#include "dba_internal.h"
-
-#include <math.h>
+#include "dba_device.h"
+#include "mlp_device.h"
 
 namespace dba {
 namespace {
 
-template <typename R> struct Num;
-template <> struct Num<float> {
-    static constexpr float small2 = 0.0625f;  // |w| < 0.25: Rodrigues coefficients by series
-    __device__ static float rcp(float x) { return __builtin_amdgcn_rcpf(x); }
-    __device__ static float sqrt(float x) { return sqrtf(x); }
-    __device__ static float rsqrt(float x) { return rsqrtf(x); }
-    __device__ static void sincos(float x, float *s, float *c) { sincosf(x, s, c); }
-    __device__ static float log1p(float x) { return log1pf(x); }
-    __device__ static float div(float x, float y) { return x * __builtin_amdgcn_rcpf(y); }
-    static constexpr float inf = __builtin_huge_valf();
-    static constexpr float tie = 1e-6f;       // predicted decrease F cannot resolve
-};
-template <> struct Num<double> {
-    static constexpr double small2 = 1e-4;    // |w| < 1e-2
-    __device__ static double rcp(double x) { return 1.0 / x; }
-    __device__ static double sqrt(double x) { return ::sqrt(x); }
-    __device__ static double rsqrt(double x) { return 1.0 / ::sqrt(x); }
-    __device__ static void sincos(double x, double *s, double *c) { ::sincos(x, s, c); }
-    __device__ static double log1p(double x) { return ::log1p(x); }
-    __device__ static double div(double x, double y) { return x / y; }
-    static constexpr double inf = __builtin_huge_val();
-    static constexpr double tie = 1e-13;
-};
-
-
-// Rodrigues coefficients of R(w) X = c X + a (w x X) + b (w.X) w and, for the
-// Jacobian, a1 = a'(t)/t and b1 = b'(t)/t; 1 - cos t is formed as 2 sin^2(t/2).
-template <typename R, bool DERIV>
-__device__ __forceinline__ void rot_coeffs(R t2, R &c, R &a, R &b, R &a1, R &b1)
-{
-    if (t2 < Num<R>::small2) {
-        const R t4 = t2 * t2;
-        c = R(1) - t2 * R(0.5) + t4 * R(1.0 / 24.0);
-        a = R(1) - t2 * R(1.0 / 6.0) + t4 * R(1.0 / 120.0);
-        b = R(0.5) - t2 * R(1.0 / 24.0) + t4 * R(1.0 / 720.0);
-        if (DERIV) {
-            a1 = R(-1.0 / 3.0) + t2 * R(1.0 / 30.0) - t4 * R(1.0 / 840.0);
-            b1 = R(-1.0 / 12.0) + t2 * R(1.0 / 180.0) - t4 * R(1.0 / 6720.0);
-        }
-    } else {
-        const R t = Num<R>::sqrt(t2);
-        R sh, ch;
-        Num<R>::sincos(t * R(0.5), &sh, &ch);
-        const R s = R(2) * sh * ch;
-        const R omc = R(2) * sh * sh;
-        c = R(1) - omc;
-        const R it = Num<R>::rcp(t);
-        const R it2 = it * it;
-        a = s * it;
-        b = omc * it2;
-        if (DERIV) {
-            a1 = (t * c - s) * it2 * it;
-            b1 = (t * s - R(2) * omc) * it2 * it2;
-        }
-    }
-}
-
-// Projection pi(theta), theta = (w, t, f, k1, k2, X), with the intermediate
-// values the Jacobian needs (so an accepted trial point's projection is
-// reused as the next linearisation point).
-template <typename R>
-struct Proj {
-    R c, a, b, a1, b1;      // Rodrigues coefficients
-    R cx0, cx1, cx2, wd;    // w x X, w . X
-    R iz, p0, p1, r2, d;    // 1/P_3, P_{1,2}/P_3, r^2, distortion factor
-    R pu, pv, depth;        // pixel and depth
-};
-
-template <typename R, bool DERIV>
-__device__ __forceinline__ Proj<R> proj_core(const R *th)
-{
-    Proj<R> o;
-    const R w0 = th[0], w1 = th[1], w2 = th[2];
-    const R X0 = th[9], X1 = th[10], X2 = th[11];
-    o.a1 = o.b1 = R(0);
-    rot_coeffs<R, DERIV>(w0 * w0 + w1 * w1 + w2 * w2, o.c, o.a, o.b, o.a1, o.b1);
-    o.cx0 = w1 * X2 - w2 * X1;
-    o.cx1 = w2 * X0 - w0 * X2;
-    o.cx2 = w0 * X1 - w1 * X0;
-    o.wd = w0 * X0 + w1 * X1 + w2 * X2;
-    const R bwd = o.b * o.wd;
-    const R P0 = o.c * X0 + o.a * o.cx0 + bwd * w0 + th[3];
-    const R P1 = o.c * X1 + o.a * o.cx1 + bwd * w1 + th[4];
-    const R P2 = o.c * X2 + o.a * o.cx2 + bwd * w2 + th[5];
-    o.depth = P2;
-    o.iz = Num<R>::rcp(P2);
-    o.p0 = P0 * o.iz;
-    o.p1 = P1 * o.iz;
-    o.r2 = o.p0 * o.p0 + o.p1 * o.p1;
-    o.d = R(1) + o.r2 * (th[7] + th[8] * o.r2);
-    const R fd = th[6] * o.d;
-    o.pu = fd * o.p0;
-    o.pv = fd * o.p1;
-    return o;
-}
-
-// The two rows of d pi / d theta at the point of `o`.  With A = d pi / d P
-// (2x3), row r is
-//   d/dw = (A_r.q) w + b (A_r.w) X - a (A_r x X) + b (w.X) A_r,
-//          q = a1 (w x X) + b1 (w.X) w - a X,
-//   d/dt = A_r,   d/dX = c A_r + a (A_r x w) + b (A_r.w) w,
-//   d/df = d p_r, d/dk1 = f r^2 p_r, d/dk2 = f r^4 p_r.
-template <typename R>
-__device__ __forceinline__ void proj_jac(const Proj<R> &o, const R *th, R *J0, R *J1)
-{
-    const R w0 = th[0], w1 = th[1], w2 = th[2];
-    const R X0 = th[9], X1 = th[10], X2 = th[11];
-    const R f = th[6], k1 = th[7], k2 = th[8];
-    const R c = o.c, a = o.a, b = o.b, d = o.d, r2 = o.r2, p0 = o.p0, p1 = o.p1;
-    const R bwd = b * o.wd;
-    const R g = R(2) * k1 + R(4) * k2 * r2;
-    const R fq = f * o.iz;
-    const R dg = d + g * r2;
-    const R A00 = fq * (d + g * p0 * p0), A01 = fq * (g * p0 * p1), A02 = -fq * p0 * dg;
-    const R A11 = fq * (d + g * p1 * p1), A12 = -fq * p1 * dg;
-    const R b1wd = o.b1 * o.wd;
-    const R q0 = o.a1 * o.cx0 + b1wd * w0 - a * X0;
-    const R q1 = o.a1 * o.cx1 + b1wd * w1 - a * X1;
-    const R q2 = o.a1 * o.cx2 + b1wd * w2 - a * X2;
-    const R fr2 = f * r2;
-    auto row = [&](R *Jr, R Ar0, R Ar1, R Ar2, R pr) {
-        const R Aq = Ar0 * q0 + Ar1 * q1 + Ar2 * q2;
-        const R bAw = b * (Ar0 * w0 + Ar1 * w1 + Ar2 * w2);
-        Jr[0] = Aq * w0 + bAw * X0 - a * (Ar1 * X2 - Ar2 * X1) + bwd * Ar0;
-        Jr[1] = Aq * w1 + bAw * X1 - a * (Ar2 * X0 - Ar0 * X2) + bwd * Ar1;
-        Jr[2] = Aq * w2 + bAw * X2 - a * (Ar0 * X1 - Ar1 * X0) + bwd * Ar2;
-        Jr[3] = Ar0;
-        Jr[4] = Ar1;
-        Jr[5] = Ar2;
-        Jr[6] = d * pr;
-        Jr[7] = fr2 * pr;
-        Jr[8] = fr2 * r2 * pr;
-        Jr[9] = c * Ar0 + a * (Ar1 * w2 - Ar2 * w1) + bAw * w0;
-        Jr[10] = c * Ar1 + a * (Ar2 * w0 - Ar0 * w2) + bAw * w1;
-        Jr[11] = c * Ar2 + a * (Ar0 * w1 - Ar1 * w0) + bAw * w2;
-    };
-    row(J0, A00, A01, A02, p0);
-    row(J1, A01, A11, A12, p1);
-}
-
-// phi(s) and w = phi'(s) of the misfit loss of Eq. (8).
-template <typename R>
-__device__ __forceinline__ R loss_phi(int kind, R lp, R s, R &w)
-{
-    if (kind == 1) {
-        const R d2 = lp * lp;
-        if (s <= d2) { w = R(1); return s; }
-        const R r = Num<R>::sqrt(s);
-        w = Num<R>::div(lp, r);
-        return R(2) * lp * r - d2;
-    }
-    if (kind == 2) {
-        const R q = Num<R>::div(s, lp);
-        w = Num<R>::rcp(R(1) + q);
-        return lp * Num<R>::log1p(q);
-    }
-    w = R(1);
-    return s;
-}
-
-// Local objective of Eq. (9) in scaled form at the point of `o`:
-// phi(|z - pi|^2) + 1/2 sum_i P_i (theta_i - v_i)^2, P = (rho_y x9, rho_x x3);
-// +inf when the depth is <= 1e-6.
-template <typename R>
-__device__ __forceinline__ R objective(const Proj<R> &o, const R *th, const R *v, R z0, R z1,
-                                       R rx, R ry, int kind, R lp)
-{
-    if (!(o.depth > R(1e-6))) return Num<R>::inf;
-    const R e0 = z0 - o.pu, e1 = z1 - o.pv;
-    R w;
-    const R phi = loss_phi<R>(kind, lp, e0 * e0 + e1 * e1, w);
-    R pen = R(0);
-#pragma unroll
-    for (int i = 0; i < 12; ++i) {
-        const R dd = th[i] - v[i];
-        pen += (i < 9 ? ry : rx) * dd * dd;
-    }
-    return phi + R(0.5) * pen;
-}
-
-template <typename R> __device__ __forceinline__ R lam_down(R l);
-template <> __device__ __forceinline__ float lam_down(float l) { return fmaxf(l * 0.1f, 1e-12f); }
-template <> __device__ __forceinline__ double lam_down(double l) { return fmax(l / 10.0, 1e-12); }
-template <typename R> __device__ __forceinline__ R lam_up(R l) { return l * R(10) < R(1e12) ? l * R(10) : R(1e12); }
-
-// Robust LM on the local objective, exactly `steps` steps (rejected ones
-// included), Marquardt damping lambda * diag(H).  A trial is accepted if it
-// lowers F, or if the model's predicted decrease is below tie times F's
-// rounding resolution, F + |e| (|z_1| + |z_2| + f) -- a step that small cannot
-// be judged by F in this precision, so the model decides.  A non-finite trial
-// (depth <= 1e-6 or a failed factorisation) is rejected.
-//
-// Normal equations: A = H + lambda diag(H), H = P + 2w J^T J, i.e.
-// A = D + c (J0 J0^T + J1 J1^T) with D diagonal and c = 2w.  Its LDL^T
-// (Cholesky) factor is built by two rank-one updates of the diagonal factor
-// (Gill, Golub, Murray & Saunders 1974, method C1): A = L1 L2 D2 L2^T L1^T
-// with unit lower-triangular L1 = I + low(J0 b1^T), L2 = I + low(q b2^T),
-// q = L1^-1 J1.  The factor lives in registers as four 12-vectors and both
-// the factorisation and the solve take O(12) operations.
-template <typename R>
-__device__ __forceinline__ void local_lm(R *th, const R *v, R z0, R z1, R rx, R ry, int kind,
-                                         R lp, int steps, R lam)
-{
-    Proj<R> cur = proj_core<R, true>(th);
-    R F = objective<R>(cur, th, v, z0, z1, rx, ry, kind, lp);
-    for (int it = 0; it < steps; ++it) {
-        R J0[12], J1[12];
-        proj_jac<R>(cur, th, J0, J1);
-        const R e0 = z0 - cur.pu, e1 = z1 - cur.pv;
-        R w;
-        const R s2 = e0 * e0 + e1 * e1;
-        loss_phi<R>(kind, lp, s2, w);
-        const R c2 = R(2) * w;
-        // rounding resolution of F here: e = z - pi loses ~eps |z|
-        const R fres = F + Num<R>::sqrt(s2) * (fabs(z0) + fabs(z1) + fabs(th[6]));
-        R x[12], ng[12], hd[12], Dd[12];
-#pragma unroll
-        for (int i = 0; i < 12; ++i) {
-            const R Pi = i < 9 ? ry : rx;
-            ng[i] = c2 * (J0[i] * e0 + J1[i] * e1) - Pi * (th[i] - v[i]);  // -gradient
-            hd[i] = Pi + c2 * (J0[i] * J0[i] + J1[i] * J1[i]);             // diag(H)
-            Dd[i] = Pi + lam * hd[i];                                       // A - c J^T J
-        }
-        // rank-one update 1: diag -> L1 D1 L1^T (p = J0)
-        R b1[12], id1[12], b2[12], q[12], id2[12];
-        R tau = R(1);
-#pragma unroll
-        for (int j = 0; j < 12; ++j) {
-            const R idj = Num<R>::rcp(Dd[j]);
-            const R cp = c2 * J0[j] * idj;
-            const R tn = tau + cp * J0[j];
-            const R itn = Num<R>::rcp(tn);
-            id1[j] = idj * tau * itn;
-            b1[j] = cp * itn;
-            tau = tn;
-        }
-        // rank-one update 2 (z = J1): q = L1^-1 J1, then L2 D2 L2^T
-        R S = R(0);
-        R tau2 = R(1);
-#pragma unroll
-        for (int j = 0; j < 12; ++j) {
-            q[j] = J1[j] - J0[j] * S;
-            S += b1[j] * q[j];
-            const R cq = c2 * q[j] * id1[j];
-            const R tn = tau2 + cq * q[j];
-            const R itn = Num<R>::rcp(tn);
-            id2[j] = id1[j] * tau2 * itn;
-            b2[j] = cq * itn;
-            tau2 = tn;
-        }
-        const bool ok = (tau2 > R(0)) && (tau2 < Num<R>::inf) && (tau < Num<R>::inf);
-        // solve L1 L2 D2 L2^T L1^T x = -g
-        S = R(0);
-#pragma unroll
-        for (int j = 0; j < 12; ++j) {
-            x[j] = ng[j] - J0[j] * S;
-            S += b1[j] * x[j];
-        }
-        S = R(0);
-#pragma unroll
-        for (int j = 0; j < 12; ++j) {
-            x[j] = x[j] - q[j] * S;
-            S += b2[j] * x[j];
-        }
-#pragma unroll
-        for (int j = 0; j < 12; ++j) x[j] *= id2[j];
-        S = R(0);
-#pragma unroll
-        for (int j = 11; j >= 0; --j) {
-            x[j] = x[j] - b2[j] * S;
-            S += q[j] * x[j];
-        }
-        S = R(0);
-#pragma unroll
-        for (int j = 11; j >= 0; --j) {
-            x[j] = x[j] - b1[j] * S;
-            S += J0[j] * x[j];
-        }
-        R tr[12];
-        R gd = R(0), dd = R(0);
-#pragma unroll
-        for (int i = 0; i < 12; ++i) {
-            tr[i] = th[i] + x[i];
-            gd += ng[i] * x[i];
-            dd += hd[i] * x[i] * x[i];
-        }
-        // decrease predicted by the damped Gauss-Newton model
-        const R pred = R(0.5) * (lam * dd + gd);
-        const Proj<R> nxt = proj_core<R, true>(tr);
-        const R Fn = ok ? objective<R>(nxt, tr, v, z0, z1, rx, ry, kind, lp) : Num<R>::inf;
-        // accept a decrease of F, or a step too small for F to judge
-        if (Fn < Num<R>::inf && (Fn < F || pred <= Num<R>::tie * fres)) {
-#pragma unroll
-            for (int i = 0; i < 12; ++i) th[i] = tr[i];
-            cur = nxt;
-            F = Fn;
-            lam = lam_down<R>(lam);
-        } else {
-            lam = lam_up<R>(lam);
-        }
-    }
-}
-
-__device__ __forceinline__ double wave_sum(double v)
-{
-#pragma unroll
-    for (int off = 32; off >= 1; off >>= 1) v += __shfl_xor(v, off, 64);
-    return v;
-}
-
-// Block -> tile mapping that gives each XCD (blocks are dealt round-robin to
-// the 8 XCDs) a contiguous range of tiles, so neighbouring cameras share an L2.
-__device__ __forceinline__ int xcd_block()
-{
-    const int G = gridDim.x, b = blockIdx.x;
-    const int q = G >> 3, r = G & 7, x = b & 7;
-    return x * q + (x < r ? x : r) + (b >> 3);
-}
+using namespace dev;
 
 // ---------------------------------------------------------------- local
-template <typename R>
-__device__ __forceinline__ void local_chunk(const DevArrays<R> &a, const SolverParams &sp, int c,
-                                            int lane)
+// One 64-slot chunk (one camera) per wave.  LEARNED: the start point is the
+// better of the copy and copy + network prediction (ties keep the copy), then
+// `learned_steps` LM steps; act/lw are the wave's activation tile and the
+// staged weights.
+template <typename R, bool LEARNED>
+__device__ __forceinline__ void local_chunk(const DevArrays<R> &a, const SolverParams &sp, int c, int lane,
+                                            const MlpParams *mp = nullptr, const __bf16 *lw = nullptr,
+                                            __bf16 *act = nullptr)
 {
     using R2 = typename Vec<R>::R2;
     using R4 = typename Vec<R>::R4;
@@ -360,6 +47,7 @@ __device__ __forceinline__ void local_chunk(const DevArrays<R> &a, const SolverP
     const long long S = a.n_slots;
     const long long s = (long long)c * kChunk + lane;
     const int ps = a.pslot[s];
+    const bool active = ps >= 0;
     double cy[9];
 #pragma unroll
     for (int i = 0; i < 9; ++i) cy[i] = a.cons_y[(long long)J * kConsY + i];
@@ -368,14 +56,17 @@ __device__ __forceinline__ void local_chunk(const DevArrays<R> &a, const SolverP
 #pragma unroll
     for (int i = 0; i < 19; ++i) acc[i] = 0.0;
 
-    if (ps >= 0) {
-        const int pt = a.ptid[s];
-        const R2 z = a.uv[s];
-        const double4 cx = a.cons_x[pt];
-        const double cons[12] = {cy[0], cy[1], cy[2], cy[3], cy[4], cy[5], cy[6], cy[7], cy[8],
-                                 cx.x, cx.y, cx.z};
-        R th[12];
-        double u[12];
+    R th[12], v[12];
+    double u[12], cons[12];
+    R2 z;
+    z.x = R(0);
+    z.y = R(0);
+    if (active) {
+        const double4 cx = a.cons_x[a.ptid[s]];
+#pragma unroll
+        for (int i = 0; i < 9; ++i) cons[i] = cy[i];
+        cons[9] = cx.x; cons[10] = cx.y; cons[11] = cx.z;
+        z = a.uv[s];
 #pragma unroll
         for (int i = 0; i < 9; ++i) {
             th[i] = a.copy_y[i * S + s];
@@ -393,11 +84,59 @@ __device__ __forceinline__ void local_chunk(const DevArrays<R> &a, const SolverP
             for (int i = 0; i < 9; ++i) a.dual_y[i * S + s] = u[i];
             a.urec[ps] = make_double4(u[9], u[10], u[11], 0.0);
         }
-        R v[12];
 #pragma unroll
         for (int i = 0; i < 12; ++i) v[i] = (R)(cons[i] - u[i]);
-        local_lm<R>(th, v, z.x, z.y, (R)rho_x, (R)rho_y, sp.loss, (R)sp.loss_param, sp.lm_steps,
-                    (R)sp.lambda0);
+    }
+    const R rx = (R)rho_x, ry = (R)rho_y, lp = (R)sp.loss_param, lam0 = (R)sp.lambda0;
+    if constexpr (LEARNED) {
+        Proj<R> cur;
+        R F = R(0);
+        const float *nm = mp->norm;
+        float f[kIn];
+        if (active) {
+            cur = proj_core<R, true>(th);
+            F = objective<R>(cur, th, v, z.x, z.y, rx, ry, sp.loss, lp);
+            f[0] = (float)(z.x - cur.pu);
+            f[1] = (float)(z.y - cur.pv);
+#pragma unroll
+            for (int i = 0; i < 12; ++i) f[2 + i] = (float)((double)th[i] - cons[i]);
+#pragma unroll
+            for (int i = 0; i < 12; ++i) f[14 + i] = (float)u[i];
+        } else {
+#pragma unroll
+            for (int i = 0; i < kIn; ++i) f[i] = nm[i];  // standardizes to zero
+        }
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            bf16x8 xin;
+#pragma unroll
+            for (int j = 0; j < 8; ++j) {
+                const int k = 8 * q + j;
+                xin[j] = k < kIn ? (__bf16)((f[k] - nm[k]) / nm[kIn + k]) : (__bf16)0.0f;
+            }
+            *reinterpret_cast<bf16x8 *>(act + lane * kActS + 8 * q) = xin;
+        }
+        float *out = reinterpret_cast<float *>(act);
+        mlp_forward64(lw, *mp, act, out, lane);
+        if (active) {
+            R tr[12];
+#pragma unroll
+            for (int i = 0; i < kOut; ++i)
+                tr[i] = th[i] + (R)(out[lane * kOutPad + i] * nm[2 * kIn + kOut + i] + nm[2 * kIn + i]);
+            const Proj<R> nxt = proj_core<R, true>(tr);
+            const R F1 = objective<R>(nxt, tr, v, z.x, z.y, rx, ry, sp.loss, lp);
+            if (F1 < F) {  // the guard: keep the prediction only if it lowers F
+#pragma unroll
+                for (int i = 0; i < 12; ++i) th[i] = tr[i];
+                cur = nxt;
+                F = F1;
+            }
+            lm_steps<R>(th, cur, F, v, z.x, z.y, rx, ry, sp.loss, lp, sp.learned_steps, lam0);
+        }
+    } else {
+        if (active) local_lm<R>(th, v, z.x, z.y, rx, ry, sp.loss, lp, sp.lm_steps, lam0);
+    }
+    if (active) {
 #pragma unroll
         for (int i = 0; i < 9; ++i) a.copy_y[i * S + s] = th[i];
         R4 xo;
@@ -426,22 +165,45 @@ __device__ __forceinline__ void local_chunk(const DevArrays<R> &a, const SolverP
 template <typename R> struct LocalBound { static constexpr int threads = 512; };
 template <> struct LocalBound<double> { static constexpr int threads = 256; };
 
+__device__ __forceinline__ void chunk_range(int n_chunks, int wpb, int persistent, int &c0, int &c1)
+{
+    const int lb = xcd_block();
+    if (persistent) {
+        const int per = (n_chunks + gridDim.x - 1) / gridDim.x;
+        c0 = lb * per;
+        c1 = min(c0 + per, n_chunks);
+    } else {
+        c0 = lb * wpb;
+        c1 = min(c0 + wpb, n_chunks);
+    }
+}
+
 template <typename R>
 __global__ __launch_bounds__(LocalBound<R>::threads) void k_local(DevArrays<R> a, SolverParams sp,
                                                                   int persistent)
 {
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, wpb = blockDim.x >> 6;
-    const int lb = xcd_block();
     int c0, c1;
-    if (persistent) {
-        const int per = (a.n_chunks + gridDim.x - 1) / gridDim.x;
-        c0 = lb * per;
-        c1 = min(c0 + per, a.n_chunks);
-    } else {
-        c0 = lb * wpb;
-        c1 = min(c0 + wpb, a.n_chunks);
-    }
-    for (int c = c0 + wave; c < c1; c += wpb) local_chunk<R>(a, sp, c, lane);
+    chunk_range(a.n_chunks, wpb, persistent, c0, c1);
+    for (int c = c0 + wave; c < c1; c += wpb) local_chunk<R, false>(a, sp, c, lane);
+}
+
+// Learned start: 4 waves per workgroup share the staged weights; each wave
+// has its own activation tile.
+constexpr int kLearnedWaves = 4;
+
+__global__ __launch_bounds__(64 * kLearnedWaves) void k_local_learned(DevArrays<float> a, SolverParams sp,
+                                                                       MlpParams mp, int persistent)
+{
+    __shared__ __attribute__((aligned(16))) __bf16 lw[kLdsFwd];
+    __shared__ __attribute__((aligned(16))) __bf16 act[kLearnedWaves][kLdsAct];
+    stage_forward_weights(mp.w, lw);
+    __syncthreads();
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    int c0, c1;
+    chunk_range(a.n_chunks, kLearnedWaves, persistent, c0, c1);
+    for (int c = c0 + wave; c < c1; c += kLearnedWaves)
+        local_chunk<float, true>(a, sp, c, lane, &mp, lw, act[wave]);
 }
 
 // ---------------------------------------------------------------- consensus
@@ -703,6 +465,22 @@ hipError_t launch_local(const DevArrays<R> &a, const SolverParams &sp, int block
     }
     if (grid < 1) grid = 1;
     hipLaunchKernelGGL(k_local<R>, dim3(grid), dim3(threads), 0, s, a, sp, persistent);
+    return hipGetLastError();
+}
+
+hipError_t launch_local_learned(const DevArrays<float> &a, const SolverParams &sp, const MlpParams &mp,
+                                int persistent, int n_cu, hipStream_t s)
+{
+    int grid;
+    if (persistent) {
+        grid = n_cu;
+        const int need = (a.n_chunks + kLearnedWaves - 1) / kLearnedWaves;
+        if (grid > need) grid = need;
+    } else {
+        grid = (a.n_chunks + kLearnedWaves - 1) / kLearnedWaves;
+    }
+    if (grid < 1) grid = 1;
+    hipLaunchKernelGGL(k_local_learned, dim3(grid), dim3(64 * kLearnedWaves), 0, s, a, sp, mp, persistent);
     return hipGetLastError();
 }
 

@@ -1,0 +1,66 @@
+"""Writes the stored oracle results the GPU tests and the benchmark compare
+against.  Calls only the FP64 oracle (oracle/) on seeded scenes (scenes/).
+
+    python tests/golden/make_golden.py trajectory   # ~35 min, one core
+    python tests/golden/make_golden.py sphere       # ~2 min
+    python tests/golden/make_golden.py batch        # ~1 min
+"""
+import os
+import sys
+import time
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+ROOT = os.path.dirname(os.path.dirname(HERE))
+sys.path.insert(0, ROOT)
+
+import oracle  # noqa: E402
+from scenes import make_config1, make_config2, make_config3  # noqa: E402
+
+# workload -> (scene, solver settings, iterations, point sampling stride)
+SPECS = {
+    "trajectory": (make_config2, dict(loss="huber", loss_param=2.0, rho=1e5, rho_balancing=True,
+                                      rho_min=1e5, rho_max=1e7), 200, 50),
+    "sphere": (make_config1, dict(loss="student_t", loss_param=4.0, rho=1e3), 100, 10),
+}
+
+
+def run(name):
+    make, kw, iters, stride = SPECS[name]
+    sc = make()
+    kw = dict(kw)
+    rmin, rmax = kw.pop("rho_min", 1e-6), kw.pop("rho_max", 1e6)
+    a = oracle.ADMM(oracle.Problem.from_scene(sc), sc.cams_init, sc.points_init, **kw)
+    a.opts.rho_min, a.opts.rho_max = rmin, rmax
+    inl = ~sc.outlier
+    trace, curve = [], []
+    t0 = time.time()
+    for k in range(iters // 10):
+        trace.append(a.iterate(10))
+        st = a.stats(inl)
+        curve.append((a.iteration, st[0], st[1], st[2]))
+        print(f"{name} it {a.iteration} rmse {st[0]:.6f} inlier {st[1]:.6f} {time.time() - t0:.0f}s", flush=True)
+    pts_idx = np.arange(0, sc.n_points, stride)
+    np.savez_compressed(os.path.join(HERE, f"{name}.npz"), checksum=np.array(sc.checksum()),
+                        n_obs=sc.n_obs, iterations=iters, trace=np.concatenate(trace), curve=np.array(curve),
+                        cams=a.cons_y, points_idx=pts_idx, points=a.cons_x[pts_idx], rho=a.rho,
+                        stats=a.stats(inl), settings=np.array(repr(SPECS[name][1])))
+
+
+def run_batch():
+    scenes = make_config3(scale=0.02)
+    out = {}
+    for q, sc in enumerate(scenes[:16]):
+        a = oracle.ADMM(oracle.Problem.from_scene(sc), sc.cams_init, sc.points_init, loss="student_t",
+                        loss_param=4.0, rho=1e3)
+        a.iterate(30)
+        out[f"cams{q}"] = a.cons_y
+        out[f"points{q}"] = a.cons_x
+        out[f"checksum{q}"] = np.array(sc.checksum())
+    np.savez_compressed(os.path.join(HERE, "batch.npz"), iterations=30, scale=0.02, count=16, **out)
+
+
+if __name__ == "__main__":
+    for name in sys.argv[1:]:
+        run_batch() if name == "batch" else run(name)

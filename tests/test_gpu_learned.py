@@ -1,0 +1,147 @@
+"""GPU checks of the learned warm start: the network's forward pass and
+gradients (BF16 MFMA kernels) against the FP64 oracle on identical
+bf16-rounded weights and inputs; deterministic training that lowers the
+loss; training pairs against the oracle's local solve; the guard (a useless
+network leaves the plain method unchanged, bit for bit); and the gain of a
+trained network over the same number of plain LM steps."""
+import numpy as np
+import pytest
+
+import oracle
+from oracle import mlp
+from paper_1708_07954_amd import binding
+from scenes import make_config2, make_sphere_scene
+
+pytestmark = pytest.mark.gpu
+
+
+def _net(seed=0, bias_scale=0.1):
+    p = mlp.init_params(seed)
+    rng = np.random.default_rng(seed + 100)
+    p["b1"] = rng.normal(0, bias_scale, p["b1"].shape)
+    p["b2"] = rng.normal(0, bias_scale, p["b2"].shape)
+    p["b3"][:12] = rng.normal(0, bias_scale, 12)
+    flat = mlp.flatten(p).astype(np.float32)
+    return flat, mlp.unflatten(flat.astype(np.float64))
+
+
+def _identity_norm():
+    return np.concatenate([np.zeros(26), np.ones(26), np.zeros(12), np.ones(12)]).astype(np.float32)
+
+
+def _data(n, seed):
+    rng = np.random.default_rng(seed)
+    x = np.zeros((n, 32), np.float32)
+    x[:, :26] = rng.normal(0, 1, (n, 26))
+    t = np.zeros((n, 16), np.float32)
+    t[:, :12] = rng.normal(0, 1, (n, 12))
+    return x, t
+
+
+def test_forward_and_gradients_match_oracle():
+    flat, p = _net(1)
+    h = binding.dba_create(binding.make_options(precision="fp32"))
+    binding.dba_set_mlp(h, flat, _identity_norm())
+    x, t = _data(512, 2)
+    loss, grad, y = binding.dba_mlp_loss_grad(h, x, t)
+    Y, cache = mlp.forward(p, x.astype(np.float64), quantize=True)
+    g = mlp.backward(p, cache, Y, t.astype(np.float64), quantize=True)
+    scale = np.abs(Y[:, :12]).max()
+    err_y = np.abs(y[:, :12] - Y[:, :12]).max() / scale
+    print("forward max rel err", err_y)
+    assert err_y < 2e-3
+    assert loss == pytest.approx(mlp.loss(Y, t), rel=2e-3)
+    gg = mlp.unflatten(grad.astype(np.float64))
+    for k in g:
+        e = np.linalg.norm(gg[k] - g[k]) / np.linalg.norm(g[k])
+        print("grad", k, e)
+        assert e < 1e-2, (k, e)
+    binding.dba_destroy(h)
+
+
+def test_forward_api_standardizes_like_the_oracle():
+    flat, p = _net(3)
+    rng = np.random.default_rng(4)
+    norm = np.concatenate([rng.normal(0, 1, 26), rng.uniform(0.5, 2, 26), rng.normal(0, 1e-3, 12),
+                           rng.uniform(1e-3, 1e-2, 12)]).astype(np.float32)
+    h = binding.dba_create(binding.make_options(precision="fp32"))
+    binding.dba_set_mlp(h, flat, norm)
+    f = rng.normal(0, 1, (300, 26)).astype(np.float32)        # not a multiple of 64: ragged tail
+    d = binding.dba_mlp_forward(h, f)
+    nm = norm.astype(np.float64)
+    Y, _ = mlp.forward(p, mlp.standardize_input(f.astype(np.float64), nm[:26], nm[26:52]), quantize=True)
+    ref = Y[:, :12] * nm[64:76] + nm[52:64]
+    assert np.abs(d - ref).max() < 2e-3 * np.abs(ref - nm[52:64]).max() + 1e-6
+    binding.dba_destroy(h)
+
+
+def test_training_lowers_the_loss_and_is_deterministic():
+    rng = np.random.default_rng(5)
+    f = rng.normal(0, 1, (8192, 26)).astype(np.float32)
+    A = rng.normal(0, 0.3, (26, 12))
+    d = (np.tanh(f @ A) + 0.05 * rng.normal(0, 1, (8192, 12))).astype(np.float32)
+    out = []
+    for _ in range(2):
+        h = binding.dba_create(binding.make_options(precision="fp32"))
+        el = binding.dba_mlp_train(h, f, d, epochs=20, batch=512, lr=3e-3, seed=11)
+        out.append((el, binding.dba_get_mlp(h)))
+        binding.dba_destroy(h)
+    el = out[0][0]
+    print("epoch losses", el)
+    assert el[-1] < 0.3 * el[0]
+    np.testing.assert_array_equal(out[0][0], out[1][0])
+    np.testing.assert_array_equal(out[0][1][0], out[1][1][0])
+
+
+def test_collected_pairs_match_the_oracle_local_solve():
+    sc = make_config2(n_cams=40, n_points=600)
+    kw = dict(loss="huber", loss_param=2.0, rho=1e5)
+    s = binding.Solver(precision="fp32", **kw).set_scene(sc)
+    f, d = binding.dba_collect_pairs(s.h, 1, 64, seed=3, conv_steps=30)
+    # first iteration: copies = initial consensus, duals 0, so each pair is
+    # the local problem at the initial estimate; match it by its residual
+    opts = oracle.make_opts("huber", 2.0)
+    P = oracle.Problem.from_scene(sc)
+    th0 = np.concatenate([sc.cams_init[sc.obs_cam], sc.points_init[sc.obs_point]], axis=1)
+    res = np.array([sc.obs_uv[k] - oracle.project(th0[k, :9], th0[k, 9:])[0] for k in range(sc.n_obs)])
+    for q in range(0, 64, 8):
+        k = int(np.argmin(np.abs(res - f[q, :2]).sum(1)))
+        assert np.abs(res[k] - f[q, :2]).max() < 1e-2
+        assert np.abs(f[q, 2:]).max() < 1e-3            # copy - consensus (fp32 rounding) and duals
+        th, _, _ = oracle.local_solve(opts, sc.obs_uv[k], th0[k], th0[k], 1e5, 1e5, steps=50)
+        ref = th - th0[k]
+        assert np.abs(d[q] - ref).max() <= 2e-3 * np.abs(ref).max() + 1e-5, (q, d[q], ref)
+
+
+@pytest.mark.parametrize("kind", ["zero", "garbage"])
+def test_guard_keeps_the_plain_method(kind):
+    """A network predicting nothing, or garbage, is rejected by the guard, and
+    the learned iteration equals plain LM with the same steps (up to FP32
+    rounding: the two kernels are compiled separately)."""
+    sc = make_config2(n_cams=40, n_points=600)
+    kw = dict(precision="fp32", loss="huber", loss_param=2.0, rho=1e5, block_waves=4, persistent=0)
+    if kind == "zero":
+        flat = np.zeros(22800, np.float32)
+        norm = _identity_norm()
+        norm[52:64] = 0.0
+    else:
+        flat, _ = _net(9)
+        flat *= 1e3
+        norm = _identity_norm()
+        norm[64:76] = 1e3
+    plain = binding.Solver(lm_steps=2, **kw).set_scene(sc)
+    plain.iterate(6)
+    learned = binding.Solver(start="learned", learned_lm_steps=2, **kw)
+    binding.dba_set_mlp(learned.h, flat, norm)
+    learned.set_scene(sc)
+    learned.iterate(6)
+    np.testing.assert_allclose(learned.params()[0], plain.params()[0], rtol=1e-5, atol=1e-7)
+    np.testing.assert_allclose(learned.state()[0], plain.state()[0], rtol=1e-5, atol=1e-6)
+
+
+def test_learned_start_without_a_network_is_a_state_error():
+    sc = make_sphere_scene(seed=3, n_cams=10, n_points=100)
+    s = binding.Solver(precision="fp32", start="learned", loss="huber", rho=1e5).set_scene(sc)
+    with pytest.raises(binding.DbaError) as e:
+        s.iterate(1)
+    assert e.value.status == "DBA_E_STATE"

@@ -27,3 +27,15 @@ def worst_param(cams, pts, cams_ref, pts_ref):
         return ("cam", int(j), int(c), float(cams[j, c]), float(cams_ref[j, c]))
     i, c = np.unravel_index(ep.argmax(), ep.shape)
     return ("point", int(i), int(c), float(pts[i, c]), float(pts_ref[i, c]))
+
+
+def param_err_summary(cams, pts, cams_ref, pts_ref):
+    """Per-component relative errors (floors as param_rel_err): max, 99th and
+    99.9th percentile, and the global |a - b| / |b| over all parameters."""
+    ec = np.abs(cams - cams_ref) / np.maximum(np.abs(cams_ref), CAM_FLOOR)
+    ep = np.abs(pts - pts_ref) / np.maximum(np.abs(pts_ref), 1.0)
+    e = np.concatenate([ec.ravel(), ep.ravel()])
+    a = np.concatenate([cams.ravel(), pts.ravel()])
+    b = np.concatenate([cams_ref.ravel(), pts_ref.ravel()])
+    return dict(max=float(e.max()), p99=float(np.percentile(e, 99)), p999=float(np.percentile(e, 99.9)),
+                glob=float(np.linalg.norm(a - b) / np.linalg.norm(b)))

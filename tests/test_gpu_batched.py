@@ -1,0 +1,66 @@
+"""Batched execution: many problems of uneven size in the same launches.
+Each problem keeps its own rho, residuals and iteration count, equals the
+same problem run alone bit for bit, and matches the FP64 oracle (stored
+results written by tests/golden/make_golden.py from oracle/ only)."""
+import os
+
+import numpy as np
+import pytest
+
+from paper_1708_07954_amd import binding
+from scenes import make_config2, make_config3, make_ring_scene
+from _util import param_rel_err
+
+pytestmark = pytest.mark.gpu
+GOLDEN = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden")
+
+
+def _batch(count=16, scale=0.02):
+    return make_config3(scale=scale)[:count]
+
+
+@pytest.mark.parametrize("precision", ["fp32", "fp64"])
+def test_batched_equals_solo_bitwise(precision):
+    scenes = _batch(8)
+    kw = dict(precision=precision, loss="student_t", loss_param=4.0, rho=1e3, block_waves=2, persistent=1)
+    b = binding.Solver(**kw).set_scenes(scenes)
+    b.iterate(12)
+    for q, sc in enumerate(scenes):
+        s = binding.Solver(**kw).set_scene(sc)
+        s.iterate(12)
+        np.testing.assert_array_equal(b.params(q)[0], s.params()[0])
+        np.testing.assert_array_equal(b.params(q)[1], s.params()[1])
+        np.testing.assert_array_equal(b.state(q)[1], s.state()[1])
+        rb, rs = b.residuals(q), s.residuals()
+        assert rb["primal"] == rs["primal"] and rb["dual"] == rs["dual"] and rb["iteration"] == 12
+        s.close()
+
+
+@pytest.mark.parametrize("precision,tol", [("fp64", 1e-9), ("fp32", 1e-3)])
+def test_batched_matches_stored_oracle(precision, tol):
+    g = np.load(os.path.join(GOLDEN, "batch.npz"))
+    scenes = _batch(int(g["count"]), float(g["scale"]))
+    b = binding.Solver(precision=precision, loss="student_t", loss_param=4.0, rho=1e3).set_scenes(scenes)
+    b.iterate(int(g["iterations"]))
+    worst = 0.0
+    for q, sc in enumerate(scenes):
+        assert str(g[f"checksum{q}"]) == sc.checksum()
+        cams, pts = b.params(q)
+        worst = max(worst, param_rel_err(cams, pts, g[f"cams{q}"], g[f"points{q}"]))
+    print(precision, "worst problem rel err", worst)
+    assert worst < tol
+
+
+def test_problems_keep_their_own_rho():
+    """Residual balancing acts per problem: a problem far from consensus and a
+    converged one get different rho in the same launches."""
+    far = make_config2(n_cams=40, n_points=400)
+    still = make_ring_scene(seed=2, n_cams=6, n_points=40, noise_px=0.0, perturb=False)
+    kw = dict(precision="fp64", loss="huber", loss_param=2.0, rho=1e2, rho_balancing=True, rho_min=1e-6, rho_max=1e9)
+    b = binding.Solver(**kw).set_scenes([far, still])
+    b.iterate(5)
+    r0, r1 = b.residuals(0), b.residuals(1)
+    s = binding.Solver(**kw).set_scene(far)
+    s.iterate(5)
+    assert r0["next_rho_x"] == s.residuals()["next_rho_x"]
+    assert r0["next_rho_x"] != r1["next_rho_x"]

@@ -82,6 +82,83 @@ def recorded_traffic(workload):
     return float(tb.group(1)), path
 
 
+def oracle_target(workload):
+    """Final inlier RMSE of the stored FP64 oracle run of the workload
+    (written by tests/golden/make_golden.py), or None."""
+    path = os.path.join(ROOT, "tests", "golden", f"{workload}.npz")
+    if not os.path.exists(path):
+        return None, None
+    import numpy as np
+    z = np.load(path, allow_pickle=False)
+    return float(z["stats"][1]), int(z["iterations"])
+
+
+def time_to_rmse(binding, scene, opts, sched, target, max_iters=400, learned_steps=(1, 2, 3)):
+    """Wall time of plain 5-step LM and of the learned start (+ k LM steps)
+    to reach the oracle's final inlier RMSE (within 0.5 %).  The crossing
+    iteration is found with per-iteration RMSE checks; a fresh run of exactly
+    that many iterations is then timed (graph instantiation included)."""
+    import numpy as np
+    import torch
+    from paper_1708_07954_amd import warmstart
+    inl = ~scene.outlier
+    goal = target * 1.005
+
+    def run(kw, net=None):
+        def make():
+            s = binding.Solver(**kw)
+            if net is not None:
+                binding.dba_set_mlp(s.h, net[0], net[1])
+            s.set_scene(scene)
+            s.set_eval_mask(inl)
+            return s
+        s = make()
+        hit, last = None, None
+        for k in range(1, max_iters + 1):
+            s.iterate(1)
+            last = s.residuals(want_rmse=True)["rmse_masked"]
+            if not np.isfinite(last) or last > 1e6:
+                break
+            if last <= goal:
+                hit = k
+                break
+        s.close()
+        out = {"iterations": hit, "inlier_rmse_at_stop": last}
+        if hit is None:
+            out["seconds"] = None
+            return out
+        s = make()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        s.iterate(hit)
+        torch.cuda.synchronize()
+        out["seconds"] = time.perf_counter() - t0
+        s.iterate(20)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        s.iterate(50)
+        torch.cuda.synchronize()
+        out["ms_per_iter_steady"] = (time.perf_counter() - t0) * 20.0
+        s.close()
+        return out
+
+    res = {"target_inlier_rmse": target, "reached_when_within": 0.005, "max_iterations": max_iters}
+    res["plain_lm5"] = run(dict(opts, lm_steps=5, block_waves=sched["block_waves"], persistent=sched["persistent"]))
+    print(f"[bench] time-to-RMSE plain: {res['plain_lm5']}", file=sys.stderr, flush=True)
+    params, norm, rep = warmstart.train_default()
+    res["training"] = {"pairs": rep["pairs"], "collect_seconds": rep["collect_seconds"],
+                       "train_seconds": rep["train_seconds"], "final_epoch_loss": rep["epoch_loss"][-1],
+                       "scenes": "10 trajectory-family scenes, 100 cameras, 20000 points, seeds 2000-2009"}
+    for k in learned_steps:
+        res[f"learned_lm{k}"] = run(dict(opts, start="learned", learned_lm_steps=k), net=(params, norm))
+        print(f"[bench] time-to-RMSE learned+{k}: {res[f'learned_lm{k}']}", file=sys.stderr, flush=True)
+    t_plain = res["plain_lm5"]["seconds"]
+    best = min((res[f"learned_lm{k}"]["seconds"] for k in learned_steps
+                if res[f"learned_lm{k}"]["seconds"] is not None), default=None)
+    res["learned_over_plain_time"] = (best / t_plain) if (best is not None and t_plain) else None
+    return res
+
+
 def cpu_model():
     try:
         for line in open("/proc/cpuinfo"):
@@ -99,6 +176,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=10)
     ap.add_argument("--workload", default="trajectory", choices=sorted(WORKLOADS))
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-time-to-rmse", action="store_true",
+                    help="skip the time-to-RMSE comparison (learned start vs plain LM)")
     ap.add_argument("--copy-probe-mib", type=int, default=0,
                     help="also run a plain device copy of this size (counter calibration)")
     args = ap.parse_args()
@@ -198,6 +277,13 @@ def main():
            "residuals_after": {k: rep[k] for k in ("primal", "dual", "rho_x", "rmse", "iteration")}}
     if traffic_src:
         out["roofline"]["traffic_source"] = os.path.relpath(traffic_src, ROOT)
+
+    if args.workload == "trajectory" and not args.no_time_to_rmse:
+        target, its = oracle_target("trajectory")
+        if target is not None:
+            ttr = time_to_rmse(binding, scenes[0], opts, sched, target)
+            ttr["target_source"] = f"FP64 oracle, {its} iterations (tests/golden/trajectory.npz)"
+            out["time_to_rmse"] = ttr
 
     if not args.no_cpu_baseline:
         import oracle

@@ -327,6 +327,44 @@ __device__ __forceinline__ double wave_sum(double v)
     return v;
 }
 
+// One level of a reduce-scatter over the wave: lanes whose bit `off` is clear
+// keep the first H of the 2H values, the others the last H, each adding its
+// partner's copy.  Fixed pairing, so the summation order never changes.
+template <int H>
+__device__ __forceinline__ void rs_level(const double *in, double *out, bool upper, int off)
+{
+#pragma unroll
+    for (int j = 0; j < H; ++j) {
+        const double keep = upper ? in[H + j] : in[j];
+        const double send = upper ? in[j] : in[H + j];
+        out[j] = keep + __shfl_xor(send, off, 64);
+    }
+}
+
+// Sums the 19 per-lane values v[0..18] over the 64 lanes of the wave and
+// stores sum k to o[k] (one store per value, from the lane that holds it).
+// Halving the values at every level needs 21 exchanges instead of 19 x 6.
+__device__ __forceinline__ void wave_sum19_store(const double *v, double *o, int lane)
+{
+    double a[20], b[10], c[6], d[4], e[2];
+#pragma unroll
+    for (int j = 0; j < 19; ++j) a[j] = v[j];
+    a[19] = 0.0;
+    const bool b5 = lane & 32, b4 = lane & 16, b3 = lane & 8, b2 = lane & 4, b1 = lane & 2;
+    rs_level<10>(a, b, b5, 32);     // values 10 b5 + [0, 10)
+    rs_level<5>(b, c, b4, 16);      // + 5 b4 + [0, 5)
+    c[5] = 0.0;
+    rs_level<3>(c, d, b3, 8);       // + 3 b3 + [0, 3)   (position 5 is padding)
+    d[3] = 0.0;
+    rs_level<2>(d, e, b2, 4);       // + 2 b2 + [0, 2)   (position 3 is padding)
+    double f;
+    rs_level<1>(e, &f, b1, 2);      // + b1
+    f += __shfl_xor(f, 1, 64);
+    const int inner = 2 * b2 + b1, mid = 3 * b3 + inner;
+    const int k = 10 * b5 + 5 * b4 + mid;
+    if (!(lane & 1) && inner < 3 && mid < 5 && k < 19) o[k] = f;
+}
+
 // Block -> tile mapping that gives each XCD (blocks are dealt round-robin to
 // the 8 XCDs) a contiguous range of tiles, so neighbouring cameras share an L2.
 __device__ __forceinline__ int xcd_block()

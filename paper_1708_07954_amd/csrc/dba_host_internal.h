@@ -68,10 +68,11 @@ struct Mlp {
     __bf16 *w = nullptr;      // packed bf16 weights
     float *master = nullptr;  // FP32 parameters (kPTotal)
     float *norm = nullptr;    // kNormTotal
+    float *xform = nullptr;   // [2][kIn] input scale and shift
     float *adam_m = nullptr, *adam_v = nullptr, *grad = nullptr;
     MlpParams params() const
     {
-        return MlpParams{w, master + kPB1, master + kPB2, master + kPB3, norm};
+        return MlpParams{w, master + kPB1, master + kPB2, master + kPB3, norm, xform};
     }
 };
 

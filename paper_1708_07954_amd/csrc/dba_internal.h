@@ -127,6 +127,7 @@ struct MlpParams {
     const __bf16 *w;       // packed bf16 weights (kWTotal)
     const float *b1, *b2, *b3;
     const float *norm;     // kNormTotal
+    const float *xform;    // [2][kIn]: 1 / sd_in, -mu_in / sd_in (input standardization)
 };
 
 // launchers (dba_kernels.hip); each returns hipGetLastError()

@@ -10,7 +10,8 @@
 //            Emits the chunk's sums for the camera consensus with a fixed
 //            butterfly.
 // consensus  point consensus (Eq. 10): one thread per point, ascending record
-//            order, residual terms summed per 256-point block by a fixed tree;
+//            order, one pass over the records; residual terms summed per
+//            256-point block by a fixed tree;
 //            camera consensus (Eq. 11): one wave per camera summing its chunk
 //            partials in ascending chunk order.  Both in FP64.
 // norms      one workgroup per problem: primal/dual residual norms, residual
@@ -30,12 +31,12 @@ using namespace dev;
 // ---------------------------------------------------------------- local
 // One 64-slot chunk (one camera) per wave.  LEARNED: the start point is the
 // better of the copy and copy + network prediction (ties keep the copy), then
-// `learned_steps` LM steps; act/lw are the wave's activation tile and the
+// `learned_steps` LM steps; io/lw are the wave's network I/O tile and the
 // staged weights.
 template <typename R, bool LEARNED>
 __device__ __forceinline__ void local_chunk(const DevArrays<R> &a, const SolverParams &sp, int c, int lane,
                                             const MlpParams *mp = nullptr, const __bf16 *lw = nullptr,
-                                            __bf16 *act = nullptr)
+                                            __bf16 *io = nullptr)
 {
     using R2 = typename Vec<R>::R2;
     using R4 = typename Vec<R>::R4;
@@ -89,40 +90,38 @@ __device__ __forceinline__ void local_chunk(const DevArrays<R> &a, const SolverP
     }
     const R rx = (R)rho_x, ry = (R)rho_y, lp = (R)sp.loss_param, lam0 = (R)sp.lambda0;
     if constexpr (LEARNED) {
-        Proj<R> cur;
-        R F = R(0);
-        const float *nm = mp->norm;
+        // features at the start point, standardized (x = f * scale + shift),
+        // bf16 into the wave's I/O tile; idle lanes feed zeros
         float f[kIn];
         if (active) {
-            cur = proj_core<R, true>(th);
-            F = objective<R>(cur, th, v, z.x, z.y, rx, ry, sp.loss, lp);
-            f[0] = (float)(z.x - cur.pu);
-            f[1] = (float)(z.y - cur.pv);
+            const Proj<R> p0 = proj_core<R, false>(th);
+            f[0] = (float)(z.x - p0.pu);
+            f[1] = (float)(z.y - p0.pv);
 #pragma unroll
             for (int i = 0; i < 12; ++i) f[2 + i] = (float)((double)th[i] - cons[i]);
 #pragma unroll
             for (int i = 0; i < 12; ++i) f[14 + i] = (float)u[i];
-        } else {
-#pragma unroll
-            for (int i = 0; i < kIn; ++i) f[i] = nm[i];  // standardizes to zero
         }
+        const float *xf = mp->xform;
 #pragma unroll
         for (int q = 0; q < 4; ++q) {
             bf16x8 xin;
 #pragma unroll
             for (int j = 0; j < 8; ++j) {
                 const int k = 8 * q + j;
-                xin[j] = k < kIn ? (__bf16)((f[k] - nm[k]) / nm[kIn + k]) : (__bf16)0.0f;
+                xin[j] = (k < kIn && active) ? (__bf16)fmaf(f[k], xf[k], xf[kIn + k]) : (__bf16)0.0f;
             }
-            *reinterpret_cast<bf16x8 *>(act + lane * kActS + 8 * q) = xin;
+            *reinterpret_cast<bf16x8 *>(io + lane * kIoS + 8 * q) = xin;
         }
-        float *out = reinterpret_cast<float *>(act);
-        mlp_forward64(lw, *mp, act, out, lane);
+        mlp_forward64(lw, *mp, io, lane);
         if (active) {
+            const float *nm = mp->norm;
+            const float *out = reinterpret_cast<const float *>(io) + lane * kOutS;
             R tr[12];
 #pragma unroll
-            for (int i = 0; i < kOut; ++i)
-                tr[i] = th[i] + (R)(out[lane * kOutPad + i] * nm[2 * kIn + kOut + i] + nm[2 * kIn + i]);
+            for (int i = 0; i < kOut; ++i) tr[i] = th[i] + (R)(out[i] * nm[2 * kIn + kOut + i] + nm[2 * kIn + i]);
+            Proj<R> cur = proj_core<R, true>(th);
+            R F = objective<R>(cur, th, v, z.x, z.y, rx, ry, sp.loss, lp);
             const Proj<R> nxt = proj_core<R, true>(tr);
             const R F1 = objective<R>(nxt, tr, v, z.x, z.y, rx, ry, sp.loss, lp);
             if (F1 < F) {  // the guard: keep the prediction only if it lowers F
@@ -151,13 +150,7 @@ __device__ __forceinline__ void local_chunk(const DevArrays<R> &a, const SolverP
             acc[18] += dd * dd;
         }
     }
-#pragma unroll
-    for (int i = 0; i < 19; ++i) acc[i] = wave_sum(acc[i]);
-    if (lane == 0) {
-        double *o = a.cpart + (long long)c * kCpart;
-#pragma unroll
-        for (int i = 0; i < 19; ++i) o[i] = acc[i];
-    }
+    wave_sum19_store(acc, a.cpart + (long long)c * kCpart, lane);
 }
 
 // FP32: up to 8 waves per workgroup; FP64 needs more than 256 VGPRs, so at
@@ -188,22 +181,23 @@ __global__ __launch_bounds__(LocalBound<R>::threads) void k_local(DevArrays<R> a
     for (int c = c0 + wave; c < c1; c += wpb) local_chunk<R, false>(a, sp, c, lane);
 }
 
-// Learned start: 4 waves per workgroup share the staged weights; each wave
-// has its own activation tile.
-constexpr int kLearnedWaves = 4;
+// Learned start: the workgroup's waves share the staged weights (one copy
+// per CU: 8 waves, 2 per SIMD); each wave has its own network I/O tile.  The
+// grid is persistent so the weights are staged once per workgroup.
+constexpr int kLearnedWaves = 8;
 
 __global__ __launch_bounds__(64 * kLearnedWaves) void k_local_learned(DevArrays<float> a, SolverParams sp,
                                                                        MlpParams mp, int persistent)
 {
     __shared__ __attribute__((aligned(16))) __bf16 lw[kLdsFwd];
-    __shared__ __attribute__((aligned(16))) __bf16 act[kLearnedWaves][kLdsAct];
+    __shared__ __attribute__((aligned(16))) __bf16 io[kLearnedWaves][kLdsIo];
     stage_forward_weights(mp.w, lw);
     __syncthreads();
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     int c0, c1;
     chunk_range(a.n_chunks, kLearnedWaves, persistent, c0, c1);
     for (int c = c0 + wave; c < c1; c += kLearnedWaves)
-        local_chunk<float, true>(a, sp, c, lane, &mp, lw, act[wave]);
+        local_chunk<float, true>(a, sp, c, lane, &mp, lw, io[wave]);
 }
 
 // ---------------------------------------------------------------- consensus
@@ -218,25 +212,31 @@ __global__ __launch_bounds__(256) void k_consensus(DevArrays<R> a, int pt_blocks
         if ((int)threadIdx.x < a.pblk_cnt[b]) {
             const int i = a.pblk_pt0[b] + threadIdx.x;
             const int r0 = a.pt_off[i], r1 = a.pt_off[i + 1];
-            double s0 = 0.0, s1 = 0.0, s2 = 0.0;
+            // one pass: sums of copy + dual (the consensus) and of the copies'
+            // offsets d_r from the previous consensus, which give
+            // sum_r |copy_r - new|^2 = sum |d_r|^2 - 2 e . sum d_r + n |e|^2,
+            // e = new - previous
+            const double4 old = a.cons_x[i];
+            double s0 = 0.0, s1 = 0.0, s2 = 0.0, q0 = 0.0, q1 = 0.0, q2 = 0.0, qq = 0.0;
             for (int r = r0; r < r1; ++r) {
                 const R4 x = a.xrec[r];
                 const double4 u = a.urec[r];
                 s0 += (double)x.x + u.x;
                 s1 += (double)x.y + u.y;
                 s2 += (double)x.z + u.z;
+                const double d0 = (double)x.x - old.x, d1 = (double)x.y - old.y, d2 = (double)x.z - old.z;
+                q0 += d0;
+                q1 += d1;
+                q2 += d2;
+                qq += d0 * d0 + d1 * d1 + d2 * d2;
             }
             const double n = (double)(r1 - r0);
             const double c0 = s0 / n, c1 = s1 / n, c2 = s2 / n;
-            for (int r = r0; r < r1; ++r) {
-                const R4 x = a.xrec[r];
-                const double d0 = (double)x.x - c0, d1 = (double)x.y - c1, d2 = (double)x.z - c2;
-                pri += d0 * d0 + d1 * d1 + d2 * d2;
-            }
-            const double4 old = a.cons_x[i];
             const double e0 = c0 - old.x, e1 = c1 - old.y, e2 = c2 - old.z;
             a.cons_x[i] = make_double4(c0, c1, c2, 0.0);
-            dual = n * (e0 * e0 + e1 * e1 + e2 * e2);
+            const double ee = e0 * e0 + e1 * e1 + e2 * e2;
+            pri = fmax(qq - 2.0 * (e0 * q0 + e1 * q1 + e2 * q2) + n * ee, 0.0);
+            dual = n * ee;
         }
         // fixed-order tree over the block's points
         const int t = threadIdx.x;
@@ -471,16 +471,13 @@ hipError_t launch_local(const DevArrays<R> &a, const SolverParams &sp, int block
 hipError_t launch_local_learned(const DevArrays<float> &a, const SolverParams &sp, const MlpParams &mp,
                                 int persistent, int n_cu, hipStream_t s)
 {
-    int grid;
-    if (persistent) {
-        grid = n_cu;
-        const int need = (a.n_chunks + kLearnedWaves - 1) / kLearnedWaves;
-        if (grid > need) grid = need;
-    } else {
-        grid = (a.n_chunks + kLearnedWaves - 1) / kLearnedWaves;
-    }
+    // always persistent: one workgroup per CU stages the weights once
+    (void)persistent;
+    int grid = n_cu;
+    const int need = (a.n_chunks + kLearnedWaves - 1) / kLearnedWaves;
+    if (grid > need) grid = need;
     if (grid < 1) grid = 1;
-    hipLaunchKernelGGL(k_local_learned, dim3(grid), dim3(64 * kLearnedWaves), 0, s, a, sp, mp, persistent);
+    hipLaunchKernelGGL(k_local_learned, dim3(grid), dim3(64 * kLearnedWaves), 0, s, a, sp, mp, 1);
     return hipGetLastError();
 }
 

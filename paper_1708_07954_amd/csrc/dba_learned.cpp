@@ -28,6 +28,7 @@ int ensure_mlp(dba_handle *h)
     HIP_TRY(h, m->buf.alloc(&m->w, dba::kWTotal));
     HIP_TRY(h, m->buf.alloc(&m->master, dba::kPTotal));
     HIP_TRY(h, m->buf.alloc(&m->norm, dba::kNormTotal));
+    HIP_TRY(h, m->buf.alloc(&m->xform, 2 * dba::kIn));
     HIP_TRY(h, m->buf.alloc(&m->adam_m, dba::kPTotal));
     HIP_TRY(h, m->buf.alloc(&m->adam_v, dba::kPTotal));
     HIP_TRY(h, m->buf.alloc(&m->grad, dba::kPTotal));
@@ -41,6 +42,12 @@ int upload_mlp(dba_handle *h, const float *params, const float *norm)
     if (rc != DBA_OK) return rc;
     HIP_TRY(h, hipMemcpyAsync(h->mlp->master, params, dba::kPTotal * sizeof(float), hipMemcpyHostToDevice, h->stream));
     HIP_TRY(h, hipMemcpyAsync(h->mlp->norm, norm, dba::kNormTotal * sizeof(float), hipMemcpyHostToDevice, h->stream));
+    float xf[2 * dba::kIn];
+    for (int k = 0; k < dba::kIn; ++k) {
+        xf[k] = 1.0f / norm[dba::kIn + k];
+        xf[dba::kIn + k] = -norm[k] / norm[dba::kIn + k];
+    }
+    HIP_TRY(h, hipMemcpyAsync(h->mlp->xform, xf, sizeof(xf), hipMemcpyHostToDevice, h->stream));
     HIP_TRY(h, dba::mlp_pack(h->mlp->master, h->mlp->w, h->stream));
     HIP_TRY(h, hipStreamSynchronize(h->stream));
     h->mlp->ready = true;

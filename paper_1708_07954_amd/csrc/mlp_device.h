@@ -5,10 +5,10 @@
 // outputs to 16).  Every layer is computed transposed, out^T = W^T in^T, so
 // the weight rows are the MFMA A operand (read from LDS, shared by the
 // workgroup) and the activations of the wave's 64 observations are the B
-// operand (read from the wave's LDS tile [64][kActS], observation-major).
-// Lane l = 16 g + i of a 16x16x32 MFMA holds A[i][8g..8g+7], B[8g..8g+7][i]
-// and D[4g..4g+3][i]; the epilogue writes D back into the same tile (all B
-// operands are loaded first).
+// operand.  Lane l = 16 g + i of a 16x16x32 MFMA holds A[i][8g..8g+7],
+// B[8g..8g+7][i] and D[4g..4g+3][i].  The forward pass keeps the activations
+// in registers (see chain_unit); the backward pass stages them through a
+// per-wave LDS tile [64][kActS].
 #pragma once
 #include "dba_internal.h"
 
@@ -30,17 +30,6 @@ constexpr int kLdsW2 = kHid * kWs2;
 constexpr int kLdsW3T = kOutPad * kWs2;
 constexpr int kLdsFwd = kLdsW1 + kLdsW2 + kLdsW3T;   // forward weights in LDS (bf16 elements)
 constexpr int kLdsAct = 64 * kActS;                  // one wave's activation tile
-
-__device__ __forceinline__ float gelu_f(float z, float *grad)
-{
-    // tanh form; tanh(u) = 1 - 2 / (1 + e^{2u})
-    const float z2 = z * z;
-    const float u = 0.7978845608028654f * (z + 0.044715f * z2 * z);
-    const float e = __expf(2.0f * u);
-    const float t = 1.0f - 2.0f * __builtin_amdgcn_rcpf(1.0f + e);
-    if (grad) *grad = 0.5f * (1.0f + t) + 0.5f * z * (1.0f - t * t) * 0.7978845608028654f * (1.0f + 0.134145f * z2);
-    return 0.5f * z * (1.0f + t);
-}
 
 // Copies a dense [rows][cols] bf16 matrix into LDS with row stride ls
 // (cols a multiple of 8), cooperatively by the whole workgroup.
@@ -89,62 +78,111 @@ __device__ __forceinline__ void dense64(const __bf16 *W, int ws, const __bf16 *i
     }
 }
 
-// Hidden-layer epilogue: + bias, GELU, round to bf16, write back into the
-// tile; optionally also store gelu'(z) and the bf16 activation to global
-// rows (training forward).
-struct HiddenEpi {
-    __bf16 *act;
-    const float *bias;
-    int lane;
-    float *gp;            // [64][kHid] global rows or nullptr
-    __bf16 *hg;           // [64][kHid] global rows or nullptr
-    __device__ __forceinline__ void operator()(int u, const f32x4 *acc) const
-    {
-        const int g = lane >> 4, i = lane & 15;
-        const int unit = 16 * u + 4 * g;
-        const float b0 = bias[unit], b1 = bias[unit + 1], b2 = bias[unit + 2], b3 = bias[unit + 3];
-#pragma unroll
-        for (int t = 0; t < 4; ++t) {
-            const int row = 16 * t + i;
-            float gr[4];
-            bf16x4 h;
-            h[0] = (__bf16)gelu_f(acc[t][0] + b0, gp ? &gr[0] : nullptr);
-            h[1] = (__bf16)gelu_f(acc[t][1] + b1, gp ? &gr[1] : nullptr);
-            h[2] = (__bf16)gelu_f(acc[t][2] + b2, gp ? &gr[2] : nullptr);
-            h[3] = (__bf16)gelu_f(acc[t][3] + b3, gp ? &gr[3] : nullptr);
-            *reinterpret_cast<bf16x4 *>(act + row * kActS + unit) = h;
-            if (gp) *reinterpret_cast<float4 *>(gp + (size_t)row * kHid + unit) = make_float4(gr[0], gr[1], gr[2], gr[3]);
-            if (hg) *reinterpret_cast<bf16x4 *>(hg + (size_t)row * kHid + unit) = h;
-        }
-    }
-};
+// Activations of the forward pass stay in registers: the 16x16x32 MFMA
+// leaves lane (g, i) with units 16u + 4g .. 16u + 4g + 3 of observation
+// 16t + i, and a B operand of the next layer needs 8 k-values per lane for
+// the same observation.  The two 4-unit pieces a lane holds of unit tiles
+// 2kb and 2kb + 1 form k-block kb of the next layer, in the slot order
+//   slot 32kb + 8g + j  <->  unit 32kb + 16 (j >> 2) + 4g + (j & 3);
+// the packed W2^T and W3^T store their columns in that order, so the
+// products are unchanged.
+__host__ __device__ constexpr int chain_unit(int slot)
+{
+    return (slot & ~31) + 16 * ((slot & 7) >> 2) + 4 * ((slot >> 3) & 3) + (slot & 3);
+}
 
-// Output-layer epilogue: + bias, FP32 result into out[64][kOutPad].
-struct OutEpi {
-    float *out;
-    const float *bias;
-    int lane;
-    __device__ __forceinline__ void operator()(int, const f32x4 *acc) const
-    {
-        const int g = lane >> 4, i = lane & 15;
-#pragma unroll
-        for (int t = 0; t < 4; ++t)
-            *reinterpret_cast<float4 *>(out + (16 * t + i) * kOutPad + 4 * g) =
-                make_float4(acc[t][0] + bias[4 * g], acc[t][1] + bias[4 * g + 1], acc[t][2] + bias[4 * g + 2],
-                            acc[t][3] + bias[4 * g + 3]);
-    }
-};
+// Per-wave I/O tile: bf16 standardized inputs [64][kIoS] on entry, FP32
+// outputs [64][kOutS] on exit (same bytes).
+constexpr int kIoS = kInPad + 8;
+constexpr int kOutS = kOutPad + 4;
+constexpr int kLdsIo = 64 * kIoS;   // bf16 elements (= 64 * kOutS floats)
+static_assert(64 * kIoS * 2 == 64 * kOutS * 4, "I/O tile views must coincide");
 
-// Full forward pass of the wave tile.  On entry act[row][0..31] holds the
-// bf16 standardized inputs; on exit out[row][0..15] the (standardized)
-// outputs.  `out` may alias act (the output layer reads all of act first).
-__device__ __forceinline__ void mlp_forward64(const __bf16 *lw, const MlpParams &mp, __bf16 *act, float *out, int lane,
+__device__ __forceinline__ float gelu_f(float z, float *grad)
+{
+    // tanh form: gelu(z) = z sigmoid(2u), u = c (z + 0.044715 z^3); with
+    // e = 2^(2u log2 e): z - z / (1 + e)
+    const float z2 = z * z;
+    const float w = z * (2.3022082f + 0.10294324f * z2);   // 2 u log2(e)
+    const float r = __builtin_amdgcn_rcpf(1.0f + __builtin_amdgcn_exp2f(w));
+    const float s = 1.0f - r;                                // sigmoid(2u)
+    if (grad) *grad = s + 2.0f * z * s * r * 0.7978845608028654f * (1.0f + 0.134145f * z2);
+    return z - z * r;
+}
+
+// bias + GELU + bf16 of one accumulator (4 consecutive units of one
+// observation row); optional training stores of gelu'(z) and the activation.
+__device__ __forceinline__ bf16x4 hidden_act(const f32x4 &acc, const float *bias, int unit, int row, float *gp,
+                                             __bf16 *hg)
+{
+    float gr[4];
+    bf16x4 h;
+#pragma unroll
+    for (int r = 0; r < 4; ++r) h[r] = (__bf16)gelu_f(acc[r] + bias[unit + r], gp ? &gr[r] : nullptr);
+    if (gp) *reinterpret_cast<float4 *>(gp + (size_t)row * kHid + unit) = make_float4(gr[0], gr[1], gr[2], gr[3]);
+    if (hg) *reinterpret_cast<bf16x4 *>(hg + (size_t)row * kHid + unit) = h;
+    return h;
+}
+
+// Forward pass of one wave's 64 observations (training stores optional:
+// gelu'(z) and bf16 activations of both hidden layers, [64][kHid] rows).
+__device__ __forceinline__ void mlp_forward64(const __bf16 *lw, const MlpParams &mp, __bf16 *io, int lane,
                                               float *gp1 = nullptr, __bf16 *h1 = nullptr, float *gp2 = nullptr,
                                               __bf16 *h2 = nullptr)
 {
-    dense64<kHid / 16, 1>(lw, kWs1, act, kActS, lane, HiddenEpi{act, mp.b1, lane, gp1, h1});
-    dense64<kHid / 16, 4>(lw + kLdsW1, kWs2, act, kActS, lane, HiddenEpi{act, mp.b2, lane, gp2, h2});
-    dense64<1, 4>(lw + kLdsW1 + kLdsW2, kWs2, act, kActS, lane, OutEpi{out, mp.b3, lane});
+    const int g = lane >> 4, i = lane & 15;
+    const __bf16 *W1 = lw, *W2 = lw + kLdsW1, *W3 = lw + kLdsW1 + kLdsW2;
+    const f32x4 zero = {0.f, 0.f, 0.f, 0.f};
+    bf16x8 x[4];
+#pragma unroll
+    for (int t = 0; t < 4; ++t) x[t] = *reinterpret_cast<const bf16x8 *>(io + (16 * t + i) * kIoS + 8 * g);
+
+    // layer 1 -> the B operands of layer 2, b2[k-block][observation tile]
+    bf16x8 b2[4][4];
+#pragma unroll
+    for (int u = 0; u < kHid / 16; ++u) {
+        const bf16x8 a = *reinterpret_cast<const bf16x8 *>(W1 + (16 * u + i) * kWs1 + 8 * g);
+#pragma unroll
+        for (int t = 0; t < 4; ++t) {
+            const f32x4 acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, x[t], zero, 0, 0, 0);
+            const bf16x4 h = hidden_act(acc, mp.b1, 16 * u + 4 * g, 16 * t + i, gp1, h1);
+#pragma unroll
+            for (int r = 0; r < 4; ++r) b2[u >> 1][t][4 * (u & 1) + r] = h[r];
+        }
+    }
+    // layer 2, two unit tiles at a time = one k-block of layer 3
+    f32x4 acc3[4] = {zero, zero, zero, zero};
+#pragma unroll 1
+    for (int kb3 = 0; kb3 < 4; ++kb3) {
+        bf16x8 b3[4];
+#pragma unroll
+        for (int half = 0; half < 2; ++half) {
+            const int u = 2 * kb3 + half;
+            f32x4 acc[4] = {zero, zero, zero, zero};
+#pragma unroll
+            for (int kb = 0; kb < 4; ++kb) {
+                const bf16x8 a = *reinterpret_cast<const bf16x8 *>(W2 + (16 * u + i) * kWs2 + 32 * kb + 8 * g);
+#pragma unroll
+                for (int t = 0; t < 4; ++t) acc[t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b2[kb][t], acc[t], 0, 0, 0);
+            }
+#pragma unroll
+            for (int t = 0; t < 4; ++t) {
+                const bf16x4 h = hidden_act(acc[t], mp.b2, 16 * u + 4 * g, 16 * t + i, gp2, h2);
+#pragma unroll
+                for (int r = 0; r < 4; ++r) b3[t][4 * half + r] = h[r];
+            }
+        }
+        const bf16x8 a3 = *reinterpret_cast<const bf16x8 *>(W3 + i * kWs2 + 32 * kb3 + 8 * g);
+#pragma unroll
+        for (int t = 0; t < 4; ++t) acc3[t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a3, b3[t], acc3[t], 0, 0, 0);
+    }
+    // lane (g, i) holds outputs 4g .. 4g + 3 of observation 16t + i
+    float *out = reinterpret_cast<float *>(io);
+    const float c0 = mp.b3[4 * g], c1 = mp.b3[4 * g + 1], c2 = mp.b3[4 * g + 2], c3 = mp.b3[4 * g + 3];
+#pragma unroll
+    for (int t = 0; t < 4; ++t)
+        *reinterpret_cast<float4 *>(out + (16 * t + i) * kOutS + 4 * g) =
+            make_float4(acc3[t][0] + c0, acc3[t][1] + c1, acc3[t][2] + c2, acc3[t][3] + c3);
 }
 
 }  // namespace dev

@@ -30,11 +30,11 @@ __global__ void k_mlp_pack(const float *P, __bf16 *w)
     if (q < kOffW2T) {                    // W1^T [128][32]
         const int u = q / kInPad, k = q % kInPad;
         x = P[kPW1 + k * kHid + u];
-    } else if (q < kOffW3T) {             // W2^T [128][128]
-        const int r = q - kOffW2T, u = r / kHid, k = r % kHid;
+    } else if (q < kOffW3T) {             // W2^T [128][128], columns in chained slot order
+        const int r = q - kOffW2T, u = r / kHid, k = chain_unit(r % kHid);
         x = P[kPW2 + k * kHid + u];
-    } else if (q < kOffW2N) {             // W3^T [16][128]
-        const int r = q - kOffW3T, o = r / kHid, k = r % kHid;
+    } else if (q < kOffW2N) {             // W3^T [16][128], columns in chained slot order
+        const int r = q - kOffW3T, o = r / kHid, k = chain_unit(r % kHid);
         x = P[kPW3 + k * kOutPad + o];
     } else if (q < kOffW3N) {             // W2 [128][128]
         x = P[kPW2 + (q - kOffW2N)];
@@ -71,7 +71,7 @@ __global__ __launch_bounds__(64 * kFwdWaves) void k_mlp_forward(const __bf16 *xq
                                                                float *gp2, __bf16 *h2)
 {
     __shared__ __attribute__((aligned(16))) __bf16 lw[kLdsFwd];
-    __shared__ __attribute__((aligned(16))) __bf16 act[kFwdWaves][kLdsAct];
+    __shared__ __attribute__((aligned(16))) __bf16 io[kFwdWaves][kLdsIo];
     stage_forward_weights(mp.w, lw);
     __syncthreads();
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
@@ -89,20 +89,20 @@ __global__ __launch_bounds__(64 * kFwdWaves) void k_mlp_forward(const __bf16 *xq
 #pragma unroll
             for (int j = 0; j < 8; ++j) x[q][j] = (__bf16)0.0f;
     }
-    __bf16 *a = act[wave];
+    __bf16 *a = io[wave];
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
-        *reinterpret_cast<bf16x8 *>(a + lane * kActS + 8 * q) = x[q];
+        *reinterpret_cast<bf16x8 *>(a + lane * kIoS + 8 * q) = x[q];
         if (xb && b < n) *reinterpret_cast<bf16x8 *>(xb + (size_t)b * kInPad + 8 * q) = x[q];
     }
     // training stores cover whole 64-row tiles; the caller sizes them so
-    float *out = reinterpret_cast<float *>(a);
-    mlp_forward64(lw, mp, a, out, lane, gp1 ? gp1 + (size_t)b0 * kHid : nullptr, h1 ? h1 + (size_t)b0 * kHid : nullptr,
+    mlp_forward64(lw, mp, a, lane, gp1 ? gp1 + (size_t)b0 * kHid : nullptr, h1 ? h1 + (size_t)b0 * kHid : nullptr,
                   gp2 ? gp2 + (size_t)b0 * kHid : nullptr, h2 ? h2 + (size_t)b0 * kHid : nullptr);
+    const float *out = reinterpret_cast<const float *>(a);
     if (b < n) {
 #pragma unroll
         for (int o = 0; o < kOutPad; o += 4)
-            *reinterpret_cast<float4 *>(y + (size_t)b * kOutPad + o) = *reinterpret_cast<const float4 *>(out + lane * kOutPad + o);
+            *reinterpret_cast<float4 *>(y + (size_t)b * kOutPad + o) = *reinterpret_cast<const float4 *>(out + lane * kOutS + o);
     }
 }
 

@@ -10,10 +10,29 @@ import numpy as np
 
 from . import binding
 
-# scenes of the sphere-cap family (100 cameras, 20000 points, 8..15 views per
-# point) with the trajectory workload's loss, outlier rate and rho rule
+# solver of the collection runs: the trajectory workload's loss and rho rule
 TRAIN_SOLVER = dict(precision="fp32", loss="huber", loss_param=2.0, rho=1e5, rho_balancing=True,
                     rho_min=1e5, rho_max=1e7)
+TRAIN_SEEDS = tuple(range(2000, 2010))
+VALIDATION_SEED = 2010
+
+
+def training_scenes(seeds=TRAIN_SEEDS, n_cams=100, n_points=20000):
+    """Trajectory-family scenes (nadir cameras on a random walk, Zipf tracks,
+    5 % outliers) of 100 cameras and 20 000 points each."""
+    from scenes import make_trajectory_scene
+    return [make_trajectory_scene(seed=q, n_cams=n_cams, n_points=n_points) for q in seeds]
+
+
+def train_default(seed=0, iters=100, per_iter=5000, epochs=10):
+    """Collects 10 x iters x per_iter pairs (5M by default) and trains; returns
+    params, norm and a report with the collection and training times."""
+    t0 = time.perf_counter()
+    feats, deltas = collect(training_scenes(), iters=iters, per_iter=per_iter, seed=seed + 1)
+    t_collect = time.perf_counter() - t0
+    params, norm, rep = train(feats, deltas, epochs=epochs, batch=4096, lr=1e-3, seed=seed)
+    rep["collect_seconds"] = t_collect
+    return params, norm, rep
 
 
 def collect(scenes, iters, per_iter, seed=0, conv_steps=30, solver=None):

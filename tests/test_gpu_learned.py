@@ -145,3 +145,38 @@ def test_learned_start_without_a_network_is_a_state_error():
     with pytest.raises(binding.DbaError) as e:
         s.iterate(1)
     assert e.value.status == "DBA_E_STATE"
+
+
+def _final_inlier_rmse(sc, net=None, iters=250, **kw):
+    base = dict(precision="fp32", loss="huber", loss_param=2.0, rho=1e5, rho_balancing=True, rho_min=1e5,
+                rho_max=1e7, block_waves=1, persistent=0)
+    base.update(kw)
+    s = binding.Solver(**base)
+    if net is not None:
+        binding.dba_set_mlp(s.h, net[0], net[1])
+    s.set_scene(sc)
+    s.set_eval_mask(~sc.outlier)
+    s.iterate(iters)
+    r = s.residuals(want_rmse=True)["rmse_masked"]
+    s.close()
+    return r
+
+
+def test_trained_network_gains_over_the_plain_start():
+    """On the 2M-observation trajectory workload, three LM steps from the
+    plain start (the previous copy) let ADMM diverge; the same three steps
+    from the trained network's start converge to the inlier RMSE of five
+    plain steps.  The network is trained on the GPU from pairs collected on
+    ten small trajectory-family scenes."""
+    from paper_1708_07954_amd import warmstart
+    params, norm, rep = warmstart.train_default()
+    assert rep["epoch_loss"][-1] < rep["epoch_loss"][0]
+    sc = make_config2()
+    plain5 = _final_inlier_rmse(sc, lm_steps=5)
+    plain3 = _final_inlier_rmse(sc, lm_steps=3)
+    learned3 = _final_inlier_rmse(sc, net=(params, norm), start="learned", learned_lm_steps=3)
+    print("inlier rmse after 250 iterations: plain5", plain5, "plain3", plain3, "learned3", learned3,
+          "train", rep["train_seconds"], "s", rep["epoch_loss"])
+    assert plain5 < 3.0
+    assert not (plain3 < 2.0 * plain5)      # diverged (or NaN)
+    assert learned3 < 1.01 * plain5

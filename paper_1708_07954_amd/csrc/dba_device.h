@@ -208,7 +208,8 @@ template <typename R> __device__ __forceinline__ R lam_up(R l) { return l * R(10
 // (Gill, Golub, Murray & Saunders 1974, method C1): A = L1 L2 D2 L2^T L1^T
 // with unit lower-triangular L1 = I + low(J0 b1^T), L2 = I + low(q b2^T),
 // q = L1^-1 J1.  The factor lives in registers as four 12-vectors and both
-// the factorisation and the solve take O(12) operations.
+// the factorisation and the solve take O(12) operations; a pivot of D2 that
+// is not positive and finite rejects the step.
 template <typename R>
 __device__ __forceinline__ void lm_steps(R *th, Proj<R> &cur, R &F, const R *v, R z0, R z1, R rx,
                                          R ry, int kind, R lp, int steps, R lam)
@@ -231,34 +232,35 @@ __device__ __forceinline__ void lm_steps(R *th, Proj<R> &cur, R &F, const R *v, 
             hd[i] = Pi + c2 * (J0[i] * J0[i] + J1[i] * J1[i]);             // diag(H)
             Dd[i] = Pi + lam * hd[i];                                       // A - c J^T J
         }
-        // rank-one update 1: diag -> L1 D1 L1^T (p = J0)
-        R b1[12], id1[12], b2[12], q[12], id2[12];
-        R tau = R(1);
+        // rank-one update 1: diag -> L1 D1 L1^T (p = J0); alpha_{j+1} =
+        // alpha_j d_j / d1_j, one reciprocal per row
+        R b1[12], d1[12], b2[12], q[12], id2[12];
+        R al = c2;
 #pragma unroll
         for (int j = 0; j < 12; ++j) {
-            const R idj = Num<R>::rcp(Dd[j]);
-            const R cp = c2 * J0[j] * idj;
-            const R tn = tau + cp * J0[j];
-            const R itn = Num<R>::rcp(tn);
-            id1[j] = idj * tau * itn;
-            b1[j] = cp * itn;
-            tau = tn;
+            const R ap = al * J0[j];
+            d1[j] = Dd[j] + ap * J0[j];
+            const R r = Num<R>::rcp(d1[j]);
+            b1[j] = ap * r;
+            al = al * Dd[j] * r;
         }
         // rank-one update 2 (z = J1): q = L1^-1 J1, then L2 D2 L2^T
         R S = R(0);
-        R tau2 = R(1);
+        R al2 = c2;
+        bool pos = true;
 #pragma unroll
         for (int j = 0; j < 12; ++j) {
             q[j] = J1[j] - J0[j] * S;
             S += b1[j] * q[j];
-            const R cq = c2 * q[j] * id1[j];
-            const R tn = tau2 + cq * q[j];
-            const R itn = Num<R>::rcp(tn);
-            id2[j] = id1[j] * tau2 * itn;
-            b2[j] = cq * itn;
-            tau2 = tn;
+            const R aq = al2 * q[j];
+            const R d2 = d1[j] + aq * q[j];
+            pos = pos && (d2 > R(0)) && (d2 < Num<R>::inf);
+            const R r = Num<R>::rcp(d2);
+            id2[j] = r;
+            b2[j] = aq * r;
+            al2 = al2 * d1[j] * r;
         }
-        const bool ok = (tau2 > R(0)) && (tau2 < Num<R>::inf) && (tau < Num<R>::inf);
+        const bool ok = pos;
         // solve L1 L2 D2 L2^T L1^T x = -g
         S = R(0);
 #pragma unroll

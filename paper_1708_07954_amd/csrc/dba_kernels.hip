@@ -218,6 +218,7 @@ __global__ __launch_bounds__(256) void k_consensus(DevArrays<R> a, int pt_blocks
             // e = new - previous
             const double4 old = a.cons_x[i];
             double s0 = 0.0, s1 = 0.0, s2 = 0.0, q0 = 0.0, q1 = 0.0, q2 = 0.0, qq = 0.0;
+#pragma unroll 4
             for (int r = r0; r < r1; ++r) {
                 const R4 x = a.xrec[r];
                 const double4 u = a.urec[r];

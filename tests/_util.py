@@ -39,3 +39,31 @@ def param_err_summary(cams, pts, cams_ref, pts_ref):
     b = np.concatenate([cams_ref.ravel(), pts_ref.ravel()])
     return dict(max=float(e.max()), p99=float(np.percentile(e, 99)), p999=float(np.percentile(e, 99.9)),
                 glob=float(np.linalg.norm(a - b) / np.linalg.norm(b)))
+
+
+def reprojection_gap(sc, cams, pts, cams_ref, pts_ref, idx, limit=20000):
+    """Largest pixel difference between the predictions of two estimates
+    (FP64 oracle projection) over observations of the points idx; pts is the
+    full point array, pts_ref holds the points idx."""
+    import oracle
+    sel = np.flatnonzero(np.isin(sc.obs_point, idx))[:limit]
+    where = {int(p): q for q, p in enumerate(idx)}
+    gap = 0.0
+    for k in sel:
+        j, i = int(sc.obs_cam[k]), int(sc.obs_point[k])
+        a, _ = oracle.project(cams[j], pts[i])
+        b, _ = oracle.project(cams_ref[j], pts_ref[where[i]])
+        gap = max(gap, float(np.abs(a - b).max()))
+    return gap, len(sel)
+
+
+# FP32-local parity against the FP64 oracle after many iterations: 99 % of
+# the parameters and the global relative error within 1e-3; the largest
+# per-parameter error (weakly observed parameters drift along nearly flat
+# directions of the objective) and the largest difference of predicted
+# pixels are reported, the former bounded at 1e-1.
+FP32_P99, FP32_GLOBAL, FP32_MAX = 1e-3, 1e-3, 1e-1
+
+
+def fp32_parity_ok(e):
+    return e["p99"] < FP32_P99 and e["glob"] < FP32_GLOBAL and e["max"] < FP32_MAX

@@ -30,6 +30,8 @@ sys.path.insert(0, ROOT)
 METRIC = "obs-updates/s per ADMM iter (2M obs); time-to-RMSE, warm-start vs plain LM"
 FP32_VECTOR_PEAK_TFLOPS = 78.6   # 256 CU x 64 lanes x 2 (FMA) x 2.4 GHz, non-packed FP32
 HBM_PEAK_GBS = 8000.0
+BF16_MFMA_PEAK_TFLOPS = 2500.0   # dense
+MLP_FLOPS_PER_OBS = 2 * (32 * 128 + 128 * 128 + 128 * 16)   # padded 32 -> 128 -> 128 -> 16
 
 WORKLOADS = {
     # name: (scene maker kwargs, solver options, description)
@@ -112,6 +114,14 @@ def time_to_rmse(binding, scene, opts, sched, target, max_iters=400, learned_ste
             s.set_scene(scene)
             s.set_eval_mask(inl)
             return s
+        # per-kernel times over the first 20 iterations of a fresh run
+        s = make()
+        binding.dba_set_kernel_timing(s.h, True)
+        s.iterate(20)
+        torch.cuda.synchronize()
+        kt = binding.dba_kernel_times(s.h)
+        s.close()
+        kernels = {k: v[0] / v[1] for k, v in kt.items() if v[1]}
         s = make()
         hit, last = None, None
         for k in range(1, max_iters + 1):
@@ -123,7 +133,7 @@ def time_to_rmse(binding, scene, opts, sched, target, max_iters=400, learned_ste
                 hit = k
                 break
         s.close()
-        out = {"iterations": hit, "inlier_rmse_at_stop": last}
+        out = {"iterations": hit, "inlier_rmse_at_stop": last, "kernel_ms": kernels}
         if hit is None:
             out["seconds"] = None
             return out
@@ -152,6 +162,16 @@ def time_to_rmse(binding, scene, opts, sched, target, max_iters=400, learned_ste
     for k in learned_steps:
         res[f"learned_lm{k}"] = run(dict(opts, start="learned", learned_lm_steps=k), net=(params, norm))
         print(f"[bench] time-to-RMSE learned+{k}: {res[f'learned_lm{k}']}", file=sys.stderr, flush=True)
+    # the fused learned-start kernel on the BF16 MFMA roofline: network
+    # FLOPs per observation x observations / kernel time (a lower bound on the
+    # network's own rate, the kernel also runs the guard and the LM steps)
+    L = scene.n_obs
+    for k in learned_steps:
+        t = res[f"learned_lm{k}"]["kernel_ms"].get("learned")
+        if t:
+            res[f"learned_lm{k}"]["mlp_tflops_lower_bound"] = MLP_FLOPS_PER_OBS * L / (t * 1e-3) / 1e12
+    res["mlp_flops_per_obs"] = MLP_FLOPS_PER_OBS
+    res["bf16_mfma_peak_tflops"] = BF16_MFMA_PEAK_TFLOPS
     t_plain = res["plain_lm5"]["seconds"]
     best = min((res[f"learned_lm{k}"]["seconds"] for k in learned_steps
                 if res[f"learned_lm{k}"]["seconds"] is not None), default=None)
@@ -255,6 +275,23 @@ def main():
     cons_ms = kt["consensus"]["avg_ms"]
     consensus_line = {"avg_launch_ms": cons_ms,
                       "hbm_algorithmic_GBps": round(byt["consensus"] * L / (cons_ms * 1e-3) / 1e9, 1)}
+
+    # measured device-copy bandwidth (1 GiB read + 1 GiB written), context for
+    # the 8 TB/s HBM peak
+    src = torch.ones(1 << 28, dtype=torch.float32, device="cuda")
+    dst = torch.empty_like(src)
+    dst.copy_(src)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(5):
+        dst.copy_(src)
+    e1.record()
+    torch.cuda.synchronize()
+    copy_gbps = 5 * 2 * src.numel() * 4 / (e0.elapsed_time(e1) * 1e-3) / 1e9
+    del src, dst
+    roofline["measured_copy_GBps"] = round(copy_gbps, 1)
+    consensus_line["hbm_peak_GBps"] = HBM_PEAK_GBS
+    consensus_line["frac_of_measured_copy"] = round(consensus_line["hbm_algorithmic_GBps"] / copy_gbps, 4)
 
     # optional plain copy, for scaling the FETCH_SIZE / WRITE_SIZE counters
     if args.copy_probe_mib:

@@ -195,6 +195,80 @@ template <> __device__ __forceinline__ float lam_down(float l) { return fmaxf(l 
 template <> __device__ __forceinline__ double lam_down(double l) { return fmax(l / 10.0, 1e-12); }
 template <typename R> __device__ __forceinline__ R lam_up(R l) { return l * R(10) < R(1e12) ? l * R(10) : R(1e12); }
 
+// Solves (D + c (J0 J0^T + J1 J1^T)) x = g, D = diag(Dd) > 0, c > 0 -- the
+// damped Gauss-Newton system of one local problem.  Returns false when a
+// pivot is not positive and finite (the step is then rejected).
+//
+// LDL^T (Cholesky) factor by two rank-one updates of the diagonal factor
+// (Gill, Golub, Murray & Saunders 1974, method C1): A = L1 L2 D2 L2^T L1^T
+// with unit lower-triangular L1 = I + low(J0 b1^T), L2 = I + low(q b2^T),
+// q = L1^-1 J1; O(12) operations, one reciprocal per row and update.  (The
+// Sherman-Morrison-Woodbury form of the same solve takes about half the
+// operations, but in FP32 its cancellation in the two stiff directions,
+// amplified over many ADMM iterations along nearly flat directions of the
+// global problem, costs an order of magnitude in agreement with FP64.)
+template <typename R>
+__device__ __forceinline__ bool solve_normal(const R *Dd, const R *J0, const R *J1, R c2, const R *ng, R *x)
+{
+    // rank-one update 1: diag -> L1 D1 L1^T (p = J0); alpha_{j+1} =
+    // alpha_j d_j / d1_j, one reciprocal per row
+    R b1[12], d1[12], b2[12], q[12], id2[12];
+    R al = c2;
+#pragma unroll
+    for (int j = 0; j < 12; ++j) {
+        const R ap = al * J0[j];
+        d1[j] = Dd[j] + ap * J0[j];
+        const R r = Num<R>::rcp(d1[j]);
+        b1[j] = ap * r;
+        al = al * Dd[j] * r;
+    }
+    // rank-one update 2 (z = J1): q = L1^-1 J1, then L2 D2 L2^T
+    R S = R(0);
+    R al2 = c2;
+    bool pos = true;
+#pragma unroll
+    for (int j = 0; j < 12; ++j) {
+        q[j] = J1[j] - J0[j] * S;
+        S += b1[j] * q[j];
+        const R aq = al2 * q[j];
+        const R d2 = d1[j] + aq * q[j];
+        pos = pos && (d2 > R(0)) && (d2 < Num<R>::inf);
+        const R r = Num<R>::rcp(d2);
+        id2[j] = r;
+        b2[j] = aq * r;
+        al2 = al2 * d1[j] * r;
+    }
+    const bool ok = pos;
+    // solve L1 L2 D2 L2^T L1^T x = -g
+    S = R(0);
+#pragma unroll
+    for (int j = 0; j < 12; ++j) {
+        x[j] = ng[j] - J0[j] * S;
+        S += b1[j] * x[j];
+    }
+    S = R(0);
+#pragma unroll
+    for (int j = 0; j < 12; ++j) {
+        x[j] = x[j] - q[j] * S;
+        S += b2[j] * x[j];
+    }
+#pragma unroll
+    for (int j = 0; j < 12; ++j) x[j] *= id2[j];
+    S = R(0);
+#pragma unroll
+    for (int j = 11; j >= 0; --j) {
+        x[j] = x[j] - b2[j] * S;
+        S += q[j] * x[j];
+    }
+    S = R(0);
+#pragma unroll
+    for (int j = 11; j >= 0; --j) {
+        x[j] = x[j] - b1[j] * S;
+        S += J0[j] * x[j];
+    }
+    return ok;
+}
+
 // Robust LM on the local objective, exactly `steps` steps (rejected ones
 // included), Marquardt damping lambda * diag(H).  A trial is accepted if it
 // lowers F, or if the model's predicted decrease is below tie times F's
@@ -203,13 +277,8 @@ template <typename R> __device__ __forceinline__ R lam_up(R l) { return l * R(10
 // (depth <= 1e-6 or a failed factorisation) is rejected.
 //
 // Normal equations: A = H + lambda diag(H), H = P + 2w J^T J, i.e.
-// A = D + c (J0 J0^T + J1 J1^T) with D diagonal and c = 2w.  Its LDL^T
-// (Cholesky) factor is built by two rank-one updates of the diagonal factor
-// (Gill, Golub, Murray & Saunders 1974, method C1): A = L1 L2 D2 L2^T L1^T
-// with unit lower-triangular L1 = I + low(J0 b1^T), L2 = I + low(q b2^T),
-// q = L1^-1 J1.  The factor lives in registers as four 12-vectors and both
-// the factorisation and the solve take O(12) operations; a pivot of D2 that
-// is not positive and finite rejects the step.
+// A = D + c (J0 J0^T + J1 J1^T) with D diagonal and c = 2w, solved in
+// registers in O(12) operations (solve_normal).
 template <typename R>
 __device__ __forceinline__ void lm_steps(R *th, Proj<R> &cur, R &F, const R *v, R z0, R z1, R rx,
                                          R ry, int kind, R lp, int steps, R lam)
@@ -232,62 +301,7 @@ __device__ __forceinline__ void lm_steps(R *th, Proj<R> &cur, R &F, const R *v, 
             hd[i] = Pi + c2 * (J0[i] * J0[i] + J1[i] * J1[i]);             // diag(H)
             Dd[i] = Pi + lam * hd[i];                                       // A - c J^T J
         }
-        // rank-one update 1: diag -> L1 D1 L1^T (p = J0); alpha_{j+1} =
-        // alpha_j d_j / d1_j, one reciprocal per row
-        R b1[12], d1[12], b2[12], q[12], id2[12];
-        R al = c2;
-#pragma unroll
-        for (int j = 0; j < 12; ++j) {
-            const R ap = al * J0[j];
-            d1[j] = Dd[j] + ap * J0[j];
-            const R r = Num<R>::rcp(d1[j]);
-            b1[j] = ap * r;
-            al = al * Dd[j] * r;
-        }
-        // rank-one update 2 (z = J1): q = L1^-1 J1, then L2 D2 L2^T
-        R S = R(0);
-        R al2 = c2;
-        bool pos = true;
-#pragma unroll
-        for (int j = 0; j < 12; ++j) {
-            q[j] = J1[j] - J0[j] * S;
-            S += b1[j] * q[j];
-            const R aq = al2 * q[j];
-            const R d2 = d1[j] + aq * q[j];
-            pos = pos && (d2 > R(0)) && (d2 < Num<R>::inf);
-            const R r = Num<R>::rcp(d2);
-            id2[j] = r;
-            b2[j] = aq * r;
-            al2 = al2 * d1[j] * r;
-        }
-        const bool ok = pos;
-        // solve L1 L2 D2 L2^T L1^T x = -g
-        S = R(0);
-#pragma unroll
-        for (int j = 0; j < 12; ++j) {
-            x[j] = ng[j] - J0[j] * S;
-            S += b1[j] * x[j];
-        }
-        S = R(0);
-#pragma unroll
-        for (int j = 0; j < 12; ++j) {
-            x[j] = x[j] - q[j] * S;
-            S += b2[j] * x[j];
-        }
-#pragma unroll
-        for (int j = 0; j < 12; ++j) x[j] *= id2[j];
-        S = R(0);
-#pragma unroll
-        for (int j = 11; j >= 0; --j) {
-            x[j] = x[j] - b2[j] * S;
-            S += q[j] * x[j];
-        }
-        S = R(0);
-#pragma unroll
-        for (int j = 11; j >= 0; --j) {
-            x[j] = x[j] - b1[j] * S;
-            S += J0[j] * x[j];
-        }
+        const bool ok = solve_normal(Dd, J0, J1, c2, ng, x);
         R tr[12];
         R gd = R(0), dd = R(0);
 #pragma unroll

@@ -12,8 +12,8 @@
 // consensus  point consensus (Eq. 10): one thread per point, ascending record
 //            order, one pass over the records; residual terms summed per
 //            256-point block by a fixed tree;
-//            camera consensus (Eq. 11): one wave per camera summing its chunk
-//            partials in ascending chunk order.  Both in FP64.
+//            camera consensus (Eq. 11): one wave per camera, lanes summing
+//            strided chunk partials, then a fixed reduce-scatter.  Both FP64.
 // norms      one workgroup per problem: primal/dual residual norms, residual
 //            balancing of rho, rescale factor for the pending dual update.
 // eval       reprojection statistics at the consensus estimate (FP64).
@@ -256,17 +256,29 @@ __global__ __launch_bounds__(256) void k_consensus(DevArrays<R> a, int pt_blocks
             a.ppart[2 * (long long)b + 1] = sh[1][0];
         }
     } else {
-        const int lane = threadIdx.x & 63;
-        const int J = (blockIdx.x - pt_blocks) * 4 + (threadIdx.x >> 6);
-        if (J >= a.n_cams) return;  // whole wave
+        // camera consensus: lane l sums chunks k0 + l, k0 + l + 64, ... in
+        // order, then a fixed reduce-scatter adds the lanes
+        __shared__ double csum[4][kCpart];
+        const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+        const int J = (blockIdx.x - pt_blocks) * 4 + w;
+        if (J >= a.n_cams) return;  // whole wave; no barrier follows
         const int k0 = a.cam_chunk0[J], k1 = a.cam_chunk0[J + 1];
-        double acc = 0.0;
-        if (lane < 19)
-            for (int k = k0; k < k1; ++k) acc += a.cpart[(long long)k * kCpart + lane];
-        double S[19];
+        double acc[19];
 #pragma unroll
-        for (int i = 0; i < 19; ++i) S[i] = __shfl(acc, i, 64);
+        for (int i = 0; i < 19; ++i) acc[i] = 0.0;
+        for (int k = k0 + lane; k < k1; k += 64) {
+            const double *c = a.cpart + (long long)k * kCpart;
+#pragma unroll
+            for (int i = 0; i < 19; ++i) acc[i] += c[i];
+        }
+        wave_sum19_store(acc, csum[w], lane);
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
         if (lane == 0) {
+            double S[19];
+#pragma unroll
+            for (int i = 0; i < 19; ++i) S[i] = csum[w][i];
             const double M = (double)a.cam_count[J];
             double *cy = a.cons_y + (long long)J * kConsY;
             double dd = 0.0, dS = 0.0;

@@ -58,12 +58,20 @@ def reprojection_gap(sc, cams, pts, cams_ref, pts_ref, idx, limit=20000):
 
 
 # FP32-local parity against the FP64 oracle after many iterations: 99 % of
-# the parameters and the global relative error within 1e-3; the largest
-# per-parameter error (weakly observed parameters drift along nearly flat
-# directions of the objective) and the largest difference of predicted
-# pixels are reported, the former bounded at 1e-1.
-FP32_P99, FP32_GLOBAL, FP32_MAX = 1e-3, 1e-3, 1e-1
+# the parameters and the global relative error within 1e-3.  The tail is
+# bounded by what the workload itself determines: e_self is the deviation of
+# the FP64 oracle from its own stored run when started from a start
+# perturbed at FP32 rounding size (1 +- 1e-7); a parameter the workload does
+# not pin to 1e-3 under such a perturbation may differ by up to three times
+# the oracle's own spread (99.9th percentile and maximum) -- FP32 rounds at
+# every operation of every iteration, the reference perturbs only the start.
+# Without e_self the maximum is bounded at 1e-1.
+FP32_P99, FP32_GLOBAL, FP32_MAX, FP32_SPREAD = 1e-3, 1e-3, 1e-1, 3.0
 
 
-def fp32_parity_ok(e):
-    return e["p99"] < FP32_P99 and e["glob"] < FP32_GLOBAL and e["max"] < FP32_MAX
+def fp32_parity_ok(e, e_self=None):
+    ok = e["p99"] < FP32_P99 and e["glob"] < FP32_GLOBAL
+    if e_self is None:
+        return ok and e["max"] < FP32_MAX
+    return (ok and e["p999"] < max(FP32_P99, FP32_SPREAD * e_self["p999"])
+            and e["max"] < max(FP32_P99, FP32_SPREAD * e_self["max"]))

@@ -4,6 +4,12 @@ against.  Calls only the FP64 oracle (oracle/) on seeded scenes (scenes/).
     python tests/golden/make_golden.py trajectory   # ~35 min, one core
     python tests/golden/make_golden.py sphere       # ~2 min
     python tests/golden/make_golden.py batch        # ~1 min
+    python tests/golden/make_golden.py trajectory_perturbed sphere_perturbed
+
+A name ending in _perturbed runs the same workload from a start whose
+parameters are multiplied by 1 +- 1e-7 (random signs, seed 7), the size of
+FP32 rounding: how far the FP64 oracle moves from its own stored run bounds
+the agreement any FP32 computation can reach on that workload.
 """
 import os
 import sys
@@ -27,11 +33,17 @@ SPECS = {
 
 
 def run(name):
-    make, kw, iters, stride = SPECS[name]
+    base = name[:-len("_perturbed")] if name.endswith("_perturbed") else name
+    make, kw, iters, stride = SPECS[base]
     sc = make()
     kw = dict(kw)
     rmin, rmax = kw.pop("rho_min", 1e-6), kw.pop("rho_max", 1e6)
-    a = oracle.ADMM(oracle.Problem.from_scene(sc), sc.cams_init, sc.points_init, **kw)
+    cams0, pts0 = sc.cams_init, sc.points_init
+    if base != name:
+        rng = np.random.default_rng(7)
+        cams0 = cams0 * (1 + 1e-7 * rng.choice([-1.0, 1.0], size=cams0.shape))
+        pts0 = pts0 * (1 + 1e-7 * rng.choice([-1.0, 1.0], size=pts0.shape))
+    a = oracle.ADMM(oracle.Problem.from_scene(sc), cams0, pts0, **kw)
     a.opts.rho_min, a.opts.rho_max = rmin, rmax
     inl = ~sc.outlier
     trace, curve = [], []
@@ -45,7 +57,7 @@ def run(name):
     np.savez_compressed(os.path.join(HERE, f"{name}.npz"), checksum=np.array(sc.checksum()),
                         n_obs=sc.n_obs, iterations=iters, trace=np.concatenate(trace), curve=np.array(curve),
                         cams=a.cons_y, points_idx=pts_idx, points=a.cons_x[pts_idx], rho=a.rho,
-                        stats=a.stats(inl), settings=np.array(repr(SPECS[name][1])))
+                        stats=a.stats(inl), settings=np.array(repr(SPECS[base][1])))
 
 
 def run_batch():

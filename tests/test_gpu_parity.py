@@ -206,21 +206,35 @@ def test_sphere_workload_matches_stored_oracle(precision, tol):
     e = param_err_summary(cams, pts[g["points_idx"]], g["cams"], g["points"])
     r = s.residuals(want_rmse=True)
     gap, n_gap = reprojection_gap(sc, cams, pts, g["cams"], g["points"], g["points_idx"])
+    spread = _self_spread("sphere", g)
     print(precision, "sphere rel err", e, worst_param(cams, pts[g["points_idx"]], g["cams"], g["points"]),
-          "rmse", r["rmse"], g["stats"][0], "reprojection gap px", gap, "over", n_gap)
+          "rmse", r["rmse"], g["stats"][0], "reprojection gap px", gap, "over", n_gap, "oracle self-spread", spread)
     if precision == "fp64":
         assert e["max"] < tol
     else:
-        assert fp32_parity_ok(e)
+        assert fp32_parity_ok(e, spread)
     assert abs(r["rmse"] - g["stats"][0]) < (1e-9 if precision == "fp64" else 5e-3) * g["stats"][0]
+
+
+def _self_spread(name, g):
+    """The oracle's own deviation from its stored run when started at FP32
+    rounding distance (tests/golden/<name>_perturbed.npz), or None."""
+    import os
+    path = os.path.join(os.path.dirname(__file__), "golden", f"{name}_perturbed.npz")
+    if not os.path.exists(path):
+        return None
+    z = np.load(path)
+    assert str(z["checksum"]) == str(g["checksum"]) and np.array_equal(z["points_idx"], g["points_idx"])
+    return param_err_summary(z["cams"], z["points"], g["cams"], g["points"])
 
 
 def test_trajectory_workload_matches_stored_oracle():
     """The benchmark workload: 1000 cameras, 200000 points, 2.006M observations,
     FP32 local solves, 200 iterations, against the stored FP64 oracle run.
     Inlier RMSE within 0.5 % and the FP32 parity bounds of _util (99 % of
-    the parameters and the global relative error within 1e-3; the largest
-    error and pixel difference are printed).  The tail belongs to weakly
+    the parameters and the global relative error within 1e-3, the tail
+    within three times the oracle's own spread under FP32-size perturbations
+    of the start; the pixel difference is printed).  The tail belongs to weakly
     observed parameters -- the radial distortion of cameras whose points sit
     near the image centre, the depth of points seen by two neighbouring
     frames -- which FP32 rounding moves along nearly flat directions of the
@@ -238,10 +252,11 @@ def test_trajectory_workload_matches_stored_oracle():
     r = s.residuals(want_rmse=True)
     gap, n_gap = reprojection_gap(sc, cams, pts, g["cams"], g["points"], g["points_idx"])
     ec = np.abs(cams - g["cams"]) / np.maximum(np.abs(g["cams"]), CAM_FLOOR)
+    spread = _self_spread("trajectory", g)
     print("trajectory rel err", e, worst_param(cams, pts[g["points_idx"]], g["cams"], g["points"]),
           "inlier rmse", r["rmse_masked"], g["stats"][1], "max per camera column", ec.max(0),
-          "reprojection gap px", gap, "over", n_gap)
-    assert fp32_parity_ok(e)
+          "reprojection gap px", gap, "over", n_gap, "oracle self-spread", spread)
+    assert fp32_parity_ok(e, spread)
     assert abs(r["rmse_masked"] - g["stats"][1]) < 5e-3 * g["stats"][1]
     assert r["next_rho_x"] == g["rho"][0]
 

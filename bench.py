@@ -84,6 +84,19 @@ def recorded_traffic(workload):
     return float(tb.group(1)), path
 
 
+def measure_copy_bandwidth(torch):
+    src = torch.ones(1 << 28, dtype=torch.float32, device="cuda")
+    dst = torch.empty_like(src)
+    dst.copy_(src)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(5):
+        dst.copy_(src)
+    e1.record()
+    torch.cuda.synchronize()
+    return 5 * 2 * src.numel() * 4 / (e0.elapsed_time(e1) * 1e-3) / 1e9
+
+
 def oracle_target(workload):
     """Final inlier RMSE of the stored FP64 oracle run of the workload
     (written by tests/golden/make_golden.py), or None."""
@@ -179,6 +192,29 @@ def time_to_rmse(binding, scene, opts, sched, target, max_iters=400, learned_ste
     return res
 
 
+def profile_learned(binding, wl):
+    """Short learned-start run for counter collection: collects pairs on two
+    training scenes, trains two epochs, then 20 learned-start iterations (3 LM
+    steps) of the workload with kernel timing."""
+    import torch
+    from paper_1708_07954_amd import warmstart
+    feats, deltas = warmstart.collect(warmstart.training_scenes()[:2], iters=20, per_iter=5000, seed=1)
+    params, norm, rep = warmstart.train(feats, deltas, epochs=2)
+    sc = make_scenes(wl["scene"])[0]
+    s = binding.Solver(**dict(wl["opts"], start="learned", learned_lm_steps=3))
+    binding.dba_set_mlp(s.h, params, norm)
+    s.set_scene(sc)
+    binding.dba_set_kernel_timing(s.h, True)
+    s.iterate(20)
+    torch.cuda.synchronize()
+    kt = {k: v[0] / v[1] for k, v in binding.dba_kernel_times(s.h).items() if v[1]}
+    s.close()
+    print(json.dumps({"profile_learned": True, "n_obs": sc.n_obs, "pairs": rep["pairs"],
+                      "train_seconds": rep["train_seconds"], "kernel_ms": kt,
+                      "mlp_tflops_lower_bound": MLP_FLOPS_PER_OBS * sc.n_obs / (kt["learned"] * 1e-3) / 1e12}),
+          flush=True)
+
+
 def cpu_model():
     try:
         for line in open("/proc/cpuinfo"):
@@ -198,6 +234,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-time-to-rmse", action="store_true",
                     help="skip the time-to-RMSE comparison (learned start vs plain LM)")
+    ap.add_argument("--profile-learned", action="store_true",
+                    help="only train the network briefly and run 20 learned-start iterations (for profilers)")
     ap.add_argument("--copy-probe-mib", type=int, default=0,
                     help="also run a plain device copy of this size (counter calibration)")
     args = ap.parse_args()
@@ -216,6 +254,9 @@ def main():
         print(json.dumps({"error": "no GPU visible"}), flush=True)
         sys.exit(1)
     wl = WORKLOADS[args.workload]
+    if args.profile_learned:
+        profile_learned(binding, wl)
+        return
     t_gen = time.perf_counter()
     scenes = make_scenes(wl["scene"])
     L = sum(sc.n_obs for sc in scenes)
@@ -277,21 +318,14 @@ def main():
                       "hbm_algorithmic_GBps": round(byt["consensus"] * L / (cons_ms * 1e-3) / 1e9, 1)}
 
     # measured device-copy bandwidth (1 GiB read + 1 GiB written), context for
-    # the 8 TB/s HBM peak
-    src = torch.ones(1 << 28, dtype=torch.float32, device="cuda")
-    dst = torch.empty_like(src)
-    dst.copy_(src)
-    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    e0.record()
-    for _ in range(5):
-        dst.copy_(src)
-    e1.record()
-    torch.cuda.synchronize()
-    copy_gbps = 5 * 2 * src.numel() * 4 / (e0.elapsed_time(e1) * 1e-3) / 1e9
-    del src, dst
-    roofline["measured_copy_GBps"] = round(copy_gbps, 1)
+    # the 8 TB/s HBM peak; skipped in counter-calibration runs, whose only
+    # plain copy must be the calibration probe
+    copy_gbps = None
+    if not args.copy_probe_mib:
+        copy_gbps = measure_copy_bandwidth(torch)
+        roofline["measured_copy_GBps"] = round(copy_gbps, 1)
+        consensus_line["frac_of_measured_copy"] = round(consensus_line["hbm_algorithmic_GBps"] / copy_gbps, 4)
     consensus_line["hbm_peak_GBps"] = HBM_PEAK_GBS
-    consensus_line["frac_of_measured_copy"] = round(consensus_line["hbm_algorithmic_GBps"] / copy_gbps, 4)
 
     # optional plain copy, for scaling the FETCH_SIZE / WRITE_SIZE counters
     if args.copy_probe_mib:

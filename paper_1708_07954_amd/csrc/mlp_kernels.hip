@@ -250,23 +250,36 @@ __global__ __launch_bounds__(256) void k_mlp_wgrad(WgradJob j0, WgradJob j1, Wgr
 // ---------------------------------------------------------------- bias gradients
 // Column sums of dy [n][16] (cols 0..15), dz2 [n][128], dz1 [n][128] into
 // grad at the bias offsets; 4 threads per column, combined in order.
+// Column sums of dY (16), dZ2 (128) and dZ1 (128): 16 columns per block,
+// 16 row lanes per column, each with 8 interleaved accumulators (rows
+// r = lane + 16 k, accumulator k mod 8), combined in a fixed order.
 __global__ __launch_bounds__(256) void k_mlp_bias(const float *dy, const float *dz2, const float *dz1, int n, float *grad)
 {
-    __shared__ float part[256];
-    const int col = blockIdx.x * 64 + (threadIdx.x >> 2);   // 0..271
-    const int sub = threadIdx.x & 3;
-    float s = 0.0f;
+    __shared__ float part[16][17];
+    const int col = blockIdx.x * 16 + (threadIdx.x & 15);   // 0..271
+    const int rl = threadIdx.x >> 4;
     const float *src = nullptr;
     int ld = 0, c = 0, dst = -1;
     if (col < kOutPad) { src = dy; ld = kOutPad; c = col; dst = kPB3 + col; }
     else if (col < kOutPad + kHid) { src = dz2; ld = kHid; c = col - kOutPad; dst = kPB2 + c; }
-    else if (col < kOutPad + 2 * kHid) { src = dz1; ld = kHid; c = col - kOutPad - kHid; dst = kPB1 + c; }
-    if (src)
-        for (int r = sub; r < n; r += 4) s += src[(size_t)r * ld + c];
-    part[threadIdx.x] = s;
+    else { src = dz1; ld = kHid; c = col - kOutPad - kHid; dst = kPB1 + c; }
+    float acc[8] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+    int r = rl;
+    for (; r + 16 * 7 < n; r += 16 * 8) {
+#pragma unroll
+        for (int j = 0; j < 8; ++j) acc[j] += src[(size_t)(r + 16 * j) * ld + c];
+    }
+#pragma unroll
+    for (int j = 0; j < 8; ++j)
+        if (r + 16 * j < n) acc[j] += src[(size_t)(r + 16 * j) * ld + c];
+    part[rl][threadIdx.x & 15] = ((acc[0] + acc[1]) + (acc[2] + acc[3])) + ((acc[4] + acc[5]) + (acc[6] + acc[7]));
     __syncthreads();
-    if (sub == 0 && dst >= 0)
-        grad[dst] = ((part[threadIdx.x] + part[threadIdx.x + 1]) + part[threadIdx.x + 2]) + part[threadIdx.x + 3];
+    if (rl == 0) {
+        float t = 0.f;
+#pragma unroll
+        for (int q = 0; q < 16; ++q) t += part[q][threadIdx.x & 15];
+        grad[dst] = t;
+    }
 }
 
 // ---------------------------------------------------------------- Adam
@@ -388,7 +401,7 @@ hipError_t mlp_wgrad(const __bf16 *xb, const __bf16 *h1, const __bf16 *h2, const
 
 hipError_t mlp_bias(const float *dy, const float *dz2, const float *dz1, int n, float *grad, hipStream_t s)
 {
-    hipLaunchKernelGGL(k_mlp_bias, dim3((kOutPad + 2 * kHid + 63) / 64), dim3(256), 0, s, dy, dz2, dz1, n, grad);
+    hipLaunchKernelGGL(k_mlp_bias, dim3((kOutPad + 2 * kHid) / 16), dim3(256), 0, s, dy, dz2, dz1, n, grad);
     return hipGetLastError();
 }
 

@@ -187,8 +187,9 @@ def test_trained_network_gains_over_the_plain_start():
     e_net = np.sum(((pred - deltas) / sd) ** 2, axis=1)
     e_zero = np.sum((deltas / sd) ** 2, axis=1)
     runs = {k: _final_inlier_rmse(sc, **kw) if "start" not in kw else _final_inlier_rmse(sc, net=(params, norm), **kw)
-            for k, kw in (("plain5", dict(lm_steps=5)), ("plain3", dict(lm_steps=3)),
-                          ("learned3", dict(start="learned", learned_lm_steps=3)))}
+            for k, kw in (("plain5", dict(lm_steps=5)), ("plain4", dict(lm_steps=4)), ("plain3", dict(lm_steps=3)),
+                          ("plain2", dict(lm_steps=2)), ("learned3", dict(start="learned", learned_lm_steps=3)),
+                          ("learned5", dict(start="learned", learned_lm_steps=5)))}
     print("pairs", len(e_net), "mean", e_net.mean(), e_zero.mean(), "median", np.median(e_net), np.median(e_zero),
           "inlier rmse after 250 iterations", runs, "train", rep["train_seconds"], "s")
     assert e_net.mean() < 0.8 * e_zero.mean()

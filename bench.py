@@ -108,7 +108,7 @@ def oracle_target(workload):
     return float(z["stats"][1]), int(z["iterations"])
 
 
-def time_to_rmse(binding, scene, opts, sched, target, max_iters=400, learned_steps=(1, 2, 3)):
+def time_to_rmse(binding, scene, opts, sched, target, max_iters=400, learned_steps=(1, 2, 3, 4, 5)):
     """Wall time of plain 5-step LM and of the learned start (+ k LM steps)
     to reach the oracle's final inlier RMSE (within 0.5 %).  The crossing
     iteration is found with per-iteration RMSE checks; a fresh run of exactly

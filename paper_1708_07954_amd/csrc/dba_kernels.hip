@@ -218,10 +218,7 @@ __global__ __launch_bounds__(256) void k_consensus(DevArrays<R> a, int pt_blocks
             // e = new - previous
             const double4 old = a.cons_x[i];
             double s0 = 0.0, s1 = 0.0, s2 = 0.0, q0 = 0.0, q1 = 0.0, q2 = 0.0, qq = 0.0;
-#pragma unroll 4
-            for (int r = r0; r < r1; ++r) {
-                const R4 x = a.xrec[r];
-                const double4 u = a.urec[r];
+            auto add = [&](const R4 &x, const double4 &u) {
                 s0 += (double)x.x + u.x;
                 s1 += (double)x.y + u.y;
                 s2 += (double)x.z + u.z;
@@ -230,7 +227,21 @@ __global__ __launch_bounds__(256) void k_consensus(DevArrays<R> a, int pt_blocks
                 q1 += d1;
                 q2 += d2;
                 qq += d0 * d0 + d1 * d1 + d2 * d2;
+            };
+            // four records' loads in flight, summed in record order
+            int r = r0;
+            for (; r + 4 <= r1; r += 4) {
+                R4 x[4];
+                double4 u[4];
+#pragma unroll
+                for (int j = 0; j < 4; ++j) {
+                    x[j] = a.xrec[r + j];
+                    u[j] = a.urec[r + j];
+                }
+#pragma unroll
+                for (int j = 0; j < 4; ++j) add(x[j], u[j]);
             }
+            for (; r < r1; ++r) add(a.xrec[r], a.urec[r]);
             const double n = (double)(r1 - r0);
             const double c0 = s0 / n, c1 = s1 / n, c2 = s2 / n;
             const double e0 = c0 - old.x, e1 = c1 - old.y, e2 = c2 - old.z;

@@ -9,9 +9,11 @@ region; the timed region runs exactly --steps iterations.
 
 Prints one JSON line: obs-updates/s (observations x iterations / second),
 the local-solve kernel on its ALU roofline (HIP events on the library's
-stream), and the FP64 oracle timed on one host core on one iteration of the
-same workload (also the reference for the FP32-vs-FP64 check printed with
-the result).
+stream), the FP64 oracle pinned to one host core on iterations 2-3 of the
+same workload (its first iteration is the reference for the GPU-vs-oracle
+check printed with the result), and, for the 2M-observation trajectory
+workload, the time to the oracle's final inlier RMSE for the plain and the
+learned start.
 """
 from __future__ import annotations
 
@@ -358,30 +360,47 @@ def main():
 
     if not args.no_cpu_baseline:
         import oracle
+        import numpy as np
         o = wl["opts"]
-        runs, dt = [], 0.0
-        for sc in scenes:
-            a = oracle.ADMM(oracle.Problem.from_scene(sc), sc.cams_init, sc.points_init, loss=o["loss"],
-                            loss_param=o["loss_param"], rho=o["rho"], rho_balancing=o.get("rho_balancing", False))
-            a.opts.rho_min, a.opts.rho_max = o.get("rho_min", 1e-6), o.get("rho_max", 1e6)
-            c0 = time.perf_counter()
-            a.iterate(1)
-            dt += time.perf_counter() - c0
-            runs.append(a)
+        # the oracle on one host core: iteration 1 is the parity reference,
+        # iterations 2 and 3 are timed (median), as the CPU baseline
+        allowed = os.sched_getaffinity(0)
+        core = min(allowed)
+        os.sched_setaffinity(0, {core})
+        runs, first, times = [], [], []
+        try:
+            for sc in scenes:
+                a = oracle.ADMM(oracle.Problem.from_scene(sc), sc.cams_init, sc.points_init, loss=o["loss"],
+                                loss_param=o["loss_param"], rho=o["rho"], rho_balancing=o.get("rho_balancing", False))
+                a.opts.rho_min, a.opts.rho_max = o.get("rho_min", 1e-6), o.get("rho_max", 1e6)
+                a.iterate(1)
+                first.append((a.cons_y.copy(), a.cons_x.copy(), a.stats()[0]))
+                runs.append(a)
+            for _ in range(2):
+                c0 = time.perf_counter()
+                for a in runs:
+                    a.iterate(1)
+                times.append(time.perf_counter() - c0)
+        finally:
+            os.sched_setaffinity(0, allowed)
+        dt = float(np.median(times))
         out["cpu_baseline"] = {"value": L / dt, "unit": "obs-updates/s", "cores": 1, "kind": "oracle",
-                               "sample": f"1 ADMM iteration over all {L} observations ({len(scenes)} problem(s)) "
-                                         f"from the initial state, single-threaded FP64 C oracle, {dt:.1f} s on "
-                                         f"{cpu_model()} ({os.cpu_count()} logical CPUs visible)"}
+                               "sample": f"ADMM iterations 2 and 3 (median) over all {L} observations "
+                                         f"({len(scenes)} problem(s)), single-threaded FP64 C oracle pinned to "
+                                         f"core {core}, {dt:.1f} s per iteration on {cpu_model()} "
+                                         f"({os.cpu_count()} logical CPUs visible)"}
         # the same first iteration on the GPU, compared with the oracle
         chk = binding.Solver(**opts).set_scenes(scenes)
         chk.iterate(1)
         sys.path.insert(0, os.path.join(ROOT, "tests"))
         from _util import param_rel_err
-        worst = 0.0
-        for q, a in enumerate(runs):
+        worst, rdiff = 0.0, 0.0
+        for q, (cy, cx, rmse) in enumerate(first):
             cams, pts = chk.params(q)
-            worst = max(worst, param_rel_err(cams, pts, a.cons_y, a.cons_x))
-        out["parity_vs_oracle_1iter"] = {"max_param_rel_err": worst, "tolerance": 1e-3 if fp32 else 1e-9}
+            worst = max(worst, param_rel_err(cams, pts, cy, cx))
+            rdiff = max(rdiff, abs(chk.residuals(q, want_rmse=True)["rmse"] - rmse) / rmse)
+        out["parity_vs_oracle_1iter"] = {"max_param_rel_err": worst, "tolerance": 1e-3 if fp32 else 1e-9,
+                                         "rmse_rel_diff": rdiff, "rmse_tolerance": 5e-3 if fp32 else 1e-9}
         chk.close()
     s.close()
     print(json.dumps(out), flush=True)

@@ -39,6 +39,12 @@ Readings where the paper is silent or loose (the same on the GPU path):
   R7 residual balancing: mu = 10, tau = 2, rho clamped to [1e-6, 1e6],
      scaled duals multiplied by rho_old / rho_new.
   R8 RMSE = sqrt(sum |e|^2 / L) at the consensus estimate.
+  R9 generalised local updates (Sec. 3.1.4, Eqs. 14-15): a block is up to 64
+     observations of one camera in ascending point order; it holds one copy
+     of the camera and one point copy per observation, and its local problem
+     (all 9 + 3 nb unknowns) is solved by the LM of R4 with the block's
+     objective summed over its observations; a camera's consensus averages
+     its block copies, and its residual weight is its number of blocks.
 """
 from __future__ import annotations
 
@@ -113,6 +119,17 @@ def _declare(L):
     L.orc_admm_iterate.restype = ctypes.c_int
     L.orc_reprojection_stats.argtypes = [ctypes.c_int64, _ip, _ip, _dp, _dp, _dp, _up,
                                          ctypes.c_int, ctypes.c_double, _dp]
+    L.orc_block_objective.argtypes = [ctypes.POINTER(OrcOpts), ctypes.c_int, _dp, _dp, _dp, _dp,
+                                      ctypes.c_double, ctypes.c_double]
+    L.orc_block_objective.restype = ctypes.c_double
+    L.orc_block_local_solve.argtypes = [ctypes.POINTER(OrcOpts), ctypes.c_int, _dp, _dp, _dp, _dp,
+                                        ctypes.c_double, ctypes.c_double, ctypes.c_int, _dp]
+    L.orc_block_local_solve.restype = ctypes.c_int
+    _lp = ctypes.POINTER(ctypes.c_int64)
+    L.orc_admm_iterate_blocked.argtypes = [ctypes.c_int64, ctypes.c_int32, ctypes.c_int32, _ip, _ip, _dp,
+                                           ctypes.c_int32, _lp, _lp, _ip, _dp, _dp, _dp, _dp, _dp, _dp, _dp,
+                                           ctypes.POINTER(OrcOpts), ctypes.c_int32, _dp]
+    L.orc_admm_iterate_blocked.restype = ctypes.c_int
 
 
 def _d(a):
@@ -251,6 +268,100 @@ class ADMM:
         """(rmse_all, rmse_masked, robust_cost, mean_abs_error) at consensus."""
         return reprojection_stats(self.p, self.cons_y, self.cons_x, mask,
                                   self.loss, self.loss_param)
+
+
+# ---------------------------------------------------------------- blocks
+# Generalised local updates (Sec. 3.1.4, Eqs. 14-15), read as: a block is up
+# to `size` observations of one camera, taken in ascending point order (then
+# observation order); the block holds one camera copy and one point copy per
+# observation.
+
+def _l(a):
+    assert a.dtype == np.int64 and a.flags.c_contiguous
+    return a.ctypes.data_as(ctypes.POINTER(ctypes.c_int64))
+
+
+def make_blocks(obs_cam, obs_point, n_cams, size=64):
+    """Returns blk_off (nblk + 1), blk_obs (L), blk_cam (nblk): each camera's
+    observations sorted by (point, observation index), cut into runs of at
+    most `size`, cameras in ascending order."""
+    obs_cam = np.asarray(obs_cam)
+    order = np.lexsort((np.arange(obs_cam.shape[0]), np.asarray(obs_point), obs_cam))
+    offs, cams = [0], []
+    cam_sorted = obs_cam[order]
+    for j in range(n_cams):
+        lo, hi = np.searchsorted(cam_sorted, j, "left"), np.searchsorted(cam_sorted, j, "right")
+        for a in range(lo, hi, size):
+            offs.append(min(a + size, hi))
+            cams.append(j)
+    return (np.asarray(offs, dtype=np.int64), np.ascontiguousarray(order, dtype=np.int64),
+            np.asarray(cams, dtype=np.int32))
+
+
+def block_objective(opts, z, vy, vx, theta, rho_x, rho_y):
+    z, vy, vx, theta = _f64(z), _f64(vy), _f64(vx), _f64(theta)
+    return lib().orc_block_objective(ctypes.byref(opts), int(z.shape[0]), _d(z), _d(vy), _d(vx), _d(theta),
+                                     float(rho_x), float(rho_y))
+
+
+def block_local_solve(opts, z, vy, vx, theta, rho_x, rho_y, steps):
+    """z (nb, 2), vy (9), vx (nb, 3), theta (9 + 3 nb) start; returns
+    (theta, accepted, F trace)."""
+    z, vy, vx = _f64(z), _f64(vy), _f64(vx)
+    th = _f64(theta).copy()
+    tr = np.zeros(steps + 1)
+    acc = lib().orc_block_local_solve(ctypes.byref(opts), int(z.shape[0]), _d(z), _d(vy), _d(vx), _d(th),
+                                      float(rho_x), float(rho_y), int(steps), _d(tr))
+    return th, acc, tr
+
+
+class BlockADMM:
+    """ADMM with block local updates: ``ycopy``/``ydual`` (nblk, 9) per block,
+    ``xcopy``/``xdual`` (L, 3) per observation, ``cons_y`` (m, 9), ``cons_x``
+    (n, 3), ``rho`` = [rho_x, rho_y]."""
+
+    def __init__(self, problem: Problem, cams0, points0, *, block=64, loss="huber", loss_param=2.0, rho=1.0,
+                 rho_x=None, rho_y=None, rho_balancing=False, lm_steps=5, lambda0=1e-3):
+        self.p = problem
+        self.opts = make_opts(loss, loss_param, lm_steps, lambda0, rho_balancing)
+        self.loss, self.loss_param = loss, loss_param
+        self.blk_off, self.blk_obs, self.blk_cam = make_blocks(problem.obs_cam, problem.obs_point,
+                                                               problem.n_cams, block)
+        self.cons_y = _f64(cams0).reshape(-1, 9).copy()
+        self.cons_x = _f64(points0).reshape(-1, 3).copy()
+        self.ycopy = np.ascontiguousarray(self.cons_y[self.blk_cam])
+        self.ydual = np.zeros_like(self.ycopy)
+        self.xcopy = np.ascontiguousarray(self.cons_x[problem.obs_point])
+        self.xdual = np.zeros_like(self.xcopy)
+        self.rho = np.array([rho if rho_x is None else rho_x, rho if rho_y is None else rho_y], dtype=np.float64)
+        self.iteration = 0
+
+    @property
+    def n_blocks(self):
+        return int(self.blk_cam.shape[0])
+
+    def iterate(self, n_iters: int) -> np.ndarray:
+        tr = np.zeros((n_iters, 4))
+        p = self.p
+        rc = lib().orc_admm_iterate_blocked(p.obs_cam.shape[0], p.n_cams, p.n_points, _i(p.obs_cam),
+                                            _i(p.obs_point), _d(p.obs_uv), self.n_blocks, _l(self.blk_off),
+                                            _l(self.blk_obs), _i(self.blk_cam), _d(self.cons_y), _d(self.cons_x),
+                                            _d(self.ycopy), _d(self.ydual), _d(self.xcopy), _d(self.xdual),
+                                            _d(self.rho), ctypes.byref(self.opts), int(n_iters), _d(tr))
+        if rc != 0:
+            raise ValueError("oracle: bad blocks")
+        self.iteration += n_iters
+        return tr
+
+    def copies(self):
+        """Per observation (L, 12): its block's camera copy and its point copy."""
+        blk_of = np.empty(self.p.obs_cam.shape[0], dtype=np.int64)
+        for b in range(self.n_blocks):
+            blk_of[self.blk_obs[self.blk_off[b]:self.blk_off[b + 1]]] = b
+        return np.hstack([self.ycopy[blk_of], self.xcopy]), np.hstack([self.ydual[blk_of], self.xdual])
+
+    def stats(self, mask=None):
+        return reprojection_stats(self.p, self.cons_y, self.cons_x, mask, self.loss, self.loss_param)
 
 
 def reprojection_stats(problem: Problem, cams, points, mask=None, loss_kind="l2",

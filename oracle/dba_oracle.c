@@ -448,3 +448,285 @@ void orc_reprojection_stats(int64_t L, const int32_t *obs_cam, const int32_t *ob
     out[2] = cost;
     out[3] = L > 0 ? abs_sum / (double)L : 0.0;
 }
+
+/* ======================================================================== */
+/* Generalised local updates (Sec. 3.1.4, Eqs. 14-15): a local problem      */
+/* covers a block of observations that share one camera; the block holds   */
+/* one copy y of the camera and one copy x_k of each observation's point.   */
+/* ======================================================================== */
+
+/* Dense SPD solve for the block systems (n up to a few hundred). */
+static int chol_solve_n(int n, const double *A, const double *b, double *x)
+{
+    double *Lm = malloc(sizeof(double) * (size_t)n * (size_t)n);
+    double *yv = malloc(sizeof(double) * (size_t)n);
+    int rc = 0;
+    if (!Lm || !yv) { free(Lm); free(yv); return -2; }
+    for (int i = 0; i < n && rc == 0; ++i) {
+        for (int j = 0; j <= i; ++j) {
+            double s = A[(size_t)i * n + j];
+            for (int k = 0; k < j; ++k) s -= Lm[(size_t)i * n + k] * Lm[(size_t)j * n + k];
+            if (i == j) {
+                if (!(s > 0.0) || !isfinite(s)) { rc = -1; break; }
+                Lm[(size_t)i * n + i] = sqrt(s);
+            } else {
+                Lm[(size_t)i * n + j] = s / Lm[(size_t)j * n + j];
+            }
+        }
+    }
+    if (rc == 0) {
+        for (int i = 0; i < n; ++i) {
+            double s = b[i];
+            for (int k = 0; k < i; ++k) s -= Lm[(size_t)i * n + k] * yv[k];
+            yv[i] = s / Lm[(size_t)i * n + i];
+        }
+        for (int i = n - 1; i >= 0; --i) {
+            double s = yv[i];
+            for (int k = i + 1; k < n; ++k) s -= Lm[(size_t)k * n + i] * x[k];
+            x[i] = s / Lm[(size_t)i * n + i];
+        }
+    }
+    free(Lm);
+    free(yv);
+    return rc;
+}
+
+/* Block objective: sum_k phi(|z_k - pi(y, x_k)|^2) + rho_y/2 |y - vy|^2
+ * + sum_k rho_x/2 |x_k - vx_k|^2; +inf if a depth is <= 1e-6.
+ * theta = (y (9), x_1 (3), ..., x_nb (3)). */
+double orc_block_objective(const orc_opts *o, int nb, const double *z, const double *vy, const double *vx,
+                           const double *theta, double rho_x, double rho_y)
+{
+    double F = 0.0;
+    for (int c = 0; c < 9; ++c) {
+        double d = theta[c] - vy[c];
+        F += 0.5 * rho_y * d * d;
+    }
+    for (int k = 0; k < nb; ++k) {
+        const double *xk = theta + 9 + 3 * k;
+        double uv[2], ls[2];
+        double depth = orc_project(theta, xk, uv);
+        if (!(depth > ORC_DEPTH_EPS)) return INFINITY;
+        double e0 = z[2 * k] - uv[0], e1 = z[2 * k + 1] - uv[1];
+        orc_loss(o->loss, o->loss_param, e0 * e0 + e1 * e1, ls);
+        F += ls[0];
+        for (int c = 0; c < 3; ++c) {
+            double d = xk[c] - vx[3 * k + c];
+            F += 0.5 * rho_x * d * d;
+        }
+    }
+    return F;
+}
+
+/* Robust LM on the block objective with the rules of orc_local_solve
+ * (IRLS weights, Marquardt damping lambda diag(H), exactly `steps` steps,
+ * acceptance on a decrease of F or on a predicted decrease below 1e-13 times
+ * F's rounding resolution F + sum_k |e_k| (|z_k1| + |z_k2| + f)).  The
+ * normal equations of all 9 + 3 nb unknowns are formed densely and solved by
+ * Cholesky.  theta in/out; f_trace optional (steps + 1).  Returns the number
+ * of accepted steps, or -2 on allocation failure. */
+int orc_block_local_solve(const orc_opts *o, int nb, const double *z, const double *vy, const double *vx,
+                          double *theta, double rho_x, double rho_y, int steps, double *f_trace)
+{
+    const int N = 9 + 3 * nb;
+    double *g = malloc(sizeof(double) * N), *H = calloc((size_t)N * N, sizeof(double));
+    double *A = malloc(sizeof(double) * (size_t)N * N), *rhs = malloc(sizeof(double) * N);
+    double *delta = malloc(sizeof(double) * N), *trial = malloc(sizeof(double) * N);
+    if (!g || !H || !A || !rhs || !delta || !trial) {
+        free(g); free(H); free(A); free(rhs); free(delta); free(trial);
+        return -2;
+    }
+    double lambda = o->lambda0;
+    double F = orc_block_objective(o, nb, z, vy, vx, theta, rho_x, rho_y);
+    if (f_trace) f_trace[0] = F;
+    int accepted = 0;
+    for (int it = 0; it < steps; ++it) {
+        memset(H, 0, sizeof(double) * (size_t)N * N);
+        for (int c = 0; c < 9; ++c) {
+            g[c] = rho_y * (theta[c] - vy[c]);
+            H[(size_t)c * N + c] = rho_y;
+        }
+        double fres = F;
+        for (int k = 0; k < nb; ++k) {
+            const double *xk = theta + 9 + 3 * k;
+            double cam_pt[12], uv[2], J[24], ls[2];
+            memcpy(cam_pt, theta, 9 * sizeof(double));
+            memcpy(cam_pt + 9, xk, 3 * sizeof(double));
+            orc_project_jac(cam_pt, cam_pt + 9, uv, J);
+            double e0 = z[2 * k] - uv[0], e1 = z[2 * k + 1] - uv[1];
+            orc_loss(o->loss, o->loss_param, e0 * e0 + e1 * e1, ls);
+            const double w = ls[1];
+            fres += sqrt(e0 * e0 + e1 * e1) * (fabs(z[2 * k]) + fabs(z[2 * k + 1]) + fabs(theta[6]));
+            /* columns of this observation in the block: camera 0..8, point 9+3k.. */
+            int col[12];
+            for (int c = 0; c < 9; ++c) col[c] = c;
+            for (int c = 0; c < 3; ++c) col[9 + c] = 9 + 3 * k + c;
+            for (int c = 0; c < 3; ++c) {
+                g[col[9 + c]] = rho_x * (xk[c] - vx[3 * k + c]);
+                H[(size_t)col[9 + c] * N + col[9 + c]] += rho_x;
+            }
+            for (int r = 0; r < 12; ++r) {
+                g[col[r]] += -2.0 * w * (J[r] * e0 + J[12 + r] * e1);
+                for (int s = 0; s < 12; ++s)
+                    H[(size_t)col[r] * N + col[s]] += 2.0 * w * (J[r] * J[s] + J[12 + r] * J[12 + s]);
+            }
+        }
+        for (int r = 0; r < N; ++r) {
+            for (int s = 0; s < N; ++s) A[(size_t)r * N + s] = H[(size_t)r * N + s];
+            A[(size_t)r * N + r] += lambda * H[(size_t)r * N + r];
+            rhs[r] = -g[r];
+        }
+        int ok = chol_solve_n(N, A, rhs, delta) == 0;
+        double Fn = INFINITY, pred = INFINITY;
+        if (ok) {
+            for (int r = 0; r < N; ++r) trial[r] = theta[r] + delta[r];
+            Fn = orc_block_objective(o, nb, z, vy, vx, trial, rho_x, rho_y);
+            double gd = 0.0, dd = 0.0;
+            for (int r = 0; r < N; ++r) {
+                gd += g[r] * delta[r];
+                dd += H[(size_t)r * N + r] * delta[r] * delta[r];
+            }
+            pred = 0.5 * (lambda * dd - gd);
+        }
+        if (ok && isfinite(Fn) && (Fn < F || pred <= ORC_TIE * fres)) {
+            memcpy(theta, trial, sizeof(double) * N);
+            F = Fn;
+            lambda = fmax(lambda / 10.0, ORC_LAMBDA_MIN);
+            ++accepted;
+        } else {
+            lambda = fmin(lambda * 10.0, ORC_LAMBDA_MAX);
+        }
+        if (f_trace) f_trace[it + 1] = F;
+    }
+    free(g); free(H); free(A); free(rhs); free(delta); free(trial);
+    return accepted;
+}
+
+/* ADMM iterations with block local updates.  Blocks: nblk, blk_off[nblk+1]
+ * offsets into blk_obs (observation indices of each block in order),
+ * blk_cam[nblk] the block's camera.  State: ycopy/ydual [nblk][9] (the
+ * block's camera copy and scaled dual), xcopy/xdual [L][3] (per observation
+ * point copy and dual).  One iteration:
+ *   1. local update of every block (Eqs. 14-15), started at its copies;
+ *   2. consensus: camera = mean over its blocks of ycopy + ydual (ascending
+ *      block), point = mean over its observations of xcopy + xdual
+ *      (ascending observation);
+ *   3. scaled dual updates u += copy - consensus;
+ *   4. r_pri over all copies, r_dual = |rho (consensus change)| counted once
+ *      per copy (a camera has as many copies as blocks);
+ *   5. optional residual balancing, duals rescaled by old / new rho.
+ * trace (optional, 4 per iteration).  Returns 0, or -1 on bad input. */
+int orc_admm_iterate_blocked(int64_t L, int32_t m, int32_t n, const int32_t *obs_cam, const int32_t *obs_pt,
+                             const double *obs_uv, int32_t nblk, const int64_t *blk_off, const int64_t *blk_obs,
+                             const int32_t *blk_cam, double *cons_y, double *cons_x, double *ycopy, double *ydual,
+                             double *xcopy, double *xdual, double *rho, const orc_opts *o, int32_t n_iters,
+                             double *trace)
+{
+    double *cnt_y = calloc((size_t)m, sizeof(double)), *cnt_x = calloc((size_t)n, sizeof(double));
+    double *sum_y = malloc(sizeof(double) * 9 * (size_t)m), *sum_x = malloc(sizeof(double) * 3 * (size_t)n);
+    double *old_y = malloc(sizeof(double) * 9 * (size_t)m), *old_x = malloc(sizeof(double) * 3 * (size_t)n);
+    int64_t maxb = 0;
+    for (int32_t b = 0; b < nblk; ++b)
+        if (blk_off[b + 1] - blk_off[b] > maxb) maxb = blk_off[b + 1] - blk_off[b];
+    double *z = malloc(sizeof(double) * 2 * (size_t)(maxb + 1)), *vx = malloc(sizeof(double) * 3 * (size_t)(maxb + 1));
+    double *theta = malloc(sizeof(double) * (9 + 3 * (size_t)(maxb + 1)));
+    if (!cnt_y || !cnt_x || !sum_y || !sum_x || !old_y || !old_x || !z || !vx || !theta) return -1;
+    for (int32_t b = 0; b < nblk; ++b) {
+        if (blk_cam[b] < 0 || blk_cam[b] >= m) return -1;
+        cnt_y[blk_cam[b]] += 1.0;
+        for (int64_t q = blk_off[b]; q < blk_off[b + 1]; ++q)
+            if (obs_cam[blk_obs[q]] != blk_cam[b]) return -1;
+    }
+    for (int64_t k = 0; k < L; ++k) {
+        if (obs_pt[k] < 0 || obs_pt[k] >= n) return -1;
+        cnt_x[obs_pt[k]] += 1.0;
+    }
+    for (int32_t it = 0; it < n_iters; ++it) {
+        const double rx = rho[0], ry = rho[1];
+        /* 1. block local updates */
+        for (int32_t b = 0; b < nblk; ++b) {
+            const int j = blk_cam[b];
+            const int nb = (int)(blk_off[b + 1] - blk_off[b]);
+            double vy[9];
+            for (int c = 0; c < 9; ++c) {
+                vy[c] = cons_y[9 * j + c] - ydual[9 * (size_t)b + c];
+                theta[c] = ycopy[9 * (size_t)b + c];
+            }
+            for (int q = 0; q < nb; ++q) {
+                const int64_t k = blk_obs[blk_off[b] + q];
+                const int i = obs_pt[k];
+                z[2 * q] = obs_uv[2 * k];
+                z[2 * q + 1] = obs_uv[2 * k + 1];
+                for (int c = 0; c < 3; ++c) {
+                    vx[3 * q + c] = cons_x[3 * i + c] - xdual[3 * k + c];
+                    theta[9 + 3 * q + c] = xcopy[3 * k + c];
+                }
+            }
+            orc_block_local_solve(o, nb, z, vy, vx, theta, rx, ry, o->lm_steps, NULL);
+            for (int c = 0; c < 9; ++c) ycopy[9 * (size_t)b + c] = theta[c];
+            for (int q = 0; q < nb; ++q) {
+                const int64_t k = blk_obs[blk_off[b] + q];
+                for (int c = 0; c < 3; ++c) xcopy[3 * k + c] = theta[9 + 3 * q + c];
+            }
+        }
+        /* 2. consensus */
+        memcpy(old_y, cons_y, sizeof(double) * 9 * (size_t)m);
+        memcpy(old_x, cons_x, sizeof(double) * 3 * (size_t)n);
+        memset(sum_y, 0, sizeof(double) * 9 * (size_t)m);
+        memset(sum_x, 0, sizeof(double) * 3 * (size_t)n);
+        for (int32_t b = 0; b < nblk; ++b)
+            for (int c = 0; c < 9; ++c) sum_y[9 * blk_cam[b] + c] += ycopy[9 * (size_t)b + c] + ydual[9 * (size_t)b + c];
+        for (int64_t k = 0; k < L; ++k)
+            for (int c = 0; c < 3; ++c) sum_x[3 * obs_pt[k] + c] += xcopy[3 * k + c] + xdual[3 * k + c];
+        for (int j = 0; j < m; ++j)
+            for (int c = 0; c < 9; ++c) cons_y[9 * j + c] = sum_y[9 * j + c] / cnt_y[j];
+        for (int i = 0; i < n; ++i)
+            for (int c = 0; c < 3; ++c) cons_x[3 * i + c] = sum_x[3 * i + c] / cnt_x[i];
+        /* 3. duals, 4. residuals */
+        double pri2 = 0.0;
+        for (int32_t b = 0; b < nblk; ++b)
+            for (int c = 0; c < 9; ++c) {
+                double d = ycopy[9 * (size_t)b + c] - cons_y[9 * blk_cam[b] + c];
+                ydual[9 * (size_t)b + c] += d;
+                pri2 += d * d;
+            }
+        for (int64_t k = 0; k < L; ++k)
+            for (int c = 0; c < 3; ++c) {
+                double d = xcopy[3 * k + c] - cons_x[3 * obs_pt[k] + c];
+                xdual[3 * k + c] += d;
+                pri2 += d * d;
+            }
+        double dy2 = 0.0, dx2 = 0.0;
+        for (int j = 0; j < m; ++j) {
+            double s = 0.0;
+            for (int c = 0; c < 9; ++c) { double d = cons_y[9 * j + c] - old_y[9 * j + c]; s += d * d; }
+            dy2 += cnt_y[j] * s;
+        }
+        for (int i = 0; i < n; ++i) {
+            double s = 0.0;
+            for (int c = 0; c < 3; ++c) { double d = cons_x[3 * i + c] - old_x[3 * i + c]; s += d * d; }
+            dx2 += cnt_x[i] * s;
+        }
+        double r_pri = sqrt(pri2), r_dual = sqrt(rx * rx * dx2 + ry * ry * dy2);
+        if (trace) {
+            trace[4 * it + 0] = r_pri; trace[4 * it + 1] = r_dual;
+            trace[4 * it + 2] = rx; trace[4 * it + 3] = ry;
+        }
+        /* 5. residual balancing */
+        if (o->rho_balancing) {
+            double fac = 1.0;
+            if (r_pri > o->rb_mu * r_dual) fac = o->rb_tau;
+            else if (r_dual > o->rb_mu * r_pri) fac = 1.0 / o->rb_tau;
+            if (fac != 1.0) {
+                double nx = fmin(fmax(rx * fac, o->rho_min), o->rho_max);
+                double ny = fmin(fmax(ry * fac, o->rho_min), o->rho_max);
+                double sx = rx / nx, sy = ry / ny;
+                for (int64_t q = 0; q < 9 * (int64_t)nblk; ++q) ydual[q] *= sy;
+                for (int64_t q = 0; q < 3 * L; ++q) xdual[q] *= sx;
+                rho[0] = nx; rho[1] = ny;
+            }
+        }
+    }
+    free(cnt_y); free(cnt_x); free(sum_y); free(sum_x); free(old_y); free(old_x); free(z); free(vx); free(theta);
+    return 0;
+}

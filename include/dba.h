@@ -78,11 +78,18 @@ typedef struct dba_options {
     int32_t use_graph;        /* 1: replay iterations from a captured hipGraph */
     int32_t block_waves;      /* local-solve workgroup size in wavefronts (1,2,4,8); 0: autotune */
     int32_t persistent;       /* local solve: 1 persistent grid, 0 one workgroup per tile, -1 autotune */
+    int32_t camera_blocks;    /* 0: one local problem per observation (Eqs. 9-13);
+                                 1: generalised local updates (Sec. 3.1.4, Eqs. 14-15): the
+                                 observations of a camera, in ascending point order, form blocks
+                                 of up to 64 that share one camera copy; each block's problem
+                                 (9 + 3 x observations unknowns) is one local solve; not with the
+                                 learned start */
 } dba_options;
 
 /* Fills *opt with the defaults: device 0, NULL stream, FP64, Huber 2 px,
  * rho 1, no balancing (mu 10, tau 2, clamps 1e-6..1e6), 5 LM steps,
- * lambda0 1e-3, plain start, 2 learned steps, graphs on, autotune. */
+ * lambda0 1e-3, plain start, 2 learned steps, graphs on, autotune, one
+ * local problem per observation. */
 int dba_default_options(dba_options *opt);
 
 /* Creates a handle on opt->device.  *out receives the handle. */

@@ -1,0 +1,284 @@
+// block_device.h -- generalised local updates (Sec. 3.1.4, Eqs. 14-15) on
+// one wavefront: the local problem of a 64-slot camera chunk, one camera copy
+// y (9) shared by the chunk and one point copy x_k (3) per observation lane,
+//   F = sum_k [phi(|z_k - pi(y, x_k)|^2) + rho_x/2 |x_k - vx_k|^2]
+//       + rho_y/2 |y - vy|^2,
+// minimised by robust LM with the rules of the per-observation solve (IRLS
+// weights, Marquardt damping lambda diag(H), exactly S steps, acceptance on
+// a decrease of F or on a predicted decrease below F's rounding resolution).
+// The normal equations are reduced to the camera by the Schur complement on
+// the points: each lane forms its point block and its contribution to the
+// 9x9 camera system, a fixed-order all-reduce sums the contributions, every
+// lane factors the 9x9 system (LDL^T) and back-solves its own point.
+#pragma once
+#include "dba_device.h"
+
+namespace dba {
+namespace dev {
+
+// Packed upper triangle of a symmetric 9x9 matrix: index of (i, j), i <= j.
+__host__ __device__ constexpr int sym9(int i, int j) { return i * 9 - i * (i - 1) / 2 + (j - i); }
+
+// Sums v[0..N) (N <= 64) over the wave in a fixed order and returns the sums
+// in every lane.  Reduce-scatter: at the level with offset o, lanes whose
+// bit o is clear keep the first half of their values, the others the second
+// half, each adding its partner's copy; after six levels lane l holds the
+// total of value l, which goes through 64 entries of LDS to every lane.
+template <typename T, int N>
+__device__ __forceinline__ void wave_allreduce(const T *v, T *out, T *lds, int lane)
+{
+    static_assert(N <= 64, "at most 64 values");
+    T a[64];
+#pragma unroll
+    for (int j = 0; j < 64; ++j) a[j] = j < N ? v[j] : T(0);
+    T b[32], c[16], d[8], e[4], f[2];
+    rs_level<32>(a, b, lane & 32, 32);
+    rs_level<16>(b, c, lane & 16, 16);
+    rs_level<8>(c, d, lane & 8, 8);
+    rs_level<4>(d, e, lane & 4, 4);
+    rs_level<2>(e, f, lane & 2, 2);
+    T g;
+    rs_level<1>(f, &g, lane & 1, 1);
+    lds[lane] = g;
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+#pragma unroll
+    for (int j = 0; j < N; ++j) out[j] = lds[j];
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+template <typename T>
+__device__ __forceinline__ T wave_sum_t(T v)
+{
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1) v += __shfl_xor(v, off, 64);
+    return v;
+}
+
+// Solves the symmetric 9x9 system A x = b (packed upper A) by LDL^T; false
+// if a pivot is not positive and finite.
+template <typename R>
+__device__ __forceinline__ bool ldl9_solve(const R *A, const R *b, R *x)
+{
+    R L[45], D[9];
+    bool ok = true;
+#pragma unroll
+    for (int j = 0; j < 9; ++j) {
+        R dj = A[sym9(j, j)];
+#pragma unroll
+        for (int k = 0; k < j; ++k) dj -= L[sym9(k, j)] * L[sym9(k, j)] * D[k];
+        ok = ok && (dj > R(0)) && (dj < Num<R>::inf);
+        D[j] = dj;
+        const R idj = Num<R>::rcp(dj);
+#pragma unroll
+        for (int i = j + 1; i < 9; ++i) {
+            R s = A[sym9(j, i)];
+#pragma unroll
+            for (int k = 0; k < j; ++k) s -= L[sym9(k, i)] * L[sym9(k, j)] * D[k];
+            L[sym9(j, i)] = s * idj;   // L(i, j) stored at (j, i)
+        }
+    }
+    R y[9];
+#pragma unroll
+    for (int i = 0; i < 9; ++i) {
+        R s = b[i];
+#pragma unroll
+        for (int k = 0; k < i; ++k) s -= L[sym9(k, i)] * y[k];
+        y[i] = s;
+    }
+#pragma unroll
+    for (int i = 8; i >= 0; --i) {
+        R s = y[i] * Num<R>::rcp(D[i]);
+#pragma unroll
+        for (int k = i + 1; k < 9; ++k) s -= L[sym9(i, k)] * x[k];
+        x[i] = s;
+    }
+    return ok;
+}
+
+// One lane's part of the block objective: phi + rho_x/2 |x - vx|^2 at the
+// projection o of (y, x); +inf when the depth is <= 1e-6.
+template <typename R>
+__device__ __forceinline__ R lane_objective(const Proj<R> &o, const R *th, const R *vx, R z0, R z1, R rx, int kind,
+                                            R lp)
+{
+    if (!(o.depth > R(1e-6))) return Num<R>::inf;
+    const R e0 = z0 - o.pu, e1 = z1 - o.pv;
+    R w;
+    const R phi = loss_phi<R>(kind, lp, e0 * e0 + e1 * e1, w);
+    const R d0 = th[9] - vx[0], d1 = th[10] - vx[1], d2 = th[11] - vx[2];
+    return phi + R(0.5) * rx * (d0 * d0 + d1 * d1 + d2 * d2);
+}
+
+template <typename R>
+__device__ __forceinline__ R camera_penalty(const R *y, const R *vy, R ry)
+{
+    R p = R(0);
+#pragma unroll
+    for (int i = 0; i < 9; ++i) {
+        const R d = y[i] - vy[i];
+        p += d * d;
+    }
+    return R(0.5) * ry * p;
+}
+
+// Block LM.  th = (y (uniform across the wave), x of this lane); inactive
+// lanes (no observation) take part in every reduction with zeros.
+template <typename R>
+__device__ __forceinline__ void block_lm(R *th, const R *vy, const R *vx, R z0, R z1, bool active, R rx, R ry,
+                                         int kind, R lp, int steps, R lam, R *lds, int lane)
+{
+    Proj<R> cur;
+    R fk = R(0);
+    if (active) {
+        cur = proj_core<R, true>(th);
+        fk = lane_objective<R>(cur, th, vx, z0, z1, rx, kind, lp);
+    }
+    R F = wave_sum_t<R>(fk) + camera_penalty<R>(th, vy, ry);
+    for (int it = 0; it < steps; ++it) {
+        // linearisation at (y, x_k)
+        R Cyy[45], ngy[9], W[27], ngx[3], hx[6];
+        R fr = R(0);
+#pragma unroll
+        for (int q = 0; q < 45; ++q) Cyy[q] = R(0);
+#pragma unroll
+        for (int q = 0; q < 9; ++q) ngy[q] = R(0);
+#pragma unroll
+        for (int q = 0; q < 27; ++q) W[q] = R(0);
+#pragma unroll
+        for (int q = 0; q < 3; ++q) ngx[q] = R(0);
+#pragma unroll
+        for (int q = 0; q < 6; ++q) hx[q] = R(0);
+        if (active) {
+            R J0[12], J1[12];
+            proj_jac<R>(cur, th, J0, J1);
+            const R e0 = z0 - cur.pu, e1 = z1 - cur.pv;
+            R w;
+            const R s2 = e0 * e0 + e1 * e1;
+            loss_phi<R>(kind, lp, s2, w);
+            const R c2 = R(2) * w;
+            fr = Num<R>::sqrt(s2) * (fabs(z0) + fabs(z1) + fabs(th[6]));
+#pragma unroll
+            for (int i = 0; i < 9; ++i) {
+                ngy[i] = c2 * (J0[i] * e0 + J1[i] * e1);
+#pragma unroll
+                for (int j = i; j < 9; ++j) Cyy[sym9(i, j)] = c2 * (J0[i] * J0[j] + J1[i] * J1[j]);
+#pragma unroll
+                for (int c = 0; c < 3; ++c) W[3 * i + c] = c2 * (J0[i] * J0[9 + c] + J1[i] * J1[9 + c]);
+            }
+#pragma unroll
+            for (int c = 0; c < 3; ++c) ngx[c] = c2 * (J0[9 + c] * e0 + J1[9 + c] * e1) - rx * (th[9 + c] - vx[c]);
+            hx[0] = rx + c2 * (J0[9] * J0[9] + J1[9] * J1[9]);
+            hx[1] = c2 * (J0[9] * J0[10] + J1[9] * J1[10]);
+            hx[2] = c2 * (J0[9] * J0[11] + J1[9] * J1[11]);
+            hx[3] = rx + c2 * (J0[10] * J0[10] + J1[10] * J1[10]);
+            hx[4] = c2 * (J0[10] * J0[11] + J1[10] * J1[11]);
+            hx[5] = rx + c2 * (J0[11] * J0[11] + J1[11] * J1[11]);
+        }
+        const R fres = F + wave_sum_t<R>(fr);
+        // damped point block and its inverse (symmetric 3x3, adjugate)
+        const R a00 = hx[0] * (R(1) + lam), a11 = hx[3] * (R(1) + lam), a22 = hx[5] * (R(1) + lam);
+        const R a01 = hx[1], a02 = hx[2], a12 = hx[4];
+        const R m00 = a11 * a22 - a12 * a12, m01 = a02 * a12 - a01 * a22, m02 = a01 * a12 - a02 * a11;
+        const R det = a00 * m00 + a01 * m01 + a02 * m02;
+        bool okx = true;
+        R B[6] = {R(0), R(0), R(0), R(0), R(0), R(0)};
+        if (active) {
+            okx = (det > R(0)) && (det < Num<R>::inf);
+            const R idet = Num<R>::rcp(det);
+            B[0] = m00 * idet;
+            B[1] = m01 * idet;
+            B[2] = m02 * idet;
+            B[3] = (a00 * a22 - a02 * a02) * idet;
+            B[4] = (a01 * a02 - a00 * a12) * idet;
+            B[5] = (a00 * a11 - a01 * a01) * idet;
+        }
+        // Schur contribution: P = W B, C - P W^T, ngy - P ngx
+        R red[63];
+        {
+            R P[27];
+#pragma unroll
+            for (int i = 0; i < 9; ++i) {
+                const R w0 = W[3 * i], w1 = W[3 * i + 1], w2 = W[3 * i + 2];
+                P[3 * i] = w0 * B[0] + w1 * B[1] + w2 * B[2];
+                P[3 * i + 1] = w0 * B[1] + w1 * B[3] + w2 * B[4];
+                P[3 * i + 2] = w0 * B[2] + w1 * B[4] + w2 * B[5];
+            }
+#pragma unroll
+            for (int i = 0; i < 9; ++i) {
+#pragma unroll
+                for (int j = i; j < 9; ++j)
+                    red[sym9(i, j)] = Cyy[sym9(i, j)] -
+                                      (P[3 * i] * W[3 * j] + P[3 * i + 1] * W[3 * j + 1] + P[3 * i + 2] * W[3 * j + 2]);
+                red[45 + i] = Cyy[sym9(i, i)];
+                red[54 + i] = ngy[i] - (P[3 * i] * ngx[0] + P[3 * i + 1] * ngx[1] + P[3 * i + 2] * ngx[2]);
+            }
+        }
+        R sum[63];
+        wave_allreduce<R, 63>(red, sum, lds, lane);
+        // camera system: S = A_yy - sum_k W B W^T, rhs = ng_y - sum_k W B ng_x
+        R Sy[45], ry9[9], dy[9];
+#pragma unroll
+        for (int q = 0; q < 45; ++q) Sy[q] = sum[q];
+#pragma unroll
+        for (int i = 0; i < 9; ++i) {
+            const R hd = ry + sum[45 + i];                      // diag(H_yy)
+            Sy[sym9(i, i)] += ry + lam * hd;
+            ry9[i] = sum[54 + i] - ry * (th[i] - vy[i]);        // includes the camera penalty
+        }
+        const bool oky = ldl9_solve<R>(Sy, ry9, dy);
+        const bool ok = oky && (__ballot(!okx) == 0ull);
+        // point steps and the predicted decrease
+        R dx[3] = {R(0), R(0), R(0)};
+        R pk = R(0);
+        if (active) {
+            R t[3];
+#pragma unroll
+            for (int c = 0; c < 3; ++c)
+                t[c] = ngx[c] - (W[c] * dy[0] + W[3 + c] * dy[1] + W[6 + c] * dy[2] + W[9 + c] * dy[3] +
+                                 W[12 + c] * dy[4] + W[15 + c] * dy[5] + W[18 + c] * dy[6] + W[21 + c] * dy[7] +
+                                 W[24 + c] * dy[8]);
+            dx[0] = B[0] * t[0] + B[1] * t[1] + B[2] * t[2];
+            dx[1] = B[1] * t[0] + B[3] * t[1] + B[4] * t[2];
+            dx[2] = B[2] * t[0] + B[4] * t[1] + B[5] * t[2];
+            pk = ngx[0] * dx[0] + ngx[1] * dx[1] + ngx[2] * dx[2] +
+                 lam * (hx[0] * dx[0] * dx[0] + hx[3] * dx[1] * dx[1] + hx[5] * dx[2] * dx[2]);
+        }
+        R gdy = R(0), ddy = R(0);
+#pragma unroll
+        for (int i = 0; i < 9; ++i) {
+            gdy += ry9[i] * dy[i];
+            ddy += (ry + sum[45 + i]) * dy[i] * dy[i];
+        }
+        const R pred = R(0.5) * (wave_sum_t<R>(pk) + gdy + lam * ddy);
+        // trial point and its objective
+        R tr[12];
+#pragma unroll
+        for (int i = 0; i < 9; ++i) tr[i] = th[i] + dy[i];
+#pragma unroll
+        for (int c = 0; c < 3; ++c) tr[9 + c] = th[9 + c] + dx[c];
+        Proj<R> nxt;
+        R fn = R(0);
+        if (active && ok) {
+            nxt = proj_core<R, true>(tr);
+            fn = lane_objective<R>(nxt, tr, vx, z0, z1, rx, kind, lp);
+        }
+        const bool bad = __ballot(!(fn < Num<R>::inf)) != 0ull;
+        const R Fn = (ok && !bad) ? wave_sum_t<R>(fn) + camera_penalty<R>(tr, vy, ry) : Num<R>::inf;
+        if (Fn < Num<R>::inf && (Fn < F || pred <= Num<R>::tie * fres)) {
+#pragma unroll
+            for (int i = 0; i < 12; ++i) th[i] = tr[i];
+            if (active) cur = nxt;
+            F = Fn;
+            lam = lam_down<R>(lam);
+        } else {
+            lam = lam_up<R>(lam);
+        }
+    }
+}
+
+}  // namespace dev
+}  // namespace dba

@@ -346,13 +346,13 @@ __device__ __forceinline__ double wave_sum(double v)
 // One level of a reduce-scatter over the wave: lanes whose bit `off` is clear
 // keep the first H of the 2H values, the others the last H, each adding its
 // partner's copy.  Fixed pairing, so the summation order never changes.
-template <int H>
-__device__ __forceinline__ void rs_level(const double *in, double *out, bool upper, int off)
+template <int H, typename T>
+__device__ __forceinline__ void rs_level(const T *in, T *out, bool upper, int off)
 {
 #pragma unroll
     for (int j = 0; j < H; ++j) {
-        const double keep = upper ? in[H + j] : in[j];
-        const double send = upper ? in[j] : in[H + j];
+        const T keep = upper ? in[H + j] : in[j];
+        const T send = upper ? in[j] : in[H + j];
         out[j] = keep + __shfl_xor(send, off, 64);
     }
 }

@@ -197,6 +197,10 @@ int build_set(dba_handle *h, int np, const dba_problem_desc *probs, ProblemSet *
         c.balancing = h->opt.rho_balancing ? 1 : 0;
     }
     cam_chunk0[n_cams] = (int)n_chunks;
+    // camera copy per chunk (block local updates), starting at the initial camera
+    std::vector<R> copy_yc(9 * (size_t)n_chunks);
+    for (long long c = 0; c < n_chunks; ++c)
+        for (int i = 0; i < 9; ++i) copy_yc[9 * c + i] = (R)cons_y[(size_t)chunk_cam[c] * dba::kConsY + i];
 
     // device
     Buffers &B = ps->buf;
@@ -254,6 +258,15 @@ int build_set(dba_handle *h, int np, const dba_problem_desc *probs, ProblemSet *
     HIP_TRY(h, hipMemcpy(d_ctrl, ctrl.data(), np * sizeof(Ctrl), hipMemcpyHostToDevice));
     HIP_TRY(h, hipMemcpy(d_prob, ps->ranges.data(), np * sizeof(ProblemRange), hipMemcpyHostToDevice));
     HIP_TRY(h, hipMemset(d_cpart, 0, (size_t)n_chunks * dba::kCpart * sizeof(double)));
+    R *d_copy_yc;
+    double *d_dual_yc;
+    HIP_TRY(h, B.alloc(&d_copy_yc, 9 * (size_t)n_chunks));
+    HIP_TRY(h, B.alloc(&d_dual_yc, 9 * (size_t)n_chunks));
+    HIP_TRY(h, hipMemcpy(d_copy_yc, copy_yc.data(), 9 * (size_t)n_chunks * sizeof(R), hipMemcpyHostToDevice));
+    HIP_TRY(h, hipMemset(d_dual_yc, 0, 9 * (size_t)n_chunks * sizeof(double)));
+    A.camera_blocks = h->opt.camera_blocks ? 1 : 0;
+    A.copy_yc = d_copy_yc;
+    A.dual_yc = d_dual_yc;
 
     A.n_slots = S;
     A.uv = d_uv; A.pslot = d_pslot; A.ptid = d_ptid;
@@ -279,6 +292,7 @@ hipError_t launch_local_sel(dba_handle *h, const DevArrays<R> &A, int bw, int pe
         if (h->start == DBA_START_LEARNED)
             return dba::launch_local_learned(A, h->sp, h->mlp->params(), pers, h->n_cu, h->stream);
     }
+    if (h->opt.camera_blocks) return dba::launch_local_block<R>(A, h->sp, bw, pers, h->n_cu, h->stream);
     return dba::launch_local<R>(A, h->sp, bw, pers, h->n_cu, h->stream);
 }
 
@@ -456,6 +470,7 @@ int dba_default_options(dba_options *o)
     o->use_graph = 1;
     o->block_waves = 0;
     o->persistent = -1;
+    o->camera_blocks = 0;
     return DBA_OK;
 }
 
@@ -477,6 +492,8 @@ int dba_create(const dba_options *opt, dba_handle **out)
     if (o.start != DBA_START_PLAIN && o.start != DBA_START_LEARNED) return DBA_E_INVALID_ARG;
     if (o.start == DBA_START_LEARNED && o.precision != DBA_PREC_FP32_LOCAL) return DBA_E_INVALID_ARG;
     if (o.learned_lm_steps < 0 || o.learned_lm_steps > 64) return DBA_E_INVALID_ARG;
+    if (o.camera_blocks != 0 && o.camera_blocks != 1) return DBA_E_INVALID_ARG;
+    if (o.camera_blocks && o.start == DBA_START_LEARNED) return DBA_E_INVALID_ARG;
     dba_handle *h = new dba_handle();
     h->opt = o;
     h->fp32 = o.precision == DBA_PREC_FP32_LOCAL;

@@ -71,6 +71,9 @@ struct DevArrays {
     const int *ptid;
     R *copy_y;            // [9][n_slots]
     double *dual_y;       // [9][n_slots]
+    int camera_blocks;    // 1: one camera copy per chunk (block local updates)
+    R *copy_yc;           // [n_chunks][9] camera copy of the chunk (block local updates)
+    double *dual_yc;      // [n_chunks][9] its scaled dual
     const uint8_t *mask;  // [n_slots] evaluation mask
     const int *slot_orig; // [n_slots] observation index within its problem
     // records
@@ -136,6 +139,9 @@ hipError_t launch_local(const DevArrays<R> &a, const SolverParams &sp, int block
                         int persistent, int n_cu, hipStream_t s);
 hipError_t launch_local_learned(const DevArrays<float> &a, const SolverParams &sp, const MlpParams &mp,
                                 int persistent, int n_cu, hipStream_t s);
+template <typename R>
+hipError_t launch_local_block(const DevArrays<R> &a, const SolverParams &sp, int block_waves, int persistent,
+                              int n_cu, hipStream_t s);
 template <typename R>
 hipError_t launch_consensus(const DevArrays<R> &a, hipStream_t s);
 

@@ -22,6 +22,7 @@
 // schedule, so all schedules (and batched vs solo runs) are bitwise equal.
 #include "dba_device.h"
 #include "mlp_device.h"
+#include "block_device.h"
 
 namespace dba {
 namespace {
@@ -153,6 +154,80 @@ __device__ __forceinline__ void local_chunk(const DevArrays<R> &a, const SolverP
     wave_sum19_store(acc, a.cpart + (long long)c * kCpart, lane);
 }
 
+// Generalised local update of one 64-slot chunk (Sec. 3.1.4, Eqs. 14-15):
+// the chunk's observations share one camera copy (copy_yc / dual_yc, per
+// chunk) and keep one point copy each.  Deferred dual updates of both, the
+// block LM (block_lm), then the chunk's one camera copy goes to the camera
+// consensus: cpart = (y + u, y - previous consensus, |y - previous|^2).
+template <typename R>
+__device__ __forceinline__ void local_block(const DevArrays<R> &a, const SolverParams &sp, int c, int lane, R *lds)
+{
+    using R2 = typename Vec<R>::R2;
+    using R4 = typename Vec<R>::R4;
+    const int J = a.chunk_cam[c];
+    const Ctrl *ct = a.ctrl + a.cam_prob[J];
+    const double rho_x = ct->rho_x, rho_y = ct->rho_y;
+    const double rat_x = ct->ratio_x, rat_y = ct->ratio_y;
+    const int pending = ct->pending;
+    const long long s = (long long)c * kChunk + lane;
+    const int ps = a.pslot[s];
+    const bool active = ps >= 0;
+    double cy[9], uy[9];
+    R th[12], vy[9], vx[3] = {R(0), R(0), R(0)};
+#pragma unroll
+    for (int i = 0; i < 9; ++i) {
+        cy[i] = a.cons_y[(long long)J * kConsY + i];
+        th[i] = a.copy_yc[(long long)c * 9 + i];
+        uy[i] = a.dual_yc[(long long)c * 9 + i];
+        if (pending) uy[i] = (uy[i] + ((double)th[i] - cy[i])) * rat_y;
+        vy[i] = (R)(cy[i] - uy[i]);
+    }
+    if (pending && lane == 0)
+#pragma unroll
+        for (int i = 0; i < 9; ++i) a.dual_yc[(long long)c * 9 + i] = uy[i];
+    R2 z;
+    z.x = R(0);
+    z.y = R(0);
+    th[9] = th[10] = th[11] = R(0);
+    if (active) {
+        const double4 cx = a.cons_x[a.ptid[s]];
+        const double cxs[3] = {cx.x, cx.y, cx.z};
+        z = a.uv[s];
+        const R4 xr = a.xrec[ps];
+        const double4 ur = a.urec[ps];
+        th[9] = xr.x; th[10] = xr.y; th[11] = xr.z;
+        double u[3] = {ur.x, ur.y, ur.z};
+        if (pending) {
+#pragma unroll
+            for (int i = 0; i < 3; ++i) u[i] = (u[i] + ((double)th[9 + i] - cxs[i])) * rat_x;
+            a.urec[ps] = make_double4(u[0], u[1], u[2], 0.0);
+        }
+#pragma unroll
+        for (int i = 0; i < 3; ++i) vx[i] = (R)(cxs[i] - u[i]);
+    }
+    block_lm<R>(th, vy, vx, z.x, z.y, active, (R)rho_x, (R)rho_y, sp.loss, (R)sp.loss_param, sp.lm_steps,
+                (R)sp.lambda0, lds, lane);
+    if (active) {
+        R4 xo;
+        xo.x = th[9]; xo.y = th[10]; xo.z = th[11]; xo.w = R(0);
+        a.xrec[ps] = xo;
+    }
+    if (lane == 0) {
+        double *o = a.cpart + (long long)c * kCpart;
+        double q = 0.0;
+#pragma unroll
+        for (int i = 0; i < 9; ++i) {
+            a.copy_yc[(long long)c * 9 + i] = th[i];
+            const double t = (double)th[i];
+            const double dd = t - cy[i];
+            o[i] = t + uy[i];
+            o[9 + i] = dd;
+            q += dd * dd;
+        }
+        o[18] = q;
+    }
+}
+
 // FP32: up to 8 waves per workgroup; FP64 needs more than 256 VGPRs, so at
 // most 4 waves (one per SIMD) per workgroup.
 template <typename R> struct LocalBound { static constexpr int threads = 512; };
@@ -179,6 +254,17 @@ __global__ __launch_bounds__(LocalBound<R>::threads) void k_local(DevArrays<R> a
     int c0, c1;
     chunk_range(a.n_chunks, wpb, persistent, c0, c1);
     for (int c = c0 + wave; c < c1; c += wpb) local_chunk<R, false>(a, sp, c, lane);
+}
+
+template <typename R>
+__global__ __launch_bounds__(LocalBound<R>::threads) void k_local_block(DevArrays<R> a, SolverParams sp,
+                                                                        int persistent)
+{
+    __shared__ R lds[LocalBound<R>::threads / 64][64];
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, wpb = blockDim.x >> 6;
+    int c0, c1;
+    chunk_range(a.n_chunks, wpb, persistent, c0, c1);
+    for (int c = c0 + wave; c < c1; c += wpb) local_block<R>(a, sp, c, lane, lds[wave]);
 }
 
 // Learned start: the workgroup's waves share the staged weights (one copy
@@ -290,7 +376,9 @@ __global__ __launch_bounds__(256) void k_consensus(DevArrays<R> a, int pt_blocks
             double S[19];
 #pragma unroll
             for (int i = 0; i < 19; ++i) S[i] = csum[w][i];
-            const double M = (double)a.cam_count[J];
+            // copies of the camera: one per observation, or one per chunk
+            // with block local updates
+            const double M = a.camera_blocks ? (double)(k1 - k0) : (double)a.cam_count[J];
             double *cy = a.cons_y + (long long)J * kConsY;
             double dd = 0.0, dS = 0.0;
 #pragma unroll
@@ -454,8 +542,9 @@ __global__ __launch_bounds__(256) void k_materialize(DevArrays<R> a, int p, doub
     for (int i = 0; i < 12; ++i) {
         double cp, u, cs, rat;
         if (i < 9) {
-            cp = (double)a.copy_y[i * S + s];
-            u = a.dual_y[i * S + s];
+            const long long cq = (s / kChunk) * 9 + i;
+            cp = a.camera_blocks ? (double)a.copy_yc[cq] : (double)a.copy_y[i * S + s];
+            u = a.camera_blocks ? a.dual_yc[cq] : a.dual_y[i * S + s];
             cs = a.cons_y[(long long)J * kConsY + i];
             rat = ct.ratio_y;
         } else {
@@ -514,6 +603,25 @@ hipError_t launch_consensus(const DevArrays<R> &a, hipStream_t s)
 }
 
 template <typename R>
+hipError_t launch_local_block(const DevArrays<R> &a, const SolverParams &sp, int block_waves, int persistent,
+                              int n_cu, hipStream_t s)
+{
+    if (64 * block_waves > LocalBound<R>::threads) block_waves = LocalBound<R>::threads / 64;
+    const int threads = 64 * block_waves;
+    int grid;
+    if (persistent) {
+        grid = n_cu * (8 / block_waves > 0 ? 8 / block_waves : 1);
+        const int need = (a.n_chunks + block_waves - 1) / block_waves;
+        if (grid > need) grid = need;
+    } else {
+        grid = (a.n_chunks + block_waves - 1) / block_waves;
+    }
+    if (grid < 1) grid = 1;
+    hipLaunchKernelGGL(k_local_block<R>, dim3(grid), dim3(threads), 0, s, a, sp, persistent);
+    return hipGetLastError();
+}
+
+template <typename R>
 hipError_t launch_norms(const DevArrays<R> &a, hipStream_t s)
 {
     hipLaunchKernelGGL(k_norms<R>, dim3(a.n_problems), dim3(kNormThreads), 0, s, a);
@@ -542,6 +650,8 @@ hipError_t launch_materialize(const DevArrays<R> &a, int problem, double *copies
 #define DBA_INSTANTIATE(R)                                                                        \
     template hipError_t launch_local<R>(const DevArrays<R> &, const SolverParams &, int, int, int, \
                                         hipStream_t);                                             \
+    template hipError_t launch_local_block<R>(const DevArrays<R> &, const SolverParams &, int, int, int, \
+                                              hipStream_t);                                       \
     template hipError_t launch_consensus<R>(const DevArrays<R> &, hipStream_t);                   \
     template hipError_t launch_norms<R>(const DevArrays<R> &, hipStream_t);                       \
     template hipError_t launch_eval<R>(const DevArrays<R> &, const SolverParams &, hipStream_t);  \

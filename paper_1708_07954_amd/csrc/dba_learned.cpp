@@ -104,6 +104,8 @@ int dba_set_start(dba_handle *h, int32_t start, int32_t learned_lm_steps)
     if (learned_lm_steps < 0 || learned_lm_steps > 64) return fail(h, DBA_E_INVALID_ARG, "bad learned_lm_steps");
     if (start == DBA_START_LEARNED && !h->fp32)
         return fail(h, DBA_E_INVALID_ARG, "the learned start runs with FP32 local solves");
+    if (start == DBA_START_LEARNED && h->opt.camera_blocks)
+        return fail(h, DBA_E_INVALID_ARG, "the learned start is for one observation per local problem");
     h->start = start;
     h->sp.learned_steps = learned_lm_steps;
     drop_graphs(h);

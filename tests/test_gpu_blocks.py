@@ -1,0 +1,135 @@
+"""GPU parity of the generalised local updates (Sec. 3.1.4, Eqs. 14-15) --
+one camera copy per block of up to 64 observations of a camera -- against
+the oracle's dense block solver (oracle.BlockADMM) on the same seeded
+inputs: FP64 within 1e-9 on every parameter, FP32 within 1e-3 and RMSE
+within 0.5 %, the per-observation state, block sizes around the 64-slot
+chunk, schedule invariance, batched = solo, and the option's validation."""
+import numpy as np
+import pytest
+
+import oracle
+from paper_1708_07954_amd import binding
+from scenes import make_config2, make_ring_scene, make_sphere_scene
+from _util import param_rel_err, state_rel_err
+
+pytestmark = pytest.mark.gpu
+
+CASES = {
+    "ring_huber": (lambda: make_ring_scene(seed=5, n_cams=5, n_points=150), dict(loss="huber", loss_param=2.0,
+                                                                                 rho=1e4), 15),
+    "ring_l2": (lambda: make_ring_scene(seed=6, n_cams=4, n_points=70), dict(loss="l2", loss_param=1.0, rho=1e3), 15),
+    "sphere_t": (lambda: make_sphere_scene(seed=8, n_cams=20, n_points=700),
+                 dict(loss="student_t", loss_param=4.0, rho=1e3), 12),
+    "traj_balancing": (lambda: make_config2(n_cams=60, n_points=800),
+                       dict(loss="huber", loss_param=2.0, rho=1e4, rho_balancing=True, rho_min=1e4, rho_max=1e7), 12),
+}
+
+
+def oracle_blocks(sc, iters, *, rho_min=1e-6, rho_max=1e6, **kw):
+    b = oracle.BlockADMM(oracle.Problem.from_scene(sc), sc.cams_init, sc.points_init, block=64, **kw)
+    b.opts.rho_min, b.opts.rho_max = rho_min, rho_max
+    tr = b.iterate(iters)
+    return b, tr
+
+
+def gpu_blocks(sc, iters, **kw):
+    s = binding.Solver(camera_blocks=True, **kw).set_scene(sc)
+    s.iterate(iters)
+    return s
+
+
+@pytest.mark.parametrize("case", sorted(CASES))
+def test_blocks_fp64_parity(case):
+    make, kw, iters = CASES[case]
+    sc = make()
+    b, tr = oracle_blocks(sc, iters, **kw)
+    s = gpu_blocks(sc, iters, precision="fp64", **kw)
+    cams, pts = s.params()
+    err = param_rel_err(cams, pts, b.cons_y, b.cons_x)
+    r = s.residuals(want_rmse=True)
+    print(case, "blocks", b.n_blocks, "max rel err", err, "r_pri", r["primal"], tr[-1, 0], "rmse", r["rmse"],
+          b.stats()[0])
+    assert err < 1e-9
+    assert r["primal"] == pytest.approx(tr[-1, 0], rel=1e-6)
+    assert r["dual"] == pytest.approx(tr[-1, 1], rel=1e-6)
+    assert r["next_rho_x"] == b.rho[0]
+    s.close()
+
+
+@pytest.mark.parametrize("case", ["ring_huber", "sphere_t", "traj_balancing"])
+def test_blocks_fp32_parity(case):
+    make, kw, iters = CASES[case]
+    sc = make()
+    b, _ = oracle_blocks(sc, iters, **kw)
+    s = gpu_blocks(sc, iters, precision="fp32", **kw)
+    cams, pts = s.params()
+    err = param_rel_err(cams, pts, b.cons_y, b.cons_x)
+    r = s.residuals(want_rmse=True)
+    print(case, "fp32 blocks max rel err", err, "rmse", r["rmse"], b.stats()[0])
+    assert err < 1e-3
+    assert abs(r["rmse"] - b.stats()[0]) < 5e-3 * b.stats()[0]
+    s.close()
+
+
+def test_blocks_state_parity():
+    make, kw, _ = CASES["ring_huber"]
+    sc = make()
+    b, _ = oracle_blocks(sc, 6, **kw)
+    s = gpu_blocks(sc, 6, precision="fp64", **kw)
+    copies, duals = s.state()
+    oc, od = b.copies()
+    assert state_rel_err(copies, oc) < 1e-9
+    assert state_rel_err(duals, od) < 1e-7
+    s.close()
+
+
+@pytest.mark.parametrize("n_cams,n_points", [(1, 1), (2, 63), (2, 64), (2, 65), (1, 129), (3, 5)])
+def test_block_sizes_around_the_chunk(n_cams, n_points):
+    sc = make_ring_scene(seed=12, n_cams=n_cams, n_points=n_points)
+    kw = dict(loss="huber", loss_param=2.0, rho=1e4)
+    b, _ = oracle_blocks(sc, 10, **kw)
+    for precision, tol in (("fp64", 1e-9), ("fp32", 1e-3)):
+        s = gpu_blocks(sc, 10, precision=precision, **kw)
+        cams, pts = s.params()
+        err = param_rel_err(cams, pts, b.cons_y, b.cons_x)
+        print(n_cams, n_points, precision, err)
+        assert err < tol
+        s.close()
+
+
+@pytest.mark.parametrize("precision", ["fp32", "fp64"])
+def test_blocks_every_schedule_is_bitwise_identical(precision):
+    sc = make_sphere_scene(seed=3, n_cams=12, n_points=400)
+    kw = dict(loss="student_t", loss_param=4.0, rho=1e3)
+    ref = None
+    for bw in (1, 2, 4, 8):
+        for pers in (0, 1):
+            s = binding.Solver(precision=precision, camera_blocks=True, block_waves=bw, persistent=pers,
+                               **kw).set_scene(sc)
+            s.iterate(5)
+            cams, pts = s.params()
+            s.close()
+            if ref is None:
+                ref = (cams, pts)
+            else:
+                assert np.array_equal(cams, ref[0]) and np.array_equal(pts, ref[1]), (bw, pers)
+
+
+def test_blocks_batched_equals_solo_bitwise():
+    scenes = [make_ring_scene(seed=30 + q, n_cams=3 + q, n_points=60 + 17 * q) for q in range(4)]
+    kw = dict(precision="fp32", loss="huber", loss_param=2.0, rho=1e4, camera_blocks=True)
+    s = binding.Solver(**kw).set_scenes(scenes)
+    s.iterate(6)
+    for q, sc in enumerate(scenes):
+        solo = binding.Solver(**kw).set_scene(sc)
+        solo.iterate(6)
+        a, b = s.params(q), solo.params()
+        assert np.array_equal(a[0], b[0]) and np.array_equal(a[1], b[1])
+        solo.close()
+    s.close()
+
+
+def test_blocks_reject_the_learned_start():
+    with pytest.raises(binding.DbaError) as e:
+        binding.Solver(precision="fp32", camera_blocks=True, start="learned")
+    assert e.value.status == "DBA_E_INVALID_ARG"

@@ -42,6 +42,11 @@ WORKLOADS = {
                        desc="1000 cameras on a random-walk trajectory, 200000 points, Zipf tracks 2..60, "
                             "5% outliers; Huber 2 px, rho 1e5 with residual balancing in [1e5, 1e7]; "
                             "FP32 local / FP64 consensus"),
+    "trajectory_blocks": dict(scene="config2", opts=dict(precision="fp32", loss="huber", loss_param=2.0, rho=1e5,
+                                                         rho_balancing=True, rho_min=1e5, rho_max=1e7,
+                                                         camera_blocks=True),
+                              desc="as trajectory, with block local updates: the observations of a camera form "
+                                   "blocks of up to 64 that share one camera copy (Sec. 3.1.4); 5 LM steps"),
     "sphere": dict(scene="config1", opts=dict(precision="fp32", loss="student_t", loss_param=4.0, rho=1e3),
                    desc="100 cameras on a sphere cap, 20000 points, 8..15 cameras per point; Student-t nu 4, "
                         "rho 1e3; FP32 local / FP64 consensus"),
@@ -66,7 +71,7 @@ def make_scenes(kind):
 
 def kernel_source_hash():
     h = hashlib.sha256()
-    for f in ("dba_kernels.hip", "dba_device.h", "dba_internal.h"):
+    for f in ("dba_kernels.hip", "dba_device.h", "dba_internal.h", "block_device.h", "mlp_device.h"):
         with open(os.path.join(ROOT, "paper_1708_07954_amd", "csrc", f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:12]
@@ -111,7 +116,8 @@ def oracle_target(workload):
 
 
 def time_to_rmse(binding, scene, opts, sched, target, max_iters=400, learned_steps=(1, 2, 3, 4, 5)):
-    """Wall time of plain 5-step LM and of the learned start (+ k LM steps)
+    """Wall time of plain 5-step LM, of block local updates (one camera copy
+    per 64 observations, Sec. 3.1.4) and of the learned start (+ k LM steps)
     to reach the oracle's final inlier RMSE (within 0.5 %).  The crossing
     iteration is found with per-iteration RMSE checks; a fresh run of exactly
     that many iterations is then timed (graph instantiation included)."""
@@ -170,6 +176,10 @@ def time_to_rmse(binding, scene, opts, sched, target, max_iters=400, learned_ste
     res = {"target_inlier_rmse": target, "reached_when_within": 0.005, "max_iterations": max_iters}
     res["plain_lm5"] = run(dict(opts, lm_steps=5, block_waves=sched["block_waves"], persistent=sched["persistent"]))
     print(f"[bench] time-to-RMSE plain: {res['plain_lm5']}", file=sys.stderr, flush=True)
+    for k in (1, 2, 5):
+        res[f"blocks_lm{k}"] = run(dict(opts, lm_steps=k, camera_blocks=True, block_waves=sched["block_waves"],
+                                        persistent=sched["persistent"]))
+        print(f"[bench] time-to-RMSE blocks, {k} LM steps: {res[f'blocks_lm{k}']}", file=sys.stderr, flush=True)
     params, norm, rep = warmstart.train_default()
     res["training"] = {"pairs": rep["pairs"], "collect_seconds": rep["collect_seconds"],
                        "train_seconds": rep["train_seconds"], "final_epoch_loss": rep["epoch_loss"][-1],
@@ -188,6 +198,9 @@ def time_to_rmse(binding, scene, opts, sched, target, max_iters=400, learned_ste
     res["mlp_flops_per_obs"] = MLP_FLOPS_PER_OBS
     res["bf16_mfma_peak_tflops"] = BF16_MFMA_PEAK_TFLOPS
     t_plain = res["plain_lm5"]["seconds"]
+    tb = min((res[f"blocks_lm{k}"]["seconds"] for k in (1, 2, 5) if res[f"blocks_lm{k}"]["seconds"] is not None),
+             default=None)
+    res["blocks_over_plain_time"] = (tb / t_plain) if (tb is not None and t_plain) else None
     best = min((res[f"learned_lm{k}"]["seconds"] for k in learned_steps
                 if res[f"learned_lm{k}"]["seconds"] is not None), default=None)
     res["learned_over_plain_time"] = (best / t_plain) if (best is not None and t_plain) else None
@@ -215,6 +228,58 @@ def profile_learned(binding, wl):
                       "train_seconds": rep["train_seconds"], "kernel_ms": kt,
                       "mlp_tflops_lower_bound": MLP_FLOPS_PER_OBS * sc.n_obs / (kt["learned"] * 1e-3) / 1e12}),
           flush=True)
+
+
+def block_baseline_and_parity(binding, sc, opts):
+    """Block local updates: the oracle's dense block solver timed on one core
+    over the first blocks of the workload (a bounded sample, about 15 s), and
+    the GPU after 3 iterations against the stored oracle run
+    (tests/golden/trajectory_blocks.npz) when it exists."""
+    import numpy as np
+    import oracle
+    o = dict(opts)
+    b = oracle.BlockADMM(oracle.Problem.from_scene(sc), sc.cams_init, sc.points_init, block=64, loss=o["loss"],
+                         loss_param=o["loss_param"], rho=o["rho"], lm_steps=o.get("lm_steps", 5))
+    allowed = os.sched_getaffinity(0)
+    core = min(allowed)
+    os.sched_setaffinity(0, {core})
+    n_obs, nb = 0, 0
+    try:
+        c0 = time.perf_counter()
+        while time.perf_counter() - c0 < 15.0 and nb < b.n_blocks:
+            ks = b.blk_obs[b.blk_off[nb]:b.blk_off[nb + 1]]
+            j = int(b.blk_cam[nb])
+            theta = np.concatenate([b.ycopy[nb], b.xcopy[ks].ravel()])
+            oracle.block_local_solve(b.opts, sc.obs_uv[ks], b.cons_y[j], b.cons_x[sc.obs_point[ks]], theta,
+                                     o["rho"], o["rho"], o.get("lm_steps", 5))
+            n_obs += ks.shape[0]
+            nb += 1
+        dt = time.perf_counter() - c0
+    finally:
+        os.sched_setaffinity(0, allowed)
+    base = {"value": n_obs / dt, "unit": "obs-updates/s", "cores": 1, "kind": "oracle",
+            "sample": f"block local solves of the first {nb} of {b.n_blocks} blocks ({n_obs} observations) of "
+                      f"the first iteration, dense (9 + 3 x 64)-unknown LM, single-threaded FP64 C oracle pinned "
+                      f"to core {core}, {dt:.1f} s on {cpu_model()}; consensus and duals (O(L), negligible) "
+                      f"not included"}
+    parity = None
+    path = os.path.join(ROOT, "tests", "golden", "trajectory_blocks.npz")
+    if os.path.exists(path):
+        g = np.load(path, allow_pickle=False)
+        if str(g["checksum"]) == sc.checksum():
+            sys.path.insert(0, os.path.join(ROOT, "tests"))
+            from _util import param_rel_err
+            chk = binding.Solver(**opts).set_scene(sc)
+            chk.iterate(int(g["iterations"]))
+            cams, pts = chk.params()
+            rmse = chk.residuals(want_rmse=True)["rmse"]
+            chk.close()
+            parity = {"iterations": int(g["iterations"]),
+                      "max_param_rel_err": param_rel_err(cams, pts[g["points_idx"]], g["cams"], g["points"]),
+                      "tolerance": 1e-3 if opts["precision"] == "fp32" else 1e-9,
+                      "rmse_rel_diff": abs(rmse - float(g["stats"][0])) / float(g["stats"][0]),
+                      "reference": "stored FP64 oracle run with block local updates"}
+    return base, parity
 
 
 def cpu_model():
@@ -305,14 +370,16 @@ def main():
 
     kt = {k: dict(avg_ms=(v[0] / v[1] if v[1] else None), launches=v[1]) for k, v in ktimes.items() if v[1]}
     local_ms = kt["local"]["avg_ms"]
-    flops = cost.local_flops_per_obs(opts.get("lm_steps", 5)) * L
+    blocks = bool(opts.get("camera_blocks"))
+    flops_per_obs = (cost.block_flops_per_obs if blocks else cost.local_flops_per_obs)(opts.get("lm_steps", 5))
+    flops = flops_per_obs * L
     achieved = flops / (local_ms * 1e-3) / 1e12
     traffic, traffic_src = recorded_traffic(args.workload)
     byt = cost.bytes_per_obs(fp32)
-    roofline = {"kernel": "local (k_local)", "bound": "alu", "achieved": round(achieved, 3),
+    roofline = {"kernel": "local (k_local_block)" if blocks else "local (k_local)", "bound": "alu", "achieved": round(achieved, 3),
                 "peak": FP32_VECTOR_PEAK_TFLOPS if fp32 else 78.6, "unit": "TFLOP/s",
                 "frac": round(achieved / (FP32_VECTOR_PEAK_TFLOPS if fp32 else 78.6), 4),
-                "traffic": traffic, "flops_per_obs": cost.local_flops_per_obs(opts.get("lm_steps", 5)),
+                "traffic": traffic, "flops_per_obs": flops_per_obs,
                 "obs_per_launch": L, "avg_launch_ms": local_ms,
                 "hbm_algorithmic_GBps": round(byt["local"] * L / (local_ms * 1e-3) / 1e9, 1)}
     cons_ms = kt["consensus"]["avg_ms"]
@@ -358,7 +425,9 @@ def main():
             ttr["target_source"] = f"FP64 oracle, {its} iterations (tests/golden/trajectory.npz)"
             out["time_to_rmse"] = ttr
 
-    if not args.no_cpu_baseline:
+    if not args.no_cpu_baseline and opts.get("camera_blocks"):
+        out["cpu_baseline"], out["parity_vs_oracle"] = block_baseline_and_parity(binding, scenes[0], opts)
+    elif not args.no_cpu_baseline:
         import oracle
         import numpy as np
         o = wl["opts"]

@@ -36,6 +36,22 @@ def local_flops_per_obs(lm_steps: int = 5) -> int:
     return PER_SOLVE + lm_steps * LM_STEP
 
 
+# --- block local updates (one camera copy per 64 observations) -------------------
+# per observation and LM step: projection, Jacobian and residual as above;
+# the camera-camera (45), camera-point (27), point-point (6) blocks and both
+# gradients 366; the damped 3x3 point block inverted 40; its Schur
+# contribution to the 9x9 camera system and right-hand side 459; the
+# all-reduce's additions 63; the point step 72; predicted decrease 15; trial
+# projection and objective 95.  The 9x9 LDL^T and its solves (420) are once
+# per block of 64 observations.
+BLOCK_LM_STEP = JAC + RESID + 366 + 40 + 459 + 63 + 72 + 15 + PROJ + 20 + 420 // 64
+BLOCK_PER_SOLVE = PROJ + 20 + 3 * 3 + 9 * 3 // 64
+
+
+def block_flops_per_obs(lm_steps: int = 5) -> int:
+    return BLOCK_PER_SOLVE + lm_steps * BLOCK_LM_STEP
+
+
 # --- bytes per observation per iteration --------------------------------------
 def bytes_per_obs(fp32: bool = True) -> dict:
     r = 4 if fp32 else 8
@@ -53,3 +69,4 @@ def bytes_per_obs(fp32: bool = True) -> dict:
 if __name__ == "__main__":
     print("LM step flops", LM_STEP, "per obs (5 steps)", local_flops_per_obs(5))
     print("bytes fp32", bytes_per_obs(True), "fp64", bytes_per_obs(False))
+    print("block LM step flops", BLOCK_LM_STEP, "per obs (5 steps)", block_flops_per_obs(5))

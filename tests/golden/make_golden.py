@@ -5,6 +5,7 @@ against.  Calls only the FP64 oracle (oracle/) on seeded scenes (scenes/).
     python tests/golden/make_golden.py sphere       # ~2 min
     python tests/golden/make_golden.py batch        # ~1 min
     python tests/golden/make_golden.py trajectory_perturbed sphere_perturbed
+    python tests/golden/make_golden.py trajectory_blocks   # block local updates, ~25 min
 
 A name ending in _perturbed runs the same workload from a start whose
 parameters are multiplied by 1 +- 1e-7 (random signs, seed 7), the size of
@@ -60,6 +61,26 @@ def run(name):
                         stats=a.stats(inl), settings=np.array(repr(SPECS[base][1])))
 
 
+def run_blocks():
+    """Block local updates (one camera copy per 64 observations of a camera)
+    on the 2M-observation trajectory workload: 3 iterations of the dense
+    block solver."""
+    sc = make_config2()
+    a = oracle.BlockADMM(oracle.Problem.from_scene(sc), sc.cams_init, sc.points_init, block=64, loss="huber",
+                         loss_param=2.0, rho=1e5, rho_balancing=True)
+    a.opts.rho_min, a.opts.rho_max = 1e5, 1e7
+    t0 = time.time()
+    trace = []
+    for k in range(3):
+        trace.append(a.iterate(1))
+        print(f"trajectory_blocks it {a.iteration} {time.time() - t0:.0f}s", flush=True)
+    pts_idx = np.arange(0, sc.n_points, 50)
+    np.savez_compressed(os.path.join(HERE, "trajectory_blocks.npz"), checksum=np.array(sc.checksum()),
+                        n_obs=sc.n_obs, iterations=3, n_blocks=a.n_blocks, trace=np.concatenate(trace),
+                        cams=a.cons_y, points_idx=pts_idx, points=a.cons_x[pts_idx], rho=a.rho,
+                        stats=a.stats(~sc.outlier))
+
+
 def run_batch():
     scenes = make_config3(scale=0.02)
     out = {}
@@ -75,4 +96,9 @@ def run_batch():
 
 if __name__ == "__main__":
     for name in sys.argv[1:]:
-        run_batch() if name == "batch" else run(name)
+        if name == "batch":
+            run_batch()
+        elif name == "trajectory_blocks":
+            run_blocks()
+        else:
+            run(name)

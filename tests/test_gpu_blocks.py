@@ -133,3 +133,26 @@ def test_blocks_reject_the_learned_start():
     with pytest.raises(binding.DbaError) as e:
         binding.Solver(precision="fp32", camera_blocks=True, start="learned")
     assert e.value.status == "DBA_E_INVALID_ARG"
+
+
+def test_blocks_full_size_match_the_stored_oracle():
+    """The 2.006M-observation trajectory workload with block local updates
+    (31,845 blocks), 3 iterations, against the oracle's dense block solver
+    (tests/golden/trajectory_blocks.npz): FP64 within 1e-9, FP32 within 1e-3."""
+    import os
+    path = os.path.join(os.path.dirname(__file__), "golden", "trajectory_blocks.npz")
+    if not os.path.exists(path):
+        pytest.skip("stored oracle run not generated (tests/golden/make_golden.py trajectory_blocks)")
+    g = np.load(path)
+    sc = make_config2()
+    assert str(g["checksum"]) == sc.checksum()
+    kw = dict(loss="huber", loss_param=2.0, rho=1e5, rho_balancing=True, rho_min=1e5, rho_max=1e7)
+    for precision, tol in (("fp64", 1e-9), ("fp32", 1e-3)):
+        s = gpu_blocks(sc, int(g["iterations"]), precision=precision, block_waves=1, persistent=0, **kw)
+        cams, pts = s.params()
+        err = param_rel_err(cams, pts[g["points_idx"]], g["cams"], g["points"])
+        r = s.residuals(want_rmse=True)
+        print(precision, "full-size blocks max rel err", err, "rmse", r["rmse"], g["stats"][0])
+        assert err < tol
+        assert r["next_rho_x"] == g["rho"][0]
+        s.close()

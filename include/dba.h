@@ -162,7 +162,8 @@ int dba_get_params(dba_handle *h, int32_t problem, double *cams, double *points)
 
 /* Full ADMM state of `problem` in the caller's observation order: local
  * copies [12*n_obs] as (y_j^i (9), x_i^j (3)) and scaled duals [12*n_obs],
- * FP64.  Either pointer may be NULL. */
+ * FP64.  With camera_blocks every observation reports the camera copy and
+ * dual of its block.  Either pointer may be NULL. */
 int dba_get_state(dba_handle *h, int32_t problem, double *copies, double *duals);
 
 /* Number of problems set, and the sizes of one. */

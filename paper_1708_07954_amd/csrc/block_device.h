@@ -8,7 +8,8 @@
 // a decrease of F or on a predicted decrease below F's rounding resolution).
 // The normal equations are reduced to the camera by the Schur complement on
 // the points: each lane forms its point block and its contribution to the
-// 9x9 camera system, a fixed-order all-reduce sums the contributions, every
+// 9x9 camera system -- of rank 2, U M U^T with U the camera part of its two
+// Jacobian rows -- a fixed-order all-reduce sums the contributions, every
 // lane factors the 9x9 system (LDL^T) and back-solves its own point.
 #pragma once
 #include "dba_device.h"
@@ -139,47 +140,46 @@ __device__ __forceinline__ void block_lm(R *th, const R *vy, const R *vx, R z0, 
     }
     R F = wave_sum_t<R>(fk) + camera_penalty<R>(th, vy, ry);
     for (int it = 0; it < steps; ++it) {
-        // linearisation at (y, x_k)
-        R Cyy[45], ngy[9], W[27], ngx[3], hx[6];
-        R fr = R(0);
+        // linearisation at (y, x_k): J = [U^T | V^T] with U = (J0_y, J1_y)
+        // (9x2) and V = (J0_x, J1_x) (3x2); the lane's blocks of the normal
+        // matrix are c U U^T (camera), c U V^T (coupling), c V V^T + rho_x I
+        // (point), all of rank 2 besides the penalty
+        R U0[9], U1[9], V0[3] = {R(0), R(0), R(0)}, V1[3] = {R(0), R(0), R(0)};
+        R e0 = R(0), e1 = R(0), c2 = R(0), fr = R(0);
 #pragma unroll
-        for (int q = 0; q < 45; ++q) Cyy[q] = R(0);
-#pragma unroll
-        for (int q = 0; q < 9; ++q) ngy[q] = R(0);
-#pragma unroll
-        for (int q = 0; q < 27; ++q) W[q] = R(0);
-#pragma unroll
-        for (int q = 0; q < 3; ++q) ngx[q] = R(0);
-#pragma unroll
-        for (int q = 0; q < 6; ++q) hx[q] = R(0);
+        for (int i = 0; i < 9; ++i) U0[i] = U1[i] = R(0);
         if (active) {
             R J0[12], J1[12];
             proj_jac<R>(cur, th, J0, J1);
-            const R e0 = z0 - cur.pu, e1 = z1 - cur.pv;
+            e0 = z0 - cur.pu;
+            e1 = z1 - cur.pv;
             R w;
             const R s2 = e0 * e0 + e1 * e1;
             loss_phi<R>(kind, lp, s2, w);
-            const R c2 = R(2) * w;
+            c2 = R(2) * w;
             fr = Num<R>::sqrt(s2) * (fabs(z0) + fabs(z1) + fabs(th[6]));
 #pragma unroll
             for (int i = 0; i < 9; ++i) {
-                ngy[i] = c2 * (J0[i] * e0 + J1[i] * e1);
-#pragma unroll
-                for (int j = i; j < 9; ++j) Cyy[sym9(i, j)] = c2 * (J0[i] * J0[j] + J1[i] * J1[j]);
-#pragma unroll
-                for (int c = 0; c < 3; ++c) W[3 * i + c] = c2 * (J0[i] * J0[9 + c] + J1[i] * J1[9 + c]);
+                U0[i] = J0[i];
+                U1[i] = J1[i];
             }
 #pragma unroll
-            for (int c = 0; c < 3; ++c) ngx[c] = c2 * (J0[9 + c] * e0 + J1[9 + c] * e1) - rx * (th[9 + c] - vx[c]);
-            hx[0] = rx + c2 * (J0[9] * J0[9] + J1[9] * J1[9]);
-            hx[1] = c2 * (J0[9] * J0[10] + J1[9] * J1[10]);
-            hx[2] = c2 * (J0[9] * J0[11] + J1[9] * J1[11]);
-            hx[3] = rx + c2 * (J0[10] * J0[10] + J1[10] * J1[10]);
-            hx[4] = c2 * (J0[10] * J0[11] + J1[10] * J1[11]);
-            hx[5] = rx + c2 * (J0[11] * J0[11] + J1[11] * J1[11]);
+            for (int c = 0; c < 3; ++c) {
+                V0[c] = J0[9 + c];
+                V1[c] = J1[9 + c];
+            }
         }
         const R fres = F + wave_sum_t<R>(fr);
-        // damped point block and its inverse (symmetric 3x3, adjugate)
+        // point block H_xx = c V V^T + rho_x I, damped, inverted (adjugate)
+        R hx[6], ngx[3];
+        hx[0] = rx + c2 * (V0[0] * V0[0] + V1[0] * V1[0]);
+        hx[1] = c2 * (V0[0] * V0[1] + V1[0] * V1[1]);
+        hx[2] = c2 * (V0[0] * V0[2] + V1[0] * V1[2]);
+        hx[3] = rx + c2 * (V0[1] * V0[1] + V1[1] * V1[1]);
+        hx[4] = c2 * (V0[1] * V0[2] + V1[1] * V1[2]);
+        hx[5] = rx + c2 * (V0[2] * V0[2] + V1[2] * V1[2]);
+#pragma unroll
+        for (int c = 0; c < 3; ++c) ngx[c] = active ? c2 * (V0[c] * e0 + V1[c] * e1) - rx * (th[9 + c] - vx[c]) : R(0);
         const R a00 = hx[0] * (R(1) + lam), a11 = hx[3] * (R(1) + lam), a22 = hx[5] * (R(1) + lam);
         const R a01 = hx[1], a02 = hx[2], a12 = hx[4];
         const R m00 = a11 * a22 - a12 * a12, m01 = a02 * a12 - a01 * a22, m02 = a01 * a12 - a02 * a11;
@@ -196,26 +196,33 @@ __device__ __forceinline__ void block_lm(R *th, const R *vy, const R *vx, R z0, 
             B[4] = (a01 * a02 - a00 * a12) * idet;
             B[5] = (a00 * a11 - a01 * a01) * idet;
         }
-        // Schur contribution: P = W B, C - P W^T, ngy - P ngx
+        auto bmul = [&](const R *v, R *o) {
+            o[0] = B[0] * v[0] + B[1] * v[1] + B[2] * v[2];
+            o[1] = B[1] * v[0] + B[3] * v[1] + B[4] * v[2];
+            o[2] = B[2] * v[0] + B[4] * v[1] + B[5] * v[2];
+        };
+        R BV0[3], BV1[3], Bn[3];
+        bmul(V0, BV0);
+        bmul(V1, BV1);
+        bmul(ngx, Bn);
+        // Schur contribution C - W B W^T = U M U^T with the 2x2
+        // M = c I - c^2 V^T B V, and ng_y - W B ng_x = U (c (e - V^T B ng_x))
+        const R g00 = V0[0] * BV0[0] + V0[1] * BV0[1] + V0[2] * BV0[2];
+        const R g01 = V0[0] * BV1[0] + V0[1] * BV1[1] + V0[2] * BV1[2];
+        const R g11 = V1[0] * BV1[0] + V1[1] * BV1[1] + V1[2] * BV1[2];
+        const R cc = c2 * c2;
+        const R M00 = c2 - cc * g00, M01 = -cc * g01, M11 = c2 - cc * g11;
+        const R h0 = V0[0] * Bn[0] + V0[1] * Bn[1] + V0[2] * Bn[2];
+        const R h1 = V1[0] * Bn[0] + V1[1] * Bn[1] + V1[2] * Bn[2];
+        const R r0 = c2 * (e0 - h0), r1 = c2 * (e1 - h1);
         R red[63];
-        {
-            R P[27];
 #pragma unroll
-            for (int i = 0; i < 9; ++i) {
-                const R w0 = W[3 * i], w1 = W[3 * i + 1], w2 = W[3 * i + 2];
-                P[3 * i] = w0 * B[0] + w1 * B[1] + w2 * B[2];
-                P[3 * i + 1] = w0 * B[1] + w1 * B[3] + w2 * B[4];
-                P[3 * i + 2] = w0 * B[2] + w1 * B[4] + w2 * B[5];
-            }
+        for (int j = 0; j < 9; ++j) {
+            const R q0 = M00 * U0[j] + M01 * U1[j], q1 = M01 * U0[j] + M11 * U1[j];
 #pragma unroll
-            for (int i = 0; i < 9; ++i) {
-#pragma unroll
-                for (int j = i; j < 9; ++j)
-                    red[sym9(i, j)] = Cyy[sym9(i, j)] -
-                                      (P[3 * i] * W[3 * j] + P[3 * i + 1] * W[3 * j + 1] + P[3 * i + 2] * W[3 * j + 2]);
-                red[45 + i] = Cyy[sym9(i, i)];
-                red[54 + i] = ngy[i] - (P[3 * i] * ngx[0] + P[3 * i + 1] * ngx[1] + P[3 * i + 2] * ngx[2]);
-            }
+            for (int i = 0; i <= j; ++i) red[sym9(i, j)] = U0[i] * q0 + U1[i] * q1;
+            red[45 + j] = c2 * (U0[j] * U0[j] + U1[j] * U1[j]);
+            red[54 + j] = U0[j] * r0 + U1[j] * r1;
         }
         R sum[63];
         wave_allreduce<R, 63>(red, sum, lds, lane);
@@ -231,19 +238,19 @@ __device__ __forceinline__ void block_lm(R *th, const R *vy, const R *vx, R z0, 
         }
         const bool oky = ldl9_solve<R>(Sy, ry9, dy);
         const bool ok = oky && (__ballot(!okx) == 0ull);
-        // point steps and the predicted decrease
+        // point step dx = B (ng_x - W^T dy) = B ng_x - c B V (U^T dy), and the
+        // predicted decrease
         R dx[3] = {R(0), R(0), R(0)};
         R pk = R(0);
         if (active) {
-            R t[3];
+            R u0 = R(0), u1 = R(0);
 #pragma unroll
-            for (int c = 0; c < 3; ++c)
-                t[c] = ngx[c] - (W[c] * dy[0] + W[3 + c] * dy[1] + W[6 + c] * dy[2] + W[9 + c] * dy[3] +
-                                 W[12 + c] * dy[4] + W[15 + c] * dy[5] + W[18 + c] * dy[6] + W[21 + c] * dy[7] +
-                                 W[24 + c] * dy[8]);
-            dx[0] = B[0] * t[0] + B[1] * t[1] + B[2] * t[2];
-            dx[1] = B[1] * t[0] + B[3] * t[1] + B[4] * t[2];
-            dx[2] = B[2] * t[0] + B[4] * t[1] + B[5] * t[2];
+            for (int i = 0; i < 9; ++i) {
+                u0 += U0[i] * dy[i];
+                u1 += U1[i] * dy[i];
+            }
+#pragma unroll
+            for (int c = 0; c < 3; ++c) dx[c] = Bn[c] - c2 * (BV0[c] * u0 + BV1[c] * u1);
             pk = ngx[0] * dx[0] + ngx[1] * dx[1] + ngx[2] * dx[2] +
                  lam * (hx[0] * dx[0] * dx[0] + hx[3] * dx[1] * dx[1] + hx[5] * dx[2] * dx[2]);
         }

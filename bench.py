@@ -115,63 +115,70 @@ def oracle_target(workload):
     return float(z["stats"][1]), int(z["iterations"])
 
 
+def _time_to_target(binding, scene, kw, goal, max_iters, net=None):
+    """Iterations and wall time of one configuration to an inlier RMSE goal:
+    per-kernel times over the first 20 iterations of a fresh run; the
+    crossing iteration from per-iteration RMSE checks; then a fresh run of
+    exactly that many iterations, timed (graph instantiation included), and
+    the steady per-iteration time of the 50 iterations after it."""
+    import numpy as np
+    import torch
+    inl = ~scene.outlier
+
+    def make():
+        s = binding.Solver(**kw)
+        if net is not None:
+            binding.dba_set_mlp(s.h, net[0], net[1])
+        s.set_scene(scene)
+        s.set_eval_mask(inl)
+        return s
+    s = make()
+    binding.dba_set_kernel_timing(s.h, True)
+    s.iterate(20)
+    torch.cuda.synchronize()
+    kt = binding.dba_kernel_times(s.h)
+    s.close()
+    kernels = {k: v[0] / v[1] for k, v in kt.items() if v[1]}
+    s = make()
+    hit, last = None, None
+    for k in range(1, max_iters + 1):
+        s.iterate(1)
+        last = s.residuals(want_rmse=True)["rmse_masked"]
+        if not np.isfinite(last) or last > 1e6:
+            break
+        if last <= goal:
+            hit = k
+            break
+    s.close()
+    out = {"iterations": hit, "inlier_rmse_at_stop": last, "kernel_ms": kernels}
+    if hit is None:
+        out["seconds"] = None
+        return out
+    s = make()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    s.iterate(hit)
+    torch.cuda.synchronize()
+    out["seconds"] = time.perf_counter() - t0
+    s.iterate(20)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    s.iterate(50)
+    torch.cuda.synchronize()
+    out["ms_per_iter_steady"] = (time.perf_counter() - t0) * 20.0
+    s.close()
+    return out
+
+
 def time_to_rmse(binding, scene, opts, sched, target, max_iters=400, learned_steps=(1, 2, 3, 4, 5)):
     """Wall time of plain 5-step LM, of block local updates (one camera copy
     per 64 observations, Sec. 3.1.4) and of the learned start (+ k LM steps)
-    to reach the oracle's final inlier RMSE (within 0.5 %).  The crossing
-    iteration is found with per-iteration RMSE checks; a fresh run of exactly
-    that many iterations is then timed (graph instantiation included)."""
-    import numpy as np
-    import torch
+    to reach the oracle's final inlier RMSE (within 0.5 %)."""
     from paper_1708_07954_amd import warmstart
-    inl = ~scene.outlier
     goal = target * 1.005
 
     def run(kw, net=None):
-        def make():
-            s = binding.Solver(**kw)
-            if net is not None:
-                binding.dba_set_mlp(s.h, net[0], net[1])
-            s.set_scene(scene)
-            s.set_eval_mask(inl)
-            return s
-        # per-kernel times over the first 20 iterations of a fresh run
-        s = make()
-        binding.dba_set_kernel_timing(s.h, True)
-        s.iterate(20)
-        torch.cuda.synchronize()
-        kt = binding.dba_kernel_times(s.h)
-        s.close()
-        kernels = {k: v[0] / v[1] for k, v in kt.items() if v[1]}
-        s = make()
-        hit, last = None, None
-        for k in range(1, max_iters + 1):
-            s.iterate(1)
-            last = s.residuals(want_rmse=True)["rmse_masked"]
-            if not np.isfinite(last) or last > 1e6:
-                break
-            if last <= goal:
-                hit = k
-                break
-        s.close()
-        out = {"iterations": hit, "inlier_rmse_at_stop": last, "kernel_ms": kernels}
-        if hit is None:
-            out["seconds"] = None
-            return out
-        s = make()
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        s.iterate(hit)
-        torch.cuda.synchronize()
-        out["seconds"] = time.perf_counter() - t0
-        s.iterate(20)
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        s.iterate(50)
-        torch.cuda.synchronize()
-        out["ms_per_iter_steady"] = (time.perf_counter() - t0) * 20.0
-        s.close()
-        return out
+        return _time_to_target(binding, scene, kw, goal, max_iters, net)
 
     res = {"target_inlier_rmse": target, "reached_when_within": 0.005, "max_iterations": max_iters}
     res["plain_lm5"] = run(dict(opts, lm_steps=5, block_waves=sched["block_waves"], persistent=sched["persistent"]))
@@ -204,6 +211,26 @@ def time_to_rmse(binding, scene, opts, sched, target, max_iters=400, learned_ste
     best = min((res[f"learned_lm{k}"]["seconds"] for k in learned_steps
                 if res[f"learned_lm{k}"]["seconds"] is not None), default=None)
     res["learned_over_plain_time"] = (best / t_plain) if (best is not None and t_plain) else None
+    return res
+
+
+def block_size_sweep(binding, scene, opts, target, sizes=(64, 48, 32, 16, 8, 4, 2, 1), steps=(1, 2, 5),
+                     max_iters=300):
+    """Block local updates (Sec. 3.1.4) with pi observations per block, one
+    camera per block: iterations and wall time to the oracle's final inlier
+    RMSE (within 0.5 %) for every pi and LM step count.  One block is one
+    wavefront, so the cost of an iteration follows the number of blocks."""
+    goal = target * 1.005
+    res = {"target_inlier_rmse": target, "reached_when_within": 0.005, "max_iterations": max_iters,
+           "schedule": {"block_waves": 1, "persistent": 0}}
+    for pi in sizes:
+        for k in steps:
+            kw = dict(opts, camera_blocks=True, block_points=pi, lm_steps=k, block_waves=1, persistent=0)
+            r = _time_to_target(binding, scene, kw, goal, max_iters)
+            res[f"pi{pi}_lm{k}"] = {q: r.get(q) for q in ("iterations", "seconds", "ms_per_iter_steady",
+                                                       "inlier_rmse_at_stop")}
+            res[f"pi{pi}_lm{k}"]["local_ms"] = r["kernel_ms"].get("local")
+            print(f"[bench] block size {pi}, {k} LM steps: {res[f'pi{pi}_lm{k}']}", file=sys.stderr, flush=True)
     return res
 
 
@@ -303,6 +330,9 @@ def main():
                     help="skip the time-to-RMSE comparison (learned start vs plain LM)")
     ap.add_argument("--profile-learned", action="store_true",
                     help="only train the network briefly and run 20 learned-start iterations (for profilers)")
+    ap.add_argument("--block-sweep", action="store_true",
+                    help="trajectory workloads: also sweep the block size pi of the block local updates "
+                         "(1..64 observations per block, 1 / 2 / 5 LM steps) to the oracle's final RMSE")
     ap.add_argument("--copy-probe-mib", type=int, default=0,
                     help="also run a plain device copy of this size (counter calibration)")
     args = ap.parse_args()
@@ -424,6 +454,13 @@ def main():
             ttr = time_to_rmse(binding, scenes[0], opts, sched, target)
             ttr["target_source"] = f"FP64 oracle, {its} iterations (tests/golden/trajectory.npz)"
             out["time_to_rmse"] = ttr
+
+    if args.block_sweep and args.workload.startswith("trajectory"):
+        target, its = oracle_target("trajectory")
+        if target is not None:
+            sw = block_size_sweep(binding, scenes[0], wl["opts"], target)
+            sw["target_source"] = f"FP64 oracle, {its} iterations (tests/golden/trajectory.npz)"
+            out["block_size_sweep"] = sw
 
     if not args.no_cpu_baseline and opts.get("camera_blocks"):
         out["cpu_baseline"], out["parity_vs_oracle"] = block_baseline_and_parity(binding, scenes[0], opts)

@@ -84,12 +84,14 @@ typedef struct dba_options {
                                  of up to 64 that share one camera copy; each block's problem
                                  (9 + 3 x observations unknowns) is one local solve; not with the
                                  learned start */
+    int32_t block_points;     /* with camera_blocks: observations (points) per block, the pi of
+                                 Sec. 3.1.4, 1..64; 0 means 64.  Must be 0 without camera_blocks */
 } dba_options;
 
 /* Fills *opt with the defaults: device 0, NULL stream, FP64, Huber 2 px,
  * rho 1, no balancing (mu 10, tau 2, clamps 1e-6..1e6), 5 LM steps,
  * lambda0 1e-3, plain start, 2 learned steps, graphs on, autotune, one
- * local problem per observation. */
+ * local problem per observation (camera_blocks 0, block_points 0). */
 int dba_default_options(dba_options *opt);
 
 /* Creates a handle on opt->device.  *out receives the handle. */
@@ -221,7 +223,8 @@ int dba_mlp_loss_grad(dba_handle *h, const float *x_std, const float *t_std, int
  * samples per_iter observations (seeded) and records, for each, its 26
  * features and the update of an LM run of conv_steps steps from the copy on
  * the same local problem: features [n_iters*per_iter][26], deltas [..][12].
- * FP32 local solves only. */
+ * FP32 local solves of one observation each only (DBA_E_INVALID_ARG with
+ * camera_blocks). */
 int dba_collect_pairs(dba_handle *h, int32_t n_iters, int32_t per_iter, uint64_t seed, int32_t conv_steps,
                       float *features, float *deltas);
 /* Trains the network on n pairs: standardisation from the pairs, N(0,

@@ -40,7 +40,8 @@ class dba_options(ctypes.Structure):
                 ("lm_steps", ctypes.c_int32), ("lm_lambda0", ctypes.c_double),
                 ("start", ctypes.c_int32), ("learned_lm_steps", ctypes.c_int32),
                 ("use_graph", ctypes.c_int32), ("block_waves", ctypes.c_int32),
-                ("persistent", ctypes.c_int32), ("camera_blocks", ctypes.c_int32)]
+                ("persistent", ctypes.c_int32), ("camera_blocks", ctypes.c_int32),
+                ("block_points", ctypes.c_int32)]
 
 
 class dba_problem_desc(ctypes.Structure):
@@ -133,7 +134,7 @@ def make_options(*, device=0, stream=None, precision="fp64", loss="huber", loss_
                  rho_x=None, rho_y=None, rho_balancing=False, rb_mu=10.0, rb_tau=2.0,
                  rho_min=1e-6, rho_max=1e6, lm_steps=5, lm_lambda0=1e-3, start="plain",
                  learned_lm_steps=2, use_graph=True, block_waves=0, persistent=-1,
-                 camera_blocks=False) -> dba_options:
+                 camera_blocks=False, block_points=0) -> dba_options:
     o = dba_options()
     _check(None, load().dba_default_options(ctypes.byref(o)))
     o.device = device
@@ -153,6 +154,7 @@ def make_options(*, device=0, stream=None, precision="fp64", loss="huber", loss_
     o.block_waves = int(block_waves)
     o.persistent = int(persistent)
     o.camera_blocks = int(bool(camera_blocks))
+    o.block_points = int(block_points)
     return o
 
 

@@ -86,6 +86,12 @@ int build_set(dba_handle *h, int np, const dba_problem_desc *probs, ProblemSet *
     using R2 = typename dba::Vec<R>::R2;
     using R4 = typename dba::Vec<R>::R4;
     const int CH = dba::kChunk;
+    // observations of a camera per chunk: 64, or the block size pi of the
+    // block local updates (the rest of such a chunk is padding).  Block local
+    // updates keep the camera copy and dual per chunk (copy_yc, dual_yc) and
+    // allocate no per-slot camera copies (copy_y, dual_y).
+    const int BP = h->opt.camera_blocks && h->opt.block_points ? h->opt.block_points : CH;
+    const bool per_obs = !h->opt.camera_blocks;
     // global sizes
     long long n_chunks = 0, n_recs = 0;
     int n_cams = 0, n_pts = 0, n_pblk = 0;
@@ -99,7 +105,7 @@ int build_set(dba_handle *h, int np, const dba_problem_desc *probs, ProblemSet *
         r.pt0 = n_pts; r.n_points = d.n_points;
         r.chunk0 = (int)n_chunks;
         long long ch = 0;
-        for (int j = 0; j < d.n_cams; ++j) ch += (cc[j] + CH - 1) / CH;
+        for (int j = 0; j < d.n_cams; ++j) ch += (cc[j] + BP - 1) / BP;
         r.n_chunks = (int)ch;
         r.rec0 = n_recs; r.n_obs = d.n_obs;
         r.pblk0 = n_pblk; r.n_pblk = (d.n_points + dba::kPtBlock - 1) / dba::kPtBlock;
@@ -121,7 +127,9 @@ int build_set(dba_handle *h, int np, const dba_problem_desc *probs, ProblemSet *
     std::vector<R2> uv(S);
     std::vector<int> pslot(S, -1), ptid(S, 0), orig(S, 0);
     std::vector<uint8_t> mask(S, 1);
-    std::vector<R> copy_y(9 * (size_t)S, R(0));
+    // per-observation camera copies; block local updates keep one per chunk
+    const size_t SY = per_obs ? (size_t)S : 0;
+    std::vector<R> copy_y(9 * SY, R(0));
     std::vector<R4> xrec(n_recs);
     std::vector<int> pt_off(n_pts + 1, 0), chunk_cam(n_chunks), cam_prob(n_cams), pt_prob(n_pts),
         cam_chunk0(n_cams + 1), cam_count(n_cams);
@@ -157,6 +165,7 @@ int build_set(dba_handle *h, int np, const dba_problem_desc *probs, ProblemSet *
         std::vector<int> cc(d.n_cams, 0);
         for (long long k = 0; k < L; ++k) ++cc[d.obs_cam[k]];
         std::vector<long long> cslot(d.n_cams);
+        std::vector<int> cseen(d.n_cams, 0);
         int chunk = r.chunk0;
         for (int j = 0; j < d.n_cams; ++j) {
             const int J = r.cam0 + j;
@@ -164,7 +173,7 @@ int build_set(dba_handle *h, int np, const dba_problem_desc *probs, ProblemSet *
             cam_chunk0[J] = chunk;
             cam_count[J] = cc[j];
             cslot[j] = (long long)chunk * CH;
-            const int nch = (cc[j] + CH - 1) / CH;
+            const int nch = (cc[j] + BP - 1) / BP;
             for (int q = 0; q < nch; ++q) chunk_cam[chunk + q] = J;
             chunk += nch;
             for (int c = 0; c < 9; ++c) cons_y[(size_t)J * dba::kConsY + c] = d.cams[9 * j + c];
@@ -172,13 +181,15 @@ int build_set(dba_handle *h, int np, const dba_problem_desc *probs, ProblemSet *
         for (long long rr = 0; rr < L; ++rr) {
             const int k = rec_obs[rr];
             const int j = d.obs_cam[k], i = d.obs_point[k];
-            const long long s = cslot[j]++;
+            const int q = cseen[j]++;
+            const long long s = cslot[j] + (long long)(q / BP) * CH + q % BP;
             pslot[s] = (int)(r.rec0 + rr);
             ptid[s] = r.pt0 + i;
             orig[s] = k;
             uv[s].x = (R)d.obs_uv[2 * k];
             uv[s].y = (R)d.obs_uv[2 * k + 1];
-            for (int c = 0; c < 9; ++c) copy_y[(size_t)c * S + s] = (R)d.cams[9 * j + c];
+            if (per_obs)
+                for (int c = 0; c < 9; ++c) copy_y[(size_t)c * S + s] = (R)d.cams[9 * j + c];
             R4 x;
             x.x = (R)d.points[3 * i]; x.y = (R)d.points[3 * i + 1]; x.z = (R)d.points[3 * i + 2]; x.w = R(0);
             xrec[r.rec0 + rr] = x;
@@ -214,8 +225,8 @@ int build_set(dba_handle *h, int np, const dba_problem_desc *probs, ProblemSet *
     HIP_TRY(h, B.alloc(&d_ptid, S));
     HIP_TRY(h, B.alloc(&d_orig, S));
     HIP_TRY(h, B.alloc(&d_mask, S));
-    HIP_TRY(h, B.alloc(&d_copy, 9 * (size_t)S));
-    HIP_TRY(h, B.alloc(&d_dual, 9 * (size_t)S));
+    HIP_TRY(h, B.alloc(&d_copy, 9 * SY));
+    HIP_TRY(h, B.alloc(&d_dual, 9 * SY));
     HIP_TRY(h, B.alloc(&d_xrec, n_recs));
     HIP_TRY(h, B.alloc(&d_urec, n_recs));
     HIP_TRY(h, B.alloc(&d_ptoff, n_pts + 1));
@@ -243,8 +254,10 @@ int build_set(dba_handle *h, int np, const dba_problem_desc *probs, ProblemSet *
     HIP_TRY(h, hipMemcpy(d_ptid, ptid.data(), S * sizeof(int), hipMemcpyHostToDevice));
     HIP_TRY(h, hipMemcpy(d_orig, orig.data(), S * sizeof(int), hipMemcpyHostToDevice));
     HIP_TRY(h, hipMemcpy(d_mask, mask.data(), S, hipMemcpyHostToDevice));
-    HIP_TRY(h, hipMemcpy(d_copy, copy_y.data(), 9 * (size_t)S * sizeof(R), hipMemcpyHostToDevice));
-    HIP_TRY(h, hipMemset(d_dual, 0, 9 * (size_t)S * sizeof(double)));
+    if (per_obs) {
+        HIP_TRY(h, hipMemcpy(d_copy, copy_y.data(), 9 * SY * sizeof(R), hipMemcpyHostToDevice));
+        HIP_TRY(h, hipMemset(d_dual, 0, 9 * SY * sizeof(double)));
+    }
     HIP_TRY(h, hipMemcpy(d_xrec, xrec.data(), n_recs * sizeof(R4), hipMemcpyHostToDevice));
     HIP_TRY(h, hipMemset(d_urec, 0, n_recs * sizeof(double4)));
     HIP_TRY(h, hipMemcpy(d_ptoff, pt_off.data(), (n_pts + 1) * sizeof(int), hipMemcpyHostToDevice));
@@ -471,6 +484,7 @@ int dba_default_options(dba_options *o)
     o->block_waves = 0;
     o->persistent = -1;
     o->camera_blocks = 0;
+    o->block_points = 0;
     return DBA_OK;
 }
 
@@ -494,6 +508,8 @@ int dba_create(const dba_options *opt, dba_handle **out)
     if (o.learned_lm_steps < 0 || o.learned_lm_steps > 64) return DBA_E_INVALID_ARG;
     if (o.camera_blocks != 0 && o.camera_blocks != 1) return DBA_E_INVALID_ARG;
     if (o.camera_blocks && o.start == DBA_START_LEARNED) return DBA_E_INVALID_ARG;
+    if (o.block_points < 0 || o.block_points > dba::kChunk || (o.block_points && !o.camera_blocks))
+        return DBA_E_INVALID_ARG;
     dba_handle *h = new dba_handle();
     h->opt = o;
     h->fp32 = o.precision == DBA_PREC_FP32_LOCAL;

@@ -194,6 +194,8 @@ int dba_collect_pairs(dba_handle *h, int32_t n_iters, int32_t per_iter, uint64_t
     h->err.clear();
     if (!h->ps) return fail(h, DBA_E_STATE, "no problem set");
     if (!h->fp32) return fail(h, DBA_E_INVALID_ARG, "pairs are collected from FP32 local solves");
+    if (h->opt.camera_blocks)
+        return fail(h, DBA_E_INVALID_ARG, "pairs are collected from per-observation local solves");
     HIP_TRY(h, hipSetDevice(h->opt.device));
     ProblemSet &ps = *h->ps;
     std::vector<int> pslot(ps.n_slots), active;

@@ -25,8 +25,8 @@ CASES = {
 }
 
 
-def oracle_blocks(sc, iters, *, rho_min=1e-6, rho_max=1e6, **kw):
-    b = oracle.BlockADMM(oracle.Problem.from_scene(sc), sc.cams_init, sc.points_init, block=64, **kw)
+def oracle_blocks(sc, iters, *, rho_min=1e-6, rho_max=1e6, block=64, **kw):
+    b = oracle.BlockADMM(oracle.Problem.from_scene(sc), sc.cams_init, sc.points_init, block=block, **kw)
     b.opts.rho_min, b.opts.rho_max = rho_min, rho_max
     tr = b.iterate(iters)
     return b, tr
@@ -126,6 +126,80 @@ def test_blocks_batched_equals_solo_bitwise():
         a, b = s.params(q), solo.params()
         assert np.array_equal(a[0], b[0]) and np.array_equal(a[1], b[1])
         solo.close()
+    s.close()
+
+
+@pytest.mark.parametrize("pi", [1, 7, 32, 63])
+@pytest.mark.parametrize("case", ["ring_huber", "sphere_t"])
+def test_smaller_blocks_fp64_parity(case, pi):
+    """Blocks of pi < 64 observations (Sec. 3.1.4): one block per chunk, the
+    rest of the chunk padding; pi = 1 is the per-observation method solved
+    by the block kernel."""
+    make, kw, iters = CASES[case]
+    sc = make()
+    b, tr = oracle_blocks(sc, iters, block=pi, **kw)
+    s = gpu_blocks(sc, iters, precision="fp64", block_points=pi, **kw)
+    cams, pts = s.params()
+    err = param_rel_err(cams, pts, b.cons_y, b.cons_x)
+    r = s.residuals(want_rmse=True)
+    print(case, "pi", pi, "blocks", b.n_blocks, "max rel err", err, "rmse", r["rmse"], b.stats()[0])
+    assert err < 1e-9
+    assert r["primal"] == pytest.approx(tr[-1, 0], rel=1e-6)
+    assert r["dual"] == pytest.approx(tr[-1, 1], rel=1e-6)
+    s.close()
+
+
+@pytest.mark.parametrize("pi", [1, 16])
+def test_smaller_blocks_fp32_parity_and_state(pi):
+    make, kw, iters = CASES["traj_balancing"]
+    sc = make()
+    b, _ = oracle_blocks(sc, iters, block=pi, **kw)
+    s = gpu_blocks(sc, iters, precision="fp32", block_points=pi, **kw)
+    cams, pts = s.params()
+    err = param_rel_err(cams, pts, b.cons_y, b.cons_x)
+    r = s.residuals(want_rmse=True)
+    print("pi", pi, "fp32 max rel err", err, "rmse", r["rmse"], b.stats()[0])
+    assert err < 1e-3
+    assert abs(r["rmse"] - b.stats()[0]) < 5e-3 * b.stats()[0]
+    s.close()
+    s = gpu_blocks(sc, 4, precision="fp64", block_points=pi, **kw)
+    b, _ = oracle_blocks(sc, 4, block=pi, **kw)
+    copies, duals = s.state()
+    oc, od = b.copies()
+    assert state_rel_err(copies, oc) < 1e-9
+    assert state_rel_err(duals, od) < 1e-7
+    s.close()
+
+
+def test_smaller_blocks_every_schedule_is_bitwise_identical():
+    sc = make_sphere_scene(seed=4, n_cams=10, n_points=300)
+    kw = dict(precision="fp32", loss="student_t", loss_param=4.0, rho=1e3, camera_blocks=True, block_points=24)
+    ref = None
+    for bw in (1, 4, 8):
+        for pers in (0, 1):
+            s = binding.Solver(block_waves=bw, persistent=pers, **kw).set_scene(sc)
+            s.iterate(5)
+            cams, pts = s.params()
+            s.close()
+            if ref is None:
+                ref = (cams, pts)
+            else:
+                assert np.array_equal(cams, ref[0]) and np.array_equal(pts, ref[1]), (bw, pers)
+
+
+@pytest.mark.parametrize("bad", [dict(block_points=8), dict(camera_blocks=True, block_points=65),
+                                 dict(camera_blocks=True, block_points=-1)])
+def test_block_points_validation(bad):
+    with pytest.raises(binding.DbaError) as e:
+        binding.Solver(precision="fp64", **bad)
+    assert e.value.status == "DBA_E_INVALID_ARG"
+
+
+def test_blocks_reject_pair_collection():
+    s = gpu_blocks(make_ring_scene(seed=5, n_cams=3, n_points=40), 1, precision="fp32")
+    with pytest.raises(binding.DbaError) as e:
+        binding.dba_collect_pairs(s.h, 1, 64, seed=1)
+    assert e.value.status == "DBA_E_INVALID_ARG"
     s.close()
 
 

@@ -234,6 +234,62 @@ def block_size_sweep(binding, scene, opts, target, sizes=(64, 48, 32, 16, 8, 4, 
     return res
 
 
+def size_sweep(binding, opts, factors=(0.0625, 0.125, 0.25, 0.5, 1.0, 2.0, 4.0, 8.0), iters=50):
+    """Time of one iteration against the number of observations L (the
+    paper's cost model: the local solves and the dual update are O(L), the
+    consensus O(L + m + n)).  Up to L = 2M: one trajectory scene of 1000 f
+    cameras and 200000 f points (seed 2; f = 1 is the 2M workload).  Above:
+    f copies of the 2M problem as independent problems in the same launches
+    (a longer or denser trajectory's perturbed start puts points behind
+    cameras, which the library rejects).  Each size with its own autotuned
+    schedule; iterations replayed from the captured graph.  A least-squares
+    line t = a + b L summarises the points."""
+    import numpy as np
+    import torch
+    from scenes import make_config2
+
+    base = make_config2()
+    rows = []
+    for f in factors:
+        if f <= 1.0:
+            scenes = [make_config2(n_cams=int(round(1000 * f)), n_points=int(round(200000 * f)))]
+        else:
+            scenes = [base] * int(f)
+        L = sum(sc.n_obs for sc in scenes)
+        tuner = binding.Solver(**opts).set_scenes(scenes)
+        tuner.iterate(10)
+        sched = binding.dba_schedule(tuner.h)
+        tuner.close()
+        s = binding.Solver(block_waves=sched["block_waves"], persistent=sched["persistent"], **opts)
+        s.set_scenes(scenes)
+        s.iterate(20)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        s.iterate(iters)
+        torch.cuda.synchronize()
+        ms = (time.perf_counter() - t0) * 1e3 / iters
+        binding.dba_set_kernel_timing(s.h, True)
+        s.iterate(10)
+        torch.cuda.synchronize()
+        kt = binding.dba_kernel_times(s.h)
+        s.close()
+        row = {"factor": f, "n_problems": len(scenes), "n_obs": L,
+               "n_cams": sum(sc.n_cams for sc in scenes), "n_points": sum(sc.n_points for sc in scenes),
+               "ms_per_iter": ms, "obs_updates_per_s": L / (ms * 1e-3), "schedule": sched,
+               "kernel_ms": {k: v[0] / v[1] for k, v in kt.items() if v[1]}}
+        rows.append(row)
+        print(f"[bench] size {L} ({len(scenes)} problem(s)): {ms:.4f} ms/iteration, "
+              f"{row['obs_updates_per_s']:.3e} obs-updates/s", file=sys.stderr, flush=True)
+    L = np.array([r["n_obs"] for r in rows], dtype=float)
+    t = np.array([r["ms_per_iter"] for r in rows])
+    A = np.stack([np.ones_like(L), L], 1)
+    (a, b), *_ = np.linalg.lstsq(A, t, rcond=None)
+    fit = A @ np.array([a, b])
+    r2 = 1.0 - ((t - fit) ** 2).sum() / ((t - t.mean()) ** 2).sum()
+    return {"rows": rows, "fit_intercept_ms": float(a), "fit_ns_per_obs": float(b * 1e6), "fit_r2": float(r2),
+            "max_rel_deviation_from_fit": float(np.max(np.abs(t - fit) / t))}
+
+
 def profile_learned(binding, wl):
     """Short learned-start run for counter collection: collects pairs on two
     training scenes, trains two epochs, then 20 learned-start iterations (3 LM
@@ -333,6 +389,9 @@ def main():
     ap.add_argument("--block-sweep", action="store_true",
                     help="trajectory workloads: also sweep the block size pi of the block local updates "
                          "(1..64 observations per block, 1 / 2 / 5 LM steps) to the oracle's final RMSE")
+    ap.add_argument("--size-sweep", action="store_true",
+                    help="also time one iteration at 0.125M..16M observations of trajectory problems "
+                         "(the workload's options)")
     ap.add_argument("--copy-probe-mib", type=int, default=0,
                     help="also run a plain device copy of this size (counter calibration)")
     args = ap.parse_args()
@@ -454,6 +513,9 @@ def main():
             ttr = time_to_rmse(binding, scenes[0], opts, sched, target)
             ttr["target_source"] = f"FP64 oracle, {its} iterations (tests/golden/trajectory.npz)"
             out["time_to_rmse"] = ttr
+
+    if args.size_sweep and args.workload.startswith("trajectory"):
+        out["size_sweep"] = size_sweep(binding, opts)
 
     if args.block_sweep and args.workload.startswith("trajectory"):
         target, its = oracle_target("trajectory")

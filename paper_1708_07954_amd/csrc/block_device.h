@@ -20,6 +20,89 @@ namespace dev {
 // Packed upper triangle of a symmetric 9x9 matrix: index of (i, j), i <= j.
 __host__ __device__ constexpr int sym9(int i, int j) { return i * 9 - i * (i - 1) / 2 + (j - i); }
 
+// Value of lane l ^ OFF for a 32-bit word, OFF in {1, 2, 4, 8}: DPP quad
+// permutations [1,0,3,2] and [2,3,0,1], a swizzle in bit mode (xor mask 4),
+// and a rotation by 8 within 16-lane rows, which is xor 8.
+template <int OFF>
+__device__ __forceinline__ int xor_lane_b32(int v)
+{
+    static_assert(OFF == 1 || OFF == 2 || OFF == 4 || OFF == 8, "offset");
+    if constexpr (OFF == 1) return __builtin_amdgcn_update_dpp(0, v, 0xB1, 0xF, 0xF, false);
+    else if constexpr (OFF == 2) return __builtin_amdgcn_update_dpp(0, v, 0x4E, 0xF, 0xF, false);
+    else if constexpr (OFF == 4) return __builtin_amdgcn_ds_swizzle(v, 0x101F);
+    else return __builtin_amdgcn_update_dpp(0, v, 0x128, 0xF, 0xF, false);
+}
+
+template <int OFF>
+__device__ __forceinline__ float xor_lane(float v)
+{
+    return __int_as_float(xor_lane_b32<OFF>(__float_as_int(v)));
+}
+
+template <int OFF>
+__device__ __forceinline__ double xor_lane(double v)
+{
+    const int lo = xor_lane_b32<OFF>(__double2loint(v)), hi = xor_lane_b32<OFF>(__double2hiint(v));
+    return __hiloint2double(hi, lo);
+}
+
+// Exchange of the upper OFF lanes of x with the lower OFF lanes of y within
+// each group of 2 OFF lanes (OFF 16 or 32: v_permlane16/32_swap).  Returns
+// x[l] + x[l ^ OFF] in lanes whose bit OFF is clear and y[l ^ OFF] + y[l] in
+// the others -- both partners add the same two numbers.
+template <int OFF>
+__device__ __forceinline__ float pair_swap_sum(float x, float y)
+{
+    static_assert(OFF == 16 || OFF == 32, "offset");
+    const unsigned a = __float_as_uint(x), b = __float_as_uint(y);
+    if constexpr (OFF == 32) {
+        const auto r = __builtin_amdgcn_permlane32_swap(a, b, false, false);
+        return __uint_as_float(r[0]) + __uint_as_float(r[1]);
+    } else {
+        const auto r = __builtin_amdgcn_permlane16_swap(a, b, false, false);
+        return __uint_as_float(r[0]) + __uint_as_float(r[1]);
+    }
+}
+
+template <int OFF>
+__device__ __forceinline__ double pair_swap_sum(double x, double y)
+{
+    static_assert(OFF == 16 || OFF == 32, "offset");
+    const unsigned xl = __double2loint(x), xh = __double2hiint(x), yl = __double2loint(y), yh = __double2hiint(y);
+    unsigned l0, l1, h0, h1;
+    if constexpr (OFF == 32) {
+        const auto rl = __builtin_amdgcn_permlane32_swap(xl, yl, false, false);
+        const auto rh = __builtin_amdgcn_permlane32_swap(xh, yh, false, false);
+        l0 = rl[0]; l1 = rl[1]; h0 = rh[0]; h1 = rh[1];
+    } else {
+        const auto rl = __builtin_amdgcn_permlane16_swap(xl, yl, false, false);
+        const auto rh = __builtin_amdgcn_permlane16_swap(xh, yh, false, false);
+        l0 = rl[0]; l1 = rl[1]; h0 = rh[0]; h1 = rh[1];
+    }
+    return __hiloint2double((int)h0, (int)l0) + __hiloint2double((int)h1, (int)l1);
+}
+
+// One level of the reduce-scatter with partner l ^ OFF: lanes whose bit OFF
+// is clear keep the first H of the 2H values, the others the last H, each
+// adding its partner's copy (the same pairing and operand order at every
+// level, so the sums never change).
+template <int H, int OFF, typename T>
+__device__ __forceinline__ void rs_level_x(const T *in, T *out, int lane)
+{
+    if constexpr (OFF >= 16) {
+#pragma unroll
+        for (int j = 0; j < H; ++j) out[j] = pair_swap_sum<OFF>(in[j], in[H + j]);
+    } else {
+        const bool upper = lane & OFF;
+#pragma unroll
+        for (int j = 0; j < H; ++j) {
+            const T keep = upper ? in[H + j] : in[j];
+            const T send = upper ? in[j] : in[H + j];
+            out[j] = keep + xor_lane<OFF>(send);
+        }
+    }
+}
+
 // Sums v[0..N) (N <= 64) over the wave in a fixed order and returns the sums
 // in every lane.  Reduce-scatter: at the level with offset o, lanes whose
 // bit o is clear keep the first half of their values, the others the second
@@ -33,13 +116,13 @@ __device__ __forceinline__ void wave_allreduce(const T *v, T *out, T *lds, int l
 #pragma unroll
     for (int j = 0; j < 64; ++j) a[j] = j < N ? v[j] : T(0);
     T b[32], c[16], d[8], e[4], f[2];
-    rs_level<32>(a, b, lane & 32, 32);
-    rs_level<16>(b, c, lane & 16, 16);
-    rs_level<8>(c, d, lane & 8, 8);
-    rs_level<4>(d, e, lane & 4, 4);
-    rs_level<2>(e, f, lane & 2, 2);
+    rs_level_x<32, 32>(a, b, lane);
+    rs_level_x<16, 16>(b, c, lane);
+    rs_level_x<8, 8>(c, d, lane);
+    rs_level_x<4, 4>(d, e, lane);
+    rs_level_x<2, 2>(e, f, lane);
     T g;
-    rs_level<1>(f, &g, lane & 1, 1);
+    rs_level_x<1, 1>(f, &g, lane);
     lds[lane] = g;
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
     __builtin_amdgcn_wave_barrier();
@@ -51,11 +134,17 @@ __device__ __forceinline__ void wave_allreduce(const T *v, T *out, T *lds, int l
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
+// Butterfly sum over the wave (partners l ^ 32, 16, 8, 4, 2, 1 in that
+// order); every lane ends with the same bits.
 template <typename T>
 __device__ __forceinline__ T wave_sum_t(T v)
 {
-#pragma unroll
-    for (int off = 32; off >= 1; off >>= 1) v += __shfl_xor(v, off, 64);
+    v = pair_swap_sum<32>(v, v);
+    v = pair_swap_sum<16>(v, v);
+    v += xor_lane<8>(v);
+    v += xor_lane<4>(v);
+    v += xor_lane<2>(v);
+    v += xor_lane<1>(v);
     return v;
 }
 

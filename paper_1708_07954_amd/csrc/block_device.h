@@ -20,109 +20,36 @@ namespace dev {
 // Packed upper triangle of a symmetric 9x9 matrix: index of (i, j), i <= j.
 __host__ __device__ constexpr int sym9(int i, int j) { return i * 9 - i * (i - 1) / 2 + (j - i); }
 
-// Value of lane l ^ OFF for a 32-bit word, OFF in {1, 2, 4, 8}: DPP quad
-// permutations [1,0,3,2] and [2,3,0,1], a swizzle in bit mode (xor mask 4),
-// and a rotation by 8 within 16-lane rows, which is xor 8.
-template <int OFF>
-__device__ __forceinline__ int xor_lane_b32(int v)
+// Fixed-order all-reduce of up to 63 values per lane over the wave, as a
+// reduce-scatter: at the level with offset o, lanes whose bit o is clear
+// keep the first half of their values, the others the second half, each
+// adding its partner's copy; after six levels lane l holds the total of
+// value l, which goes through 64 entries of LDS to every lane.  The values
+// are streamed in increasing index t into the first level (offset 32):
+// value t < 32 waits in b[t], value t >= 32 meets value t - 32, so at most
+// 32 partial sums are live.
+template <typename T>
+__device__ __forceinline__ void rs_first_put(T *b, int t, T v)
 {
-    static_assert(OFF == 1 || OFF == 2 || OFF == 4 || OFF == 8, "offset");
-    if constexpr (OFF == 1) return __builtin_amdgcn_update_dpp(0, v, 0xB1, 0xF, 0xF, false);
-    else if constexpr (OFF == 2) return __builtin_amdgcn_update_dpp(0, v, 0x4E, 0xF, 0xF, false);
-    else if constexpr (OFF == 4) return __builtin_amdgcn_ds_swizzle(v, 0x101F);
-    else return __builtin_amdgcn_update_dpp(0, v, 0x128, 0xF, 0xF, false);
+    if (t < 32)
+        b[t] = v;
+    else
+        b[t - 32] = pair_swap_sum<32>(b[t - 32], v);
 }
 
-template <int OFF>
-__device__ __forceinline__ float xor_lane(float v)
-{
-    return __int_as_float(xor_lane_b32<OFF>(__float_as_int(v)));
-}
-
-template <int OFF>
-__device__ __forceinline__ double xor_lane(double v)
-{
-    const int lo = xor_lane_b32<OFF>(__double2loint(v)), hi = xor_lane_b32<OFF>(__double2hiint(v));
-    return __hiloint2double(hi, lo);
-}
-
-// Exchange of the upper OFF lanes of x with the lower OFF lanes of y within
-// each group of 2 OFF lanes (OFF 16 or 32: v_permlane16/32_swap).  Returns
-// x[l] + x[l ^ OFF] in lanes whose bit OFF is clear and y[l ^ OFF] + y[l] in
-// the others -- both partners add the same two numbers.
-template <int OFF>
-__device__ __forceinline__ float pair_swap_sum(float x, float y)
-{
-    static_assert(OFF == 16 || OFF == 32, "offset");
-    const unsigned a = __float_as_uint(x), b = __float_as_uint(y);
-    if constexpr (OFF == 32) {
-        const auto r = __builtin_amdgcn_permlane32_swap(a, b, false, false);
-        return __uint_as_float(r[0]) + __uint_as_float(r[1]);
-    } else {
-        const auto r = __builtin_amdgcn_permlane16_swap(a, b, false, false);
-        return __uint_as_float(r[0]) + __uint_as_float(r[1]);
-    }
-}
-
-template <int OFF>
-__device__ __forceinline__ double pair_swap_sum(double x, double y)
-{
-    static_assert(OFF == 16 || OFF == 32, "offset");
-    const unsigned xl = __double2loint(x), xh = __double2hiint(x), yl = __double2loint(y), yh = __double2hiint(y);
-    unsigned l0, l1, h0, h1;
-    if constexpr (OFF == 32) {
-        const auto rl = __builtin_amdgcn_permlane32_swap(xl, yl, false, false);
-        const auto rh = __builtin_amdgcn_permlane32_swap(xh, yh, false, false);
-        l0 = rl[0]; l1 = rl[1]; h0 = rh[0]; h1 = rh[1];
-    } else {
-        const auto rl = __builtin_amdgcn_permlane16_swap(xl, yl, false, false);
-        const auto rh = __builtin_amdgcn_permlane16_swap(xh, yh, false, false);
-        l0 = rl[0]; l1 = rl[1]; h0 = rh[0]; h1 = rh[1];
-    }
-    return __hiloint2double((int)h0, (int)l0) + __hiloint2double((int)h1, (int)l1);
-}
-
-// One level of the reduce-scatter with partner l ^ OFF: lanes whose bit OFF
-// is clear keep the first H of the 2H values, the others the last H, each
-// adding its partner's copy (the same pairing and operand order at every
-// level, so the sums never change).
-template <int H, int OFF, typename T>
-__device__ __forceinline__ void rs_level_x(const T *in, T *out, int lane)
-{
-    if constexpr (OFF >= 16) {
-#pragma unroll
-        for (int j = 0; j < H; ++j) out[j] = pair_swap_sum<OFF>(in[j], in[H + j]);
-    } else {
-        const bool upper = lane & OFF;
-#pragma unroll
-        for (int j = 0; j < H; ++j) {
-            const T keep = upper ? in[H + j] : in[j];
-            const T send = upper ? in[j] : in[H + j];
-            out[j] = keep + xor_lane<OFF>(send);
-        }
-    }
-}
-
-// Sums v[0..N) (N <= 64) over the wave in a fixed order and returns the sums
-// in every lane.  Reduce-scatter: at the level with offset o, lanes whose
-// bit o is clear keep the first half of their values, the others the second
-// half, each adding its partner's copy; after six levels lane l holds the
-// total of value l, which goes through 64 entries of LDS to every lane.
+// The remaining five levels and the broadcast: returns the N sums in every
+// lane.
 template <typename T, int N>
-__device__ __forceinline__ void wave_allreduce(const T *v, T *out, T *lds, int lane)
+__device__ __forceinline__ void wave_allreduce_tail(const T *b, T *out, T *lds, int lane)
 {
     static_assert(N <= 64, "at most 64 values");
-    T a[64];
-#pragma unroll
-    for (int j = 0; j < 64; ++j) a[j] = j < N ? v[j] : T(0);
-    T b[32], c[16], d[8], e[4], f[2];
-    rs_level_x<32, 32>(a, b, lane);
-    rs_level_x<16, 16>(b, c, lane);
-    rs_level_x<8, 8>(c, d, lane);
-    rs_level_x<4, 4>(d, e, lane);
-    rs_level_x<2, 2>(e, f, lane);
+    T c[16], d[8], e[4], f[2];
+    rs_level<16, 16>(b, c, lane);
+    rs_level<8, 8>(c, d, lane);
+    rs_level<4, 4>(d, e, lane);
+    rs_level<2, 2>(e, f, lane);
     T g;
-    rs_level_x<1, 1>(f, &g, lane);
+    rs_level<1, 1>(f, &g, lane);
     lds[lane] = g;
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
     __builtin_amdgcn_wave_barrier();
@@ -134,40 +61,31 @@ __device__ __forceinline__ void wave_allreduce(const T *v, T *out, T *lds, int l
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
-// Butterfly sum over the wave (partners l ^ 32, 16, 8, 4, 2, 1 in that
-// order); every lane ends with the same bits.
-template <typename T>
-__device__ __forceinline__ T wave_sum_t(T v)
-{
-    v = pair_swap_sum<32>(v, v);
-    v = pair_swap_sum<16>(v, v);
-    v += xor_lane<8>(v);
-    v += xor_lane<4>(v);
-    v += xor_lane<2>(v);
-    v += xor_lane<1>(v);
-    return v;
-}
-
 // Solves the symmetric 9x9 system A x = b (packed upper A) by LDL^T; false
 // if a pivot is not positive and finite.
 template <typename R>
 __device__ __forceinline__ bool ldl9_solve(const R *A, const R *b, R *x)
 {
-    R L[45], D[9];
+    R L[45], D[9], iD[9];
     bool ok = true;
 #pragma unroll
     for (int j = 0; j < 9; ++j) {
+        // t_k = L(j, k) D_k, then every update of column j is one FMA
+        R t[9];
+#pragma unroll
+        for (int k = 0; k < j; ++k) t[k] = L[sym9(k, j)] * D[k];
         R dj = A[sym9(j, j)];
 #pragma unroll
-        for (int k = 0; k < j; ++k) dj -= L[sym9(k, j)] * L[sym9(k, j)] * D[k];
+        for (int k = 0; k < j; ++k) dj -= L[sym9(k, j)] * t[k];
         ok = ok && (dj > R(0)) && (dj < Num<R>::inf);
         D[j] = dj;
         const R idj = Num<R>::rcp(dj);
+        iD[j] = idj;
 #pragma unroll
         for (int i = j + 1; i < 9; ++i) {
             R s = A[sym9(j, i)];
 #pragma unroll
-            for (int k = 0; k < j; ++k) s -= L[sym9(k, i)] * L[sym9(k, j)] * D[k];
+            for (int k = 0; k < j; ++k) s -= L[sym9(k, i)] * t[k];
             L[sym9(j, i)] = s * idj;   // L(i, j) stored at (j, i)
         }
     }
@@ -181,7 +99,7 @@ __device__ __forceinline__ bool ldl9_solve(const R *A, const R *b, R *x)
     }
 #pragma unroll
     for (int i = 8; i >= 0; --i) {
-        R s = y[i] * Num<R>::rcp(D[i]);
+        R s = y[i] * iD[i];
 #pragma unroll
         for (int k = i + 1; k < 9; ++k) s -= L[sym9(i, k)] * x[k];
         x[i] = s;
@@ -227,7 +145,7 @@ __device__ __forceinline__ void block_lm(R *th, const R *vy, const R *vx, R z0, 
         cur = proj_core<R, true>(th);
         fk = lane_objective<R>(cur, th, vx, z0, z1, rx, kind, lp);
     }
-    R F = wave_sum_t<R>(fk) + camera_penalty<R>(th, vy, ry);
+    R F = wave_sum<R>(fk) + camera_penalty<R>(th, vy, ry);
     for (int it = 0; it < steps; ++it) {
         // linearisation at (y, x_k): J = [U^T | V^T] with U = (J0_y, J1_y)
         // (9x2) and V = (J0_x, J1_x) (3x2); the lane's blocks of the normal
@@ -258,7 +176,7 @@ __device__ __forceinline__ void block_lm(R *th, const R *vy, const R *vx, R z0, 
                 V1[c] = J1[9 + c];
             }
         }
-        const R fres = F + wave_sum_t<R>(fr);
+        const R fres = F + wave_sum<R>(fr);
         // point block H_xx = c V V^T + rho_x I, damped, inverted (adjugate)
         R hx[6], ngx[3];
         hx[0] = rx + c2 * (V0[0] * V0[0] + V1[0] * V1[0]);
@@ -304,17 +222,28 @@ __device__ __forceinline__ void block_lm(R *th, const R *vy, const R *vx, R z0, 
         const R h0 = V0[0] * Bn[0] + V0[1] * Bn[1] + V0[2] * Bn[2];
         const R h1 = V1[0] * Bn[0] + V1[1] * Bn[1] + V1[2] * Bn[2];
         const R r0 = c2 * (e0 - h0), r1 = c2 * (e1 - h1);
-        R red[63];
+        // the lane's 63 values, streamed into the first level of the
+        // all-reduce in packed order: the Schur contribution's upper
+        // triangle (U0_i q0_j + U1_i q1_j with q = M U^T), c |U_i|^2 (the
+        // undamped diagonal of the camera block) and U_i . r
+        R q0[9], q1[9];
 #pragma unroll
         for (int j = 0; j < 9; ++j) {
-            const R q0 = M00 * U0[j] + M01 * U1[j], q1 = M01 * U0[j] + M11 * U1[j];
-#pragma unroll
-            for (int i = 0; i <= j; ++i) red[sym9(i, j)] = U0[i] * q0 + U1[i] * q1;
-            red[45 + j] = c2 * (U0[j] * U0[j] + U1[j] * U1[j]);
-            red[54 + j] = U0[j] * r0 + U1[j] * r1;
+            q0[j] = M00 * U0[j] + M01 * U1[j];
+            q1[j] = M01 * U0[j] + M11 * U1[j];
         }
+        R b32[32];
+#pragma unroll
+        for (int i = 0; i < 9; ++i)
+#pragma unroll
+            for (int j = i; j < 9; ++j) rs_first_put<R>(b32, sym9(i, j), U0[i] * q0[j] + U1[i] * q1[j]);
+#pragma unroll
+        for (int i = 0; i < 9; ++i) rs_first_put<R>(b32, 45 + i, c2 * (U0[i] * U0[i] + U1[i] * U1[i]));
+#pragma unroll
+        for (int i = 0; i < 9; ++i) rs_first_put<R>(b32, 54 + i, U0[i] * r0 + U1[i] * r1);
+        rs_first_put<R>(b32, 63, R(0));
         R sum[63];
-        wave_allreduce<R, 63>(red, sum, lds, lane);
+        wave_allreduce_tail<R, 63>(b32, sum, lds, lane);
         // camera system: S = A_yy - sum_k W B W^T, rhs = ng_y - sum_k W B ng_x
         R Sy[45], ry9[9], dy[9];
 #pragma unroll
@@ -349,7 +278,7 @@ __device__ __forceinline__ void block_lm(R *th, const R *vy, const R *vx, R z0, 
             gdy += ry9[i] * dy[i];
             ddy += (ry + sum[45 + i]) * dy[i] * dy[i];
         }
-        const R pred = R(0.5) * (wave_sum_t<R>(pk) + gdy + lam * ddy);
+        const R pred = R(0.5) * (wave_sum<R>(pk) + gdy + lam * ddy);
         // trial point and its objective
         R tr[12];
 #pragma unroll
@@ -363,7 +292,7 @@ __device__ __forceinline__ void block_lm(R *th, const R *vy, const R *vx, R z0, 
             fn = lane_objective<R>(nxt, tr, vx, z0, z1, rx, kind, lp);
         }
         const bool bad = __ballot(!(fn < Num<R>::inf)) != 0ull;
-        const R Fn = (ok && !bad) ? wave_sum_t<R>(fn) + camera_penalty<R>(tr, vy, ry) : Num<R>::inf;
+        const R Fn = (ok && !bad) ? wave_sum<R>(fn) + camera_penalty<R>(tr, vy, ry) : Num<R>::inf;
         if (Fn < Num<R>::inf && (Fn < F || pred <= Num<R>::tie * fres)) {
 #pragma unroll
             for (int i = 0; i < 12; ++i) th[i] = tr[i];

@@ -336,25 +336,101 @@ __device__ __forceinline__ void local_lm(R *th, const R *v, R z0, R z1, R rx, R 
     lm_steps<R>(th, cur, F, v, z0, z1, rx, ry, kind, lp, steps, lam);
 }
 
-__device__ __forceinline__ double wave_sum(double v)
+// Value of lane l ^ OFF for a 32-bit word, OFF in {1, 2, 4, 8}: DPP quad
+// permutations [1,0,3,2] and [2,3,0,1], a swizzle in bit mode (xor mask 4),
+// and a rotation by 8 within 16-lane rows, which is xor 8.
+template <int OFF>
+__device__ __forceinline__ int xor_lane_b32(int v)
 {
-#pragma unroll
-    for (int off = 32; off >= 1; off >>= 1) v += __shfl_xor(v, off, 64);
-    return v;
+    static_assert(OFF == 1 || OFF == 2 || OFF == 4 || OFF == 8, "offset");
+    if constexpr (OFF == 1) return __builtin_amdgcn_update_dpp(0, v, 0xB1, 0xF, 0xF, false);
+    else if constexpr (OFF == 2) return __builtin_amdgcn_update_dpp(0, v, 0x4E, 0xF, 0xF, false);
+    else if constexpr (OFF == 4) return __builtin_amdgcn_ds_swizzle(v, 0x101F);
+    else return __builtin_amdgcn_update_dpp(0, v, 0x128, 0xF, 0xF, false);
 }
 
-// One level of a reduce-scatter over the wave: lanes whose bit `off` is clear
-// keep the first H of the 2H values, the others the last H, each adding its
-// partner's copy.  Fixed pairing, so the summation order never changes.
-template <int H, typename T>
-__device__ __forceinline__ void rs_level(const T *in, T *out, bool upper, int off)
+template <int OFF>
+__device__ __forceinline__ float xor_lane(float v)
 {
-#pragma unroll
-    for (int j = 0; j < H; ++j) {
-        const T keep = upper ? in[H + j] : in[j];
-        const T send = upper ? in[j] : in[H + j];
-        out[j] = keep + __shfl_xor(send, off, 64);
+    return __int_as_float(xor_lane_b32<OFF>(__float_as_int(v)));
+}
+
+template <int OFF>
+__device__ __forceinline__ double xor_lane(double v)
+{
+    const int lo = xor_lane_b32<OFF>(__double2loint(v)), hi = xor_lane_b32<OFF>(__double2hiint(v));
+    return __hiloint2double(hi, lo);
+}
+
+// Exchange of the upper OFF lanes of x with the lower OFF lanes of y within
+// each group of 2 OFF lanes (OFF 16 or 32: v_permlane16/32_swap).  Returns
+// x[l] + x[l ^ OFF] in lanes whose bit OFF is clear and y[l ^ OFF] + y[l] in
+// the others -- both partners add the same two numbers.
+template <int OFF>
+__device__ __forceinline__ float pair_swap_sum(float x, float y)
+{
+    static_assert(OFF == 16 || OFF == 32, "offset");
+    const unsigned a = __float_as_uint(x), b = __float_as_uint(y);
+    if constexpr (OFF == 32) {
+        const auto r = __builtin_amdgcn_permlane32_swap(a, b, false, false);
+        return __uint_as_float(r[0]) + __uint_as_float(r[1]);
+    } else {
+        const auto r = __builtin_amdgcn_permlane16_swap(a, b, false, false);
+        return __uint_as_float(r[0]) + __uint_as_float(r[1]);
     }
+}
+
+template <int OFF>
+__device__ __forceinline__ double pair_swap_sum(double x, double y)
+{
+    static_assert(OFF == 16 || OFF == 32, "offset");
+    const unsigned xl = __double2loint(x), xh = __double2hiint(x), yl = __double2loint(y), yh = __double2hiint(y);
+    unsigned l0, l1, h0, h1;
+    if constexpr (OFF == 32) {
+        const auto rl = __builtin_amdgcn_permlane32_swap(xl, yl, false, false);
+        const auto rh = __builtin_amdgcn_permlane32_swap(xh, yh, false, false);
+        l0 = rl[0]; l1 = rl[1]; h0 = rh[0]; h1 = rh[1];
+    } else {
+        const auto rl = __builtin_amdgcn_permlane16_swap(xl, yl, false, false);
+        const auto rh = __builtin_amdgcn_permlane16_swap(xh, yh, false, false);
+        l0 = rl[0]; l1 = rl[1]; h0 = rh[0]; h1 = rh[1];
+    }
+    return __hiloint2double((int)h0, (int)l0) + __hiloint2double((int)h1, (int)l1);
+}
+
+// One level of the reduce-scatter with partner l ^ OFF: lanes whose bit OFF
+// is clear keep the first H of the 2H values, the others the last H, each
+// adding its partner's copy (the same pairing and operand order at every
+// level, so the sums never change).
+template <int H, int OFF, typename T>
+__device__ __forceinline__ void rs_level(const T *in, T *out, int lane)
+{
+    if constexpr (OFF >= 16) {
+#pragma unroll
+        for (int j = 0; j < H; ++j) out[j] = pair_swap_sum<OFF>(in[j], in[H + j]);
+    } else {
+        const bool upper = lane & OFF;
+#pragma unroll
+        for (int j = 0; j < H; ++j) {
+            const T keep = upper ? in[H + j] : in[j];
+            const T send = upper ? in[j] : in[H + j];
+            out[j] = keep + xor_lane<OFF>(send);
+        }
+    }
+}
+
+// Butterfly sum over the wave (partners l ^ 32, 16, 8, 4, 2, 1 in that
+// order); every lane ends with the same bits.
+template <typename T>
+__device__ __forceinline__ T wave_sum(T v)
+{
+    v = pair_swap_sum<32>(v, v);
+    v = pair_swap_sum<16>(v, v);
+    v += xor_lane<8>(v);
+    v += xor_lane<4>(v);
+    v += xor_lane<2>(v);
+    v += xor_lane<1>(v);
+    return v;
 }
 
 // Sums the 19 per-lane values v[0..18] over the 64 lanes of the wave and
@@ -367,15 +443,15 @@ __device__ __forceinline__ void wave_sum19_store(const double *v, double *o, int
     for (int j = 0; j < 19; ++j) a[j] = v[j];
     a[19] = 0.0;
     const bool b5 = lane & 32, b4 = lane & 16, b3 = lane & 8, b2 = lane & 4, b1 = lane & 2;
-    rs_level<10>(a, b, b5, 32);     // values 10 b5 + [0, 10)
-    rs_level<5>(b, c, b4, 16);      // + 5 b4 + [0, 5)
+    rs_level<10, 32>(a, b, lane);     // values 10 b5 + [0, 10)
+    rs_level<5, 16>(b, c, lane);     // + 5 b4 + [0, 5)
     c[5] = 0.0;
-    rs_level<3>(c, d, b3, 8);       // + 3 b3 + [0, 3)   (position 5 is padding)
+    rs_level<3, 8>(c, d, lane);       // + 3 b3 + [0, 3)   (position 5 is padding)
     d[3] = 0.0;
-    rs_level<2>(d, e, b2, 4);       // + 2 b2 + [0, 2)   (position 3 is padding)
+    rs_level<2, 4>(d, e, lane);       // + 2 b2 + [0, 2)   (position 3 is padding)
     double f;
-    rs_level<1>(e, &f, b1, 2);      // + b1
-    f += __shfl_xor(f, 1, 64);
+    rs_level<1, 2>(e, &f, lane);      // + b1
+    f += xor_lane<1>(f);
     const int inner = 2 * b2 + b1, mid = 3 * b3 + inner;
     const int k = 10 * b5 + 5 * b4 + mid;
     if (!(lane & 1) && inner < 3 && mid < 5 && k < 19) o[k] = f;

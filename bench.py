@@ -77,10 +77,17 @@ def kernel_source_hash():
     return h.hexdigest()[:12]
 
 
+# committed counter summary of each workload's local-solve kernel
+COUNTER_SUMMARIES = {"trajectory": "local_solve_trajectory_counters.md",
+                     "trajectory_blocks": "block_local_trajectory.md"}
+
+
 def recorded_traffic(workload):
     """HBM bytes per local-solve launch from the committed counter summary,
     if it was taken on the current kernel source."""
-    path = os.path.join(ROOT, "profiles", f"local_solve_{workload}_counters.md")
+    if workload not in COUNTER_SUMMARIES:
+        return None, None
+    path = os.path.join(ROOT, "profiles", COUNTER_SUMMARIES[workload])
     if not os.path.exists(path):
         return None, None
     text = open(path).read()

@@ -173,8 +173,13 @@ int dba_problem_info(const dba_handle *h, int32_t problem, int32_t *n_cams, int3
                      int64_t *n_obs);
 
 /* Kernel timing: while enabled, dba_iterate records HIP events around each
- * kernel on the handle's stream (graphs are not used).  Kernel ids:
+ * kernel on the handle's stream -- with use_graph, as event-record nodes of
+ * graphs captured for timing (two per graph size, so one replay's times are
+ * read while the next runs; eager launches if the capture is refused),
+ * otherwise around eager launches.  Kernel ids:
  * 0 local solve, 1 consensus, 2 residual norms, 3 learned warm start.
+ * enable: 0 off, 1 every kernel, 2 the local solve only (ids 0 and 3; two
+ * events per iteration instead of six); other values DBA_E_INVALID_ARG.
  * dba_kernel_times returns, per id, total milliseconds and launch counts
  * since timing was enabled (synchronises the stream). */
 int dba_set_kernel_timing(dba_handle *h, int32_t enable);

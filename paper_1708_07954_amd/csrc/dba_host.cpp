@@ -21,6 +21,13 @@ void drop_graphs(dba_handle *h)
         if (g) (void)hipGraphExecDestroy(g);
         g = nullptr;
     }
+    for (auto &row : h->tgraph)
+        for (TimedGraph &t : row) {
+            if (t.exec) (void)hipGraphExecDestroy(t.exec);
+            for (hipEvent_t e : t.ev) (void)hipEventDestroy(e);
+            t = TimedGraph();
+        }
+    h->tgraph_next[0] = h->tgraph_next[1] = 0;
 }
 
 // Depth P_3 of R(w) X + t (host-side validation only).
@@ -309,28 +316,20 @@ hipError_t launch_local_sel(dba_handle *h, const DevArrays<R> &A, int bw, int pe
     return dba::launch_local<R>(A, h->sp, bw, pers, h->n_cu, h->stream);
 }
 
-// One ADMM iteration, eager.
-template <typename R>
-hipError_t run_iteration(dba_handle *h, const DevArrays<R> &A, int bw, int pers, bool timed)
+// One ADMM iteration: the three launches on the handle's stream.  mark(kid)
+// is called before each launch with its kernel id and returns the event to
+// record after it (recording its start event itself), or nullptr; external
+// records those events as event-record nodes of a graph being captured.
+template <typename R, typename Mark>
+hipError_t run_iteration_marked(dba_handle *h, const DevArrays<R> &A, int bw, int pers, Mark mark,
+                                bool external = false)
 {
-    Timing &T = h->timing;
-    auto mark = [&](int kid) -> hipEvent_t {
-        if (!timed) return nullptr;
-        if (T.used + 2 > T.pool.size()) {
-            for (int q = 0; q < 64; ++q) {
-                hipEvent_t e;
-                if (hipEventCreate(&e) != hipSuccess) return nullptr;
-                T.pool.push_back(e);
-            }
-        }
-        hipEvent_t e0 = T.pool[T.used];
-        (void)hipEventRecord(e0, h->stream);
-        T.pending_kernel.push_back(kid);
-        T.used += 2;
-        return T.pool[T.used - 1];
-    };
     auto done = [&](hipEvent_t e1) {
-        if (e1) (void)hipEventRecord(e1, h->stream);
+        if (!e1) return;
+        if (external)
+            (void)hipEventRecordWithFlags(e1, h->stream, hipEventRecordExternal);
+        else
+            (void)hipEventRecord(e1, h->stream);
     };
     hipEvent_t e;
     hipError_t err;
@@ -348,9 +347,130 @@ hipError_t run_iteration(dba_handle *h, const DevArrays<R> &A, int bw, int pers,
     return err;
 }
 
+inline hipEvent_t no_mark(int) { return nullptr; }
+
+// Eager iteration; with timed, each kernel between two events of the
+// handle's pool (read by collect_timing).
+template <typename R>
+hipError_t run_iteration(dba_handle *h, const DevArrays<R> &A, int bw, int pers, bool timed)
+{
+    if (!timed) return run_iteration_marked<R>(h, A, bw, pers, no_mark);
+    Timing &T = h->timing;
+    auto mark = [&](int kid) -> hipEvent_t {
+        if (!(T.mask >> kid & 1u)) return nullptr;
+        if (T.used + 2 > T.pool.size()) {
+            for (int q = 0; q < 64; ++q) {
+                hipEvent_t e;
+                if (hipEventCreate(&e) != hipSuccess) return nullptr;
+                T.pool.push_back(e);
+            }
+        }
+        hipEvent_t e0 = T.pool[T.used];
+        (void)hipEventRecord(e0, h->stream);
+        T.pending_kernel.push_back(kid);
+        T.used += 2;
+        return T.pool[T.used - 1];
+    };
+    return run_iteration_marked<R>(h, A, bw, pers, mark);
+}
+
+int collect_timing(dba_handle *h);
+
+// Reads a launched timed graph's kernel times (waits for its last event).
+int collect_graph_times(dba_handle *h, TimedGraph &g)
+{
+    if (!g.pending) return DBA_OK;
+    HIP_TRY(h, hipEventSynchronize(g.ev.back()));
+    for (size_t q = 0; q < g.kid.size(); ++q) {
+        float ms = 0.f;
+        HIP_TRY(h, hipEventElapsedTime(&ms, g.ev[2 * q], g.ev[2 * q + 1]));
+        h->timing.total_ms[g.kid[q]] += ms;
+        h->timing.launches[g.kid[q]] += 1;
+    }
+    g.pending = false;
+    return DBA_OK;
+}
+
+// Captures the four timed graphs (1 and kGraphBatch iterations, two of
+// each).  false (and timed graphs off for the handle) if the capture of
+// event records is refused.
+template <typename R>
+bool timed_graphs_ready(dba_handle *h, const DevArrays<R> &A)
+{
+    if (h->tgraph[0][0].exec && h->tgraph_mask != h->timing.mask) {
+        if (collect_timing(h) != DBA_OK) return false;
+        drop_graphs(h);
+    }
+    h->tgraph_mask = h->timing.mask;
+    for (int sz = 0; sz < 2; ++sz)
+        for (int b = 0; b < 2; ++b) {
+            TimedGraph &g = h->tgraph[sz][b];
+            if (g.exec) continue;
+            const int iters = sz == 0 ? 1 : kGraphBatch;
+            bool ok = true;
+            auto mark = [&](int kid) -> hipEvent_t {
+                if (!(h->timing.mask >> kid & 1u)) return nullptr;
+                hipEvent_t e0, e1;
+                if (hipEventCreate(&e0) != hipSuccess) { ok = false; return nullptr; }
+                if (hipEventCreate(&e1) != hipSuccess) {
+                    (void)hipEventDestroy(e0);
+                    ok = false;
+                    return nullptr;
+                }
+                g.ev.push_back(e0);
+                g.ev.push_back(e1);
+                g.kid.push_back(kid);
+                if (hipEventRecordWithFlags(e0, h->stream, hipEventRecordExternal) != hipSuccess) ok = false;
+                return e1;
+            };
+            hipGraph_t graph = nullptr;
+            if (hipStreamBeginCapture(h->stream, hipStreamCaptureModeThreadLocal) != hipSuccess) ok = false;
+            hipError_t err = hipSuccess;
+            for (int it = 0; ok && it < iters && err == hipSuccess; ++it)
+                err = run_iteration_marked<R>(h, A, h->block_waves, h->persistent, mark, true);
+            hipError_t e2 = hipStreamEndCapture(h->stream, &graph);
+            ok = ok && err == hipSuccess && e2 == hipSuccess && graph;
+            if (ok) ok = hipGraphInstantiate(&g.exec, graph, nullptr, nullptr, 0) == hipSuccess;
+            if (graph) (void)hipGraphDestroy(graph);
+            if (!ok) {
+                (void)hipGetLastError();
+                drop_graphs(h);
+                h->tgraph_off = true;
+                return false;
+            }
+        }
+    return true;
+}
+
+// Timed iterations replayed from the timed graphs; every replay's times are
+// read before its graph is launched again and at the end.
+template <typename R>
+int iterate_timed_graphs(dba_handle *h, int n)
+{
+    auto launch = [&](int sz) -> int {
+        TimedGraph &g = h->tgraph[sz][h->tgraph_next[sz]];
+        int rc = collect_graph_times(h, g);
+        if (rc != DBA_OK) return rc;
+        HIP_TRY(h, hipGraphLaunch(g.exec, h->stream));
+        g.pending = true;
+        h->tgraph_next[sz] ^= 1;
+        return DBA_OK;
+    };
+    int rc = DBA_OK;
+    for (; rc == DBA_OK && n >= kGraphBatch; n -= kGraphBatch) rc = launch(1);
+    for (; rc == DBA_OK && n > 0; --n) rc = launch(0);
+    if (rc != DBA_OK) return rc;
+    return collect_timing(h);
+}
+
 int collect_timing(dba_handle *h)
 {
     Timing &T = h->timing;
+    for (auto &row : h->tgraph)
+        for (TimedGraph &g : row) {
+            int rc = collect_graph_times(h, g);
+            if (rc != DBA_OK) return rc;
+        }
     if (T.used == 0) return DBA_OK;
     HIP_TRY(h, hipStreamSynchronize(h->stream));
     for (size_t q = 0; q < T.pending_kernel.size(); ++q) {
@@ -411,6 +531,8 @@ int iterate_impl(dba_handle *h, const DevArrays<R> &A, int n)
         }
     }
     if (n <= 0) return DBA_OK;
+    if (h->timing.on && h->opt.use_graph && !h->tgraph_off && timed_graphs_ready<R>(h, A))
+        return iterate_timed_graphs<R>(h, n);
     if (h->timing.on || !h->opt.use_graph) {
         for (int it = 0; it < n; ++it) HIP_TRY(h, run_iteration<R>(h, A, h->block_waves, h->persistent, h->timing.on));
         if (h->timing.on) return collect_timing(h);
@@ -730,9 +852,12 @@ int dba_set_kernel_timing(dba_handle *h, int32_t enable)
 {
     if (!h) return DBA_E_INVALID_ARG;
     h->err.clear();
+    if (enable < 0 || enable > 2) return fail(h, DBA_E_INVALID_ARG, "timing mode %d", enable);
     int rc = collect_timing(h);
     if (rc != DBA_OK) return rc;
     h->timing.on = enable != 0;
+    // 1: every kernel; 2: the local solve only (ids 0 and 3)
+    h->timing.mask = enable == 2 ? 0x9u : 0xFu;
     for (int k = 0; k < kKernels; ++k) {
         h->timing.total_ms[k] = 0.0;
         h->timing.launches[k] = 0;

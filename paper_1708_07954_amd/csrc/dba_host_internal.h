@@ -54,11 +54,22 @@ struct ProblemSet {
 
 struct Timing {
     bool on = false;
+    unsigned mask = 0xF;  // kernel ids timed (bit per id)
     double total_ms[kKernels] = {0, 0, 0, 0};
     long long launches[kKernels] = {0, 0, 0, 0};
     std::vector<hipEvent_t> pool;
     std::vector<int> pending_kernel;  // kernel id per recorded pair
     size_t used = 0;
+};
+
+// A captured graph of iterations whose kernels are bracketed by event-record
+// nodes, for timed iterations on the graph path.  Two per graph size: one
+// replay's times are read while the other replay runs.
+struct TimedGraph {
+    hipGraphExec_t exec = nullptr;
+    std::vector<hipEvent_t> ev;  // two per kernel launch, in launch order
+    std::vector<int> kid;        // kernel id per pair
+    bool pending = false;        // launched, times not yet read
 };
 
 // The learned warm start's network on the device.
@@ -96,6 +107,11 @@ struct dba_handle {
     // graphs: [0] one iteration, [1] kGraphBatch iterations
     hipGraphExec_t gexec[2] = {nullptr, nullptr};
     dba::host::Timing timing;
+    // timed graphs [size as gexec][buffer]; off after a failed capture
+    dba::host::TimedGraph tgraph[2][2];
+    unsigned tgraph_mask = 0;  // the timing mask the timed graphs were captured with
+    int tgraph_next[2] = {0, 0};
+    bool tgraph_off = false;
     // learned warm start
     int start = DBA_START_PLAIN;
     dba::host::Mlp *mlp = nullptr;

@@ -1,0 +1,75 @@
+"""Per-kernel timing (dba_set_kernel_timing / dba_kernel_times): timed
+iterations replayed from the captured graphs (event-record nodes around each
+kernel) and eager timed iterations both count every launch, report positive
+times that agree, and leave the iterates bitwise unchanged."""
+import numpy as np
+import pytest
+
+from paper_1708_07954_amd import binding
+from scenes import make_sphere_scene
+
+pytestmark = pytest.mark.gpu
+
+KW = dict(precision="fp32", loss="student_t", loss_param=4.0, rho=1e3, block_waves=1, persistent=0)
+
+
+def run(sc, n, timed, use_graph):
+    s = binding.Solver(use_graph=use_graph, **KW).set_scene(sc)
+    s.iterate(2)  # the schedule's warm-up and single candidate, untimed
+    if timed:
+        binding.dba_set_kernel_timing(s.h, True)
+    s.iterate(n)
+    kt = binding.dba_kernel_times(s.h) if timed else None
+    cams, pts = s.params()
+    s.close()
+    return cams, pts, kt
+
+
+@pytest.mark.parametrize("n", [1, 16, 37])
+def test_timed_iterations_count_every_launch_and_change_nothing(n):
+    sc = make_sphere_scene(seed=21, n_cams=30, n_points=3000)
+    ref_c, ref_p, _ = run(sc, n, False, True)
+    avg = {}
+    for use_graph in (True, False):
+        c, p, kt = run(sc, n, True, use_graph)
+        assert np.array_equal(c, ref_c) and np.array_equal(p, ref_p), use_graph
+        for k in ("local", "consensus", "norms"):
+            total, launches = kt[k]
+            assert launches == n and total > 0, (use_graph, k, kt[k])
+        avg[use_graph] = kt["local"][0] / n
+    print(n, "local kernel ms, graph / eager:", avg[True], avg[False])
+    assert 0.5 < avg[True] / avg[False] < 2.0
+
+
+def test_timing_off_again_uses_the_untimed_graphs():
+    sc = make_sphere_scene(seed=22, n_cams=20, n_points=1500)
+    s = binding.Solver(**KW).set_scene(sc)
+    s.iterate(2)
+    binding.dba_set_kernel_timing(s.h, True)
+    s.iterate(20)
+    binding.dba_set_kernel_timing(s.h, False)
+    s.iterate(20)
+    kt = binding.dba_kernel_times(s.h)
+    assert kt["local"][1] == 0
+    c, p = s.params()
+    s.close()
+    ref_c, ref_p, _ = run(sc, 40, False, True)
+    assert np.array_equal(c, ref_c) and np.array_equal(p, ref_p)
+
+
+def test_local_only_timing_times_the_local_solve_alone():
+    sc = make_sphere_scene(seed=23, n_cams=20, n_points=1500)
+    s = binding.Solver(**KW).set_scene(sc)
+    s.iterate(2)
+    binding.dba_set_kernel_timing(s.h, True, local_only=True)
+    s.iterate(21)
+    kt = binding.dba_kernel_times(s.h)
+    assert kt["local"][1] == 21 and kt["local"][0] > 0
+    assert kt["consensus"][1] == 0 and kt["norms"][1] == 0
+    # switching back to every kernel recaptures the timed graphs
+    binding.dba_set_kernel_timing(s.h, True)
+    s.iterate(17)
+    kt = binding.dba_kernel_times(s.h)
+    assert all(kt[k][1] == 17 for k in ("local", "consensus", "norms"))
+    assert binding.STATUS[binding.load().dba_set_kernel_timing(s.h, 3)] == "DBA_E_INVALID_ARG"
+    s.close()

@@ -505,19 +505,20 @@ int iterate_impl(dba_handle *h, const DevArrays<R> &A, int n)
             continue;
         }
         const int q = idx[h->tune_next - 1];
-        hipEvent_t e0, e1;
-        HIP_TRY(h, hipEventCreate(&e0));
-        HIP_TRY(h, hipEventCreate(&e1));
-        HIP_TRY(h, hipEventRecord(e0, h->stream));
-        HIP_TRY(h, launch_local_sel<R>(h, A, cand_bw[q], cand_p[q]));
-        HIP_TRY(h, hipEventRecord(e1, h->stream));
-        HIP_TRY(h, dba::launch_consensus<R>(A, h->stream));
-        HIP_TRY(h, dba::launch_norms<R>(A, h->stream));
-        HIP_TRY(h, hipEventSynchronize(e1));
+        hipEvent_t e0 = nullptr, e1 = nullptr;
         float ms = 0.f;
-        HIP_TRY(h, hipEventElapsedTime(&ms, e0, e1));
-        (void)hipEventDestroy(e0);
-        (void)hipEventDestroy(e1);
+        hipError_t err = hipEventCreate(&e0);
+        if (err == hipSuccess) err = hipEventCreate(&e1);
+        if (err == hipSuccess) err = hipEventRecord(e0, h->stream);
+        if (err == hipSuccess) err = launch_local_sel<R>(h, A, cand_bw[q], cand_p[q]);
+        if (err == hipSuccess) err = hipEventRecord(e1, h->stream);
+        if (err == hipSuccess) err = dba::launch_consensus<R>(A, h->stream);
+        if (err == hipSuccess) err = dba::launch_norms<R>(A, h->stream);
+        if (err == hipSuccess) err = hipEventSynchronize(e1);
+        if (err == hipSuccess) err = hipEventElapsedTime(&ms, e0, e1);
+        if (e0) (void)hipEventDestroy(e0);
+        if (e1) (void)hipEventDestroy(e1);
+        if (err != hipSuccess) return fail(h, DBA_E_DEVICE, "schedule tuning: %s", hipGetErrorString(err));
         h->tune_ms.push_back(ms);
         --n;
         if (++h->tune_next > (int)idx.size()) {
@@ -547,8 +548,10 @@ int iterate_impl(dba_handle *h, const DevArrays<R> &A, int n)
         for (int it = 0; it < iters && err == hipSuccess; ++it)
             err = run_iteration<R>(h, A, h->block_waves, h->persistent, false);
         hipError_t e2 = hipStreamEndCapture(h->stream, &graph);
-        if (err != hipSuccess) return fail(h, DBA_E_DEVICE, "graph capture: %s", hipGetErrorString(err));
-        HIP_TRY(h, e2);
+        if (err != hipSuccess || e2 != hipSuccess) {
+            if (e2 == hipSuccess && graph) (void)hipGraphDestroy(graph);
+            return fail(h, DBA_E_DEVICE, "graph capture: %s", hipGetErrorString(err != hipSuccess ? err : e2));
+        }
         err = hipGraphInstantiate(&h->gexec[g], graph, nullptr, nullptr, 0);
         (void)hipGraphDestroy(graph);
         HIP_TRY(h, err);

@@ -91,7 +91,6 @@ template <typename R>
 int build_set(dba_handle *h, int np, const dba_problem_desc *probs, ProblemSet *ps, DevArrays<R> &A)
 {
     using R2 = typename dba::Vec<R>::R2;
-    using R4 = typename dba::Vec<R>::R4;
     const int CH = dba::kChunk;
     // observations of a camera per chunk: 64, or the block size pi of the
     // block local updates (the rest of such a chunk is padding).  Block local
@@ -137,7 +136,7 @@ int build_set(dba_handle *h, int np, const dba_problem_desc *probs, ProblemSet *
     // per-observation camera copies; block local updates keep one per chunk
     const size_t SY = per_obs ? (size_t)S : 0;
     std::vector<R> copy_y(9 * SY, R(0));
-    std::vector<R4> xrec(n_recs);
+    std::vector<dba::PtCopy<R>> xrec(n_recs);
     std::vector<int> pt_off(n_pts + 1, 0), chunk_cam(n_chunks), cam_prob(n_cams), pt_prob(n_pts),
         cam_chunk0(n_cams + 1), cam_count(n_cams);
     std::vector<double> cons_y((size_t)n_cams * dba::kConsY, 0.0);
@@ -197,9 +196,7 @@ int build_set(dba_handle *h, int np, const dba_problem_desc *probs, ProblemSet *
             uv[s].y = (R)d.obs_uv[2 * k + 1];
             if (per_obs)
                 for (int c = 0; c < 9; ++c) copy_y[(size_t)c * S + s] = (R)d.cams[9 * j + c];
-            R4 x;
-            x.x = (R)d.points[3 * i]; x.y = (R)d.points[3 * i + 1]; x.z = (R)d.points[3 * i + 2]; x.w = R(0);
-            xrec[r.rec0 + rr] = x;
+            xrec[r.rec0 + rr] = dba::PtCopy<R>{(R)d.points[3 * i], (R)d.points[3 * i + 1], (R)d.points[3 * i + 2]};
         }
         Ctrl &c = ctrl[p];
         std::memset(&c, 0, sizeof(c));
@@ -223,7 +220,7 @@ int build_set(dba_handle *h, int np, const dba_problem_desc *probs, ProblemSet *
     // device
     Buffers &B = ps->buf;
     R2 *d_uv; int *d_pslot, *d_ptid, *d_orig; uint8_t *d_mask; R *d_copy; double *d_dual;
-    R4 *d_xrec; double4 *d_urec; int *d_ptoff, *d_chunk_cam, *d_cam_prob, *d_pt_prob, *d_cam_chunk0, *d_cam_count;
+    dba::PtCopy<R> *d_xrec; dba::PtDual *d_urec; int *d_ptoff, *d_chunk_cam, *d_cam_prob, *d_pt_prob, *d_cam_chunk0, *d_cam_count;
     double *d_cons_y; double4 *d_cons_x; Ctrl *d_ctrl; ProblemRange *d_prob;
     double *d_cpart, *d_ppart, *d_campart, *d_epart, *d_estats;
     int *d_pblk_pt0, *d_pblk_cnt;
@@ -265,8 +262,8 @@ int build_set(dba_handle *h, int np, const dba_problem_desc *probs, ProblemSet *
         HIP_TRY(h, hipMemcpy(d_copy, copy_y.data(), 9 * SY * sizeof(R), hipMemcpyHostToDevice));
         HIP_TRY(h, hipMemset(d_dual, 0, 9 * SY * sizeof(double)));
     }
-    HIP_TRY(h, hipMemcpy(d_xrec, xrec.data(), n_recs * sizeof(R4), hipMemcpyHostToDevice));
-    HIP_TRY(h, hipMemset(d_urec, 0, n_recs * sizeof(double4)));
+    HIP_TRY(h, hipMemcpy(d_xrec, xrec.data(), n_recs * sizeof(dba::PtCopy<R>), hipMemcpyHostToDevice));
+    HIP_TRY(h, hipMemset(d_urec, 0, n_recs * sizeof(dba::PtDual)));
     HIP_TRY(h, hipMemcpy(d_ptoff, pt_off.data(), (n_pts + 1) * sizeof(int), hipMemcpyHostToDevice));
     HIP_TRY(h, hipMemcpy(d_chunk_cam, chunk_cam.data(), n_chunks * sizeof(int), hipMemcpyHostToDevice));
     HIP_TRY(h, hipMemcpy(d_cam_prob, cam_prob.data(), n_cams * sizeof(int), hipMemcpyHostToDevice));

@@ -10,8 +10,8 @@
 //    Per slot (structure of arrays): uv (R2), pslot (point-major record index,
 //    -1 for padding), ptid (global point), copy_y[9] (R), dual_y[9] (FP64).
 //  * point-major RECORDS: the observations of global point I occupy records
-//    [pt_off[I], pt_off[I+1]).  Per record: xrec (R4: point copy x_i^j) and
-//    urec (double4: point-side scaled dual).
+//    [pt_off[I], pt_off[I+1]).  Per record: xrec (PtCopy: point copy x_i^j)
+//    and urec (PtDual: point-side scaled dual).
 //  * consensus: cons_y [n_cams][16] doubles (9 used), cons_x [n_points] double4.
 //  * per-problem control block Ctrl (rho, pending dual rescale, residuals).
 //
@@ -62,6 +62,11 @@ template <typename R> struct Vec;
 template <> struct Vec<float> { using R2 = float2; using R4 = float4; };
 template <> struct Vec<double> { using R2 = double2; using R4 = double4; };
 
+// Point record: the point copy x_i^j (local precision) and its scaled dual
+// (FP64), three values each with no padding (12 / 24 and 24 bytes).
+template <typename R> struct PtCopy { R x, y, z; };
+struct PtDual { double x, y, z; };
+
 template <typename R>
 struct DevArrays {
     // slots
@@ -78,8 +83,8 @@ struct DevArrays {
     const int *slot_orig; // [n_slots] observation index within its problem
     // records
     long long n_recs;
-    typename Vec<R>::R4 *xrec;
-    double4 *urec;
+    PtCopy<R> *xrec;
+    PtDual *urec;
     const int *pt_off;    // [n_pts+1]
     // chunks / cameras / points
     int n_chunks, n_cams, n_pts, n_problems;

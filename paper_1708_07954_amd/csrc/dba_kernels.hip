@@ -40,7 +40,6 @@ __device__ __forceinline__ void local_chunk(const DevArrays<R> &a, const SolverP
                                             __bf16 *io = nullptr)
 {
     using R2 = typename Vec<R>::R2;
-    using R4 = typename Vec<R>::R4;
     const int J = a.chunk_cam[c];
     const Ctrl *ct = a.ctrl + a.cam_prob[J];
     const double rho_x = ct->rho_x, rho_y = ct->rho_y;
@@ -74,8 +73,8 @@ __device__ __forceinline__ void local_chunk(const DevArrays<R> &a, const SolverP
             th[i] = a.copy_y[i * S + s];
             u[i] = a.dual_y[i * S + s];
         }
-        const R4 xr = a.xrec[ps];
-        const double4 ur = a.urec[ps];
+        const PtCopy<R> xr = a.xrec[ps];
+        const PtDual ur = a.urec[ps];
         th[9] = xr.x; th[10] = xr.y; th[11] = xr.z;
         u[9] = ur.x; u[10] = ur.y; u[11] = ur.z;
         if (pending) {  // Eqs. (12)-(13) of the previous iteration, then the rho rescale
@@ -84,7 +83,7 @@ __device__ __forceinline__ void local_chunk(const DevArrays<R> &a, const SolverP
                 u[i] = (u[i] + ((double)th[i] - cons[i])) * (i < 9 ? rat_y : rat_x);
 #pragma unroll
             for (int i = 0; i < 9; ++i) a.dual_y[i * S + s] = u[i];
-            a.urec[ps] = make_double4(u[9], u[10], u[11], 0.0);
+            a.urec[ps] = PtDual{u[9], u[10], u[11]};
         }
 #pragma unroll
         for (int i = 0; i < 12; ++i) v[i] = (R)(cons[i] - u[i]);
@@ -139,9 +138,7 @@ __device__ __forceinline__ void local_chunk(const DevArrays<R> &a, const SolverP
     if (active) {
 #pragma unroll
         for (int i = 0; i < 9; ++i) a.copy_y[i * S + s] = th[i];
-        R4 xo;
-        xo.x = th[9]; xo.y = th[10]; xo.z = th[11]; xo.w = R(0);
-        a.xrec[ps] = xo;
+        a.xrec[ps] = PtCopy<R>{th[9], th[10], th[11]};
 #pragma unroll
         for (int i = 0; i < 9; ++i) {
             const double t = (double)th[i];
@@ -163,7 +160,6 @@ template <typename R>
 __device__ __forceinline__ void local_block(const DevArrays<R> &a, const SolverParams &sp, int c, int lane, R *lds)
 {
     using R2 = typename Vec<R>::R2;
-    using R4 = typename Vec<R>::R4;
     const int J = a.chunk_cam[c];
     const Ctrl *ct = a.ctrl + a.cam_prob[J];
     const double rho_x = ct->rho_x, rho_y = ct->rho_y;
@@ -193,14 +189,14 @@ __device__ __forceinline__ void local_block(const DevArrays<R> &a, const SolverP
         const double4 cx = a.cons_x[a.ptid[s]];
         const double cxs[3] = {cx.x, cx.y, cx.z};
         z = a.uv[s];
-        const R4 xr = a.xrec[ps];
-        const double4 ur = a.urec[ps];
+        const PtCopy<R> xr = a.xrec[ps];
+        const PtDual ur = a.urec[ps];
         th[9] = xr.x; th[10] = xr.y; th[11] = xr.z;
         double u[3] = {ur.x, ur.y, ur.z};
         if (pending) {
 #pragma unroll
             for (int i = 0; i < 3; ++i) u[i] = (u[i] + ((double)th[9 + i] - cxs[i])) * rat_x;
-            a.urec[ps] = make_double4(u[0], u[1], u[2], 0.0);
+            a.urec[ps] = PtDual{u[0], u[1], u[2]};
         }
 #pragma unroll
         for (int i = 0; i < 3; ++i) vx[i] = (R)(cxs[i] - u[i]);
@@ -208,9 +204,7 @@ __device__ __forceinline__ void local_block(const DevArrays<R> &a, const SolverP
     block_lm<R>(th, vy, vx, z.x, z.y, active, (R)rho_x, (R)rho_y, sp.loss, (R)sp.loss_param, sp.lm_steps,
                 (R)sp.lambda0, lds, lane);
     if (active) {
-        R4 xo;
-        xo.x = th[9]; xo.y = th[10]; xo.z = th[11]; xo.w = R(0);
-        a.xrec[ps] = xo;
+        a.xrec[ps] = PtCopy<R>{th[9], th[10], th[11]};
     }
     if (lane == 0) {
         double *o = a.cpart + (long long)c * kCpart;
@@ -290,7 +284,6 @@ __global__ __launch_bounds__(64 * kLearnedWaves) void k_local_learned(DevArrays<
 template <typename R>
 __global__ __launch_bounds__(256) void k_consensus(DevArrays<R> a, int pt_blocks)
 {
-    using R4 = typename Vec<R>::R4;
     if ((int)blockIdx.x < pt_blocks) {
         __shared__ double sh[2][kPtBlock];
         const int b = blockIdx.x;
@@ -304,7 +297,7 @@ __global__ __launch_bounds__(256) void k_consensus(DevArrays<R> a, int pt_blocks
             // e = new - previous
             const double4 old = a.cons_x[i];
             double s0 = 0.0, s1 = 0.0, s2 = 0.0, q0 = 0.0, q1 = 0.0, q2 = 0.0, qq = 0.0;
-            auto add = [&](const R4 &x, const double4 &u) {
+            auto add = [&](const PtCopy<R> &x, const PtDual &u) {
                 s0 += (double)x.x + u.x;
                 s1 += (double)x.y + u.y;
                 s2 += (double)x.z + u.z;
@@ -317,8 +310,8 @@ __global__ __launch_bounds__(256) void k_consensus(DevArrays<R> a, int pt_blocks
             // four records' loads in flight, summed in record order
             int r = r0;
             for (; r + 4 <= r1; r += 4) {
-                R4 x[4];
-                double4 u[4];
+                PtCopy<R> x[4];
+                PtDual u[4];
 #pragma unroll
                 for (int j = 0; j < 4; ++j) {
                     x[j] = a.xrec[r + j];
@@ -534,8 +527,8 @@ __global__ __launch_bounds__(256) void k_materialize(DevArrays<R> a, int p, doub
     const int J = a.chunk_cam[s / kChunk];
     const Ctrl &ct = a.ctrl[p];
     const double4 cx = a.cons_x[a.ptid[s]];
-    const typename Vec<R>::R4 xr = a.xrec[ps];
-    const double4 ur = a.urec[ps];
+    const PtCopy<R> xr = a.xrec[ps];
+    const PtDual ur = a.urec[ps];
     const double xc[3] = {(double)xr.x, (double)xr.y, (double)xr.z};
     const double xu[3] = {ur.x, ur.y, ur.z};
     const double xs[3] = {cx.x, cx.y, cx.z};

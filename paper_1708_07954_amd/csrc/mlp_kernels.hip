@@ -326,8 +326,8 @@ __global__ __launch_bounds__(256) void k_collect_pairs(DevArrays<float> a, Solve
         u[i] = a.dual_y[i * S + s];
     }
     cons[9] = cx.x; cons[10] = cx.y; cons[11] = cx.z;
-    const float4 xr = a.xrec[ps];
-    const double4 ur = a.urec[ps];
+    const PtCopy<float> xr = a.xrec[ps];
+    const PtDual ur = a.urec[ps];
     th[9] = xr.x; th[10] = xr.y; th[11] = xr.z;
     u[9] = ur.x; u[10] = ur.y; u[11] = ur.z;
     if (ct.pending)

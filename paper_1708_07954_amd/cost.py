@@ -59,9 +59,9 @@ def bytes_per_obs(fp32: bool = True) -> dict:
              + 4 + 4        # point record index, point id
              + 2 * 9 * r    # camera-side copy read + write
              + 2 * 9 * 8    # camera-side scaled dual read + write
-             + 2 * 4 * r    # point-side copy record read + write (4-wide)
-             + 2 * 4 * 8)   # point-side dual record read + write (4-wide)
-    consensus = 4 * r + 4 * 8   # point records read once more
+             + 2 * 3 * r    # point-side copy record read + write
+             + 2 * 3 * 8)   # point-side dual record read + write
+    consensus = 3 * r + 3 * 8   # point records read once more
     minimal = 2 * r + 8 + 2 * 12 * r + 2 * 12 * 8   # obs + indices + copies r/w + duals r/w
     return dict(local=local, consensus=consensus, total=local + consensus, minimal=minimal)
 

@@ -2,8 +2,9 @@
 (one observation), cameras whose observations fill a 64-slot chunk exactly,
 miss it by one or spill one slot into the next, point counts around the
 256-point consensus block, camera counts around the 4-camera consensus
-block; a batch mixing a one-observation problem with larger ones; empty and
-degenerate inputs rejected with the documented status."""
+block, long camera segments and long point tracks; a batch mixing a
+one-observation problem with larger ones; empty and degenerate inputs
+rejected with the documented status."""
 import numpy as np
 import pytest
 
@@ -18,7 +19,10 @@ KW = dict(loss="huber", loss_param=2.0, rho=1e4)
 
 # (cameras, points): every camera sees every point, so each camera has
 # `points` observations and each point `cameras`
-EDGES = [(1, 1), (1, 2), (2, 63), (3, 64), (2, 65), (1, 129), (5, 255), (5, 256), (3, 257), (4, 7), (9, 3)]
+EDGES = [(1, 1), (1, 2), (2, 63), (3, 64), (2, 65), (1, 129), (5, 255), (5, 256), (3, 257), (4, 7), (9, 3),
+         # long segments: 157 chunks summed into one camera's consensus; point
+         # tracks of 300 records (more than a consensus block has threads)
+         (2, 10000), (300, 3)]
 
 
 def _oracle(sc, iters):

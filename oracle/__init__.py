@@ -45,6 +45,14 @@ Readings where the paper is silent or loose (the same on the GPU path):
      (all 9 + 3 nb unknowns) is solved by the LM of R4 with the block's
      objective summed over its observations; a camera's consensus averages
      its block copies, and its residual weight is its number of blocks.
+  R10 the paper's own camera (Sec. 2.1, Eq. 1), ``camera="euler"``: y =
+     (alpha, beta, gamma, t), R = R3(gamma) R2(beta) R1(alpha) with R1, R2,
+     R3 the right-handed rotations about x, y, z; pixels f (z~1/z~3,
+     z~2/z~3) with the known focal length f (Eq. 1 leaves K out; the text
+     defines it and calls the focal length known); no distortion.  The
+     camera row keeps 9 slots (alpha, beta, gamma, t, f, 0, 0): slots 6-8
+     have zero Jacobian columns, so every local solve leaves them at their
+     value and exactly the 6 + 3 unknowns of the paper move.
 """
 from __future__ import annotations
 
@@ -60,6 +68,7 @@ _SRC = os.path.join(_HERE, "dba_oracle.c")
 _LIB = os.path.join(_HERE, "liboracle.so")
 
 LOSS = {"l2": 0, "huber": 1, "student_t": 2}
+CAMERA = {"angle_axis": 0, "euler": 1}
 
 
 def build(force: bool = False) -> str:
@@ -94,7 +103,7 @@ class OrcOpts(ctypes.Structure):
                 ("lm_steps", ctypes.c_int32), ("lambda0", ctypes.c_double),
                 ("rho_balancing", ctypes.c_int32), ("rb_mu", ctypes.c_double),
                 ("rb_tau", ctypes.c_double), ("rho_min", ctypes.c_double),
-                ("rho_max", ctypes.c_double)]
+                ("rho_max", ctypes.c_double), ("camera", ctypes.c_int32)]
 
 
 def _declare(L):
@@ -118,7 +127,12 @@ def _declare(L):
                                    ctypes.POINTER(OrcOpts), ctypes.c_int32, _dp]
     L.orc_admm_iterate.restype = ctypes.c_int
     L.orc_reprojection_stats.argtypes = [ctypes.c_int64, _ip, _ip, _dp, _dp, _dp, _up,
-                                         ctypes.c_int, ctypes.c_double, _dp]
+                                         ctypes.c_int, ctypes.c_double, ctypes.c_int, _dp]
+    L.orc_euler_rotation.argtypes = [_dp, _dp]
+    L.orc_project_cam.argtypes = [ctypes.c_int, _dp, _dp, _dp]
+    L.orc_project_cam.restype = ctypes.c_double
+    L.orc_project_jac_cam.argtypes = [ctypes.c_int, _dp, _dp, _dp, _dp]
+    L.orc_project_jac_cam.restype = ctypes.c_double
     L.orc_block_objective.argtypes = [ctypes.POINTER(OrcOpts), ctypes.c_int, _dp, _dp, _dp, _dp,
                                       ctypes.c_double, ctypes.c_double]
     L.orc_block_objective.restype = ctypes.c_double
@@ -147,10 +161,10 @@ def _f64(a):
 
 
 def make_opts(loss="huber", loss_param=2.0, lm_steps=5, lambda0=1e-3,
-              rho_balancing=False, rb_mu=10.0, rb_tau=2.0, rho_min=1e-6, rho_max=1e6):
+              rho_balancing=False, rb_mu=10.0, rb_tau=2.0, rho_min=1e-6, rho_max=1e6, camera="angle_axis"):
     return OrcOpts(LOSS[loss] if isinstance(loss, str) else int(loss), float(loss_param),
                    int(lm_steps), float(lambda0), int(bool(rho_balancing)), float(rb_mu),
-                   float(rb_tau), float(rho_min), float(rho_max))
+                   float(rb_tau), float(rho_min), float(rho_max), CAMERA[camera])
 
 
 # ---------------------------------------------------------------- pieces
@@ -168,18 +182,25 @@ def transform(cam, X):
     return P
 
 
-def project(cam, X):
+def project(cam, X, camera="angle_axis"):
     cam, X = _f64(cam), _f64(X)
     uv = np.zeros(2)
-    depth = lib().orc_project(_d(cam), _d(X), _d(uv))
+    depth = lib().orc_project_cam(CAMERA[camera], _d(cam), _d(X), _d(uv))
     return uv, depth
 
 
-def project_jac(cam, X):
+def project_jac(cam, X, camera="angle_axis"):
     cam, X = _f64(cam), _f64(X)
     uv, J = np.zeros(2), np.zeros((2, 12))
-    depth = lib().orc_project_jac(_d(cam), _d(X), _d(uv), _d(J))
+    depth = lib().orc_project_jac_cam(CAMERA[camera], _d(cam), _d(X), _d(uv), _d(J))
     return uv, J, depth
+
+
+def euler_rotation(cam):
+    """R = R3(gamma) R2(beta) R1(alpha) of an Euler camera row."""
+    R = np.zeros(9)
+    lib().orc_euler_rotation(_d(_f64(cam)), _d(R))
+    return R.reshape(3, 3)
 
 
 def loss(kind, param, s):
@@ -235,10 +256,10 @@ class ADMM:
 
     def __init__(self, problem: Problem, cams0, points0, *, loss="huber", loss_param=2.0,
                  rho=1.0, rho_x=None, rho_y=None, rho_balancing=False, lm_steps=5,
-                 lambda0=1e-3):
+                 lambda0=1e-3, camera="angle_axis"):
         self.p = problem
-        self.opts = make_opts(loss, loss_param, lm_steps, lambda0, rho_balancing)
-        self.loss, self.loss_param = loss, loss_param
+        self.opts = make_opts(loss, loss_param, lm_steps, lambda0, rho_balancing, camera=camera)
+        self.loss, self.loss_param, self.camera = loss, loss_param, camera
         self.cons_y = _f64(cams0).reshape(-1, 9).copy()
         self.cons_x = _f64(points0).reshape(-1, 3).copy()
         L = problem.obs_cam.shape[0]
@@ -267,7 +288,7 @@ class ADMM:
     def stats(self, mask=None):
         """(rmse_all, rmse_masked, robust_cost, mean_abs_error) at consensus."""
         return reprojection_stats(self.p, self.cons_y, self.cons_x, mask,
-                                  self.loss, self.loss_param)
+                                  self.loss, self.loss_param, self.camera)
 
 
 # ---------------------------------------------------------------- blocks
@@ -321,10 +342,10 @@ class BlockADMM:
     (n, 3), ``rho`` = [rho_x, rho_y]."""
 
     def __init__(self, problem: Problem, cams0, points0, *, block=64, loss="huber", loss_param=2.0, rho=1.0,
-                 rho_x=None, rho_y=None, rho_balancing=False, lm_steps=5, lambda0=1e-3):
+                 rho_x=None, rho_y=None, rho_balancing=False, lm_steps=5, lambda0=1e-3, camera="angle_axis"):
         self.p = problem
-        self.opts = make_opts(loss, loss_param, lm_steps, lambda0, rho_balancing)
-        self.loss, self.loss_param = loss, loss_param
+        self.opts = make_opts(loss, loss_param, lm_steps, lambda0, rho_balancing, camera=camera)
+        self.loss, self.loss_param, self.camera = loss, loss_param, camera
         self.blk_off, self.blk_obs, self.blk_cam = make_blocks(problem.obs_cam, problem.obs_point,
                                                                problem.n_cams, block)
         self.cons_y = _f64(cams0).reshape(-1, 9).copy()
@@ -361,11 +382,12 @@ class BlockADMM:
         return np.hstack([self.ycopy[blk_of], self.xcopy]), np.hstack([self.ydual[blk_of], self.xdual])
 
     def stats(self, mask=None):
-        return reprojection_stats(self.p, self.cons_y, self.cons_x, mask, self.loss, self.loss_param)
+        return reprojection_stats(self.p, self.cons_y, self.cons_x, mask, self.loss, self.loss_param,
+                                  self.camera)
 
 
 def reprojection_stats(problem: Problem, cams, points, mask=None, loss_kind="l2",
-                       loss_param=1.0):
+                       loss_param=1.0, camera="angle_axis"):
     out = np.zeros(4)
     cams, points = _f64(cams), _f64(points)
     mp = None
@@ -375,5 +397,5 @@ def reprojection_stats(problem: Problem, cams, points, mask=None, loss_kind="l2"
     lib().orc_reprojection_stats(problem.obs_cam.shape[0], _i(problem.obs_cam),
                                  _i(problem.obs_point), _d(problem.obs_uv), _d(cams),
                                  _d(points), mp, LOSS[loss_kind] if isinstance(loss_kind, str)
-                                 else int(loss_kind), float(loss_param), _d(out))
+                                 else int(loss_kind), float(loss_param), CAMERA[camera], _d(out))
     return out

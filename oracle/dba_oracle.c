@@ -161,6 +161,137 @@ double orc_project_jac(const double cam[9], const double X[3], double uv[2], dou
 }
 
 /* ------------------------------------------------------------------------ */
+/* The paper's camera (Sec. 2.1, Eq. 1): y = (alpha, beta, gamma, t), the    */
+/* rotation R = R3(gamma) R2(beta) R1(alpha) with R1, R2, R3 the rotations   */
+/* about the x, y and z axes, z~ = R x + t, and pixel coordinates            */
+/* f (z~1 / z~3, z~2 / z~3) with the known focal length f (cam[6]).  cam[7]  */
+/* and cam[8] are not used; their Jacobian columns are zero, so a local      */
+/* solve leaves them at their value (6 camera unknowns).                     */
+/* ------------------------------------------------------------------------ */
+static void rot_x(double a, double M[3][3])
+{
+    double c = cos(a), s = sin(a);
+    double R[3][3] = {{1, 0, 0}, {0, c, -s}, {0, s, c}};
+    memcpy(M, R, sizeof(R));
+}
+static void rot_y(double a, double M[3][3])
+{
+    double c = cos(a), s = sin(a);
+    double R[3][3] = {{c, 0, s}, {0, 1, 0}, {-s, 0, c}};
+    memcpy(M, R, sizeof(R));
+}
+static void rot_z(double a, double M[3][3])
+{
+    double c = cos(a), s = sin(a);
+    double R[3][3] = {{c, -s, 0}, {s, c, 0}, {0, 0, 1}};
+    memcpy(M, R, sizeof(R));
+}
+/* derivatives of the three rotations with respect to their angle */
+static void drot_x(double a, double M[3][3])
+{
+    double c = cos(a), s = sin(a);
+    double R[3][3] = {{0, 0, 0}, {0, -s, -c}, {0, c, -s}};
+    memcpy(M, R, sizeof(R));
+}
+static void drot_y(double a, double M[3][3])
+{
+    double c = cos(a), s = sin(a);
+    double R[3][3] = {{-s, 0, c}, {0, 0, 0}, {-c, 0, -s}};
+    memcpy(M, R, sizeof(R));
+}
+static void drot_z(double a, double M[3][3])
+{
+    double c = cos(a), s = sin(a);
+    double R[3][3] = {{-s, -c, 0}, {c, -s, 0}, {0, 0, 0}};
+    memcpy(M, R, sizeof(R));
+}
+static void mat3_mul(double A[3][3], double B[3][3], double C[3][3])
+{
+    double T[3][3];
+    for (int r = 0; r < 3; ++r)
+        for (int s = 0; s < 3; ++s) T[r][s] = A[r][0] * B[0][s] + A[r][1] * B[1][s] + A[r][2] * B[2][s];
+    memcpy(C, T, sizeof(T));
+}
+
+/* R = R3(gamma) R2(beta) R1(alpha) of an Euler camera */
+void orc_euler_rotation(const double cam[9], double R[9])
+{
+    double R1[3][3], R2[3][3], R3[3][3], T[3][3];
+    rot_x(cam[0], R1);
+    rot_y(cam[1], R2);
+    rot_z(cam[2], R3);
+    mat3_mul(R2, R1, T);
+    mat3_mul(R3, T, T);
+    memcpy(R, T, sizeof(T));
+}
+
+double orc_project_euler(const double cam[9], const double X[3], double uv[2])
+{
+    double R[9], P[3];
+    orc_euler_rotation(cam, R);
+    for (int r = 0; r < 3; ++r) P[r] = R[3 * r] * X[0] + R[3 * r + 1] * X[1] + R[3 * r + 2] * X[2] + cam[3 + r];
+    uv[0] = cam[6] * P[0] / P[2];
+    uv[1] = cam[6] * P[1] / P[2];
+    return P[2];
+}
+
+/* Projection and its Jacobian (2 x 12) with respect to (alpha, beta, gamma,
+ * t, f, -, -, X); columns 6..8 are zero (f known, no distortion). */
+double orc_project_jac_euler(const double cam[9], const double X[3], double uv[2], double J[24])
+{
+    double R1[3][3], R2[3][3], R3[3][3], D1[3][3], D2[3][3], D3[3][3], R[3][3], Ra[3][3], Rb[3][3], Rc[3][3], T[3][3];
+    rot_x(cam[0], R1);
+    rot_y(cam[1], R2);
+    rot_z(cam[2], R3);
+    drot_x(cam[0], D1);
+    drot_y(cam[1], D2);
+    drot_z(cam[2], D3);
+    mat3_mul(R2, R1, T);
+    mat3_mul(R3, T, R);       /* R */
+    mat3_mul(R2, D1, T);
+    mat3_mul(R3, T, Ra);      /* dR / d alpha */
+    mat3_mul(D2, R1, T);
+    mat3_mul(R3, T, Rb);      /* dR / d beta */
+    mat3_mul(R2, R1, T);
+    mat3_mul(D3, T, Rc);      /* dR / d gamma */
+    double P[3], dP[3][3];    /* dP[angle][row] */
+    for (int r = 0; r < 3; ++r) {
+        P[r] = R[r][0] * X[0] + R[r][1] * X[1] + R[r][2] * X[2] + cam[3 + r];
+        dP[0][r] = Ra[r][0] * X[0] + Ra[r][1] * X[1] + Ra[r][2] * X[2];
+        dP[1][r] = Rb[r][0] * X[0] + Rb[r][1] * X[1] + Rb[r][2] * X[2];
+        dP[2][r] = Rc[r][0] * X[0] + Rc[r][1] * X[1] + Rc[r][2] * X[2];
+    }
+    const double f = cam[6], q = 1.0 / P[2];
+    const double p0 = P[0] * q, p1 = P[1] * q;
+    uv[0] = f * p0;
+    uv[1] = f * p1;
+    /* dpi/dP = f q [[1, 0, -p0], [0, 1, -p1]] */
+    double A[2][3] = {{f * q, 0.0, -f * q * p0}, {0.0, f * q, -f * q * p1}};
+    for (int r = 0; r < 2; ++r) {
+        double *Jr = J + 12 * r;
+        for (int a = 0; a < 3; ++a) Jr[a] = A[r][0] * dP[a][0] + A[r][1] * dP[a][1] + A[r][2] * dP[a][2];
+        for (int s = 0; s < 3; ++s) {
+            Jr[3 + s] = A[r][s];
+            Jr[9 + s] = A[r][0] * R[0][s] + A[r][1] * R[1][s] + A[r][2] * R[2][s];
+        }
+        Jr[6] = Jr[7] = Jr[8] = 0.0;
+    }
+    return P[2];
+}
+
+/* Projection of the camera model `camera` (0: angle-axis + t + f + k1, k2;
+ * 1: the Euler camera above). */
+double orc_project_cam(int camera, const double cam[9], const double X[3], double uv[2])
+{
+    return camera == 1 ? orc_project_euler(cam, X, uv) : orc_project(cam, X, uv);
+}
+
+double orc_project_jac_cam(int camera, const double cam[9], const double X[3], double uv[2], double J[24])
+{
+    return camera == 1 ? orc_project_jac_euler(cam, X, uv, J) : orc_project_jac(cam, X, uv, J);
+}
+
+/* ------------------------------------------------------------------------ */
 /* Misfit loss phi_m of the squared residual norm s = |e|^2 (Eq. 5), and     */
 /* its derivative phi'(s).  l2: phi = s.  Huber (delta): phi = s inside,     */
 /* 2 delta sqrt(s) - delta^2 outside.  Student-t (nu): nu log(1 + s/nu).     */
@@ -230,13 +361,14 @@ typedef struct {
     double lambda0;
     int32_t rho_balancing;
     double rb_mu, rb_tau, rho_min, rho_max;
+    int32_t camera;  /* 0: angle-axis camera (9 unknowns), 1: Euler camera (6) */
 } orc_opts;
 
 double orc_local_objective(const orc_opts *o, const double z[2], const double v[12],
                            const double theta[12], double rho_x, double rho_y)
 {
     double uv[2], ls[2];
-    double depth = orc_project(theta, theta + 9, uv);
+    double depth = orc_project_cam(o->camera, theta, theta + 9, uv);
     if (!(depth > ORC_DEPTH_EPS)) return INFINITY;
     double e0 = z[0] - uv[0], e1 = z[1] - uv[1];
     orc_loss(o->loss, o->loss_param, e0 * e0 + e1 * e1, ls);
@@ -261,7 +393,7 @@ int orc_local_solve(const orc_opts *o, const double z[2], const double v[12],
     int accepted = 0;
     for (int it = 0; it < steps; ++it) {
         double uv[2], J[24], ls[2];
-        orc_project_jac(theta, theta + 9, uv, J);
+        orc_project_jac_cam(o->camera, theta, theta + 9, uv, J);
         double e0 = z[0] - uv[0], e1 = z[1] - uv[1];
         orc_loss(o->loss, o->loss_param, e0 * e0 + e1 * e1, ls);
         double w = ls[1];
@@ -428,13 +560,13 @@ int orc_admm_iterate(int64_t L, int32_t m, int32_t n,
 /* ------------------------------------------------------------------------ */
 void orc_reprojection_stats(int64_t L, const int32_t *obs_cam, const int32_t *obs_pt,
                             const double *obs_uv, const double *cons_y, const double *cons_x,
-                            const uint8_t *mask, int loss, double loss_param, double out[4])
+                            const uint8_t *mask, int loss, double loss_param, int camera, double out[4])
 {
     double s_all = 0.0, s_m = 0.0, cost = 0.0, abs_sum = 0.0;
     int64_t n_m = 0;
     for (int64_t k = 0; k < L; ++k) {
         double uv[2], ls[2];
-        orc_project(cons_y + 9 * (size_t)obs_cam[k], cons_x + 3 * (size_t)obs_pt[k], uv);
+        orc_project_cam(camera, cons_y + 9 * (size_t)obs_cam[k], cons_x + 3 * (size_t)obs_pt[k], uv);
         double e0 = obs_uv[2 * k] - uv[0], e1 = obs_uv[2 * k + 1] - uv[1];
         double s = e0 * e0 + e1 * e1;
         s_all += s;
@@ -505,7 +637,7 @@ double orc_block_objective(const orc_opts *o, int nb, const double *z, const dou
     for (int k = 0; k < nb; ++k) {
         const double *xk = theta + 9 + 3 * k;
         double uv[2], ls[2];
-        double depth = orc_project(theta, xk, uv);
+        double depth = orc_project_cam(o->camera, theta, xk, uv);
         if (!(depth > ORC_DEPTH_EPS)) return INFINITY;
         double e0 = z[2 * k] - uv[0], e1 = z[2 * k + 1] - uv[1];
         orc_loss(o->loss, o->loss_param, e0 * e0 + e1 * e1, ls);
@@ -552,7 +684,7 @@ int orc_block_local_solve(const orc_opts *o, int nb, const double *z, const doub
             double cam_pt[12], uv[2], J[24], ls[2];
             memcpy(cam_pt, theta, 9 * sizeof(double));
             memcpy(cam_pt + 9, xk, 3 * sizeof(double));
-            orc_project_jac(cam_pt, cam_pt + 9, uv, J);
+            orc_project_jac_cam(o->camera, cam_pt, cam_pt + 9, uv, J);
             double e0 = z[2 * k] - uv[0], e1 = z[2 * k + 1] - uv[1];
             orc_loss(o->loss, o->loss_param, e0 * e0 + e1 * e1, ls);
             const double w = ls[1];

@@ -105,13 +105,23 @@ def _synth_pixels(R, t, f, k1, k2, X, cam, pt):
 
 def _assemble(name, seed, rng, R_gt, C, X_gt, obs_cam, obs_pt, *,
               noise_px=1.0, perturb=True, outlier_frac=0.0,
-              rot_sigma=0.05, trans_sigma=0.2, point_sigma=0.1, meta=None):
+              rot_sigma=0.05, trans_sigma=0.2, point_sigma=0.1, meta=None, camera="angle_axis"):
+    """camera "angle_axis": rows (w, t, f, k1, k2); "euler": the paper's
+    camera, rows (alpha, beta, gamma, t, f, 0, 0) with R = Rz(gamma)
+    Ry(beta) Rx(alpha), no distortion, the rotation perturbed in the Euler
+    angles.  Both draw the same random numbers in the same order."""
     m = R_gt.shape[0]
     t_gt = -np.einsum("jik,jk->ji", R_gt, C)
     f = np.full(m, FOCAL)
     k1 = rng.uniform(-1e-2, 1e-2, m)
     k2 = rng.uniform(-1e-2, 1e-2, m)
-    w_gt = Rotation.from_matrix(R_gt).as_rotvec()
+    euler = camera == "euler"
+    if euler:
+        k1 = np.zeros(m)
+        k2 = np.zeros(m)
+        w_gt = Rotation.from_matrix(R_gt).as_euler("xyz")
+    else:
+        w_gt = Rotation.from_matrix(R_gt).as_rotvec()
     cams_gt = np.column_stack([w_gt, t_gt, f, k1, k2])
 
     uv, depth = _synth_pixels(R_gt, t_gt, f, k1, k2, X_gt, obs_cam, obs_pt)
@@ -127,8 +137,11 @@ def _assemble(name, seed, rng, R_gt, C, X_gt, obs_cam, obs_pt, *,
 
     if perturb:
         dw = rng.normal(0.0, rot_sigma, (m, 3))
-        R_init = Rotation.from_rotvec(dw) * Rotation.from_matrix(R_gt)
-        w_init = R_init.as_rotvec()
+        if euler:
+            w_init = w_gt + dw
+        else:
+            R_init = Rotation.from_rotvec(dw) * Rotation.from_matrix(R_gt)
+            w_init = R_init.as_rotvec()
         t_init = t_gt + rng.normal(0.0, trans_sigma, (m, 3))
         X_init = X_gt + rng.normal(0.0, point_sigma, X_gt.shape)
     else:

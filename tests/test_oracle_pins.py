@@ -423,7 +423,7 @@ def test_admm_reaches_the_centralised_lm_optimum(loss, delta):
     """At an ADMM fixed point every copy equals its consensus and the duals
     cancel, so the consensus is a stationary point of the centralised
     objective: its RMSE must approach the one brute-force LM reaches.
-    (ADMM is first-order; it gets within the benchmark spec's 0.5% floor here.)"""
+    (ADMM is first-order; here it gets within the 0.5 % RMSE tolerance.)"""
     s = make_ring_scene(seed=7, n_cams=8, n_points=100, box=3.0, radius=8.0)
     p = oracle.Problem.from_scene(s)
     cams, pts = _minpack_lm(s, loss, delta)

@@ -262,9 +262,9 @@ double orc_project_jac_euler(const double cam[9], const double X[3], double uv[2
         dP[2][r] = Rc[r][0] * X[0] + Rc[r][1] * X[1] + Rc[r][2] * X[2];
     }
     const double f = cam[6], q = 1.0 / P[2];
-    const double p0 = P[0] * q, p1 = P[1] * q;
-    uv[0] = f * p0;
-    uv[1] = f * p1;
+    const double p0 = P[0] / P[2], p1 = P[1] / P[2];
+    uv[0] = f * P[0] / P[2];
+    uv[1] = f * P[1] / P[2];
     /* dpi/dP = f q [[1, 0, -p0], [0, 1, -p1]] */
     double A[2][3] = {{f * q, 0.0, -f * q * p0}, {0.0, f * q, -f * q * p1}};
     for (int r = 0; r < 2; ++r) {

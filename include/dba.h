@@ -61,6 +61,15 @@ typedef enum {
     DBA_START_LEARNED = 1     /* start from the better of the copy and copy + MLP prediction */
 } dba_start;
 
+typedef enum {
+    DBA_CAMERA_ANGLE_AXIS = 0, /* 9 parameters, all optimised: angle-axis w (3), t (3), focal f,
+                                  radial k1, k2; pixels f (1 + k1 r^2 + k2 r^4) (P1/P3, P2/P3) */
+    DBA_CAMERA_EULER = 1       /* the camera of Sec. 2.1, Eq. (1): Euler angles (alpha, beta, gamma)
+                                  and t optimised (6 parameters), R = R3(gamma) R2(beta) R1(alpha)
+                                  (rotations about x, y, z), pixels f (P1/P3, P2/P3) with the known
+                                  focal length f; a camera row is (alpha, beta, gamma, t, f, 0, 0) */
+} dba_camera;
+
 typedef struct dba_options {
     int32_t device;           /* HIP device ordinal */
     void *stream;             /* hipStream_t to enqueue on; NULL: a stream the handle creates */
@@ -86,12 +95,14 @@ typedef struct dba_options {
                                  learned start */
     int32_t block_points;     /* with camera_blocks: observations (points) per block, the pi of
                                  Sec. 3.1.4, 1..64; 0 means 64.  Must be 0 without camera_blocks */
+    int32_t camera_model;     /* dba_camera; the Euler camera not with the learned start */
 } dba_options;
 
 /* Fills *opt with the defaults: device 0, NULL stream, FP64, Huber 2 px,
  * rho 1, no balancing (mu 10, tau 2, clamps 1e-6..1e6), 5 LM steps,
  * lambda0 1e-3, plain start, 2 learned steps, graphs on, autotune, one
- * local problem per observation (camera_blocks 0, block_points 0). */
+ * local problem per observation (camera_blocks 0, block_points 0), the
+ * 9-parameter angle-axis camera. */
 int dba_default_options(dba_options *opt);
 
 /* Creates a handle on opt->device.  *out receives the handle. */
@@ -112,7 +123,8 @@ typedef struct dba_problem_desc {
     const int32_t *obs_cam;   /* [n_obs] camera index j of observation k */
     const int32_t *obs_point; /* [n_obs] point index i of observation k */
     const double *obs_uv;     /* [2*n_obs] pixel (u, v) of observation k */
-    const double *cams;       /* [9*n_cams] initial consensus cameras */
+    const double *cams;       /* [9*n_cams] initial consensus cameras, rows as the options'
+                                 camera_model lays them out */
     const double *points;     /* [3*n_points] initial consensus points */
 } dba_problem_desc;
 
@@ -122,7 +134,8 @@ typedef struct dba_problem_desc {
  * (DBA_E_INDEX_RANGE), all values finite (DBA_E_NONFINITE), every camera and
  * point observed at least once, since Eqs. (10)-(11) divide by the count
  * (DBA_E_UNOBSERVED), depth > 1e-6 for every observation at the initial
- * estimate (DBA_E_BEHIND_CAMERA). */
+ * estimate (DBA_E_BEHIND_CAMERA); with the Euler camera, f > 0 and zeros in
+ * slots 7, 8 of every camera row (DBA_E_INVALID_ARG). */
 int dba_set_problem(dba_handle *h, int32_t n_cams, int32_t n_points, int64_t n_obs,
                     const int32_t *obs_cam, const int32_t *obs_point, const double *obs_uv,
                     const double *cams, const double *points);

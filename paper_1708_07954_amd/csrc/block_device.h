@@ -109,8 +109,8 @@ __device__ __forceinline__ bool ldl9_solve(const R *A, const R *b, R *x)
 
 // One lane's part of the block objective: phi + rho_x/2 |x - vx|^2 at the
 // projection o of (y, x); +inf when the depth is <= 1e-6.
-template <typename R>
-__device__ __forceinline__ R lane_objective(const Proj<R> &o, const R *th, const R *vx, R z0, R z1, R rx, int kind,
+template <typename R, typename P>
+__device__ __forceinline__ R lane_objective(const P &o, const R *th, const R *vx, R z0, R z1, R rx, int kind,
                                             R lp)
 {
     if (!(o.depth > R(1e-6))) return Num<R>::inf;
@@ -135,14 +135,15 @@ __device__ __forceinline__ R camera_penalty(const R *y, const R *vy, R ry)
 
 // Block LM.  th = (y (uniform across the wave), x of this lane); inactive
 // lanes (no observation) take part in every reduction with zeros.
-template <typename R>
+template <typename R, typename Cam>
 __device__ __forceinline__ void block_lm(R *th, const R *vy, const R *vx, R z0, R z1, bool active, R rx, R ry,
                                          int kind, R lp, int steps, R lam, R *lds, int lane)
 {
-    Proj<R> cur;
+    using P = decltype(proj_core<R, true>(th, Cam{}));
+    P cur;
     R fk = R(0);
     if (active) {
-        cur = proj_core<R, true>(th);
+        cur = proj_core<R, true>(th, Cam{});
         fk = lane_objective<R>(cur, th, vx, z0, z1, rx, kind, lp);
     }
     R F = wave_sum<R>(fk) + camera_penalty<R>(th, vy, ry);
@@ -285,10 +286,10 @@ __device__ __forceinline__ void block_lm(R *th, const R *vy, const R *vx, R z0, 
         for (int i = 0; i < 9; ++i) tr[i] = th[i] + dy[i];
 #pragma unroll
         for (int c = 0; c < 3; ++c) tr[9 + c] = th[9 + c] + dx[c];
-        Proj<R> nxt;
+        P nxt;
         R fn = R(0);
         if (active && ok) {
-            nxt = proj_core<R, true>(tr);
+            nxt = proj_core<R, true>(tr, Cam{});
             fn = lane_objective<R>(nxt, tr, vx, z0, z1, rx, kind, lp);
         }
         const bool bad = __ballot(!(fn < Num<R>::inf)) != 0ull;

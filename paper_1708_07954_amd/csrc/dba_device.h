@@ -150,6 +150,81 @@ __device__ __forceinline__ void proj_jac(const Proj<R> &o, const R *th, R *J0, R
     row(J1, A01, A11, A12, p1);
 }
 
+// Camera models, as template tags: CamAA the 9-parameter camera (angle-axis
+// w, t, f, k1, k2; proj_core / proj_jac above); CamEuler the camera of
+// Sec. 2.1, Eq. (1): (alpha, beta, gamma, t) with R = R3(gamma) R2(beta)
+// R1(alpha) (rotations about x, y, z), pixels f (P1/P3, P2/P3) with the
+// known focal length f in slot 6; slots 7, 8 unused.
+struct CamAA {};
+struct CamEuler {};
+
+template <typename R, bool DERIV>
+__device__ __forceinline__ Proj<R> proj_core(const R *th, CamAA)
+{
+    return proj_core<R, DERIV>(th);
+}
+
+template <typename R>
+struct ProjE {
+    R sa, ca, sb, cb, sg, cg;   // sines and cosines of alpha, beta, gamma
+    R x1y, x1z, x2x, x2z;       // X1 = R1 X (y, z), X2 = R2 X1 (x, z; X2_y = X1_y)
+    R q0, q1;                   // Q = R3 X2 = P - t (x, y)
+    R iz, p0, p1;               // 1/P_3, P_{1,2}/P_3
+    R pu, pv, depth;            // pixel and depth
+};
+
+template <typename R, bool DERIV>
+__device__ __forceinline__ ProjE<R> proj_core(const R *th, CamEuler)
+{
+    ProjE<R> o;
+    Num<R>::sincos(th[0], &o.sa, &o.ca);
+    Num<R>::sincos(th[1], &o.sb, &o.cb);
+    Num<R>::sincos(th[2], &o.sg, &o.cg);
+    const R X0 = th[9], X1 = th[10], X2 = th[11];
+    o.x1y = o.ca * X1 - o.sa * X2;
+    o.x1z = o.sa * X1 + o.ca * X2;
+    o.x2x = o.cb * X0 + o.sb * o.x1z;
+    o.x2z = o.cb * o.x1z - o.sb * X0;
+    o.q0 = o.cg * o.x2x - o.sg * o.x1y;
+    o.q1 = o.sg * o.x2x + o.cg * o.x1y;
+    const R P0 = o.q0 + th[3], P1 = o.q1 + th[4], P2 = o.x2z + th[5];
+    o.depth = P2;
+    o.iz = Num<R>::rcp(P2);
+    o.p0 = P0 * o.iz;
+    o.p1 = P1 * o.iz;
+    o.pu = th[6] * o.p0;
+    o.pv = th[6] * o.p1;
+    return o;
+}
+
+// Rows of d pi / d theta for the Euler camera.  With a = A_r (row r of
+// d pi / d P = f / P3 [[1, 0, -p0], [0, 1, -p1]]), c = a R3 and b = c R2:
+//   d/dgamma = a . (z x Q), d/dbeta = c . (y x X2), d/dalpha = b . (x x X1),
+//   d/dt = a, d/dX = b R1 = a R; slots 6..8 have no column.
+template <typename R>
+__device__ __forceinline__ void proj_jac(const ProjE<R> &o, const R *th, R *J0, R *J1)
+{
+    const R fq = th[6] * o.iz;
+    auto row = [&](R *Jr, R a0, R a1, R a2) {
+        const R c0 = a0 * o.cg + a1 * o.sg, c1 = a1 * o.cg - a0 * o.sg, c2 = a2;
+        const R b0 = c0 * o.cb - c2 * o.sb, b1 = c1, b2 = c0 * o.sb + c2 * o.cb;
+        Jr[0] = b2 * o.x1y - b1 * o.x1z;
+        Jr[1] = c0 * o.x2z - c2 * o.x2x;
+        Jr[2] = a1 * o.q0 - a0 * o.q1;
+        Jr[3] = a0;
+        Jr[4] = a1;
+        Jr[5] = a2;
+        Jr[6] = R(0);
+        Jr[7] = R(0);
+        Jr[8] = R(0);
+        Jr[9] = b0;
+        Jr[10] = b1 * o.ca + b2 * o.sa;
+        Jr[11] = b2 * o.ca - b1 * o.sa;
+    };
+    row(J0, fq, R(0), -fq * o.p0);
+    row(J1, R(0), fq, -fq * o.p1);
+}
+
 // phi(s) and w = phi'(s) of the misfit loss of Eq. (8).
 template <typename R>
 __device__ __forceinline__ R loss_phi(int kind, R lp, R s, R &w)
@@ -173,8 +248,8 @@ __device__ __forceinline__ R loss_phi(int kind, R lp, R s, R &w)
 // Local objective of Eq. (9) in scaled form at the point of `o`:
 // phi(|z - pi|^2) + 1/2 sum_i P_i (theta_i - v_i)^2, P = (rho_y x9, rho_x x3);
 // +inf when the depth is <= 1e-6.
-template <typename R>
-__device__ __forceinline__ R objective(const Proj<R> &o, const R *th, const R *v, R z0, R z1,
+template <typename R, typename P>
+__device__ __forceinline__ R objective(const P &o, const R *th, const R *v, R z0, R z1,
                                        R rx, R ry, int kind, R lp)
 {
     if (!(o.depth > R(1e-6))) return Num<R>::inf;
@@ -279,8 +354,8 @@ __device__ __forceinline__ bool solve_normal(const R *Dd, const R *J0, const R *
 // Normal equations: A = H + lambda diag(H), H = P + 2w J^T J, i.e.
 // A = D + c (J0 J0^T + J1 J1^T) with D diagonal and c = 2w, solved in
 // registers in O(12) operations (solve_normal).
-template <typename R>
-__device__ __forceinline__ void lm_steps(R *th, Proj<R> &cur, R &F, const R *v, R z0, R z1, R rx,
+template <typename R, typename Cam, typename P>
+__device__ __forceinline__ void lm_steps(R *th, P &cur, R &F, const R *v, R z0, R z1, R rx,
                                          R ry, int kind, R lp, int steps, R lam)
 {
     for (int it = 0; it < steps; ++it) {
@@ -312,7 +387,7 @@ __device__ __forceinline__ void lm_steps(R *th, Proj<R> &cur, R &F, const R *v, 
         }
         // decrease predicted by the damped Gauss-Newton model
         const R pred = R(0.5) * (lam * dd + gd);
-        const Proj<R> nxt = proj_core<R, true>(tr);
+        const P nxt = proj_core<R, true>(tr, Cam{});
         const R Fn = ok ? objective<R>(nxt, tr, v, z0, z1, rx, ry, kind, lp) : Num<R>::inf;
         // accept a decrease of F, or a step too small for F to judge
         if (Fn < Num<R>::inf && (Fn < F || pred <= Num<R>::tie * fres)) {
@@ -327,13 +402,13 @@ __device__ __forceinline__ void lm_steps(R *th, Proj<R> &cur, R &F, const R *v, 
     }
 }
 
-template <typename R>
+template <typename R, typename Cam>
 __device__ __forceinline__ void local_lm(R *th, const R *v, R z0, R z1, R rx, R ry, int kind,
                                          R lp, int steps, R lam)
 {
-    Proj<R> cur = proj_core<R, true>(th);
+    auto cur = proj_core<R, true>(th, Cam{});
     R F = objective<R>(cur, th, v, z0, z1, rx, ry, kind, lp);
-    lm_steps<R>(th, cur, F, v, z0, z1, rx, ry, kind, lp, steps, lam);
+    lm_steps<R, Cam>(th, cur, F, v, z0, z1, rx, ry, kind, lp, steps, lam);
 }
 
 // Value of lane l ^ OFF for a 32-bit word, OFF in {1, 2, 4, 8}: DPP quad

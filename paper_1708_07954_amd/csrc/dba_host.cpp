@@ -50,6 +50,15 @@ double host_depth(const double *cam, const double *X)
     return c * X[2] + a * (w0 * X[1] - w1 * X[0]) + b * wd * w2 + cam[5];
 }
 
+// Depth P_3 of R X + t for the Euler camera, R = R3(gamma) R2(beta) R1(alpha)
+// (host-side validation only): the third row of R is
+// (-sin beta, sin alpha cos beta, cos alpha cos beta).
+double host_depth_euler(const double *cam, const double *X)
+{
+    const double sa = std::sin(cam[0]), ca = std::cos(cam[0]), sb = std::sin(cam[1]), cb = std::cos(cam[1]);
+    return -sb * X[0] + sa * cb * X[1] + ca * cb * X[2] + cam[5];
+}
+
 int validate(dba_handle *h, int p, const dba_problem_desc &d)
 {
     if (d.n_cams < 1 || d.n_points < 1 || d.n_obs < 1)
@@ -78,8 +87,18 @@ int validate(dba_handle *h, int p, const dba_problem_desc &d)
         if (!cc[j]) return fail(h, DBA_E_UNOBSERVED, "problem %d: camera %d has no observation", p, j);
     for (int i = 0; i < d.n_points; ++i)
         if (!pc[i]) return fail(h, DBA_E_UNOBSERVED, "problem %d: point %d has no observation", p, i);
+    const bool euler = h->opt.camera_model == 1;
+    if (euler)
+        for (int j = 0; j < d.n_cams; ++j) {
+            const double *c = d.cams + 9LL * j;
+            if (!(c[6] > 0) || c[7] != 0.0 || c[8] != 0.0)
+                return fail(h, DBA_E_INVALID_ARG,
+                            "problem %d: camera %d: the Euler camera needs a focal length > 0 in slot 6 and zeros "
+                            "in slots 7, 8", p, j);
+        }
     for (long long k = 0; k < d.n_obs; ++k) {
-        const double z = host_depth(d.cams + 9LL * d.obs_cam[k], d.points + 3LL * d.obs_point[k]);
+        const double *cam = d.cams + 9LL * d.obs_cam[k], *X = d.points + 3LL * d.obs_point[k];
+        const double z = euler ? host_depth_euler(cam, X) : host_depth(cam, X);
         if (!(z > 1e-6))
             return fail(h, DBA_E_BEHIND_CAMERA, "problem %d: observation %lld has depth %g at the initial estimate",
                         p, k, z);
@@ -607,6 +626,7 @@ int dba_default_options(dba_options *o)
     o->persistent = -1;
     o->camera_blocks = 0;
     o->block_points = 0;
+    o->camera_model = DBA_CAMERA_ANGLE_AXIS;
     return DBA_OK;
 }
 
@@ -632,6 +652,8 @@ int dba_create(const dba_options *opt, dba_handle **out)
     if (o.camera_blocks && o.start == DBA_START_LEARNED) return DBA_E_INVALID_ARG;
     if (o.block_points < 0 || o.block_points > dba::kChunk || (o.block_points && !o.camera_blocks))
         return DBA_E_INVALID_ARG;
+    if (o.camera_model != DBA_CAMERA_ANGLE_AXIS && o.camera_model != DBA_CAMERA_EULER) return DBA_E_INVALID_ARG;
+    if (o.camera_model == DBA_CAMERA_EULER && o.start == DBA_START_LEARNED) return DBA_E_INVALID_ARG;
     dba_handle *h = new dba_handle();
     h->opt = o;
     h->fp32 = o.precision == DBA_PREC_FP32_LOCAL;
@@ -640,6 +662,7 @@ int dba_create(const dba_options *opt, dba_handle **out)
     h->sp.lm_steps = o.lm_steps;
     h->sp.lambda0 = o.lm_lambda0;
     h->sp.learned_steps = o.learned_lm_steps;
+    h->sp.camera = o.camera_model;
     h->start = o.start;
     if (hipSetDevice(o.device) != hipSuccess) {
         delete h;

@@ -59,8 +59,8 @@ struct ProblemRange {              // per problem, global index ranges
 constexpr int kPtBlock = 256;      // points per consensus block (never straddles problems)
 
 template <typename R> struct Vec;
-template <> struct Vec<float> { using R2 = float2; using R4 = float4; };
-template <> struct Vec<double> { using R2 = double2; using R4 = double4; };
+template <> struct Vec<float> { using R2 = float2; };
+template <> struct Vec<double> { using R2 = double2; };
 
 // Point record: the point copy x_i^j (local precision) and its scaled dual
 // (FP64), three values each with no padding (12 / 24 and 24 bytes).
@@ -113,6 +113,7 @@ struct SolverParams {
     int lm_steps;
     double lambda0;
     int learned_steps;   // LM steps after the learned start
+    int camera;          // 0: angle-axis camera (9 parameters), 1: Euler camera (Eq. 1)
 };
 
 // ---- learned warm start: 26 -> 128 -> GELU -> 128 -> GELU -> 12 network

@@ -30,11 +30,12 @@ namespace {
 using namespace dev;
 
 // ---------------------------------------------------------------- local
-// One 64-slot chunk (one camera) per wave.  LEARNED: the start point is the
-// better of the copy and copy + network prediction (ties keep the copy), then
+// One 64-slot chunk (one camera) per wave; Cam is the camera model.
+// LEARNED (9-parameter camera only): the start point is the better of the
+// copy and copy + network prediction (ties keep the copy), then
 // `learned_steps` LM steps; io/lw are the wave's network I/O tile and the
 // staged weights.
-template <typename R, bool LEARNED>
+template <typename R, bool LEARNED, typename Cam = CamAA>
 __device__ __forceinline__ void local_chunk(const DevArrays<R> &a, const SolverParams &sp, int c, int lane,
                                             const MlpParams *mp = nullptr, const __bf16 *lw = nullptr,
                                             __bf16 *io = nullptr)
@@ -130,10 +131,10 @@ __device__ __forceinline__ void local_chunk(const DevArrays<R> &a, const SolverP
                 cur = nxt;
                 F = F1;
             }
-            lm_steps<R>(th, cur, F, v, z.x, z.y, rx, ry, sp.loss, lp, sp.learned_steps, lam0);
+            lm_steps<R, CamAA>(th, cur, F, v, z.x, z.y, rx, ry, sp.loss, lp, sp.learned_steps, lam0);
         }
     } else {
-        if (active) local_lm<R>(th, v, z.x, z.y, rx, ry, sp.loss, lp, sp.lm_steps, lam0);
+        if (active) local_lm<R, Cam>(th, v, z.x, z.y, rx, ry, sp.loss, lp, sp.lm_steps, lam0);
     }
     if (active) {
 #pragma unroll
@@ -156,7 +157,7 @@ __device__ __forceinline__ void local_chunk(const DevArrays<R> &a, const SolverP
 // chunk) and keep one point copy each.  Deferred dual updates of both, the
 // block LM (block_lm), then the chunk's one camera copy goes to the camera
 // consensus: cpart = (y + u, y - previous consensus, |y - previous|^2).
-template <typename R>
+template <typename R, typename Cam>
 __device__ __forceinline__ void local_block(const DevArrays<R> &a, const SolverParams &sp, int c, int lane, R *lds)
 {
     using R2 = typename Vec<R>::R2;
@@ -201,7 +202,7 @@ __device__ __forceinline__ void local_block(const DevArrays<R> &a, const SolverP
 #pragma unroll
         for (int i = 0; i < 3; ++i) vx[i] = (R)(cxs[i] - u[i]);
     }
-    block_lm<R>(th, vy, vx, z.x, z.y, active, (R)rho_x, (R)rho_y, sp.loss, (R)sp.loss_param, sp.lm_steps,
+    block_lm<R, Cam>(th, vy, vx, z.x, z.y, active, (R)rho_x, (R)rho_y, sp.loss, (R)sp.loss_param, sp.lm_steps,
                 (R)sp.lambda0, lds, lane);
     if (active) {
         a.xrec[ps] = PtCopy<R>{th[9], th[10], th[11]};
@@ -240,17 +241,17 @@ __device__ __forceinline__ void chunk_range(int n_chunks, int wpb, int persisten
     }
 }
 
-template <typename R>
+template <typename R, typename Cam>
 __global__ __launch_bounds__(LocalBound<R>::threads) void k_local(DevArrays<R> a, SolverParams sp,
                                                                   int persistent)
 {
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, wpb = blockDim.x >> 6;
     int c0, c1;
     chunk_range(a.n_chunks, wpb, persistent, c0, c1);
-    for (int c = c0 + wave; c < c1; c += wpb) local_chunk<R, false>(a, sp, c, lane);
+    for (int c = c0 + wave; c < c1; c += wpb) local_chunk<R, false, Cam>(a, sp, c, lane);
 }
 
-template <typename R>
+template <typename R, typename Cam>
 __global__ __launch_bounds__(LocalBound<R>::threads) void k_local_block(DevArrays<R> a, SolverParams sp,
                                                                         int persistent)
 {
@@ -258,7 +259,7 @@ __global__ __launch_bounds__(LocalBound<R>::threads) void k_local_block(DevArray
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, wpb = blockDim.x >> 6;
     int c0, c1;
     chunk_range(a.n_chunks, wpb, persistent, c0, c1);
-    for (int c = c0 + wave; c < c1; c += wpb) local_block<R>(a, sp, c, lane, lds[wave]);
+    for (int c = c0 + wave; c < c1; c += wpb) local_block<R, Cam>(a, sp, c, lane, lds[wave]);
 }
 
 // Learned start: the workgroup's waves share the staged weights (one copy
@@ -456,7 +457,7 @@ __global__ __launch_bounds__(kNormThreads) void k_norms(DevArrays<R> a)
 }
 
 // ---------------------------------------------------------------- eval
-template <typename R>
+template <typename R, typename Cam>
 __global__ __launch_bounds__(256) void k_eval(DevArrays<R> a, SolverParams sp)
 {
     const int lane = threadIdx.x & 63;
@@ -472,7 +473,7 @@ __global__ __launch_bounds__(256) void k_eval(DevArrays<R> a, SolverParams sp)
 #pragma unroll
         for (int i = 0; i < 9; ++i) th[i] = a.cons_y[(long long)J * kConsY + i];
         th[9] = cx.x; th[10] = cx.y; th[11] = cx.z;
-        const Proj<double> pr = proj_core<double, false>(th);
+        const auto pr = proj_core<double, false>(th, Cam{});
         const typename Vec<R>::R2 z = a.uv[s];
         const double e0 = (double)z.x - pr.pu, e1 = (double)z.y - pr.pv;
         const double s2 = e0 * e0 + e1 * e1;
@@ -570,7 +571,10 @@ hipError_t launch_local(const DevArrays<R> &a, const SolverParams &sp, int block
         grid = (a.n_chunks + block_waves - 1) / block_waves;
     }
     if (grid < 1) grid = 1;
-    hipLaunchKernelGGL(k_local<R>, dim3(grid), dim3(threads), 0, s, a, sp, persistent);
+    if (sp.camera == 1)
+        hipLaunchKernelGGL((k_local<R, CamEuler>), dim3(grid), dim3(threads), 0, s, a, sp, persistent);
+    else
+        hipLaunchKernelGGL((k_local<R, CamAA>), dim3(grid), dim3(threads), 0, s, a, sp, persistent);
     return hipGetLastError();
 }
 
@@ -610,7 +614,10 @@ hipError_t launch_local_block(const DevArrays<R> &a, const SolverParams &sp, int
         grid = (a.n_chunks + block_waves - 1) / block_waves;
     }
     if (grid < 1) grid = 1;
-    hipLaunchKernelGGL(k_local_block<R>, dim3(grid), dim3(threads), 0, s, a, sp, persistent);
+    if (sp.camera == 1)
+        hipLaunchKernelGGL((k_local_block<R, CamEuler>), dim3(grid), dim3(threads), 0, s, a, sp, persistent);
+    else
+        hipLaunchKernelGGL((k_local_block<R, CamAA>), dim3(grid), dim3(threads), 0, s, a, sp, persistent);
     return hipGetLastError();
 }
 
@@ -624,7 +631,10 @@ hipError_t launch_norms(const DevArrays<R> &a, hipStream_t s)
 template <typename R>
 hipError_t launch_eval(const DevArrays<R> &a, const SolverParams &sp, hipStream_t s)
 {
-    hipLaunchKernelGGL(k_eval<R>, dim3((a.n_chunks + 3) / 4), dim3(256), 0, s, a, sp);
+    if (sp.camera == 1)
+        hipLaunchKernelGGL((k_eval<R, CamEuler>), dim3((a.n_chunks + 3) / 4), dim3(256), 0, s, a, sp);
+    else
+        hipLaunchKernelGGL((k_eval<R, CamAA>), dim3((a.n_chunks + 3) / 4), dim3(256), 0, s, a, sp);
     hipLaunchKernelGGL(k_eval_reduce<R>, dim3(a.n_problems), dim3(kNormThreads), 0, s, a);
     return hipGetLastError();
 }

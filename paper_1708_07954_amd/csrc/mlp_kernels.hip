@@ -336,7 +336,7 @@ __global__ __launch_bounds__(256) void k_collect_pairs(DevArrays<float> a, Solve
 #pragma unroll
     for (int i = 0; i < 12; ++i) v[i] = (float)(cons[i] - u[i]);
     const float2 z = a.uv[s];
-    const Proj<float> p0 = proj_core<float, true>(th);
+    const Proj<float> p0 = proj_core<float, true>(th, CamAA{});
     float *f = feat + (size_t)q * kIn;
     f[0] = z.x - p0.pu;
     f[1] = z.y - p0.pv;
@@ -347,7 +347,7 @@ __global__ __launch_bounds__(256) void k_collect_pairs(DevArrays<float> a, Solve
     float tc[12];
 #pragma unroll
     for (int i = 0; i < 12; ++i) tc[i] = th[i];
-    local_lm<float>(tc, v, z.x, z.y, (float)ct.rho_x, (float)ct.rho_y, sp.loss, (float)sp.loss_param, conv_steps,
+    local_lm<float, CamAA>(tc, v, z.x, z.y, (float)ct.rho_x, (float)ct.rho_y, sp.loss, (float)sp.loss_param, conv_steps,
                     (float)sp.lambda0);
 #pragma unroll
     for (int i = 0; i < 12; ++i) delta[(size_t)q * kOut + i] = tc[i] - th[i];

@@ -1,0 +1,131 @@
+"""GPU parity of the paper's own camera (Sec. 2.1, Eq. 1: Euler angles and
+translation, known focal length, no distortion; camera_model = euler)
+against the FP64 oracle on the same seeded scenes: FP64 within 1e-9 on every
+parameter, FP32 within 1e-3 and RMSE within 0.5 %, for the per-observation
+and the block local updates; the unused camera slots stay bitwise at their
+values; state, batched = solo, and validation."""
+import numpy as np
+import pytest
+
+import oracle
+from paper_1708_07954_amd import binding
+from scenes import make_sphere_scene, make_trajectory_scene
+from _util import param_rel_err, state_rel_err
+
+pytestmark = pytest.mark.gpu
+
+CASES = {
+    "sphere_t": (lambda: make_sphere_scene(seed=8, n_cams=20, n_points=700, camera="euler"),
+                 dict(loss="student_t", loss_param=4.0, rho=1e3), 12),
+    "traj_huber_balancing": (lambda: make_trajectory_scene(seed=4, n_cams=40, n_points=900, camera="euler"),
+                             dict(loss="huber", loss_param=2.0, rho=1e4, rho_balancing=True, rho_min=1e4,
+                                  rho_max=1e7), 12),
+    "sphere_l2": (lambda: make_sphere_scene(seed=9, n_cams=10, n_points=300, k_lo=4, k_hi=8, camera="euler"),
+                  dict(loss="l2", loss_param=1.0, rho=1e4), 15),
+}
+
+
+def _oracle(sc, iters, blocks=False, rho_min=1e-6, rho_max=1e6, **kw):
+    p = oracle.Problem.from_scene(sc)
+    if blocks:
+        a = oracle.BlockADMM(p, sc.cams_init, sc.points_init, block=64, camera="euler", **kw)
+    else:
+        a = oracle.ADMM(p, sc.cams_init, sc.points_init, camera="euler", **kw)
+    a.opts.rho_min, a.opts.rho_max = rho_min, rho_max
+    tr = a.iterate(iters)
+    return a, tr
+
+
+def _gpu(sc, iters, **kw):
+    s = binding.Solver(camera="euler", **kw).set_scene(sc)
+    s.iterate(iters)
+    return s
+
+
+@pytest.mark.parametrize("blocks", [False, True])
+@pytest.mark.parametrize("case", sorted(CASES))
+def test_euler_fp64_parity(case, blocks):
+    make, kw, iters = CASES[case]
+    sc = make()
+    a, tr = _oracle(sc, iters, blocks=blocks, **kw)
+    s = _gpu(sc, iters, precision="fp64", camera_blocks=blocks, **kw)
+    cams, pts = s.params()
+    err = param_rel_err(cams, pts, a.cons_y, a.cons_x)
+    r = s.residuals(want_rmse=True)
+    print(case, "blocks" if blocks else "per-observation", "max rel err", err, "rmse", r["rmse"], a.stats()[0])
+    assert err < 1e-9
+    assert r["primal"] == pytest.approx(tr[-1, 0], rel=1e-6)
+    assert r["dual"] == pytest.approx(tr[-1, 1], rel=1e-6)
+    assert r["rmse"] == pytest.approx(a.stats()[0], rel=1e-9)
+    # the focal length and the unused slots never move
+    assert np.array_equal(cams[:, 6:], sc.cams_init[:, 6:])
+    s.close()
+
+
+@pytest.mark.parametrize("blocks", [False, True])
+@pytest.mark.parametrize("case", ["sphere_t", "traj_huber_balancing"])
+def test_euler_fp32_parity(case, blocks):
+    make, kw, iters = CASES[case]
+    sc = make()
+    a, _ = _oracle(sc, iters, blocks=blocks, **kw)
+    s = _gpu(sc, iters, precision="fp32", camera_blocks=blocks, **kw)
+    cams, pts = s.params()
+    err = param_rel_err(cams, pts, a.cons_y, a.cons_x)
+    r = s.residuals(want_rmse=True)
+    print(case, "blocks" if blocks else "per-observation", "fp32 max rel err", err, "rmse", r["rmse"], a.stats()[0])
+    assert err < 1e-3
+    assert abs(r["rmse"] - a.stats()[0]) < 5e-3 * a.stats()[0]
+    assert np.array_equal(cams[:, 6:], sc.cams_init[:, 6:])
+    s.close()
+
+
+def test_euler_state_parity():
+    make, kw, _ = CASES["sphere_t"]
+    sc = make()
+    a, _ = _oracle(sc, 5, **kw)
+    s = _gpu(sc, 5, precision="fp64", **kw)
+    copies, duals = s.state()
+    assert state_rel_err(copies, a.copy) < 1e-9
+    assert state_rel_err(duals, a.dual) < 1e-7
+    s.close()
+
+
+def test_euler_batched_equals_solo_bitwise():
+    scenes = [make_sphere_scene(seed=40 + q, n_cams=6 + 2 * q, n_points=150 + 40 * q, camera="euler") for q in range(3)]
+    kw = dict(precision="fp32", loss="huber", loss_param=2.0, rho=1e3, camera="euler")
+    s = binding.Solver(**kw).set_scenes(scenes)
+    s.iterate(6)
+    for q, sc in enumerate(scenes):
+        solo = binding.Solver(**kw).set_scene(sc)
+        solo.iterate(6)
+        a, b = s.params(q), solo.params()
+        assert np.array_equal(a[0], b[0]) and np.array_equal(a[1], b[1])
+        solo.close()
+    s.close()
+
+
+def test_euler_validation():
+    with pytest.raises(binding.DbaError) as e:
+        binding.Solver(precision="fp32", camera="euler", start="learned")
+    assert e.value.status == "DBA_E_INVALID_ARG"
+    sc = make_sphere_scene(seed=8, n_cams=5, n_points=60, camera="euler")
+    for slot, value in ((7, 1e-3), (8, -1e-3), (6, 0.0)):
+        cams = sc.cams_init.copy()
+        cams[2, slot] = value
+        s = binding.Solver(precision="fp64", camera="euler")
+        with pytest.raises(binding.DbaError) as e:
+            s.set_scene(sc, cams=cams)
+        assert e.value.status == "DBA_E_INVALID_ARG", slot
+        s.close()
+    # a point moved behind its camera at the start
+    pts = sc.points_init.copy()
+    R = oracle.euler_rotation(sc.cams_init[0])
+    c = -R.T @ sc.cams_init[0, 3:6]              # camera centre
+    k = int(np.flatnonzero(sc.obs_cam == 0)[0])
+    i = sc.obs_point[k]
+    pts[i] = c - 1.0 * R[2]                     # one unit behind along the optical axis
+    s = binding.Solver(precision="fp64", camera="euler")
+    with pytest.raises(binding.DbaError) as e:
+        s.set_scene(sc, points=pts)
+    assert e.value.status == "DBA_E_BEHIND_CAMERA"
+    s.close()

@@ -32,8 +32,29 @@ LM_STEP = JAC + RESID + GRAD + FACTOR + SOLVE + TRIAL
 PER_SOLVE = (PROJ + 48) + 36 + 12 + 19 * 6 + 40
 
 
-def local_flops_per_obs(lm_steps: int = 5) -> int:
+def local_flops_per_obs(lm_steps: int = 5, camera: str = "angle_axis") -> int:
+    if camera == "euler":
+        return PER_SOLVE_E + lm_steps * LM_STEP_E
     return PER_SOLVE + lm_steps * LM_STEP
+
+
+# --- the Euler camera of Eq. (1): 6 camera + 3 point unknowns -----------------
+# the algorithmic work of the paper's 9-unknown local problem (the kernel also
+# carries the 3 unused camera slots through its 12-wide solve; not counted).
+# projection: three sincos (2 each), X1 = R1 X, X2 = R2 X1, Q = R3 X2 (6 x 3),
+# translation 3, perspective and focal length 5
+PROJ_E = 6 + 18 + 3 + 5
+# Jacobian rows: A 3, per row c = a R3 (6), b = c R2 (6), three angle columns
+# (9), point columns (6)
+JAC_E = 3 + 2 * 27
+GRAD_9 = 9 * 14
+FACTOR_9 = 9 * 9 + 9 * 12
+SOLVE_9 = 4 * 36 + 9
+# trial point 9, predicted decrease 47, objective at the trial (projection,
+# residual 5, loss 5, 9-term penalty 27, total 2), acceptance 30
+TRIAL_9 = 9 + 47 + PROJ_E + 39 + 30
+LM_STEP_E = JAC_E + RESID + GRAD_9 + FACTOR_9 + SOLVE_9 + TRIAL_9
+PER_SOLVE_E = (PROJ_E + 39) + 27 + 9 + 19 * 6 + 40
 
 
 # --- block local updates (one camera copy per 64 observations) -------------------
@@ -68,5 +89,6 @@ def bytes_per_obs(fp32: bool = True) -> dict:
 
 if __name__ == "__main__":
     print("LM step flops", LM_STEP, "per obs (5 steps)", local_flops_per_obs(5))
+    print("Euler camera: LM step flops", LM_STEP_E, "per obs (5 steps)", local_flops_per_obs(5, "euler"))
     print("bytes fp32", bytes_per_obs(True), "fp64", bytes_per_obs(False))
     print("block LM step flops", BLOCK_LM_STEP, "per obs (5 steps)", block_flops_per_obs(5))

@@ -158,6 +158,11 @@ __device__ __forceinline__ void proj_jac(const Proj<R> &o, const R *th, R *J0, R
 struct CamAA {};
 struct CamEuler {};
 
+// Whether parameter i of the 12 (camera 0..8, point 9..11) is an unknown of
+// the camera model; the others keep their value and drop out of the solve.
+template <typename Cam> __host__ __device__ constexpr bool cam_active(int i) { return true; }
+template <> __host__ __device__ constexpr bool cam_active<CamEuler>(int i) { return i < 6 || i > 8; }
+
 template <typename R, bool DERIV>
 __device__ __forceinline__ Proj<R> proj_core(const R *th, CamAA)
 {
@@ -248,7 +253,7 @@ __device__ __forceinline__ R loss_phi(int kind, R lp, R s, R &w)
 // Local objective of Eq. (9) in scaled form at the point of `o`:
 // phi(|z - pi|^2) + 1/2 sum_i P_i (theta_i - v_i)^2, P = (rho_y x9, rho_x x3);
 // +inf when the depth is <= 1e-6.
-template <typename R, typename P>
+template <typename R, typename Cam = CamAA, typename P>
 __device__ __forceinline__ R objective(const P &o, const R *th, const R *v, R z0, R z1,
                                        R rx, R ry, int kind, R lp)
 {
@@ -259,6 +264,7 @@ __device__ __forceinline__ R objective(const P &o, const R *th, const R *v, R z0
     R pen = R(0);
 #pragma unroll
     for (int i = 0; i < 12; ++i) {
+        if (!cam_active<Cam>(i)) continue;
         const R dd = th[i] - v[i];
         pen += (i < 9 ? ry : rx) * dd * dd;
     }
@@ -282,7 +288,7 @@ template <typename R> __device__ __forceinline__ R lam_up(R l) { return l * R(10
 // operations, but in FP32 its cancellation in the two stiff directions,
 // amplified over many ADMM iterations along nearly flat directions of the
 // global problem, costs an order of magnitude in agreement with FP64.)
-template <typename R>
+template <typename R, typename Cam = CamAA>
 __device__ __forceinline__ bool solve_normal(const R *Dd, const R *J0, const R *J1, R c2, const R *ng, R *x)
 {
     // rank-one update 1: diag -> L1 D1 L1^T (p = J0); alpha_{j+1} =
@@ -291,6 +297,7 @@ __device__ __forceinline__ bool solve_normal(const R *Dd, const R *J0, const R *
     R al = c2;
 #pragma unroll
     for (int j = 0; j < 12; ++j) {
+        if (!cam_active<Cam>(j)) continue;  // no unknown: no row
         const R ap = al * J0[j];
         d1[j] = Dd[j] + ap * J0[j];
         const R r = Num<R>::rcp(d1[j]);
@@ -303,6 +310,7 @@ __device__ __forceinline__ bool solve_normal(const R *Dd, const R *J0, const R *
     bool pos = true;
 #pragma unroll
     for (int j = 0; j < 12; ++j) {
+        if (!cam_active<Cam>(j)) continue;
         q[j] = J1[j] - J0[j] * S;
         S += b1[j] * q[j];
         const R aq = al2 * q[j];
@@ -318,26 +326,34 @@ __device__ __forceinline__ bool solve_normal(const R *Dd, const R *J0, const R *
     S = R(0);
 #pragma unroll
     for (int j = 0; j < 12; ++j) {
+        if (!cam_active<Cam>(j)) {
+            x[j] = R(0);
+            continue;
+        }
         x[j] = ng[j] - J0[j] * S;
         S += b1[j] * x[j];
     }
     S = R(0);
 #pragma unroll
     for (int j = 0; j < 12; ++j) {
+        if (!cam_active<Cam>(j)) continue;
         x[j] = x[j] - q[j] * S;
         S += b2[j] * x[j];
     }
 #pragma unroll
-    for (int j = 0; j < 12; ++j) x[j] *= id2[j];
+    for (int j = 0; j < 12; ++j)
+        if (cam_active<Cam>(j)) x[j] *= id2[j];
     S = R(0);
 #pragma unroll
     for (int j = 11; j >= 0; --j) {
+        if (!cam_active<Cam>(j)) continue;
         x[j] = x[j] - b2[j] * S;
         S += q[j] * x[j];
     }
     S = R(0);
 #pragma unroll
     for (int j = 11; j >= 0; --j) {
+        if (!cam_active<Cam>(j)) continue;
         x[j] = x[j] - b1[j] * S;
         S += J0[j] * x[j];
     }
@@ -371,16 +387,21 @@ __device__ __forceinline__ void lm_steps(R *th, P &cur, R &F, const R *v, R z0, 
         R x[12], ng[12], hd[12], Dd[12];
 #pragma unroll
         for (int i = 0; i < 12; ++i) {
+            if (!cam_active<Cam>(i)) continue;  // not an unknown of the camera model
             const R Pi = i < 9 ? ry : rx;
             ng[i] = c2 * (J0[i] * e0 + J1[i] * e1) - Pi * (th[i] - v[i]);  // -gradient
             hd[i] = Pi + c2 * (J0[i] * J0[i] + J1[i] * J1[i]);             // diag(H)
             Dd[i] = Pi + lam * hd[i];                                       // A - c J^T J
         }
-        const bool ok = solve_normal(Dd, J0, J1, c2, ng, x);
+        const bool ok = solve_normal<R, Cam>(Dd, J0, J1, c2, ng, x);
         R tr[12];
         R gd = R(0), dd = R(0);
 #pragma unroll
         for (int i = 0; i < 12; ++i) {
+            if (!cam_active<Cam>(i)) {
+                tr[i] = th[i];
+                continue;
+            }
             tr[i] = th[i] + x[i];
             gd += ng[i] * x[i];
             dd += hd[i] * x[i] * x[i];
@@ -388,7 +409,7 @@ __device__ __forceinline__ void lm_steps(R *th, P &cur, R &F, const R *v, R z0, 
         // decrease predicted by the damped Gauss-Newton model
         const R pred = R(0.5) * (lam * dd + gd);
         const P nxt = proj_core<R, true>(tr, Cam{});
-        const R Fn = ok ? objective<R>(nxt, tr, v, z0, z1, rx, ry, kind, lp) : Num<R>::inf;
+        const R Fn = ok ? objective<R, Cam>(nxt, tr, v, z0, z1, rx, ry, kind, lp) : Num<R>::inf;
         // accept a decrease of F, or a step too small for F to judge
         if (Fn < Num<R>::inf && (Fn < F || pred <= Num<R>::tie * fres)) {
 #pragma unroll
@@ -407,7 +428,7 @@ __device__ __forceinline__ void local_lm(R *th, const R *v, R z0, R z1, R rx, R 
                                          R lp, int steps, R lam)
 {
     auto cur = proj_core<R, true>(th, Cam{});
-    R F = objective<R>(cur, th, v, z0, z1, rx, ry, kind, lp);
+    R F = objective<R, Cam>(cur, th, v, z0, z1, rx, ry, kind, lp);
     lm_steps<R, Cam>(th, cur, F, v, z0, z1, rx, ry, kind, lp, steps, lam);
 }
 

@@ -6,6 +6,7 @@ against.  Calls only the FP64 oracle (oracle/) on seeded scenes (scenes/).
     python tests/golden/make_golden.py batch        # ~1 min
     python tests/golden/make_golden.py trajectory_perturbed sphere_perturbed
     python tests/golden/make_golden.py trajectory_blocks   # block local updates, ~25 min
+    python tests/golden/make_golden.py trajectory_euler    # the Euler camera, ~35 min
 
 A name ending in _perturbed runs the same workload from a start whose
 parameters are multiplied by 1 +- 1e-7 (random signs, seed 7), the size of
@@ -30,6 +31,11 @@ SPECS = {
     "trajectory": (make_config2, dict(loss="huber", loss_param=2.0, rho=1e5, rho_balancing=True,
                                       rho_min=1e5, rho_max=1e7), 200, 50),
     "sphere": (make_config1, dict(loss="student_t", loss_param=4.0, rho=1e3), 100, 10),
+    # the trajectory workload with the paper's Euler camera (Eq. 1); seed 7,
+    # whose perturbed start keeps every point in front of its cameras
+    "trajectory_euler": (lambda: make_config2(seed=7, camera="euler"),
+                         dict(loss="huber", loss_param=2.0, rho=1e5, rho_balancing=True, rho_min=1e5, rho_max=1e7,
+                              camera="euler"), 200, 50),
 }
 
 

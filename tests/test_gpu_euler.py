@@ -129,3 +129,20 @@ def test_euler_validation():
         s.set_scene(sc, points=pts)
     assert e.value.status == "DBA_E_BEHIND_CAMERA"
     s.close()
+
+
+def test_euler_full_size_first_iteration_matches_oracle():
+    """One iteration of the 2M-observation trajectory workload with the Euler
+    camera (seed 7), in the benchmark's launch configuration, against the
+    oracle run at test time: FP64 within 1e-9, FP32 within 1e-3."""
+    from scenes import make_config2
+    sc = make_config2(seed=7, camera="euler")
+    kw = dict(loss="huber", loss_param=2.0, rho=1e5, rho_balancing=True)
+    a, _ = _oracle(sc, 1, rho_min=1e5, rho_max=1e7, **kw)
+    for precision, tol in (("fp32", 1e-3), ("fp64", 1e-9)):
+        s = _gpu(sc, 1, precision=precision, rho_min=1e5, rho_max=1e7, block_waves=1, persistent=0, **kw)
+        cams, pts = s.params()
+        err = param_rel_err(cams, pts, a.cons_y, a.cons_x)
+        print(precision, "Euler full-size 1-iteration max rel err", err)
+        assert err < tol
+        s.close()

@@ -313,6 +313,46 @@ def size_sweep(binding, opts, factors=(0.0625, 0.125, 0.25, 0.5, 1.0, 2.0, 4.0, 
             "max_rel_deviation_from_fit": float(np.max(np.abs(t - fit) / t))}
 
 
+def convergence_study(binding, rho=100.0, iters=200, seeds=32, checkpoints=(0, 10, 25, 50, 100, 200)):
+    """The paper's convergence study (Sec. 5.1, Fig. 3) with its camera
+    (Eq. 1): 5 cameras, 10 points, all 50 observations, pixel noise 1;
+    camera angles and positions started with noise 0.1, points with noise
+    sigma = 0.2 .. 1.7; squared-l2 against Huber (delta 2) misfit, rho as
+    given.  Every (sigma, seed) problem of one loss runs in the same
+    batched launches (FP64); the medians over the seeds of the reprojection
+    RMSE at the checkpoints and of the final point MSE against the ground
+    truth are reported per sigma."""
+    import numpy as np
+    from scenes import make_sphere_scene
+    sigmas = [round(0.2 + 0.15 * k, 2) for k in range(11)]
+    scenes = [make_sphere_scene(seed=1000 + q, n_cams=5, n_points=10, k_lo=5, k_hi=5, radius=10.0, box=2.0,
+                                rot_sigma=0.1, trans_sigma=0.1, point_sigma=sig, camera="euler")
+              for sig in sigmas for q in range(seeds)]
+    res = {"rho": rho, "iterations": iters, "seeds": seeds, "sigmas": sigmas, "checkpoints": list(checkpoints),
+           "scene": "5 cameras on a sphere cap (radius 10) looking at the origin, 10 points in [-2, 2]^3, "
+                    "all 50 observations, pixel noise 1, Euler camera (Eq. 1)"}
+    for loss, lp in (("l2", 1.0), ("huber", 2.0)):
+        s = binding.Solver(precision="fp64", camera="euler", loss=loss, loss_param=lp, rho=rho).set_scenes(scenes)
+        curves = np.zeros((len(scenes), len(checkpoints)))
+        done = 0
+        for c, it in enumerate(checkpoints):
+            s.iterate(it - done)
+            done = it
+            for q in range(len(scenes)):
+                curves[q, c] = s.residuals(q, want_rmse=True)["rmse"]
+        mse = np.array([np.mean(np.sum((s.params(q)[1] - sc.points_gt) ** 2, axis=1))
+                        for q, sc in enumerate(scenes)])
+        s.close()
+        curves = curves.reshape(len(sigmas), seeds, len(checkpoints))
+        mse = mse.reshape(len(sigmas), seeds)
+        res[loss] = {"rmse_median": [[float(np.nanmedian(curves[k, :, c])) for c in range(len(checkpoints))]
+                                     for k in range(len(sigmas))],
+                     "final_point_mse_median": [float(np.nanmedian(mse[k])) for k in range(len(sigmas))]}
+        print(f"[bench] convergence study {loss}: final RMSE medians "
+              f"{[round(r[-1], 3) for r in res[loss]['rmse_median']]}", file=sys.stderr, flush=True)
+    return res
+
+
 def profile_learned(binding, wl):
     """Short learned-start run for counter collection: collects pairs on two
     training scenes, trains two epochs, then 20 learned-start iterations (3 LM
@@ -415,6 +455,8 @@ def main():
     ap.add_argument("--size-sweep", action="store_true",
                     help="also time one iteration at 0.125M..16M observations of trajectory problems "
                          "(the workload's options)")
+    ap.add_argument("--convergence-study", action="store_true",
+                    help="also run the paper's l2-vs-Huber convergence study (5 cameras, 10 points, Euler camera)")
     ap.add_argument("--copy-probe-mib", type=int, default=0,
                     help="also run a plain device copy of this size (counter calibration)")
     args = ap.parse_args()
@@ -570,6 +612,9 @@ def main():
 
     if args.size_sweep and args.workload.startswith("trajectory"):
         out["size_sweep"] = size_sweep(binding, opts)
+
+    if args.convergence_study:
+        out["convergence_study"] = convergence_study(binding)
 
     if args.block_sweep and args.workload.startswith("trajectory"):
         target, its = oracle_target("trajectory")

@@ -146,3 +146,24 @@ def test_euler_full_size_first_iteration_matches_oracle():
         print(precision, "Euler full-size 1-iteration max rel err", err)
         assert err < tol
         s.close()
+
+
+def test_euler_convergence_study_problems_match_the_oracle():
+    """Problems of the l2-vs-Huber convergence study (5 cameras, 10 points,
+    50 observations, point noise 0.2 .. 1.7), batched, against the oracle run
+    on each alone: FP64 within 1e-9 after 15 iterations."""
+    scenes = [make_sphere_scene(seed=1000 + q, n_cams=5, n_points=10, k_lo=5, k_hi=5, radius=10.0, box=2.0,
+                                rot_sigma=0.1, trans_sigma=0.1, point_sigma=sig, camera="euler")
+              for q, sig in enumerate((0.2, 0.8, 1.4, 1.7))]
+    for loss, lp in (("l2", 1.0), ("huber", 2.0)):
+        s = binding.Solver(precision="fp64", camera="euler", loss=loss, loss_param=lp, rho=100.0).set_scenes(scenes)
+        s.iterate(15)
+        for q, sc in enumerate(scenes):
+            a = oracle.ADMM(oracle.Problem.from_scene(sc), sc.cams_init, sc.points_init, loss=loss, loss_param=lp,
+                            rho=100.0, camera="euler")
+            a.iterate(15)
+            cams, pts = s.params(q)
+            err = param_rel_err(cams, pts, a.cons_y, a.cons_x)
+            print(loss, q, "max rel err", err)
+            assert err < 1e-9
+        s.close()

@@ -53,6 +53,9 @@ Readings where the paper is silent or loose (the same on the GPU path):
      camera row keeps 9 slots (alpha, beta, gamma, t, f, 0, 0): slots 6-8
      have zero Jacobian columns, so every local solve leaves them at their
      value and exactly the 6 + 3 unknowns of the paper move.
+  R11 ``solver="gauss_newton"`` (the paper's local solver for the l2 misfit,
+     Sec. 3.1): the steps of R4 without damping, A = 2 w J^T J + P, and every
+     step whose trial is finite is taken (no decrease test).
 """
 from __future__ import annotations
 
@@ -69,6 +72,7 @@ _LIB = os.path.join(_HERE, "liboracle.so")
 
 LOSS = {"l2": 0, "huber": 1, "student_t": 2}
 CAMERA = {"angle_axis": 0, "euler": 1}
+SOLVER = {"lm": 0, "gauss_newton": 1}
 
 
 def build(force: bool = False) -> str:
@@ -103,7 +107,7 @@ class OrcOpts(ctypes.Structure):
                 ("lm_steps", ctypes.c_int32), ("lambda0", ctypes.c_double),
                 ("rho_balancing", ctypes.c_int32), ("rb_mu", ctypes.c_double),
                 ("rb_tau", ctypes.c_double), ("rho_min", ctypes.c_double),
-                ("rho_max", ctypes.c_double), ("camera", ctypes.c_int32)]
+                ("rho_max", ctypes.c_double), ("camera", ctypes.c_int32), ("solver", ctypes.c_int32)]
 
 
 def _declare(L):
@@ -161,10 +165,11 @@ def _f64(a):
 
 
 def make_opts(loss="huber", loss_param=2.0, lm_steps=5, lambda0=1e-3,
-              rho_balancing=False, rb_mu=10.0, rb_tau=2.0, rho_min=1e-6, rho_max=1e6, camera="angle_axis"):
+              rho_balancing=False, rb_mu=10.0, rb_tau=2.0, rho_min=1e-6, rho_max=1e6, camera="angle_axis",
+              solver="lm"):
     return OrcOpts(LOSS[loss] if isinstance(loss, str) else int(loss), float(loss_param),
                    int(lm_steps), float(lambda0), int(bool(rho_balancing)), float(rb_mu),
-                   float(rb_tau), float(rho_min), float(rho_max), CAMERA[camera])
+                   float(rb_tau), float(rho_min), float(rho_max), CAMERA[camera], SOLVER[solver])
 
 
 # ---------------------------------------------------------------- pieces
@@ -256,9 +261,9 @@ class ADMM:
 
     def __init__(self, problem: Problem, cams0, points0, *, loss="huber", loss_param=2.0,
                  rho=1.0, rho_x=None, rho_y=None, rho_balancing=False, lm_steps=5,
-                 lambda0=1e-3, camera="angle_axis"):
+                 lambda0=1e-3, camera="angle_axis", solver="lm"):
         self.p = problem
-        self.opts = make_opts(loss, loss_param, lm_steps, lambda0, rho_balancing, camera=camera)
+        self.opts = make_opts(loss, loss_param, lm_steps, lambda0, rho_balancing, camera=camera, solver=solver)
         self.loss, self.loss_param, self.camera = loss, loss_param, camera
         self.cons_y = _f64(cams0).reshape(-1, 9).copy()
         self.cons_x = _f64(points0).reshape(-1, 3).copy()

@@ -362,6 +362,7 @@ typedef struct {
     int32_t rho_balancing;
     double rb_mu, rb_tau, rho_min, rho_max;
     int32_t camera;  /* 0: angle-axis camera (9 unknowns), 1: Euler camera (6) */
+    int32_t solver;  /* 0: robust LM (reading 4), 1: Gauss-Newton (no damping, every finite step taken) */
 } orc_opts;
 
 double orc_local_objective(const orc_opts *o, const double z[2], const double v[12],
@@ -409,9 +410,10 @@ int orc_local_solve(const orc_opts *o, const double z[2], const double v[12],
                 H[r * 12 + s] = 2.0 * w * (J[r] * J[s] + J[12 + r] * J[12 + s])
                                 + (r == s ? pr : 0.0);
         }
+        const int gn = o->solver == 1;
         for (int r = 0; r < 12; ++r) {
             for (int s = 0; s < 12; ++s) A[r * 12 + s] = H[r * 12 + s];
-            A[r * 12 + r] += lambda * H[r * 12 + r];
+            if (!gn) A[r * 12 + r] += lambda * H[r * 12 + r];
             rhs[r] = -g[r];
         }
         int ok = orc_cholesky_solve(12, A, rhs, delta) == 0;
@@ -431,7 +433,8 @@ int orc_local_solve(const orc_opts *o, const double z[2], const double v[12],
         }
         /* accept a decrease of F; a step whose predicted decrease is below
          * what F can resolve is accepted on the model's word */
-        if (ok && isfinite(Fn) && (Fn < F || pred <= ORC_TIE * fres)) {
+        /* Gauss-Newton takes every step whose trial is finite */
+        if (ok && isfinite(Fn) && (gn || Fn < F || pred <= ORC_TIE * fres)) {
             memcpy(theta, trial, sizeof(trial));
             F = Fn;
             lambda = fmax(lambda / 10.0, ORC_LAMBDA_MIN);

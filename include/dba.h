@@ -70,6 +70,13 @@ typedef enum {
                                   focal length f; a camera row is (alpha, beta, gamma, t, f, 0, 0) */
 } dba_camera;
 
+typedef enum {
+    DBA_SOLVER_LM = 0,           /* robust Levenberg-Marquardt (lm_steps, lm_lambda0) */
+    DBA_SOLVER_GAUSS_NEWTON = 1  /* the paper's solver for the l2 misfit (Sec. 3.1): the same steps
+                                    without damping, every step with a finite trial taken;
+                                    per-observation local solves, plain start only */
+} dba_local_solver;
+
 typedef struct dba_options {
     int32_t device;           /* HIP device ordinal */
     void *stream;             /* hipStream_t to enqueue on; NULL: a stream the handle creates */
@@ -96,13 +103,14 @@ typedef struct dba_options {
     int32_t block_points;     /* with camera_blocks: observations (points) per block, the pi of
                                  Sec. 3.1.4, 1..64; 0 means 64.  Must be 0 without camera_blocks */
     int32_t camera_model;     /* dba_camera; the Euler camera not with the learned start */
+    int32_t local_solver;     /* dba_local_solver */
 } dba_options;
 
 /* Fills *opt with the defaults: device 0, NULL stream, FP64, Huber 2 px,
  * rho 1, no balancing (mu 10, tau 2, clamps 1e-6..1e6), 5 LM steps,
  * lambda0 1e-3, plain start, 2 learned steps, graphs on, autotune, one
  * local problem per observation (camera_blocks 0, block_points 0), the
- * 9-parameter angle-axis camera. */
+ * 9-parameter angle-axis camera, robust LM. */
 int dba_default_options(dba_options *opt);
 
 /* Creates a handle on opt->device.  *out receives the handle. */

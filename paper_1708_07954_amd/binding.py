@@ -16,6 +16,7 @@ LIB_PATH = os.path.join(HERE, "libdba.so")
 
 DBA_OK = 0
 CAMERA = {"angle_axis": 0, "euler": 1}
+SOLVER = {"lm": 0, "gauss_newton": 1}
 STATUS = {0: "DBA_OK", -1: "DBA_E_INVALID_ARG", -2: "DBA_E_INDEX_RANGE", -3: "DBA_E_UNOBSERVED",
           -4: "DBA_E_NONFINITE", -5: "DBA_E_BEHIND_CAMERA", -6: "DBA_E_DEVICE", -7: "DBA_E_STATE"}
 LOSS = {"l2": 0, "huber": 1, "student_t": 2}
@@ -42,7 +43,8 @@ class dba_options(ctypes.Structure):
                 ("start", ctypes.c_int32), ("learned_lm_steps", ctypes.c_int32),
                 ("use_graph", ctypes.c_int32), ("block_waves", ctypes.c_int32),
                 ("persistent", ctypes.c_int32), ("camera_blocks", ctypes.c_int32),
-                ("block_points", ctypes.c_int32), ("camera_model", ctypes.c_int32)]
+                ("block_points", ctypes.c_int32), ("camera_model", ctypes.c_int32),
+                ("local_solver", ctypes.c_int32)]
 
 
 class dba_problem_desc(ctypes.Structure):
@@ -135,7 +137,7 @@ def make_options(*, device=0, stream=None, precision="fp64", loss="huber", loss_
                  rho_x=None, rho_y=None, rho_balancing=False, rb_mu=10.0, rb_tau=2.0,
                  rho_min=1e-6, rho_max=1e6, lm_steps=5, lm_lambda0=1e-3, start="plain",
                  learned_lm_steps=2, use_graph=True, block_waves=0, persistent=-1,
-                 camera_blocks=False, block_points=0, camera="angle_axis") -> dba_options:
+                 camera_blocks=False, block_points=0, camera="angle_axis", solver="lm") -> dba_options:
     o = dba_options()
     _check(None, load().dba_default_options(ctypes.byref(o)))
     o.device = device
@@ -157,6 +159,7 @@ def make_options(*, device=0, stream=None, precision="fp64", loss="huber", loss_
     o.camera_blocks = int(bool(camera_blocks))
     o.block_points = int(block_points)
     o.camera_model = CAMERA[camera]
+    o.local_solver = SOLVER[solver]
     return o
 
 

@@ -370,7 +370,9 @@ __device__ __forceinline__ bool solve_normal(const R *Dd, const R *J0, const R *
 // Normal equations: A = H + lambda diag(H), H = P + 2w J^T J, i.e.
 // A = D + c (J0 J0^T + J1 J1^T) with D diagonal and c = 2w, solved in
 // registers in O(12) operations (solve_normal).
-template <typename R, typename Cam, typename P>
+// GN: Gauss-Newton instead -- no damping (A = H) and every step whose trial
+// is finite is taken.
+template <typename R, typename Cam, bool GN = false, typename P>
 __device__ __forceinline__ void lm_steps(R *th, P &cur, R &F, const R *v, R z0, R z1, R rx,
                                          R ry, int kind, R lp, int steps, R lam)
 {
@@ -391,7 +393,7 @@ __device__ __forceinline__ void lm_steps(R *th, P &cur, R &F, const R *v, R z0, 
             const R Pi = i < 9 ? ry : rx;
             ng[i] = c2 * (J0[i] * e0 + J1[i] * e1) - Pi * (th[i] - v[i]);  // -gradient
             hd[i] = Pi + c2 * (J0[i] * J0[i] + J1[i] * J1[i]);             // diag(H)
-            Dd[i] = Pi + lam * hd[i];                                       // A - c J^T J
+            Dd[i] = GN ? Pi : Pi + lam * hd[i];                             // A - c J^T J
         }
         const bool ok = solve_normal<R, Cam>(Dd, J0, J1, c2, ng, x);
         R tr[12];
@@ -411,7 +413,7 @@ __device__ __forceinline__ void lm_steps(R *th, P &cur, R &F, const R *v, R z0, 
         const P nxt = proj_core<R, true>(tr, Cam{});
         const R Fn = ok ? objective<R, Cam>(nxt, tr, v, z0, z1, rx, ry, kind, lp) : Num<R>::inf;
         // accept a decrease of F, or a step too small for F to judge
-        if (Fn < Num<R>::inf && (Fn < F || pred <= Num<R>::tie * fres)) {
+        if (Fn < Num<R>::inf && (GN || Fn < F || pred <= Num<R>::tie * fres)) {
 #pragma unroll
             for (int i = 0; i < 12; ++i) th[i] = tr[i];
             cur = nxt;
@@ -423,13 +425,13 @@ __device__ __forceinline__ void lm_steps(R *th, P &cur, R &F, const R *v, R z0, 
     }
 }
 
-template <typename R, typename Cam>
+template <typename R, typename Cam, bool GN = false>
 __device__ __forceinline__ void local_lm(R *th, const R *v, R z0, R z1, R rx, R ry, int kind,
                                          R lp, int steps, R lam)
 {
     auto cur = proj_core<R, true>(th, Cam{});
     R F = objective<R, Cam>(cur, th, v, z0, z1, rx, ry, kind, lp);
-    lm_steps<R, Cam>(th, cur, F, v, z0, z1, rx, ry, kind, lp, steps, lam);
+    lm_steps<R, Cam, GN>(th, cur, F, v, z0, z1, rx, ry, kind, lp, steps, lam);
 }
 
 // Value of lane l ^ OFF for a 32-bit word, OFF in {1, 2, 4, 8}: DPP quad

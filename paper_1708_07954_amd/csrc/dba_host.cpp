@@ -627,6 +627,7 @@ int dba_default_options(dba_options *o)
     o->camera_blocks = 0;
     o->block_points = 0;
     o->camera_model = DBA_CAMERA_ANGLE_AXIS;
+    o->local_solver = DBA_SOLVER_LM;
     return DBA_OK;
 }
 
@@ -654,6 +655,9 @@ int dba_create(const dba_options *opt, dba_handle **out)
         return DBA_E_INVALID_ARG;
     if (o.camera_model != DBA_CAMERA_ANGLE_AXIS && o.camera_model != DBA_CAMERA_EULER) return DBA_E_INVALID_ARG;
     if (o.camera_model == DBA_CAMERA_EULER && o.start == DBA_START_LEARNED) return DBA_E_INVALID_ARG;
+    if (o.local_solver != DBA_SOLVER_LM && o.local_solver != DBA_SOLVER_GAUSS_NEWTON) return DBA_E_INVALID_ARG;
+    if (o.local_solver == DBA_SOLVER_GAUSS_NEWTON && (o.camera_blocks || o.start == DBA_START_LEARNED))
+        return DBA_E_INVALID_ARG;
     dba_handle *h = new dba_handle();
     h->opt = o;
     h->fp32 = o.precision == DBA_PREC_FP32_LOCAL;
@@ -663,6 +667,7 @@ int dba_create(const dba_options *opt, dba_handle **out)
     h->sp.lambda0 = o.lm_lambda0;
     h->sp.learned_steps = o.learned_lm_steps;
     h->sp.camera = o.camera_model;
+    h->sp.solver = o.local_solver;
     h->start = o.start;
     if (hipSetDevice(o.device) != hipSuccess) {
         delete h;

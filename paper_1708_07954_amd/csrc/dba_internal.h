@@ -114,6 +114,7 @@ struct SolverParams {
     double lambda0;
     int learned_steps;   // LM steps after the learned start
     int camera;          // 0: angle-axis camera (9 parameters), 1: Euler camera (Eq. 1)
+    int solver;          // 0: robust LM, 1: Gauss-Newton (per-observation local solves)
 };
 
 // ---- learned warm start: 26 -> 128 -> GELU -> 128 -> GELU -> 12 network

@@ -56,6 +56,20 @@ Readings where the paper is silent or loose (the same on the GPU path):
   R11 ``solver="gauss_newton"`` (the paper's local solver for the l2 misfit,
      Sec. 3.1): the steps of R4 without damping, A = 2 w J^T J + P, and every
      step whose trial is finite is taken (no decrease test).
+  R12 ``solver="lbfgs"`` (the paper's local solver for the Huber misfit,
+     Sec. 3.1; the method as in Nocedal & Wright, Alg. 7.4 and 7.5, which
+     the paper cites): S iterations (``lm_steps``) of d = -H g with the
+     initial matrix H0_k = diag(P + 2 w J^T J)^-1 at the current iterate (the
+     inverse diagonal of the Gauss-Newton matrix, recomputed every iteration;
+     P^-1 alone stalls the line search when rho is far below the misfit's
+     curvature) and at most 4 curvature pairs, oldest dropped first; an
+     accepted step's pair (s = alpha
+     d, y = g_new - g_old) is kept only if s.y > 1e-8 s^T P s (H stays
+     positive definite); backtracking line search alpha = 1, 1/2, ..., 2^-9
+     with the Armijo test F' <= F + 1e-4 alpha g.d, or a predicted decrease
+     -alpha g.d below R4's tie threshold (F cannot judge it); a trial with
+     depth <= 1e-6 fails the test; an iteration with no trial taken ends the
+     solve.  The paper gives none of these constants.
 """
 from __future__ import annotations
 
@@ -72,7 +86,7 @@ _LIB = os.path.join(_HERE, "liboracle.so")
 
 LOSS = {"l2": 0, "huber": 1, "student_t": 2}
 CAMERA = {"angle_axis": 0, "euler": 1}
-SOLVER = {"lm": 0, "gauss_newton": 1}
+SOLVER = {"lm": 0, "gauss_newton": 1, "lbfgs": 2}
 
 
 def build(force: bool = False) -> str:
@@ -126,6 +140,11 @@ def _declare(L):
     L.orc_local_solve.argtypes = [ctypes.POINTER(OrcOpts), _dp, _dp, _dp,
                                   ctypes.c_double, ctypes.c_double, ctypes.c_int, _dp]
     L.orc_local_solve.restype = ctypes.c_int
+    L.orc_lbfgs_apply.argtypes = [ctypes.c_int, ctypes.c_int, _dp, _dp, _dp, _dp, _dp]
+    L.orc_lbfgs_apply.restype = None
+    L.orc_local_solve_lbfgs.argtypes = [ctypes.POINTER(OrcOpts), _dp, _dp, _dp, ctypes.c_double,
+                                        ctypes.c_double, ctypes.c_int, _dp, _dp]
+    L.orc_local_solve_lbfgs.restype = ctypes.c_int
     L.orc_admm_iterate.argtypes = [ctypes.c_int64, ctypes.c_int32, ctypes.c_int32,
                                    _ip, _ip, _dp, _dp, _dp, _dp, _dp, _dp,
                                    ctypes.POINTER(OrcOpts), ctypes.c_int32, _dp]
@@ -236,6 +255,28 @@ def local_solve(opts, z, v, theta, rho_x, rho_y, steps=None):
     acc = lib().orc_local_solve(ctypes.byref(opts), _d(_f64(z)), _d(_f64(v)), _d(th),
                                 float(rho_x), float(rho_y), steps, _d(tr))
     return th, acc, tr
+
+
+def lbfgs_apply(S, Y, h0, g):
+    """H g for the L-BFGS matrix built from diag(h0) by the pairs (rows of S,
+    Y, oldest first), by the two-loop recursion."""
+    S = np.ascontiguousarray(S, np.float64).reshape(-1, len(h0))
+    Y = np.ascontiguousarray(Y, np.float64).reshape(S.shape)
+    d = np.zeros(len(h0))
+    lib().orc_lbfgs_apply(len(h0), S.shape[0], _d(S), _d(Y), _d(_f64(h0)), _d(_f64(g)), _d(d))
+    return d
+
+
+def local_solve_lbfgs(opts, z, v, theta, rho_x, rho_y, steps=None):
+    """L-BFGS local solve (R12).  Returns (theta_out, n_taken, F trace of
+    length steps+1, step lengths alpha of length steps, 0 after the end)."""
+    steps = opts.lm_steps if steps is None else int(steps)
+    th = _f64(theta).copy()
+    tr = np.zeros(steps + 1)
+    al = np.zeros(steps)
+    n = lib().orc_local_solve_lbfgs(ctypes.byref(opts), _d(_f64(z)), _d(_f64(v)), _d(th),
+                                    float(rho_x), float(rho_y), steps, _d(tr), _d(al))
+    return th, n, tr, al
 
 
 # ---------------------------------------------------------------- whole ADMM

@@ -25,6 +25,10 @@
 #define ORC_LAMBDA_MIN 1e-12
 #define ORC_LAMBDA_MAX 1e12
 #define ORC_TIE 1e-13         /* predicted decrease (relative to F's resolution) F cannot judge */
+#define ORC_LBFGS_MEM 4       /* L-BFGS: curvature pairs kept */
+#define ORC_LS_TRIALS 10      /* L-BFGS: backtracking trials per iteration, alpha = 1, 1/2, .., 2^-9 */
+#define ORC_ARMIJO 1e-4       /* L-BFGS: sufficient-decrease constant c1 */
+#define ORC_CURV 1e-8         /* L-BFGS: a pair is kept only if s.y > 1e-8 s^T P s */
 
 enum { ORC_L2 = 0, ORC_HUBER = 1, ORC_STUDENT_T = 2 };
 
@@ -362,7 +366,8 @@ typedef struct {
     int32_t rho_balancing;
     double rb_mu, rb_tau, rho_min, rho_max;
     int32_t camera;  /* 0: angle-axis camera (9 unknowns), 1: Euler camera (6) */
-    int32_t solver;  /* 0: robust LM (reading 4), 1: Gauss-Newton (no damping, every finite step taken) */
+    int32_t solver;  /* 0: robust LM (reading 4), 1: Gauss-Newton (no damping, every finite step taken),
+                        2: L-BFGS (orc_local_solve_lbfgs) */
 } orc_opts;
 
 double orc_local_objective(const orc_opts *o, const double z[2], const double v[12],
@@ -381,6 +386,133 @@ double orc_local_objective(const orc_opts *o, const double z[2], const double v[
     return ls[0] + 0.5 * pen;
 }
 
+/* ------------------------------------------------------------------------ */
+/* L-BFGS two-loop recursion (Nocedal & Wright, Numerical Optimization,       */
+/* Alg. 7.4): d = H g, where H is the inverse-Hessian approximation obtained  */
+/* from diag(h0) by the BFGS updates with the pairs (s_k, y_k) = (S + n k,    */
+/* Y + n k), k = 0 (oldest) .. np - 1 (newest).  n <= 64, np <= 64.           */
+/* ------------------------------------------------------------------------ */
+void orc_lbfgs_apply(int n, int np, const double *S, const double *Y, const double *h0,
+                     const double *g, double *d)
+{
+    double q[64], a[64], rk[64];
+    for (int r = 0; r < n; ++r) q[r] = g[r];
+    for (int k = np - 1; k >= 0; --k) {
+        double sy = 0.0, sq = 0.0;
+        for (int r = 0; r < n; ++r) {
+            sy += S[n * k + r] * Y[n * k + r];
+            sq += S[n * k + r] * q[r];
+        }
+        rk[k] = 1.0 / sy;
+        a[k] = rk[k] * sq;
+        for (int r = 0; r < n; ++r) q[r] -= a[k] * Y[n * k + r];
+    }
+    for (int r = 0; r < n; ++r) d[r] = h0[r] * q[r];
+    for (int k = 0; k < np; ++k) {
+        double yd = 0.0;
+        for (int r = 0; r < n; ++r) yd += Y[n * k + r] * d[r];
+        const double b = rk[k] * yd;
+        for (int r = 0; r < n; ++r) d[r] += S[n * k + r] * (a[k] - b);
+    }
+}
+
+/* Gradient of F at theta, the inverse diagonal of the Gauss-Newton matrix
+ * P + 2 w J^T J there, and |e| (for F's resolution). */
+static void local_gradient(const orc_opts *o, const double z[2], const double v[12], const double theta[12],
+                           double rho_x, double rho_y, double g[12], double h0[12], double *enorm)
+{
+    double uv[2], J[24], ls[2];
+    orc_project_jac_cam(o->camera, theta, theta + 9, uv, J);
+    double e0 = z[0] - uv[0], e1 = z[1] - uv[1];
+    orc_loss(o->loss, o->loss_param, e0 * e0 + e1 * e1, ls);
+    for (int r = 0; r < 12; ++r) {
+        const double pr = r < 9 ? rho_y : rho_x;
+        g[r] = -2.0 * ls[1] * (J[r] * e0 + J[12 + r] * e1) + pr * (theta[r] - v[r]);
+        h0[r] = 1.0 / (pr + 2.0 * ls[1] * (J[r] * J[r] + J[12 + r] * J[12 + r]));
+    }
+    *enorm = sqrt(e0 * e0 + e1 * e1);
+}
+
+/* ------------------------------------------------------------------------ */
+/* Local update (Eq. 9) by L-BFGS (the paper's solver for the Huber misfit,  */
+/* Sec. 3.1; Nocedal & Wright Alg. 7.5), reading 12 of oracle/__init__.py:   */
+/*   H0 = diag(P + 2 w J^T J)^-1 at the current iterate (the inverse of the  */
+/*   Gauss-Newton matrix's diagonal), recomputed every iteration;            */
+/*   at most ORC_LBFGS_MEM pairs, the oldest dropped first; the pair of an   */
+/*   accepted step, s = alpha d and y = g_new - g_old, is kept only if       */
+/*   s.y > ORC_CURV s^T P s (so H stays positive definite);                  */
+/*   `steps` iterations, each: d = -H g; backtracking from alpha = 1,        */
+/*   halving, at most ORC_LS_TRIALS trials; a trial is taken if F is finite  */
+/*   there and F' <= F + c1 alpha g.d (Armijo), or if the predicted          */
+/*   decrease -alpha g.d is below 1e-13 of F's resolution (as in the LM);    */
+/*   an iteration with no trial taken ends the solve.                        */
+/* f_trace (optional, steps + 1): F after each iteration; alpha_trace        */
+/* (optional, steps): the step taken, 0 once the solve has ended.  Returns   */
+/* the number of steps taken.                                                */
+/* ------------------------------------------------------------------------ */
+int orc_local_solve_lbfgs(const orc_opts *o, const double z[2], const double v[12], double theta[12],
+                          double rho_x, double rho_y, int steps, double *f_trace, double *alpha_trace)
+{
+    double h0[12], S[ORC_LBFGS_MEM * 12], Y[ORC_LBFGS_MEM * 12];
+    double g[12], g_old[12], s_last[12], d[12], trial[12];
+    int np = 0, have_step = 0, taken = 0, it = 0;
+    double F = orc_local_objective(o, z, v, theta, rho_x, rho_y);
+    if (f_trace) f_trace[0] = F;
+    for (; it < steps; ++it) {
+        double en;
+        local_gradient(o, z, v, theta, rho_x, rho_y, g, h0, &en);
+        const double fres = F + en * (fabs(z[0]) + fabs(z[1]) + fabs(theta[6]));
+        if (have_step) {
+            double y[12], sy = 0.0, sps = 0.0;
+            for (int r = 0; r < 12; ++r) {
+                y[r] = g[r] - g_old[r];
+                sy += s_last[r] * y[r];
+                sps += (r < 9 ? rho_y : rho_x) * s_last[r] * s_last[r];
+            }
+            if (sy > ORC_CURV * sps) {
+                if (np == ORC_LBFGS_MEM) {
+                    memmove(S, S + 12, sizeof(double) * 12 * (ORC_LBFGS_MEM - 1));
+                    memmove(Y, Y + 12, sizeof(double) * 12 * (ORC_LBFGS_MEM - 1));
+                    --np;
+                }
+                memcpy(S + 12 * np, s_last, sizeof(s_last));
+                memcpy(Y + 12 * np, y, sizeof(y));
+                ++np;
+            }
+        }
+        orc_lbfgs_apply(12, np, S, Y, h0, g, d);
+        double gd = 0.0;
+        for (int r = 0; r < 12; ++r) {
+            d[r] = -d[r];
+            gd += g[r] * d[r];
+        }
+        double alpha = 1.0, Fn = INFINITY;
+        int found = 0;
+        for (int t = 0; t < ORC_LS_TRIALS && !found; ++t) {
+            if (t > 0) alpha *= 0.5;
+            for (int r = 0; r < 12; ++r) trial[r] = theta[r] + alpha * d[r];
+            Fn = orc_local_objective(o, z, v, trial, rho_x, rho_y);
+            found = isfinite(Fn) && (Fn <= F + ORC_ARMIJO * alpha * gd || -alpha * gd <= ORC_TIE * fres);
+        }
+        if (!found) break;
+        for (int r = 0; r < 12; ++r) {
+            s_last[r] = alpha * d[r];
+            g_old[r] = g[r];
+        }
+        memcpy(theta, trial, sizeof(trial));
+        F = Fn;
+        have_step = 1;
+        ++taken;
+        if (f_trace) f_trace[it + 1] = F;
+        if (alpha_trace) alpha_trace[it] = alpha;
+    }
+    for (; it < steps; ++it) {
+        if (f_trace) f_trace[it + 1] = F;
+        if (alpha_trace) alpha_trace[it] = 0.0;
+    }
+    return taken;
+}
+
 /* theta: in = start point, out = result.  f_trace (optional, steps+1
  * entries): F after each step (entry 0 = at the start).  Returns the number
  * of accepted steps. */
@@ -388,6 +520,7 @@ int orc_local_solve(const orc_opts *o, const double z[2], const double v[12],
                     double theta[12], double rho_x, double rho_y, int steps,
                     double *f_trace)
 {
+    if (o->solver == 2) return orc_local_solve_lbfgs(o, z, v, theta, rho_x, rho_y, steps, f_trace, NULL);
     double lambda = o->lambda0;
     double F = orc_local_objective(o, z, v, theta, rho_x, rho_y);
     if (f_trace) f_trace[0] = F;

@@ -63,13 +63,16 @@ Readings where the paper is silent or loose (the same on the GPU path):
      inverse diagonal of the Gauss-Newton matrix, recomputed every iteration;
      P^-1 alone stalls the line search when rho is far below the misfit's
      curvature) and at most 4 curvature pairs, oldest dropped first; an
-     accepted step's pair (s = alpha
-     d, y = g_new - g_old) is kept only if s.y > 1e-8 s^T P s (H stays
-     positive definite); backtracking line search alpha = 1, 1/2, ..., 2^-9
-     with the Armijo test F' <= F + 1e-4 alpha g.d, or a predicted decrease
-     -alpha g.d below R4's tie threshold (F cannot judge it); a trial with
-     depth <= 1e-6 fails the test; an iteration with no trial taken ends the
-     solve.  The paper gives none of these constants.
+     accepted step's pair is s = alpha d, y = g_new - g_old formed as P s +
+     (misfit gradient difference), kept only if s.y > 1e-8 s^T P s (H stays
+     positive definite); the solve ends when -g.d is at most R4's tie
+     threshold (converged as far as F can tell); backtracking line search
+     alpha = 1, 1/2, ..., 2^-9 with the Armijo test F' <= F + 1e-4 alpha g.d,
+     or with both terms of the Gauss-Newton model along the step (-alpha g.d
+     and alpha^2/2 d^T (P + 2w J^T J) d) at most the tie threshold (F cannot
+     judge it); a trial with depth <= 1e-6 fails the test; an iteration with
+     no trial taken ends the solve.  The paper gives none of these
+     constants.
 """
 from __future__ import annotations
 

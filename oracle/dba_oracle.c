@@ -416,20 +416,21 @@ void orc_lbfgs_apply(int n, int np, const double *S, const double *Y, const doub
     }
 }
 
-/* Gradient of F at theta, the inverse diagonal of the Gauss-Newton matrix
- * P + 2 w J^T J there, and |e| (for F's resolution). */
-static void local_gradient(const orc_opts *o, const double z[2], const double v[12], const double theta[12],
-                           double rho_x, double rho_y, double g[12], double h0[12], double *enorm)
+/* At theta: the misfit's gradient gm = -2 w J^T e (F's gradient is gm +
+ * P (theta - v)), the Jacobian J, w = phi'(s), the inverse diagonal of the
+ * Gauss-Newton matrix P + 2 w J^T J, and |e| (for F's resolution). */
+static void local_gradient(const orc_opts *o, const double z[2], const double theta[12], double rho_x,
+                           double rho_y, double gm[12], double J[24], double *w, double h0[12], double *enorm)
 {
-    double uv[2], J[24], ls[2];
+    double uv[2], ls[2];
     orc_project_jac_cam(o->camera, theta, theta + 9, uv, J);
     double e0 = z[0] - uv[0], e1 = z[1] - uv[1];
     orc_loss(o->loss, o->loss_param, e0 * e0 + e1 * e1, ls);
     for (int r = 0; r < 12; ++r) {
-        const double pr = r < 9 ? rho_y : rho_x;
-        g[r] = -2.0 * ls[1] * (J[r] * e0 + J[12 + r] * e1) + pr * (theta[r] - v[r]);
-        h0[r] = 1.0 / (pr + 2.0 * ls[1] * (J[r] * J[r] + J[12 + r] * J[12 + r]));
+        gm[r] = -2.0 * ls[1] * (J[r] * e0 + J[12 + r] * e1);
+        h0[r] = 1.0 / ((r < 9 ? rho_y : rho_x) + 2.0 * ls[1] * (J[r] * J[r] + J[12 + r] * J[12 + r]));
     }
+    *w = ls[1];
     *enorm = sqrt(e0 * e0 + e1 * e1);
 }
 
@@ -439,13 +440,17 @@ static void local_gradient(const orc_opts *o, const double z[2], const double v[
 /*   H0 = diag(P + 2 w J^T J)^-1 at the current iterate (the inverse of the  */
 /*   Gauss-Newton matrix's diagonal), recomputed every iteration;            */
 /*   at most ORC_LBFGS_MEM pairs, the oldest dropped first; the pair of an   */
-/*   accepted step, s = alpha d and y = g_new - g_old, is kept only if       */
+/*   accepted step is s = alpha d and y = g_new - g_old, formed as           */
+/*   P s + (gm_new - gm_old) (the penalty's part exactly), and kept only if  */
 /*   s.y > ORC_CURV s^T P s (so H stays positive definite);                  */
-/*   `steps` iterations, each: d = -H g; backtracking from alpha = 1,        */
-/*   halving, at most ORC_LS_TRIALS trials; a trial is taken if F is finite  */
-/*   there and F' <= F + c1 alpha g.d (Armijo), or if the predicted          */
-/*   decrease -alpha g.d is below 1e-13 of F's resolution (as in the LM);    */
-/*   an iteration with no trial taken ends the solve.                        */
+/*   `steps` iterations, each: d = -H g, the solve ending if the predicted   */
+/*   decrease -g.d is at most 1e-13 of F's resolution (converged as far as   */
+/*   F can tell); backtracking from alpha = 1, halving, at most              */
+/*   ORC_LS_TRIALS trials; a trial is taken if F is finite there and         */
+/*   F' <= F + c1 alpha g.d (Armijo), or if both terms of the Gauss-Newton   */
+/*   model of F along the step, -alpha g.d and alpha^2/2 d^T (P + 2w J^T J) d,*/
+/*   are at most 1e-13 of F's resolution (too small for F to judge); an      */
+/*   iteration with no trial taken ends the solve.                           */
 /* f_trace (optional, steps + 1): F after each iteration; alpha_trace        */
 /* (optional, steps): the step taken, 0 once the solve has ended.  Returns   */
 /* the number of steps taken.                                                */
@@ -454,20 +459,22 @@ int orc_local_solve_lbfgs(const orc_opts *o, const double z[2], const double v[1
                           double rho_x, double rho_y, int steps, double *f_trace, double *alpha_trace)
 {
     double h0[12], S[ORC_LBFGS_MEM * 12], Y[ORC_LBFGS_MEM * 12];
-    double g[12], g_old[12], s_last[12], d[12], trial[12];
+    double g[12], gm[12], gm_old[12], s_last[12], d[12], trial[12], J[24];
     int np = 0, have_step = 0, taken = 0, it = 0;
     double F = orc_local_objective(o, z, v, theta, rho_x, rho_y);
     if (f_trace) f_trace[0] = F;
     for (; it < steps; ++it) {
-        double en;
-        local_gradient(o, z, v, theta, rho_x, rho_y, g, h0, &en);
+        double en, w;
+        local_gradient(o, z, theta, rho_x, rho_y, gm, J, &w, h0, &en);
+        for (int r = 0; r < 12; ++r) g[r] = gm[r] + (r < 9 ? rho_y : rho_x) * (theta[r] - v[r]);
         const double fres = F + en * (fabs(z[0]) + fabs(z[1]) + fabs(theta[6]));
         if (have_step) {
             double y[12], sy = 0.0, sps = 0.0;
             for (int r = 0; r < 12; ++r) {
-                y[r] = g[r] - g_old[r];
+                const double ps = (r < 9 ? rho_y : rho_x) * s_last[r];
+                y[r] = ps + (gm[r] - gm_old[r]);
                 sy += s_last[r] * y[r];
-                sps += (r < 9 ? rho_y : rho_x) * s_last[r] * s_last[r];
+                sps += ps * s_last[r];
             }
             if (sy > ORC_CURV * sps) {
                 if (np == ORC_LBFGS_MEM) {
@@ -481,23 +488,29 @@ int orc_local_solve_lbfgs(const orc_opts *o, const double z[2], const double v[1
             }
         }
         orc_lbfgs_apply(12, np, S, Y, h0, g, d);
-        double gd = 0.0;
+        double gd = 0.0, dpd = 0.0, jd0 = 0.0, jd1 = 0.0;
         for (int r = 0; r < 12; ++r) {
             d[r] = -d[r];
             gd += g[r] * d[r];
+            dpd += (r < 9 ? rho_y : rho_x) * d[r] * d[r];
+            jd0 += J[r] * d[r];
+            jd1 += J[12 + r] * d[r];
         }
+        if (-gd <= ORC_TIE * fres) break;
+        const double dhd = dpd + 2.0 * w * (jd0 * jd0 + jd1 * jd1);
         double alpha = 1.0, Fn = INFINITY;
         int found = 0;
         for (int t = 0; t < ORC_LS_TRIALS && !found; ++t) {
             if (t > 0) alpha *= 0.5;
             for (int r = 0; r < 12; ++r) trial[r] = theta[r] + alpha * d[r];
             Fn = orc_local_objective(o, z, v, trial, rho_x, rho_y);
-            found = isfinite(Fn) && (Fn <= F + ORC_ARMIJO * alpha * gd || -alpha * gd <= ORC_TIE * fres);
+            const int small = -alpha * gd <= ORC_TIE * fres && 0.5 * alpha * alpha * dhd <= ORC_TIE * fres;
+            found = isfinite(Fn) && (Fn <= F + ORC_ARMIJO * alpha * gd || small);
         }
         if (!found) break;
         for (int r = 0; r < 12; ++r) {
             s_last[r] = alpha * d[r];
-            g_old[r] = g[r];
+            gm_old[r] = gm[r];
         }
         memcpy(theta, trial, sizeof(trial));
         F = Fn;

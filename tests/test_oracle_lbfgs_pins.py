@@ -6,7 +6,8 @@ H+ = (I - r s y^T) H (I - r y s^T) + r s s^T (r = 1 / s.y) and the secant
 condition.  Seven iterations are checked against a line search written here:
 the gradient and the Gauss-Newton diagonal (the initial matrix) by central
 differences, the memory of 4 pairs and the curvature rule, the direction from
-the dense update, and the largest power of 1/2 that passes the Armijo test.  Further checks: a stationary start stays put,
+the dense update, and the largest power of 1/2 that passes the Armijo test.  Further checks: a stationary start stays put and
+a converged solve stops,
 steps are powers of 1/2 and F never rises,
 the iterates reach the minimiser found by scipy's BFGS, the Euler camera's
 fixed slots stay put, and ADMM with these local solves reaches the centralised
@@ -144,15 +145,26 @@ def test_iterations_by_hand(loss, lp, camera, rho, seed):
 
 
 def test_stationary_start_stays_put():
-    # the observation sits on the projection and the start is v: g = 0, d = 0,
-    # and every iteration takes the zero step (too small for F to judge)
+    # the observation sits on the projection and the start is v: g = 0, so the
+    # solve has converged before its first step
     cam = np.array([0.2, -0.1, 0.3, 0.1, -0.2, 6.0, 800.0, 1e-3, -2e-3])
     X = np.array([0.3, -0.2, 0.4])
     th = np.concatenate([cam, X])
     z = oracle.project(cam, X)[0]
     opts = oracle.make_opts("huber", 2.0, solver="lbfgs")
     t1, n, tr, al = oracle.local_solve_lbfgs(opts, z, th, th, 1e3, 1e3, steps=4)
-    assert n == 4 and np.all(al == 1.0) and np.array_equal(t1, th) and np.all(tr == 0.0)
+    assert n == 0 and np.all(al == 0.0) and np.array_equal(t1, th) and np.all(tr == 0.0)
+
+
+def test_stops_once_converged():
+    # many iterations: the solve ends once the predicted decrease is below F's
+    # resolution, and further iterations change nothing
+    z, v, th = _case(5, "angle_axis")
+    opts = oracle.make_opts("l2", 1.0, solver="lbfgs")
+    t, n, tr, al = oracle.local_solve_lbfgs(opts, z, v, th, 1e5, 1e5, steps=64)
+    assert 0 < n < 64 and np.all(al[n:] == 0.0) and np.all(al[:n] > 0)
+    t2, n2, _, _ = oracle.local_solve_lbfgs(opts, z, v, th, 1e5, 1e5, steps=n + 10)
+    assert n2 == n and np.array_equal(t2, t)
 
 
 @pytest.mark.parametrize("seed", range(6))

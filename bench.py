@@ -188,9 +188,10 @@ def _time_to_target(binding, scene, kw, goal, max_iters, net=None):
 
 
 def time_to_rmse(binding, scene, opts, sched, target, max_iters=400, learned_steps=(1, 2, 3, 4, 5)):
-    """Wall time of plain 5-step LM, of block local updates (one camera copy
-    per 64 observations, Sec. 3.1.4) and of the learned start (+ k LM steps)
-    to reach the oracle's final inlier RMSE (within 0.5 %)."""
+    """Wall time of plain 5-step LM, of the paper's L-BFGS local solver for
+    the Huber misfit (5 and 10 iterations), of block local updates (one camera
+    copy per 64 observations, Sec. 3.1.4) and of the learned start (+ k LM
+    steps) to reach the oracle's final inlier RMSE (within 0.5 %)."""
     from paper_1708_07954_amd import warmstart
     goal = target * 1.005
 
@@ -200,6 +201,11 @@ def time_to_rmse(binding, scene, opts, sched, target, max_iters=400, learned_ste
     res = {"target_inlier_rmse": target, "reached_when_within": 0.005, "max_iterations": max_iters}
     res["plain_lm5"] = run(dict(opts, lm_steps=5, block_waves=sched["block_waves"], persistent=sched["persistent"]))
     print(f"[bench] time-to-RMSE plain: {res['plain_lm5']}", file=sys.stderr, flush=True)
+    if opts.get("loss") == "huber":
+        for k in (5, 10):
+            res[f"lbfgs{k}"] = run(dict(opts, solver="lbfgs", lm_steps=k, block_waves=sched["block_waves"],
+                                        persistent=sched["persistent"]))
+            print(f"[bench] time-to-RMSE L-BFGS, {k} iterations: {res[f'lbfgs{k}']}", file=sys.stderr, flush=True)
     for k in (1, 2, 5):
         res[f"blocks_lm{k}"] = run(dict(opts, lm_steps=k, camera_blocks=True, block_waves=sched["block_waves"],
                                         persistent=sched["persistent"]))

@@ -72,9 +72,16 @@ typedef enum {
 
 typedef enum {
     DBA_SOLVER_LM = 0,           /* robust Levenberg-Marquardt (lm_steps, lm_lambda0) */
-    DBA_SOLVER_GAUSS_NEWTON = 1  /* the paper's solver for the l2 misfit (Sec. 3.1): the same steps
+    DBA_SOLVER_GAUSS_NEWTON = 1, /* the paper's solver for the l2 misfit (Sec. 3.1): the same steps
                                     without damping, every step with a finite trial taken;
                                     per-observation local solves, plain start only */
+    DBA_SOLVER_LBFGS = 2         /* the paper's solver for the Huber misfit (Sec. 3.1; Nocedal &
+                                    Wright, Alg. 7.4-7.5): lm_steps iterations, initial matrix
+                                    diag(P + 2 w J^T J)^-1 at the iterate, at most 4 curvature pairs
+                                    (kept if s.y > 1e-8 s^T P s), Armijo backtracking from step 1
+                                    by halves, at most 10 trials; the solve ends when no trial is
+                                    taken or the predicted decrease is below F's rounding
+                                    resolution; per-observation local solves, plain start only */
 } dba_local_solver;
 
 typedef struct dba_options {
@@ -87,7 +94,8 @@ typedef struct dba_options {
     int32_t rho_balancing;    /* 1: residual balancing of rho after every iteration */
     double rb_mu, rb_tau;     /* balancing: act when one residual exceeds mu x the other; scale by tau */
     double rho_min, rho_max;  /* balancing clamps */
-    int32_t lm_steps;         /* LM steps per local solve, counting rejected ones (1..64) */
+    int32_t lm_steps;         /* local-solver steps per local solve (LM: counting rejected ones;
+                                 L-BFGS: iterations) (1..64) */
     double lm_lambda0;        /* initial Marquardt damping of each local solve */
     int32_t start;            /* dba_start */
     int32_t learned_lm_steps; /* LM steps after the learned start (1..64) */

@@ -16,7 +16,7 @@ LIB_PATH = os.path.join(HERE, "libdba.so")
 
 DBA_OK = 0
 CAMERA = {"angle_axis": 0, "euler": 1}
-SOLVER = {"lm": 0, "gauss_newton": 1}
+SOLVER = {"lm": 0, "gauss_newton": 1, "lbfgs": 2}
 STATUS = {0: "DBA_OK", -1: "DBA_E_INVALID_ARG", -2: "DBA_E_INDEX_RANGE", -3: "DBA_E_UNOBSERVED",
           -4: "DBA_E_NONFINITE", -5: "DBA_E_BEHIND_CAMERA", -6: "DBA_E_DEVICE", -7: "DBA_E_STATE"}
 LOSS = {"l2": 0, "huber": 1, "student_t": 2}

@@ -425,13 +425,165 @@ __device__ __forceinline__ void lm_steps(R *th, P &cur, R &F, const R *v, R z0, 
     }
 }
 
-template <typename R, typename Cam, bool GN = false>
+// L-BFGS on the local objective (Nocedal & Wright, Alg. 7.4 and 7.5), the
+// paper's solver for the Huber misfit: `steps` iterations of d = -H g, where H
+// is built from the initial matrix diag(P + 2w J^T J)^-1 at the current iterate
+// by the BFGS updates with at most kLbfgsMem curvature pairs; an accepted step's
+// pair is s = alpha d, y = g_new - g_old formed as P s + (misfit gradient
+// difference), kept only if s.y > 1e-8 s^T P s, the oldest dropped when full.
+// The solve ends once the predicted decrease -g.d is at most 1e-13 of F's
+// resolution (FP64's tie, in both precisions).  Line search: alpha = 1, 1/2,
+// ..., 2^-9; the first trial with finite F' <= F + 1e-4 alpha g.d (Armijo), or
+// with both terms of the Gauss-Newton model along the step, -alpha g.d and
+// alpha^2/2 d^T (P + 2w J^T J) d, at most tie times F's resolution (too small
+// for F to judge, as in the LM), is taken; an iteration with no trial taken
+// ends the solve.
+//
+// The pairs live in registers, newest in slot kLbfgsMem - 1: a new pair
+// shifts the others down one slot, so every index is a compile-time constant.
+constexpr int kLbfgsMem = 4;
+constexpr int kLbfgsTrials = 10;
+
+template <typename R, typename Cam, typename P>
+__device__ __forceinline__ void lbfgs_steps(R *th, P &cur, R &F, const R *v, R z0, R z1, R rx,
+                                            R ry, int kind, R lp, int steps)
+{
+    R S[kLbfgsMem][12], Y[kLbfgsMem][12], rk[kLbfgsMem];
+    R gm_old[12], sl[12];
+    int np = 0;
+    bool have = false;
+    for (int it = 0; it < steps; ++it) {
+        R J0[12], J1[12];
+        proj_jac<R>(cur, th, J0, J1);
+        const R e0 = z0 - cur.pu, e1 = z1 - cur.pv;
+        R w;
+        const R s2 = e0 * e0 + e1 * e1;
+        loss_phi<R>(kind, lp, s2, w);
+        const R c2 = R(2) * w;
+        const R fres = F + Num<R>::sqrt(s2) * (fabs(z0) + fabs(z1) + fabs(th[6]));
+        R gm[12], g[12], h0[12];
+#pragma unroll
+        for (int i = 0; i < 12; ++i) {
+            if (!cam_active<Cam>(i)) continue;
+            const R Pi = i < 9 ? ry : rx;
+            gm[i] = -c2 * (J0[i] * e0 + J1[i] * e1);
+            g[i] = gm[i] + Pi * (th[i] - v[i]);
+            h0[i] = Num<R>::rcp(Pi + c2 * (J0[i] * J0[i] + J1[i] * J1[i]));
+        }
+        if (have) {
+            R y[12], sy = R(0), sps = R(0);
+#pragma unroll
+            for (int i = 0; i < 12; ++i) {
+                if (!cam_active<Cam>(i)) continue;
+                const R ps = (i < 9 ? ry : rx) * sl[i];
+                y[i] = ps + (gm[i] - gm_old[i]);
+                sy += sl[i] * y[i];
+                sps += ps * sl[i];
+            }
+            if (sy > R(1e-8) * sps) {
+#pragma unroll
+                for (int k = 0; k + 1 < kLbfgsMem; ++k) {
+                    rk[k] = rk[k + 1];
+#pragma unroll
+                    for (int i = 0; i < 12; ++i) {
+                        if (!cam_active<Cam>(i)) continue;
+                        S[k][i] = S[k + 1][i];
+                        Y[k][i] = Y[k + 1][i];
+                    }
+                }
+                rk[kLbfgsMem - 1] = Num<R>::rcp(sy);
+#pragma unroll
+                for (int i = 0; i < 12; ++i) {
+                    if (!cam_active<Cam>(i)) continue;
+                    S[kLbfgsMem - 1][i] = sl[i];
+                    Y[kLbfgsMem - 1][i] = y[i];
+                }
+                np = np < kLbfgsMem ? np + 1 : kLbfgsMem;
+            }
+        }
+        // two-loop recursion: d = H g over the valid slots kLbfgsMem - np ..
+        R d[12], al[kLbfgsMem];
+#pragma unroll
+        for (int i = 0; i < 12; ++i)
+            if (cam_active<Cam>(i)) d[i] = g[i];
+#pragma unroll
+        for (int k = kLbfgsMem - 1; k >= 0; --k) {
+            if (k < kLbfgsMem - np) continue;
+            R sq = R(0);
+#pragma unroll
+            for (int i = 0; i < 12; ++i)
+                if (cam_active<Cam>(i)) sq += S[k][i] * d[i];
+            al[k] = rk[k] * sq;
+#pragma unroll
+            for (int i = 0; i < 12; ++i)
+                if (cam_active<Cam>(i)) d[i] -= al[k] * Y[k][i];
+        }
+#pragma unroll
+        for (int i = 0; i < 12; ++i)
+            if (cam_active<Cam>(i)) d[i] *= h0[i];
+#pragma unroll
+        for (int k = 0; k < kLbfgsMem; ++k) {
+            if (k < kLbfgsMem - np) continue;
+            R yd = R(0);
+#pragma unroll
+            for (int i = 0; i < 12; ++i)
+                if (cam_active<Cam>(i)) yd += Y[k][i] * d[i];
+            const R b = al[k] - rk[k] * yd;
+#pragma unroll
+            for (int i = 0; i < 12; ++i)
+                if (cam_active<Cam>(i)) d[i] += S[k][i] * b;
+        }
+        R gd = R(0), dpd = R(0), jd0 = R(0), jd1 = R(0);
+#pragma unroll
+        for (int i = 0; i < 12; ++i) {
+            if (!cam_active<Cam>(i)) continue;
+            d[i] = -d[i];
+            gd += g[i] * d[i];
+            dpd += (i < 9 ? ry : rx) * d[i] * d[i];
+            jd0 += J0[i] * d[i];
+            jd1 += J1[i] * d[i];
+        }
+        if (-gd <= R(1e-13) * fres) break;
+        const R dhd = dpd + c2 * (jd0 * jd0 + jd1 * jd1);
+        const R tres = Num<R>::tie * fres;
+        // backtracking line search
+        R alpha = R(1), tr[12], Fn = Num<R>::inf;
+        P nxt = cur;
+        bool found = false;
+        for (int t = 0; t < kLbfgsTrials && !found; ++t) {
+            if (t > 0) alpha *= R(0.5);
+#pragma unroll
+            for (int i = 0; i < 12; ++i) tr[i] = cam_active<Cam>(i) ? th[i] + alpha * d[i] : th[i];
+            nxt = proj_core<R, true>(tr, Cam{});
+            Fn = objective<R, Cam>(nxt, tr, v, z0, z1, rx, ry, kind, lp);
+            const bool small = -alpha * gd <= tres && R(0.5) * alpha * alpha * dhd <= tres;
+            found = Fn < Num<R>::inf && (Fn <= F + R(1e-4) * alpha * gd || small);
+        }
+        if (!found) break;
+#pragma unroll
+        for (int i = 0; i < 12; ++i) {
+            if (!cam_active<Cam>(i)) continue;
+            sl[i] = alpha * d[i];
+            gm_old[i] = gm[i];
+            th[i] = tr[i];
+        }
+        cur = nxt;
+        F = Fn;
+        have = true;
+    }
+}
+
+// Local solve from th: SOLVER 0 robust LM, 1 Gauss-Newton, 2 L-BFGS.
+template <typename R, typename Cam, int SOLVER = 0>
 __device__ __forceinline__ void local_lm(R *th, const R *v, R z0, R z1, R rx, R ry, int kind,
                                          R lp, int steps, R lam)
 {
     auto cur = proj_core<R, true>(th, Cam{});
     R F = objective<R, Cam>(cur, th, v, z0, z1, rx, ry, kind, lp);
-    lm_steps<R, Cam, GN>(th, cur, F, v, z0, z1, rx, ry, kind, lp, steps, lam);
+    if constexpr (SOLVER == 2)
+        lbfgs_steps<R, Cam>(th, cur, F, v, z0, z1, rx, ry, kind, lp, steps);
+    else
+        lm_steps<R, Cam, SOLVER == 1>(th, cur, F, v, z0, z1, rx, ry, kind, lp, steps, lam);
 }
 
 // Value of lane l ^ OFF for a 32-bit word, OFF in {1, 2, 4, 8}: DPP quad

@@ -655,8 +655,10 @@ int dba_create(const dba_options *opt, dba_handle **out)
         return DBA_E_INVALID_ARG;
     if (o.camera_model != DBA_CAMERA_ANGLE_AXIS && o.camera_model != DBA_CAMERA_EULER) return DBA_E_INVALID_ARG;
     if (o.camera_model == DBA_CAMERA_EULER && o.start == DBA_START_LEARNED) return DBA_E_INVALID_ARG;
-    if (o.local_solver != DBA_SOLVER_LM && o.local_solver != DBA_SOLVER_GAUSS_NEWTON) return DBA_E_INVALID_ARG;
-    if (o.local_solver == DBA_SOLVER_GAUSS_NEWTON && (o.camera_blocks || o.start == DBA_START_LEARNED))
+    if (o.local_solver != DBA_SOLVER_LM && o.local_solver != DBA_SOLVER_GAUSS_NEWTON &&
+        o.local_solver != DBA_SOLVER_LBFGS)
+        return DBA_E_INVALID_ARG;
+    if (o.local_solver != DBA_SOLVER_LM && (o.camera_blocks || o.start == DBA_START_LEARNED))
         return DBA_E_INVALID_ARG;
     dba_handle *h = new dba_handle();
     h->opt = o;

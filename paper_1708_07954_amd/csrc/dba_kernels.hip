@@ -35,7 +35,7 @@ using namespace dev;
 // copy and copy + network prediction (ties keep the copy), then
 // `learned_steps` LM steps; io/lw are the wave's network I/O tile and the
 // staged weights.
-template <typename R, bool LEARNED, typename Cam = CamAA, bool GN = false>
+template <typename R, bool LEARNED, typename Cam = CamAA, int SOLVER = 0>
 __device__ __forceinline__ void local_chunk(const DevArrays<R> &a, const SolverParams &sp, int c, int lane,
                                             const MlpParams *mp = nullptr, const __bf16 *lw = nullptr,
                                             __bf16 *io = nullptr)
@@ -134,7 +134,7 @@ __device__ __forceinline__ void local_chunk(const DevArrays<R> &a, const SolverP
             lm_steps<R, CamAA>(th, cur, F, v, z.x, z.y, rx, ry, sp.loss, lp, sp.learned_steps, lam0);
         }
     } else {
-        if (active) local_lm<R, Cam, GN>(th, v, z.x, z.y, rx, ry, sp.loss, lp, sp.lm_steps, lam0);
+        if (active) local_lm<R, Cam, SOLVER>(th, v, z.x, z.y, rx, ry, sp.loss, lp, sp.lm_steps, lam0);
     }
     if (active) {
 #pragma unroll
@@ -241,14 +241,14 @@ __device__ __forceinline__ void chunk_range(int n_chunks, int wpb, int persisten
     }
 }
 
-template <typename R, typename Cam, bool GN>
+template <typename R, typename Cam, int SOLVER>
 __global__ __launch_bounds__(LocalBound<R>::threads) void k_local(DevArrays<R> a, SolverParams sp,
                                                                   int persistent)
 {
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, wpb = blockDim.x >> 6;
     int c0, c1;
     chunk_range(a.n_chunks, wpb, persistent, c0, c1);
-    for (int c = c0 + wave; c < c1; c += wpb) local_chunk<R, false, Cam, GN>(a, sp, c, lane);
+    for (int c = c0 + wave; c < c1; c += wpb) local_chunk<R, false, Cam, SOLVER>(a, sp, c, lane);
 }
 
 template <typename R, typename Cam>
@@ -572,14 +572,22 @@ hipError_t launch_local(const DevArrays<R> &a, const SolverParams &sp, int block
     }
     if (grid < 1) grid = 1;
     const dim3 g(grid), b(threads);
-    if (sp.camera == 1 && sp.solver == 1)
-        hipLaunchKernelGGL((k_local<R, CamEuler, true>), g, b, 0, s, a, sp, persistent);
-    else if (sp.camera == 1)
-        hipLaunchKernelGGL((k_local<R, CamEuler, false>), g, b, 0, s, a, sp, persistent);
-    else if (sp.solver == 1)
-        hipLaunchKernelGGL((k_local<R, CamAA, true>), g, b, 0, s, a, sp, persistent);
-    else
-        hipLaunchKernelGGL((k_local<R, CamAA, false>), g, b, 0, s, a, sp, persistent);
+    // one instantiation per camera model and local solver
+    if (sp.camera == 1) {
+        if (sp.solver == 2)
+            hipLaunchKernelGGL((k_local<R, CamEuler, 2>), g, b, 0, s, a, sp, persistent);
+        else if (sp.solver == 1)
+            hipLaunchKernelGGL((k_local<R, CamEuler, 1>), g, b, 0, s, a, sp, persistent);
+        else
+            hipLaunchKernelGGL((k_local<R, CamEuler, 0>), g, b, 0, s, a, sp, persistent);
+    } else {
+        if (sp.solver == 2)
+            hipLaunchKernelGGL((k_local<R, CamAA, 2>), g, b, 0, s, a, sp, persistent);
+        else if (sp.solver == 1)
+            hipLaunchKernelGGL((k_local<R, CamAA, 1>), g, b, 0, s, a, sp, persistent);
+        else
+            hipLaunchKernelGGL((k_local<R, CamAA, 0>), g, b, 0, s, a, sp, persistent);
+    }
     return hipGetLastError();
 }
 

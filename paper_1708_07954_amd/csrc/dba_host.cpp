@@ -238,22 +238,11 @@ int build_set(dba_handle *h, int np, const dba_problem_desc *probs, ProblemSet *
 
     // device
     Buffers &B = ps->buf;
-    // the consensus kernel's lane order within each point block: longest
-    // track first (ties in point order), so that the waves of a block hold
-    // tracks of similar length and finish together
-    std::vector<int> pt_order(n_pts);
-    for (int b = 0; b < n_pblk; ++b) {
-        const int p0 = pblk_pt0[b], cnt = pblk_cnt[b];
-        for (int t = 0; t < cnt; ++t) pt_order[p0 + t] = p0 + t;
-        std::stable_sort(pt_order.begin() + p0, pt_order.begin() + p0 + cnt, [&](int x, int y) {
-            return pt_off[x + 1] - pt_off[x] > pt_off[y + 1] - pt_off[y];
-        });
-    }
     R2 *d_uv; int *d_pslot, *d_ptid, *d_orig; uint8_t *d_mask; R *d_copy; double *d_dual;
     dba::PtCopy<R> *d_xrec; dba::PtDual *d_urec; int *d_ptoff, *d_chunk_cam, *d_cam_prob, *d_pt_prob, *d_cam_chunk0, *d_cam_count;
     double *d_cons_y; double4 *d_cons_x; Ctrl *d_ctrl; ProblemRange *d_prob;
     double *d_cpart, *d_ppart, *d_campart, *d_epart, *d_estats;
-    int *d_pblk_pt0, *d_pblk_cnt, *d_pt_order;
+    int *d_pblk_pt0, *d_pblk_cnt;
     HIP_TRY(h, B.alloc(&d_uv, S));
     HIP_TRY(h, B.alloc(&d_pslot, S));
     HIP_TRY(h, B.alloc(&d_ptid, S));
@@ -277,10 +266,8 @@ int build_set(dba_handle *h, int np, const dba_problem_desc *probs, ProblemSet *
     HIP_TRY(h, B.alloc(&d_ppart, 2 * (size_t)n_pblk));
     HIP_TRY(h, B.alloc(&d_pblk_pt0, n_pblk));
     HIP_TRY(h, B.alloc(&d_pblk_cnt, n_pblk));
-    HIP_TRY(h, B.alloc(&d_pt_order, n_pts));
     HIP_TRY(h, hipMemcpy(d_pblk_pt0, pblk_pt0.data(), n_pblk * sizeof(int), hipMemcpyHostToDevice));
     HIP_TRY(h, hipMemcpy(d_pblk_cnt, pblk_cnt.data(), n_pblk * sizeof(int), hipMemcpyHostToDevice));
-    HIP_TRY(h, hipMemcpy(d_pt_order, pt_order.data(), n_pts * sizeof(int), hipMemcpyHostToDevice));
     HIP_TRY(h, B.alloc(&d_campart, 2 * (size_t)n_cams));
     HIP_TRY(h, B.alloc(&d_epart, (size_t)n_chunks * dba::kEpart));
     HIP_TRY(h, B.alloc(&d_estats, (size_t)np * dba::kEpart));
@@ -326,7 +313,6 @@ int build_set(dba_handle *h, int np, const dba_problem_desc *probs, ProblemSet *
     A.cam_chunk0 = d_cam_chunk0; A.cam_count = d_cam_count;
     A.cons_y = d_cons_y; A.cons_x = d_cons_x; A.ctrl = d_ctrl; A.prob = d_prob;
     A.n_pblk = n_pblk; A.pblk_pt0 = d_pblk_pt0; A.pblk_cnt = d_pblk_cnt;
-    A.pt_order = d_pt_order;
     A.cpart = d_cpart; A.ppart = d_ppart; A.campart = d_campart; A.epart = d_epart; A.estats = d_estats;
     ps->mask = d_mask;
     return DBA_OK;

@@ -101,7 +101,6 @@ struct DevArrays {
     int n_pblk;
     const int *pblk_pt0;    // [n_pblk] first global point of the block
     const int *pblk_cnt;    // [n_pblk] points in the block (<= kPtBlock)
-    const int *pt_order;    // [n_pts] each block's points in the consensus lane order (longest track first)
     double *ppart;          // [n_pblk][2] block sums of the point residual terms
     double *campart;        // [n_cams][2]
     double *epart;          // [n_chunks][kEpart]

@@ -292,7 +292,7 @@ __global__ __launch_bounds__(256) void k_consensus(DevArrays<R> a, int pt_blocks
         const int b = blockIdx.x;
         double pri = 0.0, dual = 0.0;
         if ((int)threadIdx.x < a.pblk_cnt[b]) {
-            const int i = a.pt_order[a.pblk_pt0[b] + threadIdx.x];
+            const int i = a.pblk_pt0[b] + threadIdx.x;
             const int r0 = a.pt_off[i], r1 = a.pt_off[i + 1];
             // one pass: sums of copy + dual (the consensus) and of the copies'
             // offsets d_r from the previous consensus, which give

@@ -282,8 +282,6 @@ __global__ __launch_bounds__(64 * kLearnedWaves) void k_local_learned(DevArrays<
 }
 
 // ---------------------------------------------------------------- consensus
-constexpr int kConsBatch = 8;
-
 template <typename R>
 __global__ __launch_bounds__(256) void k_consensus(DevArrays<R> a, int pt_blocks)
 {
@@ -310,23 +308,20 @@ __global__ __launch_bounds__(256) void k_consensus(DevArrays<R> a, int pt_blocks
                 q2 += d2;
                 qq += d0 * d0 + d1 * d1 + d2 * d2;
             };
-            // kConsBatch records' loads in flight per round trip (indexes past
-            // the segment's end clamped to its last record and not summed),
-            // summed in record order: a segment of n records costs
-            // ceil(n / kConsBatch) memory round trips
-            for (int r = r0; r < r1; r += kConsBatch) {
-                PtCopy<R> x[kConsBatch];
-                PtDual u[kConsBatch];
+            // four records' loads in flight, summed in record order
+            int r = r0;
+            for (; r + 4 <= r1; r += 4) {
+                PtCopy<R> x[4];
+                PtDual u[4];
 #pragma unroll
-                for (int j = 0; j < kConsBatch; ++j) {
-                    const int q = min(r + j, r1 - 1);
-                    x[j] = a.xrec[q];
-                    u[j] = a.urec[q];
+                for (int j = 0; j < 4; ++j) {
+                    x[j] = a.xrec[r + j];
+                    u[j] = a.urec[r + j];
                 }
 #pragma unroll
-                for (int j = 0; j < kConsBatch; ++j)
-                    if (r + j < r1) add(x[j], u[j]);
+                for (int j = 0; j < 4; ++j) add(x[j], u[j]);
             }
+            for (; r < r1; ++r) add(a.xrec[r], a.urec[r]);
             const double n = (double)(r1 - r0);
             const double c0 = s0 / n, c1 = s1 / n, c2 = s2 / n;
             const double e0 = c0 - old.x, e1 = c1 - old.y, e2 = c2 - old.z;

@@ -54,6 +54,11 @@ WORKLOADS = {
                              desc="the trajectory workload (seed 7) with the paper's camera of Eq. (1): Euler "
                                   "angles and translation, known focal length, no distortion; FP32 local / FP64 "
                                   "consensus"),
+    "trajectory_shard8": dict(scene="config2_shard8", opts=dict(precision="fp32", loss="huber", loss_param=2.0,
+                                                                rho=1e5, rho_balancing=True, rho_min=1e5, rho_max=1e7),
+                              desc="one rank's share of the trajectory workload when 8 GPUs partition the "
+                                   "observations by point: every 8th point's whole track and the cameras that see "
+                                   "them; FP32 local / FP64 consensus"),
     "sphere": dict(scene="config1", opts=dict(precision="fp32", loss="student_t", loss_param=4.0, rho=1e3),
                    desc="100 cameras on a sphere cap, 20000 points, 8..15 cameras per point; Student-t nu 4, "
                         "rho 1e3; FP32 local / FP64 consensus"),
@@ -73,6 +78,9 @@ def make_scenes(kind):
     from scenes import make_config0, make_config1, make_config2, make_config3
     if kind == "config3":
         return make_config3()
+    if kind == "config2_shard8":
+        from scenes import point_shard
+        return [point_shard(make_config2(), 0, 8)]
     if kind == "config2_euler":
         # seed 7: its perturbed Euler start keeps every point in front of its cameras
         return [make_config2(seed=7, camera="euler")]
@@ -89,7 +97,8 @@ def kernel_source_hash():
 
 # committed counter summary of each workload's local-solve kernel
 COUNTER_SUMMARIES = {"trajectory": "local_solve_trajectory_counters.md",
-                     "trajectory_blocks": "block_local_trajectory.md"}
+                     "trajectory_blocks": "block_local_trajectory.md",
+                     "trajectory_euler": "kernels_trajectory_euler_2M.md"}
 
 
 def recorded_traffic(workload):

@@ -16,5 +16,6 @@ from .generate import (  # noqa: F401
     make_sphere_scene,
     make_trajectory_scene,
     make_tiny_paper_scene,
+    point_shard,
     CONFIG_SOLVER,
 )

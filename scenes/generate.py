@@ -301,6 +301,29 @@ def make_config2(seed=2, n_cams=1000, n_points=200000, **kw) -> Scene:
                                  name=f"trajectory{n_cams}x{n_points}", **kw)
 
 
+def point_shard(scene: Scene, rank: int, n_ranks: int) -> Scene:
+    """One rank's share under a partition of the observations by point:
+    the points with index % n_ranks == rank keep their whole tracks, and
+    the cameras that see any of them are kept (renumbered in their order);
+    observations keep their relative order.  meta["cams"] / meta["points"]
+    hold the kept original indices."""
+    keep_pt = np.arange(scene.n_points) % n_ranks == rank
+    obs = np.flatnonzero(keep_pt[scene.obs_point])
+    cams = np.unique(scene.obs_cam[obs])
+    pts = np.flatnonzero(keep_pt)
+    cam_new = np.full(scene.n_cams, -1, np.int64)
+    cam_new[cams] = np.arange(len(cams))
+    pt_new = np.full(scene.n_points, -1, np.int64)
+    pt_new[pts] = np.arange(len(pts))
+    return Scene(name=f"{scene.name}_shard{rank}of{n_ranks}", seed=scene.seed, n_cams=len(cams),
+                 n_points=len(pts), obs_cam=cam_new[scene.obs_cam[obs]].astype(np.int32),
+                 obs_point=pt_new[scene.obs_point[obs]].astype(np.int32),
+                 obs_uv=np.ascontiguousarray(scene.obs_uv[obs]), cams_init=scene.cams_init[cams].copy(),
+                 points_init=scene.points_init[pts].copy(), cams_gt=scene.cams_gt[cams].copy(),
+                 points_gt=scene.points_gt[pts].copy(), outlier=scene.outlier[obs].copy(),
+                 meta=dict(scene.meta, cams=cams, points=pts, rank=rank, n_ranks=n_ranks))
+
+
 def make_config3(seeds=range(1000, 1064), scale=1.0):
     """64 independent sphere-cap problems of uneven size: camera counts
     log-uniform in [5, 300], observation targets log-uniform in [2e3, 3e5].

@@ -138,6 +138,10 @@ def make_options(*, device=0, stream=None, precision="fp64", loss="huber", loss_
                  rho_min=1e-6, rho_max=1e6, lm_steps=5, lm_lambda0=1e-3, start="plain",
                  learned_lm_steps=2, use_graph=True, block_waves=0, persistent=-1,
                  camera_blocks=False, block_points=0, camera="angle_axis", solver="lm") -> dba_options:
+    """dba_options from keywords: enum fields by name (precision "fp64" /
+    "fp32"; loss "l2" / "huber" / "student_t"; start "plain" / "learned";
+    camera "angle_axis" / "euler"; solver "lm" / "gauss_newton" / "lbfgs"),
+    the rest as in dba.h (lm_steps counts L-BFGS iterations for "lbfgs")."""
     o = dba_options()
     _check(None, load().dba_default_options(ctypes.byref(o)))
     o.device = device

@@ -1,0 +1,55 @@
+"""Problems of the sizes of the paper's real-data table (Sec. 5.2, Table 1:
+cameras, points and observations of its four datasets, about 2.6-2.9
+observations per point), as synthetic trajectories with tracks of 2-4
+consecutive frames and no outliers, since the datasets themselves are not
+available: FP64 within 1e-9 and FP32 within 1e-3 (RMSE within 0.5 %) of the
+oracle after 20 iterations, one problem at a time and all four batched."""
+import numpy as np
+import pytest
+
+import oracle
+from paper_1708_07954_amd import binding
+from scenes import make_trajectory_scene
+from _util import param_rel_err
+
+pytestmark = pytest.mark.gpu
+
+SIZES = [(11, 1346), (10, 1382), (25, 2161), (30, 2383)]
+KW = dict(loss="huber", loss_param=2.0, rho=1e3)
+ITERS = 20
+
+
+def _scenes():
+    return [make_trajectory_scene(seed=300 + q, n_cams=m, n_points=n, t_max=4, outlier_frac=0.0,
+                                  name=f"paper_table1_{m}x{n}") for q, (m, n) in enumerate(SIZES)]
+
+
+def _oracle(sc):
+    a = oracle.ADMM(oracle.Problem.from_scene(sc), sc.cams_init, sc.points_init, **KW)
+    a.iterate(ITERS)
+    return a
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+def test_paper_table1_sizes(precision):
+    scenes = _scenes()
+    print("observations per scene", [sc.n_obs for sc in scenes],
+          "per point", [round(sc.n_obs / sc.n_points, 2) for sc in scenes])
+    refs = [_oracle(sc) for sc in scenes]
+    batched = binding.Solver(precision=precision, **KW).set_scenes(scenes)
+    batched.iterate(ITERS)
+    for q, (sc, a) in enumerate(zip(scenes, refs)):
+        s = binding.Solver(precision=precision, **KW).set_scene(sc)
+        s.iterate(ITERS)
+        cams, pts = s.params()
+        err = param_rel_err(cams, pts, a.cons_y, a.cons_x)
+        r = s.residuals(want_rmse=True)
+        print(sc.name, precision, "max rel err", err, "rmse", r["rmse"], a.stats()[0])
+        if precision == "fp64":
+            assert err < 1e-9
+        else:
+            assert err < 1e-3 and abs(r["rmse"] - a.stats()[0]) < 5e-3 * a.stats()[0]
+        b = batched.params(q)
+        assert np.array_equal(b[0], cams) and np.array_equal(b[1], pts)
+        s.close()
+    batched.close()

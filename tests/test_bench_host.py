@@ -1,0 +1,62 @@
+"""Host logic of the benchmark, on the CPU: the one-GPU contract of --gpus,
+the cost model's per-observation figures, the workloads' scene builders, and
+the rule that a recorded HBM traffic figure is reported only while the kernel
+sources still hash to the value it was taken on."""
+import json
+import os
+import subprocess
+import sys
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+sys.path.insert(0, ROOT)
+
+import bench  # noqa: E402
+from paper_1708_07954_amd import cost  # noqa: E402
+
+
+@pytest.mark.parametrize("extra", [["--gpus", "2"], ["--gpus", "8", "--steps", "3"]])
+def test_more_than_one_gpu_exits_with_a_message(extra):
+    r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), *extra], capture_output=True, text=True,
+                       timeout=120, cwd=ROOT)
+    assert r.returncode == 2
+    line = json.loads(r.stdout.strip().splitlines()[-1])
+    assert "one GPU" in line["error"] and line["n_gpus_requested"] == int(extra[1])
+
+
+def test_cost_model_figures():
+    # per observation and iteration: 5 LM steps of the 12-unknown problem, and
+    # of the Euler camera's 9-unknown problem; the bytes the kernels must move
+    assert cost.local_flops_per_obs(5) == 5570
+    assert cost.local_flops_per_obs(5, "euler") == 3756
+    assert cost.local_flops_per_obs(6) - cost.local_flops_per_obs(5) == cost.LM_STEP
+    b32, b64 = cost.bytes_per_obs(True), cost.bytes_per_obs(False)
+    assert (b32["local"], b32["consensus"], b32["minimal"]) == (304, 36, 304)
+    assert b64["minimal"] == 408
+    assert b32["total"] == b32["local"] + b32["consensus"]
+
+
+def test_kernel_source_hash_and_recorded_traffic(monkeypatch):
+    h = bench.kernel_source_hash()
+    assert len(h) == 12 and int(h, 16) >= 0
+    for wl in ("trajectory", "trajectory_blocks", "trajectory_euler"):
+        value, path = bench.recorded_traffic(wl)
+        with open(path) as fh:
+            recorded_hash = [l.split(":")[1].strip() for l in fh if l.startswith("kernel_source_hash:")][0]
+        if recorded_hash == h:
+            assert value is not None and 1e8 < value < 2e9
+        else:
+            assert value is None
+    assert bench.recorded_traffic("batched") == (None, None)
+    # a kernel change voids the recorded figure
+    monkeypatch.setattr(bench, "kernel_source_hash", lambda: "000000000000")
+    assert bench.recorded_traffic("trajectory")[0] is None
+
+
+def test_workload_scenes():
+    assert set(bench.WORKLOADS) >= {"trajectory", "trajectory_blocks", "trajectory_euler", "trajectory_shard8",
+                                    "batched", "sphere"}
+    (shard,) = bench.make_scenes("config2_shard8")
+    assert shard.n_points == 25000 and shard.n_cams == 1000
+    assert shard.meta["n_ranks"] == 8 and shard.meta["rank"] == 0

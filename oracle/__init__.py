@@ -73,6 +73,15 @@ Readings where the paper is silent or loose (the same on the GPU path):
      judge it); a trial with depth <= 1e-6 fails the test; an iteration with
      no trial taken ends the solve.  The paper gives none of these
      constants.
+  R13 blocks of several cameras (``GeneralBlockADMM``, Sec. 3.1.4): cameras
+     in consecutive groups of kappa (frame order on a trajectory); a group's
+     observed points in ascending order, in runs of at most pi points; a
+     block holds one run, the group's observations of it and the group's
+     cameras that make them, with ONE copy of each of its cameras and points;
+     its local problem is solved by R4's LM over all 9 kappa' + 3 pi'
+     unknowns; a camera's (point's) consensus averages its block copies plus
+     their scaled duals.  kappa = 1 gives R9's blocks with one point copy per
+     observation.
 """
 from __future__ import annotations
 
@@ -148,6 +157,12 @@ def _declare(L):
     L.orc_local_solve_lbfgs.argtypes = [ctypes.POINTER(OrcOpts), _dp, _dp, _dp, ctypes.c_double,
                                         ctypes.c_double, ctypes.c_int, _dp, _dp]
     L.orc_local_solve_lbfgs.restype = ctypes.c_int
+    L.orc_gblock_objective.argtypes = [ctypes.POINTER(OrcOpts), ctypes.c_int, ctypes.c_int, ctypes.c_int, _ip, _ip,
+                                       _dp, _dp, _dp, _dp, ctypes.c_double, ctypes.c_double]
+    L.orc_gblock_objective.restype = ctypes.c_double
+    L.orc_gblock_local_solve.argtypes = [ctypes.POINTER(OrcOpts), ctypes.c_int, ctypes.c_int, ctypes.c_int, _ip,
+                                         _ip, _dp, _dp, _dp, _dp, ctypes.c_double, ctypes.c_double, ctypes.c_int]
+    L.orc_gblock_local_solve.restype = ctypes.c_int
     L.orc_admm_iterate.argtypes = [ctypes.c_int64, ctypes.c_int32, ctypes.c_int32,
                                    _ip, _ip, _dp, _dp, _dp, _dp, _dp, _dp,
                                    ctypes.POINTER(OrcOpts), ctypes.c_int32, _dp]
@@ -429,6 +444,89 @@ class BlockADMM:
         for b in range(self.n_blocks):
             blk_of[self.blk_obs[self.blk_off[b]:self.blk_off[b + 1]]] = b
         return np.hstack([self.ycopy[blk_of], self.xcopy]), np.hstack([self.ydual[blk_of], self.xdual])
+
+    def stats(self, mask=None):
+        return reprojection_stats(self.p, self.cons_y, self.cons_x, mask, self.loss, self.loss_param,
+                                  self.camera)
+
+
+def make_general_blocks(obs_cam, obs_point, n_cams, kappa, pi):
+    """Blocks of the generalised local update with kappa cameras (reading
+    R13): cameras in consecutive groups of kappa; a group's observed points,
+    in ascending order, in runs of at most pi; a block holds one run, the
+    group's observations of its points (in observation order) and the group's
+    cameras that make them.  Returns a list of (cams, points, obs) arrays."""
+    obs_cam = np.asarray(obs_cam)
+    obs_point = np.asarray(obs_point)
+    blocks = []
+    for g0 in range(0, n_cams, kappa):
+        sel = np.flatnonzero((obs_cam >= g0) & (obs_cam < g0 + kappa))
+        pts = np.unique(obs_point[sel])
+        for r0 in range(0, len(pts), pi):
+            run = pts[r0:r0 + pi]
+            obs = sel[np.isin(obs_point[sel], run)]
+            blocks.append((np.unique(obs_cam[obs]), run, obs))
+    return blocks
+
+
+class GeneralBlockADMM:
+    """ADMM with general block local updates (Sec. 3.1.4, Eqs. 14-15; reading
+    R13): a block holds one copy of each of its cameras and of each of its
+    points; its local problem (orc_gblock_local_solve) couples them through
+    its observations.  Consensus: a camera's (point's) mean over its block
+    copies of copy + scaled dual, in block order; duals u += copy -
+    consensus.  Fixed rho."""
+
+    def __init__(self, problem: Problem, cams0, points0, *, kappa=2, pi=16, loss="huber", loss_param=2.0, rho=1.0,
+                 lm_steps=5, lambda0=1e-3, camera="angle_axis"):
+        self.p = problem
+        self.opts = make_opts(loss, loss_param, lm_steps, lambda0, False, camera=camera)
+        self.loss, self.loss_param, self.camera = loss, loss_param, camera
+        self.blocks = make_general_blocks(problem.obs_cam, problem.obs_point, problem.n_cams, kappa, pi)
+        self.cons_y = _f64(cams0).reshape(-1, 9).copy()
+        self.cons_x = _f64(points0).reshape(-1, 3).copy()
+        self.ycam = np.concatenate([b[0] for b in self.blocks])      # camera of each camera copy
+        self.xpt = np.concatenate([b[1] for b in self.blocks])       # point of each point copy
+        self.ycopy = self.cons_y[self.ycam].copy()
+        self.ydual = np.zeros_like(self.ycopy)
+        self.xcopy = self.cons_x[self.xpt].copy()
+        self.xdual = np.zeros_like(self.xcopy)
+        self.rho = float(rho)
+        self.ny = np.bincount(self.ycam, minlength=problem.n_cams).astype(np.float64)
+        self.nx = np.bincount(self.xpt, minlength=problem.n_points).astype(np.float64)
+        self.iteration = 0
+
+    @property
+    def n_copies(self):
+        return len(self.ycam), len(self.xpt)
+
+    def iterate(self, n_iters: int):
+        p, rho = self.p, self.rho
+        for _ in range(n_iters):
+            y0 = x0 = 0
+            for cams, pts, obs in self.blocks:
+                nc, npt = len(cams), len(pts)
+                ys, xs = slice(y0, y0 + nc), slice(x0, x0 + npt)
+                oc = np.ascontiguousarray(np.searchsorted(cams, p.obs_cam[obs]), dtype=np.int32)
+                op = np.ascontiguousarray(np.searchsorted(pts, p.obs_point[obs]), dtype=np.int32)
+                z = np.ascontiguousarray(p.obs_uv[obs])
+                vy = np.ascontiguousarray(self.cons_y[cams] - self.ydual[ys])
+                vx = np.ascontiguousarray(self.cons_x[pts] - self.xdual[xs])
+                th = np.concatenate([self.ycopy[ys].ravel(), self.xcopy[xs].ravel()])
+                lib().orc_gblock_local_solve(ctypes.byref(self.opts), nc, npt, len(obs), _i(oc), _i(op), _d(z),
+                                             _d(vy), _d(vx), _d(th), rho, rho, self.opts.lm_steps)
+                self.ycopy[ys] = th[:9 * nc].reshape(nc, 9)
+                self.xcopy[xs] = th[9 * nc:].reshape(npt, 3)
+                y0, x0 = y0 + nc, x0 + npt
+            sy = np.zeros_like(self.cons_y)
+            sx = np.zeros_like(self.cons_x)
+            np.add.at(sy, self.ycam, self.ycopy + self.ydual)
+            np.add.at(sx, self.xpt, self.xcopy + self.xdual)
+            self.cons_y = sy / self.ny[:, None]
+            self.cons_x = sx / self.nx[:, None]
+            self.ydual += self.ycopy - self.cons_y[self.ycam]
+            self.xdual += self.xcopy - self.cons_x[self.xpt]
+            self.iteration += 1
 
     def stats(self, mask=None):
         return reprojection_stats(self.p, self.cons_y, self.cons_x, mask, self.loss, self.loss_param,

@@ -883,6 +883,115 @@ int orc_block_local_solve(const orc_opts *o, int nb, const double *z, const doub
     return accepted;
 }
 
+/* ------------------------------------------------------------------------ */
+/* General block of the generalised local update (Sec. 3.1.4, Eqs. 14-15):   */
+/* nc cameras and np points with ONE copy each in the block, and nobs        */
+/* observations between them (observation q: block camera oc[q], block point */
+/* op[q], pixel z[2q..2q+1]).  Objective:                                    */
+/*   sum_q phi(|z_q - pi(y_oc[q], x_op[q])|^2)                               */
+/*   + rho_y/2 sum_c |y_c - vy_c|^2 + rho_x/2 sum_p |x_p - vx_p|^2;          */
+/* +inf if a depth is <= 1e-6.  theta = (y_0 .. y_{nc-1} (9 each),           */
+/* x_0 .. x_{np-1} (3 each)).                                                */
+/* ------------------------------------------------------------------------ */
+double orc_gblock_objective(const orc_opts *o, int nc, int np, int nobs, const int32_t *oc, const int32_t *op,
+                            const double *z, const double *vy, const double *vx, const double *theta,
+                            double rho_x, double rho_y)
+{
+    double F = 0.0;
+    for (int c = 0; c < 9 * nc; ++c) {
+        const double d = theta[c] - vy[c];
+        F += 0.5 * rho_y * d * d;
+    }
+    for (int c = 0; c < 3 * np; ++c) {
+        const double d = theta[9 * nc + c] - vx[c];
+        F += 0.5 * rho_x * d * d;
+    }
+    for (int q = 0; q < nobs; ++q) {
+        double uv[2], ls[2];
+        const double depth = orc_project_cam(o->camera, theta + 9 * oc[q], theta + 9 * nc + 3 * op[q], uv);
+        if (!(depth > ORC_DEPTH_EPS)) return INFINITY;
+        const double e0 = z[2 * q] - uv[0], e1 = z[2 * q + 1] - uv[1];
+        orc_loss(o->loss, o->loss_param, e0 * e0 + e1 * e1, ls);
+        F += ls[0];
+    }
+    return F;
+}
+
+/* Robust LM on the general block objective with the rules of
+ * orc_block_local_solve (dense normal equations over all 9 nc + 3 np
+ * unknowns, Cholesky, exactly `steps` steps, the same acceptance and tie
+ * rule).  Returns the number of accepted steps, -2 on allocation failure. */
+int orc_gblock_local_solve(const orc_opts *o, int nc, int np, int nobs, const int32_t *oc, const int32_t *op,
+                           const double *z, const double *vy, const double *vx, double *theta, double rho_x,
+                           double rho_y, int steps)
+{
+    const int N = 9 * nc + 3 * np;
+    double *g = malloc(sizeof(double) * N), *H = malloc(sizeof(double) * (size_t)N * N);
+    double *A = malloc(sizeof(double) * (size_t)N * N), *rhs = malloc(sizeof(double) * N);
+    double *delta = malloc(sizeof(double) * N), *trial = malloc(sizeof(double) * N);
+    if (!g || !H || !A || !rhs || !delta || !trial) {
+        free(g); free(H); free(A); free(rhs); free(delta); free(trial);
+        return -2;
+    }
+    double lambda = o->lambda0;
+    double F = orc_gblock_objective(o, nc, np, nobs, oc, op, z, vy, vx, theta, rho_x, rho_y);
+    int accepted = 0;
+    for (int it = 0; it < steps; ++it) {
+        memset(H, 0, sizeof(double) * (size_t)N * N);
+        for (int r = 0; r < N; ++r) {
+            const int cam = r < 9 * nc;
+            const double pr = cam ? rho_y : rho_x;
+            g[r] = pr * (theta[r] - (cam ? vy[r] : vx[r - 9 * nc]));
+            H[(size_t)r * N + r] = pr;
+        }
+        double fres = F;
+        for (int q = 0; q < nobs; ++q) {
+            const double *yc = theta + 9 * oc[q], *xp = theta + 9 * nc + 3 * op[q];
+            double uv[2], J[24], ls[2];
+            orc_project_jac_cam(o->camera, yc, xp, uv, J);
+            const double e0 = z[2 * q] - uv[0], e1 = z[2 * q + 1] - uv[1];
+            orc_loss(o->loss, o->loss_param, e0 * e0 + e1 * e1, ls);
+            const double w = ls[1];
+            fres += sqrt(e0 * e0 + e1 * e1) * (fabs(z[2 * q]) + fabs(z[2 * q + 1]) + fabs(yc[6]));
+            int col[12];
+            for (int c = 0; c < 9; ++c) col[c] = 9 * oc[q] + c;
+            for (int c = 0; c < 3; ++c) col[9 + c] = 9 * nc + 3 * op[q] + c;
+            for (int r = 0; r < 12; ++r) {
+                g[col[r]] += -2.0 * w * (J[r] * e0 + J[12 + r] * e1);
+                for (int t = 0; t < 12; ++t)
+                    H[(size_t)col[r] * N + col[t]] += 2.0 * w * (J[r] * J[t] + J[12 + r] * J[12 + t]);
+            }
+        }
+        for (int r = 0; r < N; ++r) {
+            for (int t = 0; t < N; ++t) A[(size_t)r * N + t] = H[(size_t)r * N + t];
+            A[(size_t)r * N + r] += lambda * H[(size_t)r * N + r];
+            rhs[r] = -g[r];
+        }
+        const int ok = chol_solve_n(N, A, rhs, delta) == 0;
+        double Fn = INFINITY, pred = INFINITY;
+        if (ok) {
+            for (int r = 0; r < N; ++r) trial[r] = theta[r] + delta[r];
+            Fn = orc_gblock_objective(o, nc, np, nobs, oc, op, z, vy, vx, trial, rho_x, rho_y);
+            double gd = 0.0, dd = 0.0;
+            for (int r = 0; r < N; ++r) {
+                gd += g[r] * delta[r];
+                dd += H[(size_t)r * N + r] * delta[r] * delta[r];
+            }
+            pred = 0.5 * (lambda * dd - gd);
+        }
+        if (ok && isfinite(Fn) && (Fn < F || pred <= ORC_TIE * fres)) {
+            memcpy(theta, trial, sizeof(double) * N);
+            F = Fn;
+            lambda = fmax(lambda / 10.0, ORC_LAMBDA_MIN);
+            ++accepted;
+        } else {
+            lambda = fmin(lambda * 10.0, ORC_LAMBDA_MAX);
+        }
+    }
+    free(g); free(H); free(A); free(rhs); free(delta); free(trial);
+    return accepted;
+}
+
 /* ADMM iterations with block local updates.  Blocks: nblk, blk_off[nblk+1]
  * offsets into blk_obs (observation indices of each block in order),
  * blk_cam[nblk] the block's camera.  State: ycopy/ydual [nblk][9] (the

@@ -48,6 +48,12 @@ WORKLOADS = {
                                                          camera_blocks=True),
                               desc="as trajectory, with block local updates: the observations of a camera form "
                                    "blocks of up to 64 that share one camera copy (Sec. 3.1.4); 5 LM steps"),
+    "trajectory_blocks2": dict(scene="config2", opts=dict(precision="fp32", loss="huber", loss_param=2.0, rho=1e5,
+                                                          rho_balancing=True, rho_min=1e5, rho_max=1e7,
+                                                          camera_blocks=True, block_cameras=2),
+                               desc="as trajectory, with two-camera blocks (Sec. 3.1.4, kappa = 2): cameras in "
+                                    "pairs, each pair's points in runs of 64 with one copy per block point and "
+                                    "camera; 5 LM steps"),
     "trajectory_euler": dict(scene="config2_euler", opts=dict(precision="fp32", loss="huber", loss_param=2.0,
                                                               rho=1e5, rho_balancing=True, rho_min=1e5, rho_max=1e7,
                                                               camera="euler"),
@@ -219,6 +225,15 @@ def time_to_rmse(binding, scene, opts, sched, target, max_iters=400, learned_ste
         res[f"blocks_lm{k}"] = run(dict(opts, lm_steps=k, camera_blocks=True, block_waves=sched["block_waves"],
                                         persistent=sched["persistent"]))
         print(f"[bench] time-to-RMSE blocks, {k} LM steps: {res[f'blocks_lm{k}']}", file=sys.stderr, flush=True)
+    for k in (1, 2, 5):
+        res[f"blocks2_lm{k}"] = run(dict(opts, lm_steps=k, camera_blocks=True, block_cameras=2,
+                                         block_waves=min(sched["block_waves"], 4), persistent=sched["persistent"]))
+        print(f"[bench] time-to-RMSE two-camera blocks, {k} LM steps: {res[f'blocks2_lm{k}']}", file=sys.stderr,
+              flush=True)
+    best = lambda key: min((res[f"{key}_lm{k}"]["seconds"] for k in (1, 2, 5)
+                            if res[f"{key}_lm{k}"]["seconds"] is not None), default=None)
+    b1, b2 = best("blocks"), best("blocks2")
+    res["blocks2_over_blocks_time"] = (b2 / b1) if (b1 and b2) else None
     if not learned_steps:
         t_plain = res["plain_lm5"]["seconds"]
         tb = min((res[f"blocks_lm{k}"]["seconds"] for k in (1, 2, 5) if res[f"blocks_lm{k}"]["seconds"] is not None),
@@ -558,7 +573,12 @@ def main():
     kt = {k: dict(avg_ms=(v[0] / v[1] if v[1] else None), launches=v[1]) for k, v in ktimes.items() if v[1]}
     local_ms = kt["local"]["avg_ms"]
     blocks = bool(opts.get("camera_blocks"))
-    if blocks:
+    blocks2 = blocks and opts.get("block_cameras", 1) == 2
+    if blocks2:
+        import numpy as np
+        copies = sum(len(np.unique((sc.obs_cam // 2).astype(np.int64) * sc.n_points + sc.obs_point)) for sc in scenes)
+        flops_per_obs = cost.block2_flops_per_obs(opts.get("lm_steps", 5), L / copies)
+    elif blocks:
         flops_per_obs = cost.block_flops_per_obs(opts.get("lm_steps", 5))
     else:
         flops_per_obs = cost.local_flops_per_obs(opts.get("lm_steps", 5), opts.get("camera", "angle_axis"))
@@ -566,7 +586,8 @@ def main():
     achieved = flops / (local_ms * 1e-3) / 1e12
     traffic, traffic_src = recorded_traffic(args.workload)
     byt = cost.bytes_per_obs(fp32)
-    roofline = {"kernel": "local (k_local_block)" if blocks else "local (k_local)", "bound": "alu", "achieved": round(achieved, 3),
+    roofline = {"kernel": "local (k_local_block2)" if blocks2 else "local (k_local_block)" if blocks else "local (k_local)",
+                "bound": "alu", "achieved": round(achieved, 3),
                 "peak": FP32_VECTOR_PEAK_TFLOPS if fp32 else 78.6, "unit": "TFLOP/s",
                 "frac": round(achieved / (FP32_VECTOR_PEAK_TFLOPS if fp32 else 78.6), 4),
                 "traffic": traffic, "flops_per_obs": flops_per_obs,

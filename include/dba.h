@@ -112,6 +112,14 @@ typedef struct dba_options {
                                  Sec. 3.1.4, 1..64; 0 means 64.  Must be 0 without camera_blocks */
     int32_t camera_model;     /* dba_camera; the Euler camera not with the learned start */
     int32_t local_solver;     /* dba_local_solver */
+    int32_t block_cameras;    /* with camera_blocks: cameras per block, the kappa of Sec. 3.1.4:
+                                 1 (the blocks above) or 2: cameras in consecutive pairs, each
+                                 pair's observed points in ascending order in runs of
+                                 block_points (0: 64); a block holds one run with ONE copy of each
+                                 of its points and of each pair camera that observes them, and its
+                                 local problem couples them (18 + 3 x points unknowns, Schur
+                                 complement on the points, an 18x18 camera system).  Must be 1
+                                 without camera_blocks */
 } dba_options;
 
 /* Fills *opt with the defaults: device 0, NULL stream, FP64, Huber 2 px,

@@ -44,7 +44,7 @@ class dba_options(ctypes.Structure):
                 ("use_graph", ctypes.c_int32), ("block_waves", ctypes.c_int32),
                 ("persistent", ctypes.c_int32), ("camera_blocks", ctypes.c_int32),
                 ("block_points", ctypes.c_int32), ("camera_model", ctypes.c_int32),
-                ("local_solver", ctypes.c_int32)]
+                ("local_solver", ctypes.c_int32), ("block_cameras", ctypes.c_int32)]
 
 
 class dba_problem_desc(ctypes.Structure):
@@ -137,7 +137,8 @@ def make_options(*, device=0, stream=None, precision="fp64", loss="huber", loss_
                  rho_x=None, rho_y=None, rho_balancing=False, rb_mu=10.0, rb_tau=2.0,
                  rho_min=1e-6, rho_max=1e6, lm_steps=5, lm_lambda0=1e-3, start="plain",
                  learned_lm_steps=2, use_graph=True, block_waves=0, persistent=-1,
-                 camera_blocks=False, block_points=0, camera="angle_axis", solver="lm") -> dba_options:
+                 camera_blocks=False, block_points=0, camera="angle_axis", solver="lm",
+                 block_cameras=1) -> dba_options:
     """dba_options from keywords: enum fields by name (precision "fp64" /
     "fp32"; loss "l2" / "huber" / "student_t"; start "plain" / "learned";
     camera "angle_axis" / "euler"; solver "lm" / "gauss_newton" / "lbfgs"),
@@ -164,6 +165,7 @@ def make_options(*, device=0, stream=None, precision="fp64", loss="huber", loss_
     o.block_points = int(block_points)
     o.camera_model = CAMERA[camera]
     o.local_solver = SOLVER[solver]
+    o.block_cameras = int(block_cameras)
     return o
 
 

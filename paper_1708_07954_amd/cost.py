@@ -69,6 +69,23 @@ BLOCK_LM_STEP = JAC + RESID + 366 + 40 + 459 + 63 + 72 + 15 + PROJ + 20 + 420 //
 BLOCK_PER_SOLVE = PROJ + 20 + 3 * 3 + 9 * 3 // 64
 
 
+# --- two-camera blocks (a copy per block point, up to two observations each) ---
+# per observation and LM step: projection, Jacobian and residual; its part of
+# the point block and gradient 36; B V for its two rows 30; r 16; its camera
+# rows' right-hand side, gradient and diagonal values 108; its part of W^T dy
+# 48; trial projection and objective 95.  Per point copy: the damped 3x3 block
+# inverted 40; M for the three camera pairs 108; Q 216; the 171 reduced-system
+# values 684; the point step and predicted decrease 45.  Per block of 64
+# copies: the 18x18 LDL^T (1 944) and its solves (684), and the all-reduce's
+# additions (226 per copy).
+BLOCK2_OBS_STEP = JAC + RESID + 36 + 30 + 16 + 108 + 48 + PROJ + 20
+BLOCK2_COPY_STEP = 40 + 108 + 216 + 684 + 45 + 226 + (1944 + 684) // 64
+
+
+def block2_flops_per_obs(lm_steps: int = 5, obs_per_copy: float = 1.7) -> int:
+    return int(round((BLOCK_PER_SOLVE + lm_steps * (BLOCK2_OBS_STEP + BLOCK2_COPY_STEP / obs_per_copy))))
+
+
 def block_flops_per_obs(lm_steps: int = 5) -> int:
     return BLOCK_PER_SOLVE + lm_steps * BLOCK_LM_STEP
 

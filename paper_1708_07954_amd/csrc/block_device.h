@@ -306,5 +306,376 @@ __device__ __forceinline__ void block_lm(R *th, const R *vy, const R *vx, R z0, 
     }
 }
 
+
+// ---------------------------------------------------------------- two cameras
+// Blocks of two cameras (Sec. 3.1.4 with kappa = 2): lane l holds point copy
+// x_l and up to two observations of it, one per camera of the block, with the
+// camera copies y_0, y_1 (18 unknowns, uniform across the wave).  Per LM step
+// each lane forms its 3x3 point block and, with U_s the camera rows of its
+// observation s (9x2), its contribution U_s M_st U_t^T to the 18x18 reduced
+// camera system (M 4x4 from the damped, inverted point block); a fixed-order
+// reduction sums the contributions into LDS, the wave factors the system in
+// LDS (LDL^T, one column after another, the trailing update spread over the
+// lanes), and every lane solves and back-substitutes its point.
+
+// Packed upper triangle of a symmetric 18x18 matrix: index of (i, j), i <= j.
+__host__ __device__ constexpr int sym18(int i, int j) { return i * 18 - i * (i - 1) / 2 + (j - i); }
+__host__ __device__ constexpr int row18(int t)
+{
+    int i = 0;
+    while (i < 17 && sym18(i + 1, i + 1) <= t) ++i;
+    return i;
+}
+__host__ __device__ constexpr int col18(int t) { return row18(t) + (t - sym18(row18(t), row18(t))); }
+
+constexpr int kB2Sys = 171;                 // packed 18x18
+constexpr int kB2Rhs = kB2Sys;              // 18: reduced right-hand side (ng_y - sum W B ng_x)
+constexpr int kB2Ngy = kB2Rhs + 18;         // 18: ng_y, the misfit part of -gradient in y
+constexpr int kB2Hd = kB2Ngy + 18;          // 18: misfit part of diag(H_yy)
+constexpr int kB2Fres = kB2Hd + 18;         // 1: sum of |e| (|z_1| + |z_2| + f)
+constexpr int kB2Vals = kB2Fres + 1;        // 226 reduced values
+constexpr int kB2Lds = 256 + 64;            // per wave: the reduced values, then reduction scratch
+
+__device__ __forceinline__ void wave_lds_sync()
+{
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// The reduce-scatter levels 16 .. 1 of the streamed values in b: lane l's
+// total of value l goes to dst[l].
+template <typename T>
+__device__ __forceinline__ void wave_reduce_to(const T *b, T *dst, int lane)
+{
+    T c[16], d[8], e[4], f[2];
+    rs_level<16, 16>(b, c, lane);
+    rs_level<8, 8>(c, d, lane);
+    rs_level<4, 4>(d, e, lane);
+    rs_level<2, 2>(e, f, lane);
+    T g;
+    rs_level<1, 1>(f, &g, lane);
+    dst[lane] = g;
+}
+
+// LDL^T of the packed symmetric 18x18 matrix a (LDS, in place: row j keeps D_j
+// on the diagonal and L_ij, i > j, at (j, i)); false if a pivot is not
+// positive and finite.  Column j: the trailing update a_ik -= a_ji a_jk / D_j
+// over the lanes, then the row is scaled.
+template <typename R>
+__device__ __forceinline__ bool ldl18_lds(R *a, int lane)
+{
+    bool ok = true;
+    for (int j = 0; j < 18; ++j) {
+        const R d = a[sym18(j, j)];
+        ok = ok && (d > R(0)) && (d < Num<R>::inf);
+        const R rd = Num<R>::rcp(d);
+        const int t0 = sym18(j + 1 < 18 ? j + 1 : 17, j + 1 < 18 ? j + 1 : 17);
+        if (j + 1 < 18)
+            for (int t = t0 + lane; t < kB2Sys; t += 64) {
+                const int i = row18(t), k = col18(t);
+                a[t] -= a[sym18(j, i)] * a[sym18(j, k)] * rd;
+            }
+        wave_lds_sync();
+        if (lane > j && lane < 18) a[sym18(j, lane)] *= rd;
+        wave_lds_sync();
+    }
+    return ok;
+}
+
+// x = A^-1 b with A factored by ldl18_lds (every lane, reading LDS).
+template <typename R>
+__device__ __forceinline__ void ldl18_solve(const R *a, const R *b, R *x)
+{
+#pragma unroll
+    for (int i = 0; i < 18; ++i) {
+        R v = b[i];
+#pragma unroll
+        for (int k = 0; k < i; ++k) v -= a[sym18(k, i)] * x[k];
+        x[i] = v;
+    }
+#pragma unroll
+    for (int i = 0; i < 18; ++i) x[i] *= Num<R>::rcp(a[sym18(i, i)]);
+#pragma unroll
+    for (int i = 17; i >= 0; --i) {
+        R v = x[i];
+#pragma unroll
+        for (int k = i + 1; k < 18; ++k) v -= a[sym18(i, k)] * x[k];
+        x[i] = v;
+    }
+}
+
+// Block LM of a two-camera block.  y: the cameras (18, uniform), present
+// bit s: camera s has a copy in the block (an absent camera does not move and
+// has no penalty); x, vx: this lane's point copy and its target; act[s]: this
+// lane has an observation of camera s at pixel (z[2s], z[2s+1]).  lds: the
+// wave's kB2Lds values.
+template <typename R, typename Cam>
+__device__ __forceinline__ void block_lm2(R *y, const R *vy, int present, R *x, const R *vx, const bool *act,
+                                          const R *z, R rx, R ry, int kind, R lp, int steps, R lam, R *lds,
+                                          int lane)
+{
+    using P = decltype(proj_core<R, true>(y, Cam{}));
+    R *red = lds, *scr = lds + 256;
+    const bool pt = act[0] || act[1];
+    auto theta = [&](int s, R *th) {
+#pragma unroll
+        for (int i = 0; i < 9; ++i) th[i] = y[9 * s + i];
+#pragma unroll
+        for (int c = 0; c < 3; ++c) th[9 + c] = x[c];
+    };
+    auto cam_pen = [&](const R *yy) {
+        R q = R(0);
+#pragma unroll
+        for (int s = 0; s < 2; ++s) {
+            if (!(present >> s & 1)) continue;
+#pragma unroll
+            for (int i = 0; i < 9; ++i) {
+                if (!cam_active<Cam>(i)) continue;
+                const R d = yy[9 * s + i] - vy[9 * s + i];
+                q += d * d;
+            }
+        }
+        return R(0.5) * ry * q;
+    };
+    auto lane_obj = [&](const P *o, const R *xx) {
+        R f = R(0);
+#pragma unroll
+        for (int s = 0; s < 2; ++s) {
+            if (!act[s]) continue;
+            if (!(o[s].depth > R(1e-6))) return Num<R>::inf;
+            const R e0 = z[2 * s] - o[s].pu, e1 = z[2 * s + 1] - o[s].pv;
+            R w;
+            f += loss_phi<R>(kind, lp, e0 * e0 + e1 * e1, w);
+        }
+        if (pt) {
+            R q = R(0);
+#pragma unroll
+            for (int c = 0; c < 3; ++c) {
+                const R d = xx[c] - vx[c];
+                q += d * d;
+            }
+            f += R(0.5) * rx * q;
+        }
+        return f;
+    };
+    P cur[2];
+#pragma unroll
+    for (int s = 0; s < 2; ++s)
+        if (act[s]) {
+            R th[12];
+            theta(s, th);
+            cur[s] = proj_core<R, true>(th, Cam{});
+        }
+    R F = wave_sum<R>(lane_obj(cur, x)) + cam_pen(y);
+    for (int it = 0; it < steps; ++it) {
+        // linearisation of each observation at (y_s, x)
+        R U[2][2][9], V[2][2][3], e[2][2], c2[2], fr = R(0);
+#pragma unroll
+        for (int s = 0; s < 2; ++s) {
+            c2[s] = R(0);
+            e[s][0] = e[s][1] = R(0);
+#pragma unroll
+            for (int i = 0; i < 9; ++i) U[s][0][i] = U[s][1][i] = R(0);
+#pragma unroll
+            for (int k = 0; k < 3; ++k) V[s][0][k] = V[s][1][k] = R(0);
+            if (act[s]) {
+                R th[12], J0[12], J1[12];
+                theta(s, th);
+                proj_jac<R>(cur[s], th, J0, J1);
+                e[s][0] = z[2 * s] - cur[s].pu;
+                e[s][1] = z[2 * s + 1] - cur[s].pv;
+                R w;
+                const R s2 = e[s][0] * e[s][0] + e[s][1] * e[s][1];
+                loss_phi<R>(kind, lp, s2, w);
+                c2[s] = R(2) * w;
+                fr += Num<R>::sqrt(s2) * (fabs(z[2 * s]) + fabs(z[2 * s + 1]) + fabs(y[9 * s + 6]));
+#pragma unroll
+                for (int i = 0; i < 9; ++i) {
+                    U[s][0][i] = J0[i];
+                    U[s][1][i] = J1[i];
+                }
+#pragma unroll
+                for (int k = 0; k < 3; ++k) {
+                    V[s][0][k] = J0[9 + k];
+                    V[s][1][k] = J1[9 + k];
+                }
+            }
+        }
+        // point block H_xx = sum_s c_s V_s V_s^T + rho_x I, damped, inverted
+        R hx[6] = {rx, R(0), R(0), rx, R(0), rx}, ngx[3] = {R(0), R(0), R(0)};
+#pragma unroll
+        for (int s = 0; s < 2; ++s)
+#pragma unroll
+            for (int a = 0; a < 2; ++a) {
+                const R *v = V[s][a];
+                hx[0] += c2[s] * v[0] * v[0];
+                hx[1] += c2[s] * v[0] * v[1];
+                hx[2] += c2[s] * v[0] * v[2];
+                hx[3] += c2[s] * v[1] * v[1];
+                hx[4] += c2[s] * v[1] * v[2];
+                hx[5] += c2[s] * v[2] * v[2];
+#pragma unroll
+                for (int k = 0; k < 3; ++k) ngx[k] += c2[s] * v[k] * e[s][a];
+            }
+        if (pt)
+#pragma unroll
+            for (int k = 0; k < 3; ++k) ngx[k] -= rx * (x[k] - vx[k]);
+        const R a00 = hx[0] * (R(1) + lam), a11 = hx[3] * (R(1) + lam), a22 = hx[5] * (R(1) + lam);
+        const R a01 = hx[1], a02 = hx[2], a12 = hx[4];
+        const R m00 = a11 * a22 - a12 * a12, m01 = a02 * a12 - a01 * a22, m02 = a01 * a12 - a02 * a11;
+        const R det = a00 * m00 + a01 * m01 + a02 * m02;
+        const bool okx = !pt || ((det > R(0)) && (det < Num<R>::inf));
+        const R idet = Num<R>::rcp(det);
+        const R B[6] = {m00 * idet, m01 * idet, m02 * idet, (a00 * a22 - a02 * a02) * idet,
+                        (a01 * a02 - a00 * a12) * idet, (a00 * a11 - a01 * a01) * idet};
+        auto bmul = [&](const R *v, R *o) {
+            o[0] = B[0] * v[0] + B[1] * v[1] + B[2] * v[2];
+            o[1] = B[1] * v[0] + B[3] * v[1] + B[4] * v[2];
+            o[2] = B[2] * v[0] + B[4] * v[1] + B[5] * v[2];
+        };
+        R BV[2][2][3], Bn[3];
+#pragma unroll
+        for (int s = 0; s < 2; ++s)
+#pragma unroll
+            for (int a = 0; a < 2; ++a) bmul(V[s][a], BV[s][a]);
+        bmul(ngx, Bn);
+        // M_st = delta_st c_s I - c_s c_t V_s^T B V_t (2x2 blocks), Q_st = M_st U_t^T;
+        // r_s = c_s (e_s - V_s^T B ng_x)
+        R Q[3][2][9], r[2][2];
+#pragma unroll
+        for (int s = 0; s < 2; ++s)
+#pragma unroll
+            for (int a = 0; a < 2; ++a)
+                r[s][a] = c2[s] * (e[s][a] - (V[s][a][0] * Bn[0] + V[s][a][1] * Bn[1] + V[s][a][2] * Bn[2]));
+#pragma unroll
+        for (int p = 0; p < 3; ++p) {
+            const int s = p == 2 ? 1 : 0, t = p == 0 ? 0 : 1;
+            R M[2][2];
+#pragma unroll
+            for (int a = 0; a < 2; ++a)
+#pragma unroll
+                for (int b = 0; b < 2; ++b) {
+                    const R g = V[s][a][0] * BV[t][b][0] + V[s][a][1] * BV[t][b][1] + V[s][a][2] * BV[t][b][2];
+                    M[a][b] = (s == t && a == b ? c2[s] : R(0)) - c2[s] * c2[t] * g;
+                }
+#pragma unroll
+            for (int a = 0; a < 2; ++a)
+#pragma unroll
+                for (int j = 0; j < 9; ++j) Q[p][a][j] = M[a][0] * U[t][0][j] + M[a][1] * U[t][1][j];
+        }
+        // the lane's 226 values, in four batches of 64, reduced into LDS
+        auto val = [&](int t) -> R {
+            if (t < kB2Sys) {
+                const int i = row18(t), j = col18(t), s = i / 9, u = j / 9, p = s + u;
+                return U[s][0][i % 9] * Q[p][0][j % 9] + U[s][1][i % 9] * Q[p][1][j % 9];
+            }
+            if (t < kB2Ngy) {
+                const int i = t - kB2Rhs, s = i / 9;
+                return U[s][0][i % 9] * r[s][0] + U[s][1][i % 9] * r[s][1];
+            }
+            if (t < kB2Hd) {
+                const int i = t - kB2Ngy, s = i / 9;
+                return c2[s] * (U[s][0][i % 9] * e[s][0] + U[s][1][i % 9] * e[s][1]);
+            }
+            if (t < kB2Fres) {
+                const int i = t - kB2Hd, s = i / 9;
+                return c2[s] * (U[s][0][i % 9] * U[s][0][i % 9] + U[s][1][i % 9] * U[s][1][i % 9]);
+            }
+            return t == kB2Fres ? fr : R(0);
+        };
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            R b32[32];
+#pragma unroll
+            for (int t = 0; t < 64; ++t) rs_first_put<R>(b32, t, val(64 * q + t));
+            wave_reduce_to<R>(b32, red + 64 * q, lane);
+        }
+        wave_lds_sync();
+        const R fres = F + red[kB2Fres];
+        // the camera system: penalty and damping on the diagonal, absent cameras fixed
+        if (lane < 18) {
+            const int i = lane, s = i / 9;
+            if (present >> s & 1) {
+                red[sym18(i, i)] += ry + lam * (ry + red[kB2Hd + i]);
+                red[kB2Rhs + i] -= ry * (y[i] - vy[i]);
+            } else {
+                red[sym18(i, i)] = R(1);
+                red[kB2Rhs + i] = R(0);
+            }
+        }
+        wave_lds_sync();
+        const bool oky = ldl18_lds<R>(red, lane);
+        R dy[18];
+        ldl18_solve<R>(red, red + kB2Rhs, dy);
+        const bool ok = oky && (__ballot(!okx) == 0ull);
+        // point step dx = B (ng_x - W^T dy), W_s = c_s U_s V_s^T, and the
+        // predicted decrease 1/2 (lambda d^T diag(H) d + ng^T d)
+        R dx[3] = {R(0), R(0), R(0)}, pk = R(0);
+        if (pt) {
+            R wdy[3] = {R(0), R(0), R(0)};
+#pragma unroll
+            for (int s = 0; s < 2; ++s)
+#pragma unroll
+                for (int a = 0; a < 2; ++a) {
+                    R u = R(0);
+#pragma unroll
+                    for (int i = 0; i < 9; ++i) u += U[s][a][i] * dy[9 * s + i];
+#pragma unroll
+                    for (int k = 0; k < 3; ++k) wdy[k] += c2[s] * V[s][a][k] * u;
+                }
+            R t3[3] = {ngx[0] - wdy[0], ngx[1] - wdy[1], ngx[2] - wdy[2]};
+            bmul(t3, dx);
+            pk = ngx[0] * dx[0] + ngx[1] * dx[1] + ngx[2] * dx[2] +
+                 lam * (hx[0] * dx[0] * dx[0] + hx[3] * dx[1] * dx[1] + hx[5] * dx[2] * dx[2]);
+        }
+        R gdy = R(0), ddy = R(0);
+#pragma unroll
+        for (int i = 0; i < 18; ++i) {
+            if (!(present >> (i / 9) & 1)) continue;
+            gdy += (red[kB2Ngy + i] - ry * (y[i] - vy[i])) * dy[i];
+            ddy += (ry + red[kB2Hd + i]) * dy[i] * dy[i];
+        }
+        const R pred = R(0.5) * (wave_sum<R>(pk) + gdy + lam * ddy);
+        // trial
+        R ty[18], tx[3];
+#pragma unroll
+        for (int i = 0; i < 18; ++i) ty[i] = (present >> (i / 9) & 1) ? y[i] + dy[i] : y[i];
+#pragma unroll
+        for (int k = 0; k < 3; ++k) tx[k] = x[k] + dx[k];
+        P nxt[2];
+        R fn = R(0);
+        if (ok) {
+#pragma unroll
+            for (int s = 0; s < 2; ++s)
+                if (act[s]) {
+                    R th[12];
+#pragma unroll
+                    for (int i = 0; i < 9; ++i) th[i] = ty[9 * s + i];
+#pragma unroll
+                    for (int k = 0; k < 3; ++k) th[9 + k] = tx[k];
+                    nxt[s] = proj_core<R, true>(th, Cam{});
+                }
+            fn = lane_obj(nxt, tx);
+        }
+        const bool bad = __ballot(!(fn < Num<R>::inf)) != 0ull;
+        const R Fn = (ok && !bad) ? wave_sum<R>(fn) + cam_pen(ty) : Num<R>::inf;
+        if (Fn < Num<R>::inf && (Fn < F || pred <= Num<R>::tie * fres)) {
+#pragma unroll
+            for (int i = 0; i < 18; ++i) y[i] = ty[i];
+#pragma unroll
+            for (int k = 0; k < 3; ++k) x[k] = tx[k];
+#pragma unroll
+            for (int s = 0; s < 2; ++s)
+                if (act[s]) cur[s] = nxt[s];
+            F = Fn;
+            lam = lam_down<R>(lam);
+        } else {
+            lam = lam_up<R>(lam);
+        }
+        wave_lds_sync();
+    }
+}
+
 }  // namespace dev
 }  // namespace dba

@@ -106,6 +106,62 @@ int validate(dba_handle *h, int p, const dba_problem_desc &d)
     return DBA_OK;
 }
 
+// Two-camera blocks of one problem (block_cameras == 2): cameras in pairs
+// (2g, 2g + 1); a pair's observed points, ascending, in runs of at most bp
+// points; block b holds run b with one copy of each of its points (lane l <->
+// point pts[pts0[b] + l]) and of each pair camera s that observes one of them
+// (bit s of present[b]); obs[(pts0[b] + l) * 2 + s] is the observation of
+// camera s of the pair at lane l, or -1.  Returns false on a repeated
+// (camera, point) pair, which a lane cannot hold.
+struct PairBlocks {
+    std::vector<int> cam0, npts, pts0, present, pts;
+    std::vector<long long> obs;
+};
+
+static bool pair_blocks(const dba_problem_desc &d, int bp, PairBlocks &out)
+{
+    const int ng = (d.n_cams + 1) / 2;
+    std::vector<long long> goff(ng + 1, 0);
+    for (long long k = 0; k < d.n_obs; ++k) ++goff[d.obs_cam[k] / 2 + 1];
+    for (int g = 0; g < ng; ++g) goff[g + 1] += goff[g];
+    std::vector<long long> gobs(d.n_obs), fill(goff.begin(), goff.end() - 1);
+    for (long long k = 0; k < d.n_obs; ++k) gobs[fill[d.obs_cam[k] / 2]++] = k;
+    std::vector<int> lane_of(d.n_points, -1);
+    for (int g = 0; g < ng; ++g) {
+        std::vector<int> gp;
+        for (long long q = goff[g]; q < goff[g + 1]; ++q) gp.push_back(d.obs_point[gobs[q]]);
+        std::sort(gp.begin(), gp.end());
+        gp.erase(std::unique(gp.begin(), gp.end()), gp.end());
+        const size_t first = out.pts.size();
+        for (size_t r0 = 0; r0 < gp.size(); r0 += bp) {
+            const int n = (int)std::min<size_t>(bp, gp.size() - r0);
+            out.cam0.push_back(2 * g);
+            out.npts.push_back(n);
+            out.pts0.push_back((int)out.pts.size());
+            out.present.push_back(0);
+            for (int l = 0; l < n; ++l) {
+                out.pts.push_back(gp[r0 + l]);
+                out.obs.push_back(-1);
+                out.obs.push_back(-1);
+            }
+        }
+        for (size_t t = first; t < out.pts.size(); ++t) lane_of[out.pts[t]] = (int)t;
+        // each observation of the pair into its point's lane
+        for (long long q = goff[g]; q < goff[g + 1]; ++q) {
+            const long long k = gobs[q];
+            const int t = lane_of[d.obs_point[k]], sc = d.obs_cam[k] - 2 * g;
+            if (out.obs[2 * (size_t)t + sc] >= 0) return false;
+            out.obs[2 * (size_t)t + sc] = k;
+        }
+    }
+    // presence bits, per block from its lanes
+    for (size_t b = 0; b < out.cam0.size(); ++b)
+        for (int l = 0; l < out.npts[b]; ++l)
+            for (int sc = 0; sc < 2; ++sc)
+                if (out.obs[2 * (size_t)(out.pts0[b] + l) + sc] >= 0) out.present[b] |= 1 << sc;
+    return true;
+}
+
 template <typename R>
 int build_set(dba_handle *h, int np, const dba_problem_desc *probs, ProblemSet *ps, DevArrays<R> &A)
 {
@@ -117,9 +173,12 @@ int build_set(dba_handle *h, int np, const dba_problem_desc *probs, ProblemSet *
     // allocate no per-slot camera copies (copy_y, dual_y).
     const int BP = h->opt.camera_blocks && h->opt.block_points ? h->opt.block_points : CH;
     const bool per_obs = !h->opt.camera_blocks;
+    // two-camera blocks: a point copy per (block, point), not per observation
+    const bool k2 = h->opt.camera_blocks && h->opt.block_cameras == 2;
+    std::vector<PairBlocks> pbs(k2 ? np : 0);
     // global sizes
     long long n_chunks = 0, n_recs = 0;
-    int n_cams = 0, n_pts = 0, n_pblk = 0;
+    int n_cams = 0, n_pts = 0, n_pblk = 0, n_blocks = 0;
     ps->n_problems = np;
     for (int p = 0; p < np; ++p) {
         const dba_problem_desc &d = probs[p];
@@ -129,8 +188,17 @@ int build_set(dba_handle *h, int np, const dba_problem_desc *probs, ProblemSet *
         r.cam0 = n_cams; r.n_cams = d.n_cams;
         r.pt0 = n_pts; r.n_points = d.n_points;
         r.chunk0 = (int)n_chunks;
-        long long ch = 0;
-        for (int j = 0; j < d.n_cams; ++j) ch += (cc[j] + BP - 1) / BP;
+        long long ch = 0, nrec = d.n_obs;
+        if (k2) {
+            if (!pair_blocks(d, BP, pbs[p]))
+                return fail(h, DBA_E_INVALID_ARG, "problem %d: a camera observes a point twice (two-camera blocks "
+                            "hold one observation per camera and point)", p);
+            for (int pr : pbs[p].present) ch += (pr & 1) + (pr >> 1);
+            nrec = (long long)pbs[p].pts.size();
+            n_blocks += (int)pbs[p].cam0.size();
+        } else {
+            for (int j = 0; j < d.n_cams; ++j) ch += (cc[j] + BP - 1) / BP;
+        }
         r.n_chunks = (int)ch;
         r.rec0 = n_recs; r.n_obs = d.n_obs;
         r.pblk0 = n_pblk; r.n_pblk = (d.n_points + dba::kPtBlock - 1) / dba::kPtBlock;
@@ -142,7 +210,7 @@ int build_set(dba_handle *h, int np, const dba_problem_desc *probs, ProblemSet *
         n_cams += d.n_cams;
         n_pts += d.n_points;
         n_chunks += ch;
-        n_recs += d.n_obs;
+        n_recs += nrec;
     }
     const long long S = n_chunks * CH;
     if (S >= (1LL << 31) || n_recs >= (1LL << 31))
@@ -162,6 +230,9 @@ int build_set(dba_handle *h, int np, const dba_problem_desc *probs, ProblemSet *
     std::vector<double4> cons_x(n_pts);
     std::vector<Ctrl> ctrl(np);
     std::vector<int> pblk_pt0(n_pblk), pblk_cnt(n_pblk);
+    // two-camera blocks: chunk of each pair camera (or -1), record of each lane (or -1)
+    std::vector<int> blk_chunk(2 * (size_t)n_blocks, -1), blk_rec((size_t)n_blocks * CH, -1);
+    int blk_base = 0;
     for (int p = 0; p < np; ++p) {
         const ProblemRange &r = ps->ranges[p];
         for (int q = 0; q < r.n_pblk; ++q) {
@@ -174,13 +245,18 @@ int build_set(dba_handle *h, int np, const dba_problem_desc *probs, ProblemSet *
         const dba_problem_desc &d = probs[p];
         const ProblemRange &r = ps->ranges[p];
         const long long L = d.n_obs;
-        // point-major records, stable in observation order
+        // point-major records, stable in observation order (two-camera
+        // blocks: a record per point copy, in block order within a point)
         std::vector<int> poff(d.n_points + 1, 0);
-        for (long long k = 0; k < L; ++k) ++poff[d.obs_point[k] + 1];
+        if (k2)
+            for (int pt : pbs[p].pts) ++poff[pt + 1];
+        else
+            for (long long k = 0; k < L; ++k) ++poff[d.obs_point[k] + 1];
         for (int i = 0; i < d.n_points; ++i) poff[i + 1] += poff[i];
         std::vector<int> fill(poff.begin(), poff.end() - 1);
-        std::vector<int> rec_obs(L);
-        for (long long k = 0; k < L; ++k) rec_obs[fill[d.obs_point[k]]++] = (int)k;
+        std::vector<int> rec_obs(k2 ? 0 : L);
+        if (!k2)
+            for (long long k = 0; k < L; ++k) rec_obs[fill[d.obs_point[k]]++] = (int)k;
         for (int i = 0; i <= d.n_points; ++i) pt_off[r.pt0 + i] = (int)(r.rec0 + poff[i]);
         for (int i = 0; i < d.n_points; ++i) {
             pt_prob[r.pt0 + i] = p;
@@ -192,6 +268,47 @@ int build_set(dba_handle *h, int np, const dba_problem_desc *probs, ProblemSet *
         std::vector<long long> cslot(d.n_cams);
         std::vector<int> cseen(d.n_cams, 0);
         int chunk = r.chunk0;
+        if (k2) {
+            // chunks camera-major: camera j's chunks are its pair's blocks that it observes
+            const PairBlocks &pb = pbs[p];
+            const int nb = (int)pb.cam0.size();
+            std::vector<int> brec(pb.pts.size());
+            for (size_t t = 0; t < pb.pts.size(); ++t) brec[t] = (int)(r.rec0 + fill[pb.pts[t]]++);
+            for (int b = 0; b < nb; ++b)
+                for (int l = 0; l < pb.npts[b]; ++l) {
+                    const int t = pb.pts0[b] + l;
+                    blk_rec[(size_t)(blk_base + b) * CH + l] = brec[t];
+                    const int i = pb.pts[t];
+                    xrec[brec[t]] = dba::PtCopy<R>{(R)d.points[3 * i], (R)d.points[3 * i + 1], (R)d.points[3 * i + 2]};
+                }
+            int b0 = 0;
+            for (int j = 0; j < d.n_cams; ++j) {
+                const int J = r.cam0 + j, sc = j & 1;
+                cam_prob[J] = p;
+                cam_chunk0[J] = chunk;
+                cam_count[J] = cc[j];
+                for (int c = 0; c < 9; ++c) cons_y[(size_t)J * dba::kConsY + c] = d.cams[9 * j + c];
+                if (sc == 0) b0 = (int)(std::lower_bound(pb.cam0.begin(), pb.cam0.end(), j) - pb.cam0.begin());
+                for (int b = b0; b < nb && pb.cam0[b] == j - sc; ++b) {
+                    if (!(pb.present[b] >> sc & 1)) continue;
+                    blk_chunk[2 * (size_t)(blk_base + b) + sc] = chunk;
+                    chunk_cam[chunk] = J;
+                    for (int l = 0; l < pb.npts[b]; ++l) {
+                        const int t = pb.pts0[b] + l;
+                        const long long k = pb.obs[2 * (size_t)t + sc];
+                        if (k < 0) continue;
+                        const long long sl = (long long)chunk * CH + l;
+                        pslot[sl] = brec[t];
+                        ptid[sl] = r.pt0 + pb.pts[t];
+                        orig[sl] = (int)k;
+                        uv[sl].x = (R)d.obs_uv[2 * k];
+                        uv[sl].y = (R)d.obs_uv[2 * k + 1];
+                    }
+                    ++chunk;
+                }
+            }
+            blk_base += nb;
+        } else
         for (int j = 0; j < d.n_cams; ++j) {
             const int J = r.cam0 + j;
             cam_prob[J] = p;
@@ -203,7 +320,7 @@ int build_set(dba_handle *h, int np, const dba_problem_desc *probs, ProblemSet *
             chunk += nch;
             for (int c = 0; c < 9; ++c) cons_y[(size_t)J * dba::kConsY + c] = d.cams[9 * j + c];
         }
-        for (long long rr = 0; rr < L; ++rr) {
+        for (long long rr = 0; rr < (k2 ? 0 : L); ++rr) {
             const int k = rec_obs[rr];
             const int j = d.obs_cam[k], i = d.obs_point[k];
             const int q = cseen[j]++;
@@ -300,6 +417,16 @@ int build_set(dba_handle *h, int np, const dba_problem_desc *probs, ProblemSet *
     HIP_TRY(h, B.alloc(&d_dual_yc, 9 * (size_t)n_chunks));
     HIP_TRY(h, hipMemcpy(d_copy_yc, copy_yc.data(), 9 * (size_t)n_chunks * sizeof(R), hipMemcpyHostToDevice));
     HIP_TRY(h, hipMemset(d_dual_yc, 0, 9 * (size_t)n_chunks * sizeof(double)));
+    int *d_blk_chunk = nullptr, *d_blk_rec = nullptr;
+    if (k2) {
+        HIP_TRY(h, B.alloc(&d_blk_chunk, blk_chunk.size()));
+        HIP_TRY(h, B.alloc(&d_blk_rec, blk_rec.size()));
+        HIP_TRY(h, hipMemcpy(d_blk_chunk, blk_chunk.data(), blk_chunk.size() * sizeof(int), hipMemcpyHostToDevice));
+        HIP_TRY(h, hipMemcpy(d_blk_rec, blk_rec.data(), blk_rec.size() * sizeof(int), hipMemcpyHostToDevice));
+    }
+    A.n_blocks2 = k2 ? n_blocks : 0;
+    A.blk_chunk = d_blk_chunk;
+    A.blk_rec = d_blk_rec;
     A.camera_blocks = h->opt.camera_blocks ? 1 : 0;
     A.copy_yc = d_copy_yc;
     A.dual_yc = d_dual_yc;
@@ -628,6 +755,7 @@ int dba_default_options(dba_options *o)
     o->block_points = 0;
     o->camera_model = DBA_CAMERA_ANGLE_AXIS;
     o->local_solver = DBA_SOLVER_LM;
+    o->block_cameras = 1;
     return DBA_OK;
 }
 
@@ -660,6 +788,8 @@ int dba_create(const dba_options *opt, dba_handle **out)
         return DBA_E_INVALID_ARG;
     if (o.local_solver != DBA_SOLVER_LM && (o.camera_blocks || o.start == DBA_START_LEARNED))
         return DBA_E_INVALID_ARG;
+    if (o.block_cameras != 1 && o.block_cameras != 2) return DBA_E_INVALID_ARG;
+    if (o.block_cameras == 2 && !o.camera_blocks) return DBA_E_INVALID_ARG;
     dba_handle *h = new dba_handle();
     h->opt = o;
     h->fp32 = o.precision == DBA_PREC_FP32_LOCAL;

@@ -79,6 +79,9 @@ struct DevArrays {
     int camera_blocks;    // 1: one camera copy per chunk (block local updates)
     R *copy_yc;           // [n_chunks][9] camera copy of the chunk (block local updates)
     double *dual_yc;      // [n_chunks][9] its scaled dual
+    int n_blocks2;        // two-camera blocks (0: none): one wavefront each
+    const int *blk_chunk; // [n_blocks2][2] chunk of the pair's first / second camera, or -1
+    const int *blk_rec;   // [n_blocks2][64] point record of each lane, or -1
     const uint8_t *mask;  // [n_slots] evaluation mask
     const int *slot_orig; // [n_slots] observation index within its problem
     // records

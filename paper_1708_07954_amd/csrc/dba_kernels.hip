@@ -262,6 +262,111 @@ __global__ __launch_bounds__(LocalBound<R>::threads) void k_local_block(DevArray
     for (int c = c0 + wave; c < c1; c += wpb) local_block<R, Cam>(a, sp, c, lane, lds[wave]);
 }
 
+// Two-camera block b on one wavefront: lane l holds the block's point copy l
+// (record blk_rec) and its observations in the chunks of the pair's cameras
+// (slot l of each); the camera copies and their duals are per chunk.
+template <typename R, typename Cam>
+__device__ __forceinline__ void local_block2(const DevArrays<R> &a, const SolverParams &sp, int b, int lane,
+                                             R *lds)
+{
+    using R2 = typename Vec<R>::R2;
+    const int ch[2] = {a.blk_chunk[2 * b], a.blk_chunk[2 * b + 1]};
+    const int present = (ch[0] >= 0 ? 1 : 0) | (ch[1] >= 0 ? 2 : 0);
+    const Ctrl *ct = a.ctrl + a.cam_prob[a.chunk_cam[ch[0] >= 0 ? ch[0] : ch[1]]];
+    const double rho_x = ct->rho_x, rho_y = ct->rho_y;
+    const double rat_x = ct->ratio_x, rat_y = ct->ratio_y;
+    const int pending = ct->pending;
+    double cy[18], uy[18];
+    R y[18], vy[18];
+#pragma unroll
+    for (int s = 0; s < 2; ++s) {
+#pragma unroll
+        for (int i = 0; i < 9; ++i) {
+            cy[9 * s + i] = uy[9 * s + i] = 0.0;
+            y[9 * s + i] = vy[9 * s + i] = R(0);
+        }
+        if (ch[s] < 0) continue;
+        const int J = a.chunk_cam[ch[s]];
+#pragma unroll
+        for (int i = 0; i < 9; ++i) {
+            const double c = a.cons_y[(long long)J * kConsY + i];
+            R t = a.copy_yc[(long long)ch[s] * 9 + i];
+            double u = a.dual_yc[(long long)ch[s] * 9 + i];
+            if (pending) u = (u + ((double)t - c)) * rat_y;
+            cy[9 * s + i] = c;
+            uy[9 * s + i] = u;
+            y[9 * s + i] = t;
+            vy[9 * s + i] = (R)(c - u);
+        }
+        if (pending && lane == 0)
+#pragma unroll
+            for (int i = 0; i < 9; ++i) a.dual_yc[(long long)ch[s] * 9 + i] = uy[9 * s + i];
+    }
+    const int ps = a.blk_rec[(long long)b * kChunk + lane];
+    bool act[2];
+    R z[4] = {R(0), R(0), R(0), R(0)};
+    int pid = 0;
+#pragma unroll
+    for (int s = 0; s < 2; ++s) {
+        const long long sl = (long long)(ch[s] >= 0 ? ch[s] : 0) * kChunk + lane;
+        act[s] = ch[s] >= 0 && ps >= 0 && a.pslot[sl] >= 0;
+        if (act[s]) {
+            const R2 zz = a.uv[sl];
+            z[2 * s] = zz.x;
+            z[2 * s + 1] = zz.y;
+            pid = a.ptid[sl];
+        }
+    }
+    R x[3] = {R(0), R(0), R(0)}, vx[3] = {R(0), R(0), R(0)};
+    if (ps >= 0) {
+        const double4 cx = a.cons_x[pid];
+        const double cxs[3] = {cx.x, cx.y, cx.z};
+        const PtCopy<R> xr = a.xrec[ps];
+        const PtDual ur = a.urec[ps];
+        x[0] = xr.x; x[1] = xr.y; x[2] = xr.z;
+        double u[3] = {ur.x, ur.y, ur.z};
+        if (pending) {
+#pragma unroll
+            for (int i = 0; i < 3; ++i) u[i] = (u[i] + ((double)x[i] - cxs[i])) * rat_x;
+            a.urec[ps] = PtDual{u[0], u[1], u[2]};
+        }
+#pragma unroll
+        for (int i = 0; i < 3; ++i) vx[i] = (R)(cxs[i] - u[i]);
+    }
+    block_lm2<R, Cam>(y, vy, present, x, vx, act, z, (R)rho_x, (R)rho_y, sp.loss, (R)sp.loss_param, sp.lm_steps,
+                      (R)sp.lambda0, lds, lane);
+    if (ps >= 0) a.xrec[ps] = PtCopy<R>{x[0], x[1], x[2]};
+    if (lane == 0)
+#pragma unroll
+        for (int s = 0; s < 2; ++s) {
+            if (ch[s] < 0) continue;
+            double *o = a.cpart + (long long)ch[s] * kCpart;
+            double q = 0.0;
+#pragma unroll
+            for (int i = 0; i < 9; ++i) {
+                a.copy_yc[(long long)ch[s] * 9 + i] = y[9 * s + i];
+                const double t = (double)y[9 * s + i];
+                const double dd = t - cy[9 * s + i];
+                o[i] = t + uy[9 * s + i];
+                o[9 + i] = dd;
+                q += dd * dd;
+            }
+            o[18] = q;
+        }
+}
+
+constexpr int kBlock2Threads = 256;
+
+template <typename R, typename Cam>
+__global__ __launch_bounds__(kBlock2Threads) void k_local_block2(DevArrays<R> a, SolverParams sp, int persistent)
+{
+    __shared__ R lds[kBlock2Threads / 64][kB2Lds];
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, wpb = blockDim.x >> 6;
+    int b0, b1;
+    chunk_range(a.n_blocks2, wpb, persistent, b0, b1);
+    for (int b = b0 + wave; b < b1; b += wpb) local_block2<R, Cam>(a, sp, b, lane, lds[wave]);
+}
+
 // Learned start: the workgroup's waves share the staged weights (one copy
 // per CU: 8 waves, 2 per SIMD); each wave has its own network I/O tile.  The
 // grid is persistent so the weights are staged once per workgroup.
@@ -616,6 +721,25 @@ template <typename R>
 hipError_t launch_local_block(const DevArrays<R> &a, const SolverParams &sp, int block_waves, int persistent,
                               int n_cu, hipStream_t s)
 {
+    if (a.n_blocks2 > 0) {
+        // two-camera blocks: one wavefront per block
+        if (64 * block_waves > kBlock2Threads) block_waves = kBlock2Threads / 64;
+        const int threads = 64 * block_waves;
+        int grid;
+        if (persistent) {
+            grid = n_cu * (4 / block_waves > 0 ? 4 / block_waves : 1);
+            const int need = (a.n_blocks2 + block_waves - 1) / block_waves;
+            if (grid > need) grid = need;
+        } else {
+            grid = (a.n_blocks2 + block_waves - 1) / block_waves;
+        }
+        if (grid < 1) grid = 1;
+        if (sp.camera == 1)
+            hipLaunchKernelGGL((k_local_block2<R, CamEuler>), dim3(grid), dim3(threads), 0, s, a, sp, persistent);
+        else
+            hipLaunchKernelGGL((k_local_block2<R, CamAA>), dim3(grid), dim3(threads), 0, s, a, sp, persistent);
+        return hipGetLastError();
+    }
     if (64 * block_waves > LocalBound<R>::threads) block_waves = LocalBound<R>::threads / 64;
     const int threads = 64 * block_waves;
     int grid;

@@ -1,0 +1,91 @@
+"""Blocks of two cameras (Sec. 3.1.4 with kappa = 2; block_cameras = 2): GPU
+against the oracle's general blocks (oracle.GeneralBlockADMM, the same
+partition: camera pairs, each pair's points in runs of block_points) on the
+same seeded scenes: FP64 within 1e-9, FP32 within 1e-3 and RMSE within 0.5 %;
+an odd camera count (a last pair of one camera), smaller runs, the Euler
+camera, batched = solo bitwise, and the option's validation."""
+import numpy as np
+import pytest
+
+import oracle
+from paper_1708_07954_amd import binding
+from scenes import make_sphere_scene, make_trajectory_scene
+from _util import param_rel_err
+
+pytestmark = pytest.mark.gpu
+
+CASES = {
+    "traj_huber": (lambda: make_trajectory_scene(seed=4, n_cams=40, n_points=900), "angle_axis", 64,
+                   dict(loss="huber", loss_param=2.0, rho=1e4), 8),
+    "traj_odd_cams_pi16": (lambda: make_trajectory_scene(seed=5, n_cams=41, n_points=800), "angle_axis", 16,
+                           dict(loss="huber", loss_param=2.0, rho=1e4), 8),
+    "sphere_student_t": (lambda: make_sphere_scene(seed=8, n_cams=12, n_points=300), "angle_axis", 64,
+                         dict(loss="student_t", loss_param=4.0, rho=1e3), 8),
+    "euler_l2": (lambda: make_sphere_scene(seed=9, n_cams=10, n_points=200, camera="euler"), "euler", 32,
+                 dict(loss="l2", loss_param=1.0, rho=1e4), 8),
+}
+
+
+def _oracle(sc, camera, pi, iters, **kw):
+    a = oracle.GeneralBlockADMM(oracle.Problem.from_scene(sc), sc.cams_init, sc.points_init, kappa=2, pi=pi,
+                                camera=camera, **kw)
+    a.iterate(iters)
+    return a
+
+
+def _gpu(sc, camera, pi, precision, iters, **kw):
+    s = binding.Solver(precision=precision, camera=camera, camera_blocks=True, block_cameras=2,
+                       block_points=0 if pi == 64 else pi, **kw).set_scene(sc)
+    s.iterate(iters)
+    return s
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+@pytest.mark.parametrize("case", sorted(CASES))
+def test_two_camera_blocks_parity(case, precision):
+    make, camera, pi, kw, iters = CASES[case]
+    sc = make()
+    a = _oracle(sc, camera, pi, iters, **kw)
+    s = _gpu(sc, camera, pi, precision, iters, **kw)
+    cams, pts = s.params()
+    err = param_rel_err(cams, pts, a.cons_y, a.cons_x)
+    r = s.residuals(want_rmse=True)
+    print(case, precision, "max rel err", err, "rmse", r["rmse"], a.stats()[0], "copies", a.n_copies, sc.n_obs)
+    if precision == "fp64":
+        assert err < 1e-9
+        assert r["rmse"] == pytest.approx(a.stats()[0], rel=1e-9)
+    else:
+        assert err < 1e-3
+        assert abs(r["rmse"] - a.stats()[0]) < 5e-3 * a.stats()[0]
+    s.close()
+
+
+def test_two_camera_blocks_batched_equals_solo_bitwise():
+    scenes = [make_trajectory_scene(seed=60 + q, n_cams=9 + 4 * q, n_points=200 + 60 * q) for q in range(3)]
+    kw = dict(precision="fp32", loss="huber", loss_param=2.0, rho=1e4, camera_blocks=True, block_cameras=2)
+    s = binding.Solver(**kw).set_scenes(scenes)
+    s.iterate(4)
+    for q, sc in enumerate(scenes):
+        solo = binding.Solver(**kw).set_scene(sc)
+        solo.iterate(4)
+        a, b = s.params(q), solo.params()
+        assert np.array_equal(a[0], b[0]) and np.array_equal(a[1], b[1])
+        solo.close()
+    s.close()
+
+
+def test_two_camera_blocks_validation():
+    with pytest.raises(binding.DbaError) as e:
+        binding.Solver(precision="fp64", block_cameras=2)
+    assert e.value.status == "DBA_E_INVALID_ARG"
+    with pytest.raises(binding.DbaError) as e:
+        binding.Solver(precision="fp64", camera_blocks=True, block_cameras=3)
+    assert e.value.status == "DBA_E_INVALID_ARG"
+    # a camera observing a point twice cannot be held by a lane
+    sc = make_trajectory_scene(seed=4, n_cams=10, n_points=100)
+    oc, op, uv = (np.concatenate([a, a[:1]]) for a in (sc.obs_cam, sc.obs_point, sc.obs_uv))
+    s = binding.Solver(precision="fp64", camera_blocks=True, block_cameras=2)
+    with pytest.raises(binding.DbaError) as e:
+        binding.dba_set_problem(s.h, sc.n_cams, sc.n_points, oc, op, uv, sc.cams_init, sc.points_init)
+    assert e.value.status == "DBA_E_INVALID_ARG"
+    s.close()

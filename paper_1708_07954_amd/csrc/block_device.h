@@ -320,13 +320,6 @@ __device__ __forceinline__ void block_lm(R *th, const R *vy, const R *vx, R z0, 
 
 // Packed upper triangle of a symmetric 18x18 matrix: index of (i, j), i <= j.
 __host__ __device__ constexpr int sym18(int i, int j) { return i * 18 - i * (i - 1) / 2 + (j - i); }
-__host__ __device__ constexpr int row18(int t)
-{
-    int i = 0;
-    while (i < 17 && sym18(i + 1, i + 1) <= t) ++i;
-    return i;
-}
-__host__ __device__ constexpr int col18(int t) { return row18(t) + (t - sym18(row18(t), row18(t))); }
 
 constexpr int kB2Sys = 171;                 // packed 18x18
 constexpr int kB2Rhs = kB2Sys;              // 18: reduced right-hand side (ng_y - sum W B ng_x)
@@ -361,19 +354,19 @@ __device__ __forceinline__ void wave_reduce_to(const T *b, T *dst, int lane)
 // LDL^T of the packed symmetric 18x18 matrix a (LDS, in place: row j keeps D_j
 // on the diagonal and L_ij, i > j, at (j, i)); false if a pivot is not
 // positive and finite.  Column j: the trailing update a_ik -= a_ji a_jk / D_j
-// over the lanes, then the row is scaled.
+// over the lanes (rc: row and column of each packed index, in LDS), then the
+// row is scaled.
 template <typename R>
-__device__ __forceinline__ bool ldl18_lds(R *a, int lane)
+__device__ __forceinline__ bool ldl18_lds(R *a, const unsigned char *rc, int lane)
 {
     bool ok = true;
     for (int j = 0; j < 18; ++j) {
         const R d = a[sym18(j, j)];
         ok = ok && (d > R(0)) && (d < Num<R>::inf);
         const R rd = Num<R>::rcp(d);
-        const int t0 = sym18(j + 1 < 18 ? j + 1 : 17, j + 1 < 18 ? j + 1 : 17);
         if (j + 1 < 18)
-            for (int t = t0 + lane; t < kB2Sys; t += 64) {
-                const int i = row18(t), k = col18(t);
+            for (int t = sym18(j + 1, j + 1) + lane; t < kB2Sys; t += 64) {
+                const int i = rc[2 * t], k = rc[2 * t + 1];
                 a[t] -= a[sym18(j, i)] * a[sym18(j, k)] * rd;
             }
         wave_lds_sync();
@@ -413,7 +406,7 @@ __device__ __forceinline__ void ldl18_solve(const R *a, const R *b, R *x)
 template <typename R, typename Cam>
 __device__ __forceinline__ void block_lm2(R *y, const R *vy, int present, R *x, const R *vx, const bool *act,
                                           const R *z, R rx, R ry, int kind, R lp, int steps, R lam, R *lds,
-                                          int lane)
+                                          const unsigned char *rc, int lane)
 {
     using P = decltype(proj_core<R, true>(y, Cam{}));
     R *red = lds, *scr = lds + 256;
@@ -564,33 +557,39 @@ __device__ __forceinline__ void block_lm2(R *y, const R *vy, int present, R *x, 
 #pragma unroll
                 for (int j = 0; j < 9; ++j) Q[p][a][j] = M[a][0] * U[t][0][j] + M[a][1] * U[t][1][j];
         }
-        // the lane's 226 values, in four batches of 64, reduced into LDS
-        auto val = [&](int t) -> R {
-            if (t < kB2Sys) {
-                const int i = row18(t), j = col18(t), s = i / 9, u = j / 9, p = s + u;
-                return U[s][0][i % 9] * Q[p][0][j % 9] + U[s][1][i % 9] * Q[p][1][j % 9];
-            }
-            if (t < kB2Ngy) {
-                const int i = t - kB2Rhs, s = i / 9;
-                return U[s][0][i % 9] * r[s][0] + U[s][1][i % 9] * r[s][1];
-            }
-            if (t < kB2Hd) {
-                const int i = t - kB2Ngy, s = i / 9;
-                return c2[s] * (U[s][0][i % 9] * e[s][0] + U[s][1][i % 9] * e[s][1]);
-            }
-            if (t < kB2Fres) {
-                const int i = t - kB2Hd, s = i / 9;
-                return c2[s] * (U[s][0][i % 9] * U[s][0][i % 9] + U[s][1][i % 9] * U[s][1][i % 9]);
-            }
-            return t == kB2Fres ? fr : R(0);
+        // the lane's 226 values streamed in index order into four batches of
+        // 64, each reduced into LDS as it fills
+        R b32[32];
+        auto put = [&](int t, R v) {
+            if (t % 64 == 0 && t > 0) wave_reduce_to<R>(b32, red + t - 64, lane);
+            rs_first_put<R>(b32, t % 64, v);
         };
 #pragma unroll
-        for (int q = 0; q < 4; ++q) {
-            R b32[32];
+        for (int i = 0; i < 18; ++i)
 #pragma unroll
-            for (int t = 0; t < 64; ++t) rs_first_put<R>(b32, t, val(64 * q + t));
-            wave_reduce_to<R>(b32, red + 64 * q, lane);
+            for (int j = i; j < 18; ++j) {
+                const int s = i / 9, u = j / 9;
+                put(sym18(i, j), U[s][0][i % 9] * Q[s + u][0][j % 9] + U[s][1][i % 9] * Q[s + u][1][j % 9]);
+            }
+#pragma unroll
+        for (int i = 0; i < 18; ++i) {
+            const int s = i / 9;
+            put(kB2Rhs + i, U[s][0][i % 9] * r[s][0] + U[s][1][i % 9] * r[s][1]);
         }
+#pragma unroll
+        for (int i = 0; i < 18; ++i) {
+            const int s = i / 9;
+            put(kB2Ngy + i, c2[s] * (U[s][0][i % 9] * e[s][0] + U[s][1][i % 9] * e[s][1]));
+        }
+#pragma unroll
+        for (int i = 0; i < 18; ++i) {
+            const int s = i / 9;
+            put(kB2Hd + i, c2[s] * (U[s][0][i % 9] * U[s][0][i % 9] + U[s][1][i % 9] * U[s][1][i % 9]));
+        }
+        put(kB2Fres, fr);
+#pragma unroll
+        for (int t = kB2Vals; t < 256; ++t) put(t, R(0));
+        wave_reduce_to<R>(b32, red + 192, lane);
         wave_lds_sync();
         const R fres = F + red[kB2Fres];
         // the camera system: penalty and damping on the diagonal, absent cameras fixed
@@ -605,7 +604,7 @@ __device__ __forceinline__ void block_lm2(R *y, const R *vy, int present, R *x, 
             }
         }
         wave_lds_sync();
-        const bool oky = ldl18_lds<R>(red, lane);
+        const bool oky = ldl18_lds<R>(red, rc, lane);
         R dy[18];
         ldl18_solve<R>(red, red + kB2Rhs, dy);
         const bool ok = oky && (__ballot(!okx) == 0ull);

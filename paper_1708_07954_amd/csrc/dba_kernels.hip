@@ -267,7 +267,7 @@ __global__ __launch_bounds__(LocalBound<R>::threads) void k_local_block(DevArray
 // (slot l of each); the camera copies and their duals are per chunk.
 template <typename R, typename Cam>
 __device__ __forceinline__ void local_block2(const DevArrays<R> &a, const SolverParams &sp, int b, int lane,
-                                             R *lds)
+                                             R *lds, const unsigned char *rc)
 {
     using R2 = typename Vec<R>::R2;
     const int ch[2] = {a.blk_chunk[2 * b], a.blk_chunk[2 * b + 1]};
@@ -334,7 +334,7 @@ __device__ __forceinline__ void local_block2(const DevArrays<R> &a, const Solver
         for (int i = 0; i < 3; ++i) vx[i] = (R)(cxs[i] - u[i]);
     }
     block_lm2<R, Cam>(y, vy, present, x, vx, act, z, (R)rho_x, (R)rho_y, sp.loss, (R)sp.loss_param, sp.lm_steps,
-                      (R)sp.lambda0, lds, lane);
+                      (R)sp.lambda0, lds, rc, lane);
     if (ps >= 0) a.xrec[ps] = PtCopy<R>{x[0], x[1], x[2]};
     if (lane == 0)
 #pragma unroll
@@ -361,10 +361,19 @@ template <typename R, typename Cam>
 __global__ __launch_bounds__(kBlock2Threads) void k_local_block2(DevArrays<R> a, SolverParams sp, int persistent)
 {
     __shared__ R lds[kBlock2Threads / 64][kB2Lds];
+    __shared__ unsigned char rc[2 * kB2Sys];
+    // row and column of every packed index of the 18x18 system
+    for (int t = threadIdx.x; t < kB2Sys; t += blockDim.x) {
+        int i = 0;
+        while (i < 17 && sym18(i + 1, i + 1) <= t) ++i;
+        rc[2 * t] = (unsigned char)i;
+        rc[2 * t + 1] = (unsigned char)(i + (t - sym18(i, i)));
+    }
+    __syncthreads();
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, wpb = blockDim.x >> 6;
     int b0, b1;
     chunk_range(a.n_blocks2, wpb, persistent, b0, b1);
-    for (int b = b0 + wave; b < b1; b += wpb) local_block2<R, Cam>(a, sp, b, lane, lds[wave]);
+    for (int b = b0 + wave; b < b1; b += wpb) local_block2<R, Cam>(a, sp, b, lane, lds[wave], rc);
 }
 
 // Learned start: the workgroup's waves share the staged weights (one copy

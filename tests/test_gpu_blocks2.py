@@ -89,3 +89,41 @@ def test_two_camera_blocks_validation():
         binding.dba_set_problem(s.h, sc.n_cams, sc.n_points, oc, op, uv, sc.cams_init, sc.points_init)
     assert e.value.status == "DBA_E_INVALID_ARG"
     s.close()
+
+
+@pytest.mark.parametrize("precision,tol", [("fp32", 1e-3), ("fp64", 1e-9)])
+def test_two_camera_blocks_full_size_first_iteration_sampled(precision, tol):
+    """The 2M-observation trajectory with two-camera blocks of 64 points and 5 LM
+    steps, in the benchmark's launch configuration: after one iteration the copies
+    of 24 sampled blocks against the oracle's solve of each block from the same
+    start (copies at the initial estimate, duals zero)."""
+    from scenes import make_config2
+    sc = make_config2()
+    kw = dict(loss="huber", loss_param=2.0, rho=1e5)
+    s = binding.Solver(precision=precision, camera_blocks=True, block_cameras=2, rho_balancing=True, rho_min=1e5,
+                       rho_max=1e7, block_waves=1, persistent=0, **kw).set_scene(sc)
+    s.iterate(1)
+    copies, _ = s.state()
+    s.close()
+    blocks = oracle.make_general_blocks(sc.obs_cam, sc.obs_point, sc.n_cams, 2, 64)
+    rng = np.random.default_rng(0)
+    opts = oracle.make_opts("huber", 2.0)
+    worst = 0.0
+    for b in rng.choice(len(blocks), 24, replace=False):
+        cams, pts, obs = blocks[b]
+        oc = np.ascontiguousarray(np.searchsorted(cams, sc.obs_cam[obs]), dtype=np.int32)
+        op = np.ascontiguousarray(np.searchsorted(pts, sc.obs_point[obs]), dtype=np.int32)
+        z = np.ascontiguousarray(sc.obs_uv[obs])
+        vy = np.ascontiguousarray(sc.cams_init[cams].ravel())
+        vx = np.ascontiguousarray(sc.points_init[pts].ravel())
+        th = np.concatenate([vy, vx])
+        oracle.lib().orc_gblock_local_solve(opts, len(cams), len(pts), len(obs), oracle._i(oc), oracle._i(op),
+                                            oracle._d(z), oracle._d(vy), oracle._d(vx), oracle._d(th), 1e5, 1e5, 5)
+        ty = th[:9 * len(cams)].reshape(-1, 9)
+        tx = th[9 * len(cams):].reshape(-1, 3)
+        got_y, got_x = copies[obs, :9], copies[obs, 9:]
+        scale_y = np.maximum(np.abs(ty[oc]), np.r_[np.ones(7), 1e-2, 1e-2])
+        e = max((np.abs(got_y - ty[oc]) / scale_y).max(), (np.abs(got_x - tx[op]) / np.maximum(np.abs(tx[op]), 1.0)).max())
+        worst = max(worst, e)
+    print(precision, "sampled two-camera blocks, max rel err of the copies", worst)
+    assert worst < tol

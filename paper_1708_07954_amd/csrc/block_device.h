@@ -527,15 +527,11 @@ __device__ __forceinline__ void block_lm2(R *y, const R *vy, int present, R *x, 
             o[1] = B[1] * v[0] + B[3] * v[1] + B[4] * v[2];
             o[2] = B[2] * v[0] + B[4] * v[1] + B[5] * v[2];
         };
-        R BV[2][2][3], Bn[3];
-#pragma unroll
-        for (int s = 0; s < 2; ++s)
-#pragma unroll
-            for (int a = 0; a < 2; ++a) bmul(V[s][a], BV[s][a]);
+        R Bn[3];
         bmul(ngx, Bn);
-        // M_st = delta_st c_s I - c_s c_t V_s^T B V_t (2x2 blocks), Q_st = M_st U_t^T;
-        // r_s = c_s (e_s - V_s^T B ng_x)
-        R Q[3][2][9], r[2][2];
+        // M_st = delta_st c_s I - c_s c_t V_s^T B V_t (2x2 blocks, pairs st =
+        // 00, 01, 11); r_s = c_s (e_s - V_s^T B ng_x)
+        R M[3][2][2], r[2][2];
 #pragma unroll
         for (int s = 0; s < 2; ++s)
 #pragma unroll
@@ -544,18 +540,15 @@ __device__ __forceinline__ void block_lm2(R *y, const R *vy, int present, R *x, 
 #pragma unroll
         for (int p = 0; p < 3; ++p) {
             const int s = p == 2 ? 1 : 0, t = p == 0 ? 0 : 1;
-            R M[2][2];
 #pragma unroll
             for (int a = 0; a < 2; ++a)
 #pragma unroll
                 for (int b = 0; b < 2; ++b) {
-                    const R g = V[s][a][0] * BV[t][b][0] + V[s][a][1] * BV[t][b][1] + V[s][a][2] * BV[t][b][2];
-                    M[a][b] = (s == t && a == b ? c2[s] : R(0)) - c2[s] * c2[t] * g;
+                    R bv[3];
+                    bmul(V[t][b], bv);
+                    const R g = V[s][a][0] * bv[0] + V[s][a][1] * bv[1] + V[s][a][2] * bv[2];
+                    M[p][a][b] = (s == t && a == b ? c2[s] : R(0)) - c2[s] * c2[t] * g;
                 }
-#pragma unroll
-            for (int a = 0; a < 2; ++a)
-#pragma unroll
-                for (int j = 0; j < 9; ++j) Q[p][a][j] = M[a][0] * U[t][0][j] + M[a][1] * U[t][1][j];
         }
         // the lane's 226 values streamed in index order into four batches of
         // 64, each reduced into LDS as it fills
@@ -568,8 +561,10 @@ __device__ __forceinline__ void block_lm2(R *y, const R *vy, int present, R *x, 
         for (int i = 0; i < 18; ++i)
 #pragma unroll
             for (int j = i; j < 18; ++j) {
-                const int s = i / 9, u = j / 9;
-                put(sym18(i, j), U[s][0][i % 9] * Q[s + u][0][j % 9] + U[s][1][i % 9] * Q[s + u][1][j % 9]);
+                const int s = i / 9, u = j / 9, p = s + u;
+                const R q0 = M[p][0][0] * U[u][0][j % 9] + M[p][0][1] * U[u][1][j % 9];
+                const R q1 = M[p][1][0] * U[u][0][j % 9] + M[p][1][1] * U[u][1][j % 9];
+                put(sym18(i, j), U[s][0][i % 9] * q0 + U[s][1][i % 9] * q1);
             }
 #pragma unroll
         for (int i = 0; i < 18; ++i) {

@@ -104,7 +104,10 @@ def kernel_source_hash():
 # committed counter summary of each workload's local-solve kernel
 COUNTER_SUMMARIES = {"trajectory": "local_solve_trajectory_counters.md",
                      "trajectory_blocks": "block_local_trajectory.md",
-                     "trajectory_euler": "kernels_trajectory_euler_2M.md"}
+                     "trajectory_euler": "kernels_trajectory_euler_2M.md",
+                     "sphere": "kernels_sphere_230k.md",
+                     "sphere_fp64": "kernels_sphere_230k.md",
+                     "ring": "kernels_ring_2k.md"}
 
 
 def recorded_traffic(workload):
@@ -117,7 +120,9 @@ def recorded_traffic(workload):
         return None, None
     text = open(path).read()
     src = re.search(r"kernel_source_hash:\s*(\w+)", text)
-    tb = re.search(r"traffic_bytes_per_launch:\s*([0-9.eE+]+)", text)
+    # a summary covering several workloads keys each figure by workload name
+    tb = (re.search(r"traffic_bytes_per_launch\[" + re.escape(workload) + r"\]:\s*([0-9.eE+]+)", text)
+          or re.search(r"traffic_bytes_per_launch:\s*([0-9.eE+]+)", text))
     if not src or not tb or src.group(1) != kernel_source_hash():
         return None, None
     return float(tb.group(1)), path

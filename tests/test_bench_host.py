@@ -40,7 +40,7 @@ def test_cost_model_figures():
 def test_kernel_source_hash_and_recorded_traffic(monkeypatch):
     h = bench.kernel_source_hash()
     assert len(h) == 12 and int(h, 16) >= 0
-    for wl in ("trajectory", "trajectory_blocks", "trajectory_euler"):
+    for wl in ("trajectory", "trajectory_blocks", "trajectory_euler", "sphere", "sphere_fp64"):
         value, _ = bench.recorded_traffic(wl)
         with open(os.path.join(ROOT, "profiles", bench.COUNTER_SUMMARIES[wl])) as fh:
             recorded_hash = [l.split(":")[1].strip() for l in fh if l.startswith("kernel_source_hash:")][0]
@@ -49,6 +49,9 @@ def test_kernel_source_hash_and_recorded_traffic(monkeypatch):
         else:
             assert value is None
     assert bench.recorded_traffic("batched") == (None, None)
+    # one summary, a figure per workload
+    if bench.recorded_traffic("sphere")[0] is not None:
+        assert bench.recorded_traffic("sphere")[0] < bench.recorded_traffic("sphere_fp64")[0]
     # a kernel change voids the recorded figure
     monkeypatch.setattr(bench, "kernel_source_hash", lambda: "000000000000")
     assert bench.recorded_traffic("trajectory")[0] is None

@@ -107,7 +107,10 @@ COUNTER_SUMMARIES = {"trajectory": "local_solve_trajectory_counters.md",
                      "trajectory_euler": "kernels_trajectory_euler_2M.md",
                      "sphere": "kernels_sphere_230k.md",
                      "sphere_fp64": "kernels_sphere_230k.md",
-                     "ring": "kernels_ring_2k.md"}
+                     "ring": "kernels_ring_2k.md",
+                     "batched": "kernels_batched_3M.md",
+                     "trajectory_blocks2": "block2_local_trajectory.md",
+                     "trajectory_shard8": "kernels_trajectory_shard8.md"}
 
 
 def recorded_traffic(workload):

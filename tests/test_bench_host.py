@@ -40,15 +40,16 @@ def test_cost_model_figures():
 def test_kernel_source_hash_and_recorded_traffic(monkeypatch):
     h = bench.kernel_source_hash()
     assert len(h) == 12 and int(h, 16) >= 0
-    for wl in ("trajectory", "trajectory_blocks", "trajectory_euler", "sphere", "sphere_fp64"):
+    for wl in ("trajectory", "trajectory_blocks", "trajectory_blocks2", "trajectory_euler", "trajectory_shard8",
+               "sphere", "sphere_fp64", "ring", "batched"):
         value, _ = bench.recorded_traffic(wl)
         with open(os.path.join(ROOT, "profiles", bench.COUNTER_SUMMARIES[wl])) as fh:
             recorded_hash = [l.split(":")[1].strip() for l in fh if l.startswith("kernel_source_hash:")][0]
         if recorded_hash == h:
-            assert value is not None and 1e8 < value < 2e9
+            assert value is not None and 1e6 < value < 2e9
         else:
             assert value is None
-    assert bench.recorded_traffic("batched") == (None, None)
+    assert bench.recorded_traffic("no_such_workload") == (None, None)
     # one summary, a figure per workload
     if bench.recorded_traffic("sphere")[0] is not None:
         assert bench.recorded_traffic("sphere")[0] < bench.recorded_traffic("sphere_fp64")[0]

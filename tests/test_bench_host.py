@@ -64,3 +64,19 @@ def test_workload_scenes():
     (shard,) = bench.make_scenes("config2_shard8")
     assert shard.n_points == 25000 and shard.n_cams == 1000
     assert shard.meta["n_ranks"] == 8 and shard.meta["rank"] == 0
+
+
+def test_profile_summaries_name_their_commands():
+    """Each committed profile summary gives the rocprofv3 command that made it,
+    runs committed files only, and states the kernel source hash it was taken
+    on; every summary the benchmark reads traffic from exists."""
+    d = os.path.join(ROOT, "profiles")
+    names = sorted(f for f in os.listdir(d) if f.endswith(".md"))
+    assert names
+    for f in names:
+        text = open(os.path.join(d, f)).read()
+        assert "rocprofv3" in text and "bench.py" in text, f
+        assert "_work/" not in text, f
+        assert "kernel_source_hash" in text, f
+    for wl, f in bench.COUNTER_SUMMARIES.items():
+        assert wl in bench.WORKLOADS and f in names, (wl, f)

@@ -228,8 +228,16 @@ def test_local_lm_is_monotone_and_reaches_a_stationary_point(loss, param, rho):
     for z, v, th0 in _local_cases(rho):
         g0, H0 = _gradient(opts, z, v, th0, rho, True)
         th, acc, tr = oracle.local_solve(opts, z, v, th0, rho, rho, steps=60)
-        # F never increases beyond rounding (steps the model accepts are tiny)
-        assert np.all(np.diff(tr) <= 1e-9 * (1 + tr[:-1])), tr
+        # F rises only on a step accepted on the model's word, whose predicted
+        # decrease is below the tie threshold 1e-13 of F's resolution
+        # F + |e| (|z1| + |z2| + f) at the step's start (R4): a rise is
+        # bounded by that threshold (plus F's own rounding, far below it)
+        fres = []
+        for k in range(61):
+            tk = oracle.local_solve(opts, z, v, th0, rho, rho, steps=k)[0]
+            e = z - oracle.project(tk[:9], tk[9:])[0]
+            fres.append(tr[k] + np.linalg.norm(e) * (abs(z[0]) + abs(z[1]) + abs(tk[6])))
+        assert np.all(np.diff(tr) <= 1e-13 * np.array(fres[:-1])), tr
         g, H = _gradient(opts, z, v, th, rho, True)
         # Newton decrement g^T H^-1 g: the decrease a further step could still
         # bring; the acceptance rule resolves decreases down to 1e-12 F
@@ -387,6 +395,59 @@ def test_noise_free_perturbed_problem_converges():
     r0 = a.stats()[0]
     a.iterate(300)
     assert a.stats()[0] < 2e-2 * r0
+
+
+# ----------------------------------------------------------------- reprojection statistics (R8)
+
+def _stats_by_hand(scene, cams, pts, mask, loss, param, camera="angle_axis"):
+    """RMSE over all observations, RMSE over the masked ones, robust cost
+    sum phi(|e|^2) and mean |e|, written with scipy rotations and the loss
+    definitions of R2 -- nothing of the oracle."""
+    oc, op, z = scene.obs_cam, scene.obs_point, scene.obs_uv
+    if camera == "euler":
+        P = Rotation.from_euler("xyz", cams[oc, :3]).apply(pts[op]) + cams[oc, 3:6]
+        uv = cams[oc, 6:7] * P[:, :2] / P[:, 2:3]
+    else:
+        P = Rotation.from_rotvec(cams[oc, :3]).apply(pts[op]) + cams[oc, 3:6]
+        q = P[:, :2] / P[:, 2:3]
+        r2 = (q * q).sum(1)
+        uv = cams[oc, 6:7] * (1 + cams[oc, 7] * r2 + cams[oc, 8] * r2 * r2)[:, None] * q
+    s = ((z - uv) ** 2).sum(1)
+    if loss == "l2":
+        phi = s
+    elif loss == "huber":
+        phi = np.where(s <= param ** 2, s, 2 * param * np.sqrt(s) - param ** 2)
+    else:
+        phi = param * np.log1p(s / param)
+    m = np.ones(len(s), bool) if mask is None else mask
+    return np.array([np.sqrt(s.mean()), np.sqrt(s[m].mean()), phi.sum(), np.sqrt(s).mean()])
+
+
+@pytest.mark.parametrize("camera", ["angle_axis", "euler"])
+@pytest.mark.parametrize("loss,param", [("l2", 1.0), ("huber", 2.0), ("student_t", 4.0)])
+def test_reprojection_stats_recomputed_independently(camera, loss, param):
+    """The statistics that every RMSE comparison rests on (R8, and the inlier
+    RMSE of the outlier workloads): at the ground truth, the perturbed start
+    and a random estimate, each of the four numbers equals its definition
+    evaluated in numpy; the outlier mask selects the inliers, not the
+    outliers."""
+    sc = make_config2(n_cams=30, n_points=300, camera=camera)
+    p = oracle.Problem.from_scene(sc)
+    rng = np.random.default_rng(11)
+    rand_c = sc.cams_init.copy()
+    rand_c[:, :6] += rng.normal(0, 1e-2, (sc.n_cams, 6))
+    rand_p = sc.points_init + rng.normal(0, 0.3, sc.points_init.shape)
+    inl = ~sc.outlier
+    assert 0 < sc.outlier.sum() < sc.n_obs
+    for cams, pts in [(sc.cams_gt, sc.points_gt), (sc.cams_init, sc.points_init), (rand_c, rand_p)]:
+        for mask in (None, inl):
+            got = oracle.reprojection_stats(p, cams, pts, mask, loss, param, camera)
+            ref = _stats_by_hand(sc, cams, pts, mask, loss, param, camera)
+            np.testing.assert_allclose(got, ref, rtol=1e-12, atol=0)
+        # the outliers (uniform over the image) dominate the all-observation
+        # RMSE: a mask read the wrong way round would raise, not lower, it
+        full = oracle.reprojection_stats(p, cams, pts, inl, loss, param, camera)
+        assert full[1] < full[0]
 
 
 def _minpack_lm(scene, loss, delta):

@@ -143,10 +143,15 @@ def test_admm_reaches_the_centralised_lm_optimum():
     lm = oracle.reprojection_stats(p, cams, pts, None, "l2", 1.0, "euler")
     a = oracle.ADMM(p, s.cams_init, s.points_init, loss="l2", loss_param=1.0, rho=1e4, camera="euler")
     init = a.stats()
-    a.iterate(400)
+    # run until both residual norms are below 1e-9 (about 3 000 iterations)
+    for _ in range(60):
+        tr = a.iterate(100)
+        if tr[-1, 0] < 1e-9 and tr[-1, 1] < 1e-9:
+            break
+    assert tr[-1, 0] < 1e-9 and tr[-1, 1] < 1e-9, (a.iteration, tr[-1])
     ad = a.stats()
     assert init[0] > 10 * lm[0]
-    assert abs(ad[0] - lm[0]) < 5e-3 * lm[0], (ad[0], lm[0])
+    assert abs(ad[0] - lm[0]) < 1e-6 * lm[0], (ad[0], lm[0])
     np.testing.assert_allclose(a.cons_y[:, 6:], s.cams_init[:, 6:], rtol=0, atol=0)
 
 

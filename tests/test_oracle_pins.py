@@ -13,7 +13,7 @@ from scipy.optimize import minimize
 from scipy.spatial.transform import Rotation
 
 import oracle
-from scenes import make_config0, make_config2, make_ring_scene
+from scenes import make_config0, make_config2, make_ring_scene, make_sphere_scene
 
 F0 = 800.0
 
@@ -483,8 +483,17 @@ def _minpack_lm(scene, loss, delta):
 def test_admm_reaches_the_centralised_lm_optimum(loss, delta):
     """At an ADMM fixed point every copy equals its consensus and the duals
     cancel, so the consensus is a stationary point of the centralised
-    objective: its RMSE must approach the one brute-force LM reaches.
-    (ADMM is first-order; here it gets within the 0.5 % RMSE tolerance.)"""
+    objective: its RMSE must approach the one brute-force LM reaches.  With
+    the 9-parameter camera (focal length and distortion unknown per camera)
+    ADMM, a first-order method, crawls along the nearly flat valley that
+    focal length, depth and distortion form on such narrow-field scenes (on
+    a 5-camera, 10-point ring, 200 000 iterations at rho = 1e3 leave the dual
+    residual at 5e-2 and the RMSE 3.4 % above MINPACK's, still falling), so
+    this case holds it to the 0.5 % RMSE tolerance after 1 000 iterations;
+    the paper's own camera, whose focal length is known, is held
+    to 1e-6 at residual norms below 1e-9
+    (test_admm_converges_to_the_centralised_optimum_on_the_papers_problem_size
+    and the Euler-camera pins)."""
     s = make_ring_scene(seed=7, n_cams=8, n_points=100, box=3.0, radius=8.0)
     p = oracle.Problem.from_scene(s)
     cams, pts = _minpack_lm(s, loss, delta)
@@ -496,6 +505,65 @@ def test_admm_reaches_the_centralised_lm_optimum(loss, delta):
     assert init[0] > 10 * lm[0]
     assert abs(ad[0] - lm[0]) < 5e-3 * lm[0], (ad[0], lm[0])
     assert abs(ad[2] - lm[2]) < 1e-2 * lm[2], (ad[2], lm[2])
+
+
+def _minpack_lm_camera(scene, loss, delta, camera):
+    """MINPACK LM on the centralised objective (Eq. 2 with phi_m) for either
+    camera: the paper's Euler camera of Eq. 1 optimises its 6 pose
+    parameters (focal length known), the 9-parameter camera all 9; residuals
+    with scipy rotations, as in _minpack_lm."""
+    from scipy.optimize import least_squares
+    if camera != "euler":
+        return _minpack_lm(scene, loss, delta)
+    m, n = scene.n_cams, scene.n_points
+    oc, op, z = scene.obs_cam, scene.obs_point, scene.obs_uv
+    f = scene.cams_init[:, 6]
+
+    def res(th):
+        cams = th[:6 * m].reshape(m, 6)
+        pts = th[6 * m:].reshape(n, 3)
+        P = Rotation.from_euler("xyz", cams[oc, :3]).apply(pts[op]) + cams[oc, 3:6]
+        e = z - f[oc, None] * P[:, :2] / P[:, 2:3]
+        if loss == "huber":
+            s = (e * e).sum(1)
+            phi = np.where(s <= delta ** 2, s, 2 * delta * np.sqrt(s) - delta ** 2)
+            e = e * np.sqrt(np.where(s > 0, phi / np.maximum(s, 1e-300), 1.0))[:, None]
+        return e.ravel()
+
+    x0 = np.concatenate([scene.cams_init[:, :6].ravel(), scene.points_init.ravel()])
+    r = least_squares(res, x0, method="lm", xtol=1e-15, ftol=1e-15, gtol=1e-15, max_nfev=100000)
+    cams = scene.cams_init.copy()
+    cams[:, :6] = r.x[:6 * m].reshape(m, 6)
+    return cams, r.x[6 * m:].reshape(n, 3)
+
+
+@pytest.mark.parametrize("loss,delta", [("l2", 1.0), ("huber", 2.0)])
+@pytest.mark.parametrize("rho", [1e3, 1e4])
+def test_admm_converges_to_the_centralised_optimum_on_the_papers_problem_size(loss, delta, rho):
+    """The paper's synthetic problem size (5 cameras, 10 points, all 50
+    observations) with its camera (Eq. 1, focal length known): ADMM run
+    until both residual norms are below 1e-9 ends at a stationary point of
+    the centralised objective, the one MINPACK's Levenberg-Marquardt reaches
+    from the same start: reprojection RMSE and robust cost within 1e-6
+    relative, and every copy equal to its consensus."""
+    s = make_sphere_scene(seed=7, n_cams=5, n_points=10, radius=8.0, box=3.0, k_lo=5, k_hi=5, camera="euler")
+    assert s.n_obs == 50
+    p = oracle.Problem.from_scene(s)
+    cams, pts = _minpack_lm_camera(s, loss, delta, "euler")
+    lm = oracle.reprojection_stats(p, cams, pts, None, loss, delta, "euler")
+    a = _admm(s, loss=loss, loss_param=delta, rho=rho, camera="euler")
+    init = a.stats()
+    for _ in range(200):
+        tr = a.iterate(100)
+        if tr[-1, 0] < 1e-9 and tr[-1, 1] < 1e-9:
+            break
+    assert tr[-1, 0] < 1e-9 and tr[-1, 1] < 1e-9, (a.iteration, tr[-1])
+    ad = a.stats()
+    assert init[0] > 10 * lm[0]
+    assert abs(ad[0] - lm[0]) < 1e-6 * lm[0], (ad[0], lm[0])
+    assert abs(ad[2] - lm[2]) < 1e-6 * lm[2], (ad[2], lm[2])
+    cons = np.concatenate([a.cons_y[p.obs_cam], a.cons_x[p.obs_point]], axis=1)
+    assert np.abs(a.copy - cons).max() < 1e-9
 
 
 def test_small_rho_diverges_and_the_workload_rho_converges():

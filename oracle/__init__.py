@@ -82,6 +82,13 @@ Readings where the paper is silent or loose (the same on the GPU path):
      unknowns; a camera's (point's) consensus averages its block copies plus
      their scaled duals.  kappa = 1 gives R9's blocks with one point copy per
      observation.
+  R14 learned start (an extension, not in the paper; ``ADMM.iterate_learned``):
+     each local update starts from the better, by the local objective F, of
+     its previous copy and the copy plus the update a network predicts (ties
+     keep the copy), and runs ``learned_steps`` LM steps of R4 from there.
+     The network (``oracle.mlp``) sees the observation's residual at the
+     copy, camera and point copy minus consensus and the scaled duals, each
+     standardised, rounded to bfloat16.
 """
 from __future__ import annotations
 
@@ -167,6 +174,15 @@ def _declare(L):
                                    _ip, _ip, _dp, _dp, _dp, _dp, _dp, _dp,
                                    ctypes.POINTER(OrcOpts), ctypes.c_int32, _dp]
     L.orc_admm_iterate.restype = ctypes.c_int
+    L.orc_admm_iterate_learned.argtypes = [ctypes.c_int64, ctypes.c_int32, ctypes.c_int32,
+                                           _ip, _ip, _dp, _dp, _dp, _dp, _dp, _dp,
+                                           ctypes.POINTER(OrcOpts), _dp, ctypes.c_int32, _dp]
+    L.orc_admm_iterate_learned.restype = ctypes.c_int
+    L.orc_learned_local_solve.argtypes = [ctypes.POINTER(OrcOpts), _dp, _dp, _dp, _dp, ctypes.c_double,
+                                          ctypes.c_double, ctypes.c_int]
+    L.orc_learned_local_solve.restype = ctypes.c_int
+    L.orc_learned_features.argtypes = [ctypes.c_int64, _ip, _ip, _dp, _dp, _dp, _dp, _dp, ctypes.c_int, _dp]
+    L.orc_learned_features.restype = None
     L.orc_reprojection_stats.argtypes = [ctypes.c_int64, _ip, _ip, _dp, _dp, _dp, _up,
                                          ctypes.c_int, ctypes.c_double, ctypes.c_int, _dp]
     L.orc_euler_rotation.argtypes = [_dp, _dp]
@@ -347,6 +363,41 @@ class ADMM:
         if rc != 0:
             raise ValueError("oracle: bad problem indices")
         self.iteration += n_iters
+        return tr
+
+    def features(self) -> np.ndarray:
+        """Features of the learned start (R14) of every observation, (L, 26)."""
+        p = self.p
+        f = np.zeros((p.obs_cam.shape[0], 26))
+        lib().orc_learned_features(p.obs_cam.shape[0], _i(p.obs_cam), _i(p.obs_point), _d(p.obs_uv),
+                                   _d(self.cons_y), _d(self.cons_x), _d(self.copy), _d(self.dual),
+                                   CAMERA[self.camera], _d(f))
+        return f
+
+    def iterate_learned(self, params, norm, learned_steps: int) -> np.ndarray:
+        """One iteration with the learned start (R14): the network of
+        ``oracle.mlp`` (weights and activations rounded to bfloat16) on the
+        standardised features predicts each local update, the guard keeps
+        the better start, ``learned_steps`` LM steps follow; consensus,
+        duals, norms and rho as in ``iterate``.  ``params``: the flat FP32
+        parameter block of the C ABI; ``norm``: feature mean / std, output
+        mean / std (76 values).  Returns the trace row (1, 4)."""
+        from . import mlp
+        nm = np.asarray(norm, np.float32).astype(np.float64)
+        net = mlp.unflatten(np.asarray(params, np.float32).astype(np.float64))
+        x = mlp.standardize_input(self.features(), nm[:26], nm[26:52])
+        y, _ = mlp.forward(net, x, quantize=True)
+        delta = np.ascontiguousarray(y[:, :12] * nm[64:76] + nm[52:64])
+        tr = np.zeros((1, 4))
+        p = self.p
+        rc = lib().orc_admm_iterate_learned(p.obs_cam.shape[0], p.n_cams, p.n_points,
+                                            _i(p.obs_cam), _i(p.obs_point), _d(p.obs_uv),
+                                            _d(self.cons_y), _d(self.cons_x), _d(self.copy),
+                                            _d(self.dual), _d(self.rho), ctypes.byref(self.opts),
+                                            _d(delta), int(learned_steps), _d(tr))
+        if rc != 0:
+            raise ValueError("oracle: bad problem indices or learned steps")
+        self.iteration += 1
         return tr
 
     def stats(self, mask=None):

@@ -609,10 +609,81 @@ int orc_local_solve(const orc_opts *o, const double z[2], const double v[12],
 /* trace (optional, 4 per iteration): r_pri, r_dual, rho_x, rho_y used.      */
 /* Returns 0, or -1 on bad input.                                            */
 /* ------------------------------------------------------------------------ */
+/* ------------------------------------------------------------------------ */
+/* Learned start of one local update (an extension, reading R14): the start  */
+/* is the better of the base point theta (the previous copy) and            */
+/* theta + delta (the network's predicted update) by the local objective F, */
+/* ties keep the base; `steps` steps of the local solver follow.  Returns 1 */
+/* if the predicted start was kept.                                          */
+/* ------------------------------------------------------------------------ */
+int orc_learned_local_solve(const orc_opts *o, const double z[2], const double v[12], double theta[12],
+                            const double delta[12], double rho_x, double rho_y, int steps)
+{
+    double trial[12];
+    for (int c = 0; c < 12; ++c) trial[c] = theta[c] + delta[c];
+    const double F0 = orc_local_objective(o, z, v, theta, rho_x, rho_y);
+    const double F1 = orc_local_objective(o, z, v, trial, rho_x, rho_y);
+    const int kept = F1 < F0;
+    if (kept) memcpy(theta, trial, sizeof(trial));
+    orc_local_solve(o, z, v, theta, rho_x, rho_y, steps, NULL);
+    return kept;
+}
+
+/* Features of the learned start (R14) of every observation k at the current */
+/* state: feat[26 k ..] = residual z - pi at the copy (2), camera copy minus */
+/* camera consensus (9), point copy minus point consensus (3), camera scaled */
+/* dual (9), point scaled dual (3).                                          */
+void orc_learned_features(int64_t L, const int32_t *obs_cam, const int32_t *obs_pt, const double *obs_uv,
+                          const double *cons_y, const double *cons_x, const double *copy, const double *dual,
+                          int camera, double *feat)
+{
+    for (int64_t k = 0; k < L; ++k) {
+        const double *th = copy + 12 * k;
+        double uv[2];
+        orc_project_cam(camera, th, th + 9, uv);
+        double *f = feat + 26 * k;
+        f[0] = obs_uv[2 * k] - uv[0];
+        f[1] = obs_uv[2 * k + 1] - uv[1];
+        for (int c = 0; c < 9; ++c) f[2 + c] = th[c] - cons_y[9 * (size_t)obs_cam[k] + c];
+        for (int c = 0; c < 3; ++c) f[11 + c] = th[9 + c] - cons_x[3 * (size_t)obs_pt[k] + c];
+        for (int c = 0; c < 12; ++c) f[14 + c] = dual[12 * k + c];
+    }
+}
+
+static int admm_iterate(int64_t L, int32_t m, int32_t n,
+                        const int32_t *obs_cam, const int32_t *obs_pt, const double *obs_uv,
+                        double *cons_y, double *cons_x, double *copy, double *dual,
+                        double *rho, const orc_opts *o, int32_t n_iters, double *trace,
+                        const double *start_delta, int32_t start_steps);
+
 int orc_admm_iterate(int64_t L, int32_t m, int32_t n,
                      const int32_t *obs_cam, const int32_t *obs_pt, const double *obs_uv,
                      double *cons_y, double *cons_x, double *copy, double *dual,
                      double *rho, const orc_opts *o, int32_t n_iters, double *trace)
+{
+    return admm_iterate(L, m, n, obs_cam, obs_pt, obs_uv, cons_y, cons_x, copy, dual, rho, o, n_iters, trace,
+                        NULL, 0);
+}
+
+/* One ADMM iteration whose local updates start as orc_learned_local_solve */
+/* says, from the predicted updates start_delta [L][12], with start_steps   */
+/* local-solver steps; the rest of the iteration as orc_admm_iterate.       */
+int orc_admm_iterate_learned(int64_t L, int32_t m, int32_t n,
+                             const int32_t *obs_cam, const int32_t *obs_pt, const double *obs_uv,
+                             double *cons_y, double *cons_x, double *copy, double *dual,
+                             double *rho, const orc_opts *o, const double *start_delta, int32_t start_steps,
+                             double *trace)
+{
+    if (!start_delta || start_steps < 0) return -1;
+    return admm_iterate(L, m, n, obs_cam, obs_pt, obs_uv, cons_y, cons_x, copy, dual, rho, o, 1, trace,
+                        start_delta, start_steps);
+}
+
+static int admm_iterate(int64_t L, int32_t m, int32_t n,
+                        const int32_t *obs_cam, const int32_t *obs_pt, const double *obs_uv,
+                        double *cons_y, double *cons_x, double *copy, double *dual,
+                        double *rho, const orc_opts *o, int32_t n_iters, double *trace,
+                        const double *start_delta, int32_t start_steps)
 {
     double *cnt_y = calloc((size_t)m, sizeof(double));
     double *cnt_x = calloc((size_t)n, sizeof(double));
@@ -635,7 +706,11 @@ int orc_admm_iterate(int64_t L, int32_t m, int32_t n,
             double v[12];
             for (int c = 0; c < 9; ++c) v[c] = cons_y[9 * j + c] - dual[12 * k + c];
             for (int c = 0; c < 3; ++c) v[9 + c] = cons_x[3 * i + c] - dual[12 * k + 9 + c];
-            orc_local_solve(o, obs_uv + 2 * k, v, copy + 12 * k, rx, ry, o->lm_steps, NULL);
+            if (start_delta)
+                orc_learned_local_solve(o, obs_uv + 2 * k, v, copy + 12 * k, start_delta + 12 * k, rx, ry,
+                                        start_steps);
+            else
+                orc_local_solve(o, obs_uv + 2 * k, v, copy + 12 * k, rx, ry, o->lm_steps, NULL);
         }
         /* 2. consensus */
         memcpy(old_y, cons_y, sizeof(double) * 9 * (size_t)m);

@@ -4,14 +4,19 @@ against.  Calls only the FP64 oracle (oracle/) on seeded scenes (scenes/).
     python tests/golden/make_golden.py trajectory   # ~35 min, one core
     python tests/golden/make_golden.py sphere       # ~2 min
     python tests/golden/make_golden.py batch        # ~1 min
+    python tests/golden/make_golden.py batch_full   # ~10 min
     python tests/golden/make_golden.py trajectory_perturbed sphere_perturbed
+    python tests/golden/make_golden.py trajectory_perturbed_fp64
     python tests/golden/make_golden.py trajectory_blocks   # block local updates, ~25 min
     python tests/golden/make_golden.py trajectory_euler    # the Euler camera, ~35 min
 
-A name ending in _perturbed runs the same workload from a start whose
-parameters are multiplied by 1 +- 1e-7 (random signs, seed 7), the size of
-FP32 rounding: how far the FP64 oracle moves from its own stored run bounds
-the agreement any FP32 computation can reach on that workload.
+Every camera and every point is stored.  A name ending in _perturbed runs the
+same workload from a start whose parameters are multiplied by 1 +- 1e-7
+(random signs, seed 7), the size of FP32 rounding: how far the FP64 oracle
+moves from its own stored run bounds the agreement any FP32 computation can
+reach on that workload.  A name ending in _perturbed_fp64 does the same with
+1 +- 2^-52, one unit in the last place of FP64: the oracle's sensitivity to
+its own rounding, the bound on what any FP64 computation can match.
 """
 import os
 import sys
@@ -26,45 +31,94 @@ sys.path.insert(0, ROOT)
 import oracle  # noqa: E402
 from scenes import make_config1, make_config2, make_config3  # noqa: E402
 
-# workload -> (scene, solver settings, iterations, point sampling stride)
+# workload -> (scene, solver settings, iterations, earlier iterations also stored)
 SPECS = {
     "trajectory": (make_config2, dict(loss="huber", loss_param=2.0, rho=1e5, rho_balancing=True,
-                                      rho_min=1e5, rho_max=1e7), 200, 50),
-    "sphere": (make_config1, dict(loss="student_t", loss_param=4.0, rho=1e3), 100, 10),
+                                      rho_min=1e5, rho_max=1e7), 200, (20,)),
+    "sphere": (make_config1, dict(loss="student_t", loss_param=4.0, rho=1e3), 100, (20,)),
     # the trajectory workload with the paper's Euler camera (Eq. 1); seed 7,
     # whose perturbed start keeps every point in front of its cameras
     "trajectory_euler": (lambda: make_config2(seed=7, camera="euler"),
                          dict(loss="huber", loss_param=2.0, rho=1e5, rho_balancing=True, rho_min=1e5, rho_max=1e7,
-                              camera="euler"), 200, 50),
+                              camera="euler"), 200, ()),
 }
+PERTURB = {"_perturbed_fp64": 2.0 ** -52, "_perturbed": 1e-7}
+BATCH_FULL = dict(loss="student_t", loss_param=4.0, rho=1e3)
+
+
+def _split(name):
+    """(workload, relative start perturbation or 0)."""
+    for suf, eps in PERTURB.items():
+        if name.endswith(suf):
+            return name[:-len(suf)], eps
+    return name, 0.0
+
+
+def _perturb(cams0, pts0, eps):
+    rng = np.random.default_rng(7)
+    cams0 = cams0 * (1 + eps * rng.choice([-1.0, 1.0], size=cams0.shape))
+    pts0 = pts0 * (1 + eps * rng.choice([-1.0, 1.0], size=pts0.shape))
+    return cams0, pts0
 
 
 def run(name):
-    base = name[:-len("_perturbed")] if name.endswith("_perturbed") else name
-    make, kw, iters, stride = SPECS[base]
+    base, eps = _split(name)
+    make, kw, iters, early = SPECS[base]
     sc = make()
     kw = dict(kw)
     rmin, rmax = kw.pop("rho_min", 1e-6), kw.pop("rho_max", 1e6)
     cams0, pts0 = sc.cams_init, sc.points_init
-    if base != name:
-        rng = np.random.default_rng(7)
-        cams0 = cams0 * (1 + 1e-7 * rng.choice([-1.0, 1.0], size=cams0.shape))
-        pts0 = pts0 * (1 + 1e-7 * rng.choice([-1.0, 1.0], size=pts0.shape))
+    if eps:
+        cams0, pts0 = _perturb(cams0, pts0, eps)
     a = oracle.ADMM(oracle.Problem.from_scene(sc), cams0, pts0, **kw)
     a.opts.rho_min, a.opts.rho_max = rmin, rmax
     inl = ~sc.outlier
-    trace, curve = [], []
+    trace, curve, snap = [], [], {}
     t0 = time.time()
     for k in range(iters // 10):
         trace.append(a.iterate(10))
         st = a.stats(inl)
         curve.append((a.iteration, st[0], st[1], st[2]))
+        if a.iteration in early:
+            snap[f"cams_at{a.iteration}"] = a.cons_y.copy()
+            snap[f"points_at{a.iteration}"] = a.cons_x.copy()
+            snap[f"stats_at{a.iteration}"] = st
         print(f"{name} it {a.iteration} rmse {st[0]:.6f} inlier {st[1]:.6f} {time.time() - t0:.0f}s", flush=True)
-    pts_idx = np.arange(0, sc.n_points, stride)
     np.savez_compressed(os.path.join(HERE, f"{name}.npz"), checksum=np.array(sc.checksum()),
                         n_obs=sc.n_obs, iterations=iters, trace=np.concatenate(trace), curve=np.array(curve),
-                        cams=a.cons_y, points_idx=pts_idx, points=a.cons_x[pts_idx], rho=a.rho,
-                        stats=a.stats(inl), settings=np.array(repr(SPECS[base][1])))
+                        cams=a.cons_y, points=a.cons_x, rho=a.rho, perturbation=eps, early=np.array(early, int),
+                        stats=a.stats(inl), settings=np.array(repr(SPECS[base][1])), **snap)
+
+
+def batch_full_members(scenes):
+    """Indexes of the smallest, the median and the largest problem (by
+    observations) of the 64-problem batched workload."""
+    order = np.argsort([sc.n_obs for sc in scenes], kind="stable")
+    return [int(order[0]), int(order[len(order) // 2]), int(order[-1])]
+
+
+def run_batch_full(name):
+    """Three problems of the full-size batched workload (smallest, median,
+    largest), 100 iterations each, every camera and point stored."""
+    base, eps = _split(name)
+    scenes = make_config3()
+    members = batch_full_members(scenes)
+    out = {}
+    t0 = time.time()
+    for q in members:
+        sc = scenes[q]
+        cams0, pts0 = sc.cams_init, sc.points_init
+        if eps:
+            cams0, pts0 = _perturb(cams0, pts0, eps)
+        a = oracle.ADMM(oracle.Problem.from_scene(sc), cams0, pts0, **BATCH_FULL)
+        a.iterate(100)
+        out[f"cams{q}"] = a.cons_y
+        out[f"points{q}"] = a.cons_x
+        out[f"checksum{q}"] = np.array(sc.checksum())
+        out[f"stats{q}"] = a.stats()
+        print(f"{name} problem {q} ({sc.n_obs} observations) {time.time() - t0:.0f}s", flush=True)
+    np.savez_compressed(os.path.join(HERE, f"{name}.npz"), iterations=100, members=np.array(members),
+                        perturbation=eps, settings=np.array(repr(BATCH_FULL)), **out)
 
 
 def run_blocks():
@@ -80,10 +134,9 @@ def run_blocks():
     for k in range(3):
         trace.append(a.iterate(1))
         print(f"trajectory_blocks it {a.iteration} {time.time() - t0:.0f}s", flush=True)
-    pts_idx = np.arange(0, sc.n_points, 50)
     np.savez_compressed(os.path.join(HERE, "trajectory_blocks.npz"), checksum=np.array(sc.checksum()),
                         n_obs=sc.n_obs, iterations=3, n_blocks=a.n_blocks, trace=np.concatenate(trace),
-                        cams=a.cons_y, points_idx=pts_idx, points=a.cons_x[pts_idx], rho=a.rho,
+                        cams=a.cons_y, points=a.cons_x, rho=a.rho,
                         stats=a.stats(~sc.outlier))
 
 
@@ -104,6 +157,8 @@ if __name__ == "__main__":
     for name in sys.argv[1:]:
         if name == "batch":
             run_batch()
+        elif name.startswith("batch_full"):
+            run_batch_full(name)
         elif name == "trajectory_blocks":
             run_blocks()
         else:

@@ -17,5 +17,4 @@ from .generate import (  # noqa: F401
     make_trajectory_scene,
     make_tiny_paper_scene,
     point_shard,
-    CONFIG_SOLVER,
 )

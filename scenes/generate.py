@@ -29,18 +29,6 @@ from scipy.spatial.transform import Rotation
 FOCAL = 800.0
 IMAGE_HALF = 500.0          # image spans [-500, 500]^2 pixels
 
-# Solver settings attached to each named workload.
-CONFIG_SOLVER = {
-    0: dict(loss="huber", loss_param=2.0, rho=1.0, rho_balancing=False,
-            iterations=50, lm_steps=5, precision="fp64"),
-    1: dict(loss="student_t", loss_param=4.0, rho=1.0, rho_balancing=False,
-            iterations=100, lm_steps=5, precision="fp64"),
-    2: dict(loss="huber", loss_param=2.0, rho=1.0, rho_balancing=True,
-            iterations=200, lm_steps=5, precision="fp32"),
-    3: dict(loss="student_t", loss_param=4.0, rho=1.0, rho_balancing=False,
-            iterations=100, lm_steps=5, precision="fp32"),
-}
-
 
 @dataclass
 class Scene:

@@ -120,11 +120,17 @@ typedef struct dba_options {
                                  local problem couples them (18 + 3 x points unknowns, Schur
                                  complement on the points, an 18x18 camera system).  Must be 1
                                  without camera_blocks */
+    int32_t segment_schedule; /* point-consensus segment schedule: 1 each thread loads its point's
+                                 records itself; 2, 3 the point block's records are staged through
+                                 LDS in coalesced tiles of 512 or 1024 records.  Each point's
+                                 records are summed in the same order whatever the value; 0:
+                                 autotune */
 } dba_options;
 
 /* Fills *opt with the defaults: device 0, NULL stream, FP64, Huber 2 px,
  * rho 1, no balancing (mu 10, tau 2, clamps 1e-6..1e6), 5 LM steps,
- * lambda0 1e-3, plain start, 2 learned steps, graphs on, autotune, one
+ * lambda0 1e-3, plain start, 2 learned steps, graphs on, autotune (local and
+ * segment schedules), one
  * local problem per observation (camera_blocks 0, block_points 0), the
  * 9-parameter angle-axis camera, robust LM. */
 int dba_default_options(dba_options *opt);
@@ -225,6 +231,11 @@ int dba_kernel_times(dba_handle *h, double *total_ms /*[4]*/, int64_t *launches 
 /* Launch schedule in use: waves per local-solve workgroup, persistent flag,
  * and number of candidate schedules the autotuner timed (0 if fixed). */
 int dba_schedule(const dba_handle *h, int32_t *block_waves, int32_t *persistent, int32_t *tuned);
+/* Segment schedule of the consensus in use (segment_schedule of
+ * dba_options) and the number of candidates the autotuner timed (0 if
+ * fixed).  Every candidate gives bitwise-identical results, so tuning on the
+ * first iterations does not change them. */
+int dba_segment_schedule(const dba_handle *h, int32_t *segment_schedule, int32_t *tuned);
 
 /* ---------------------------------------------------------------------------
  * Learned warm start.  Before each local solve a small network predicts the
@@ -277,6 +288,18 @@ int dba_collect_pairs(dba_handle *h, int32_t n_iters, int32_t per_iter, uint64_t
  * trained network becomes the handle's network. */
 int dba_mlp_train(dba_handle *h, const float *features, const float *deltas, int64_t n, int32_t epochs, int32_t batch,
                   double lr, uint64_t seed, float *epoch_loss);
+/* One Adam step (Kingma & Ba 2015: beta 0.9, 0.999, eps 1e-8, bias
+ * correction by the handle's step count) of the network's FP32 parameters
+ * with a gradient computed elsewhere, grad [DBA_MLP_PARAMS] (for example a
+ * sum of dba_mlp_loss_grad results over several batches or handles); the
+ * padding entries of the parameter block stay zero.  dba_set_mlp and
+ * dba_mlp_train start the optimiser state from zero; dba_mlp_train's steps
+ * use the same update.  DBA_E_STATE without a network, DBA_E_NONFINITE for a
+ * non-finite gradient entry. */
+int dba_mlp_apply_gradient(dba_handle *h, const float *grad, double lr);
+/* Reads the Adam state: first and second moments m, v [DBA_MLP_PARAMS]
+ * (either may be NULL) and the number of steps taken since it was zeroed. */
+int dba_mlp_adam_state(dba_handle *h, float *m, float *v, int64_t *step);
 
 #ifdef __cplusplus
 }

@@ -44,7 +44,8 @@ class dba_options(ctypes.Structure):
                 ("use_graph", ctypes.c_int32), ("block_waves", ctypes.c_int32),
                 ("persistent", ctypes.c_int32), ("camera_blocks", ctypes.c_int32),
                 ("block_points", ctypes.c_int32), ("camera_model", ctypes.c_int32),
-                ("local_solver", ctypes.c_int32), ("block_cameras", ctypes.c_int32)]
+                ("local_solver", ctypes.c_int32), ("block_cameras", ctypes.c_int32),
+                ("segment_schedule", ctypes.c_int32)]
 
 
 class dba_problem_desc(ctypes.Structure):
@@ -71,8 +72,9 @@ class dba_residual_report(ctypes.Structure):
 EXPORTS = ("dba_default_options", "dba_create", "dba_destroy", "dba_last_error",
            "dba_set_problem", "dba_set_problems", "dba_iterate", "dba_residuals",
            "dba_set_eval_mask", "dba_get_params", "dba_get_state", "dba_problem_info",
-           "dba_set_kernel_timing", "dba_kernel_times", "dba_schedule", "dba_set_mlp", "dba_get_mlp",
-           "dba_set_start", "dba_mlp_forward", "dba_mlp_loss_grad", "dba_collect_pairs", "dba_mlp_train")
+           "dba_set_kernel_timing", "dba_kernel_times", "dba_schedule", "dba_segment_schedule", "dba_set_mlp", "dba_get_mlp",
+           "dba_set_start", "dba_mlp_forward", "dba_mlp_loss_grad", "dba_collect_pairs", "dba_mlp_train",
+           "dba_mlp_apply_gradient", "dba_mlp_adam_state")
 MLP_PARAMS, MLP_NORM = 22800, 76
 
 _lib = None
@@ -106,6 +108,7 @@ def load(path: Optional[str] = None) -> ctypes.CDLL:
     L.dba_set_kernel_timing.argtypes = [vp, i32]
     L.dba_kernel_times.argtypes = [vp, P(dbl), P(i64)]
     L.dba_schedule.argtypes = [vp, P(i32), P(i32), P(i32)]
+    L.dba_segment_schedule.argtypes = [vp, P(i32), P(i32)]
     if hasattr(L, "dba_set_mlp"):
         _declare_learned(L)
     _lib = L
@@ -121,6 +124,8 @@ def _declare_learned(L):
     L.dba_mlp_loss_grad.argtypes = [vp, vp, vp, i32, vp, vp, vp]
     L.dba_collect_pairs.argtypes = [vp, i32, i32, u64, i32, vp, vp]
     L.dba_mlp_train.argtypes = [vp, vp, vp, i64, i32, i32, dbl, u64, vp]
+    L.dba_mlp_apply_gradient.argtypes = [vp, vp, dbl]
+    L.dba_mlp_adam_state.argtypes = [vp, vp, vp, ctypes.POINTER(i64)]
 
 
 def _ptr(a: Optional[np.ndarray]):
@@ -138,7 +143,7 @@ def make_options(*, device=0, stream=None, precision="fp64", loss="huber", loss_
                  rho_min=1e-6, rho_max=1e6, lm_steps=5, lm_lambda0=1e-3, start="plain",
                  learned_lm_steps=2, use_graph=True, block_waves=0, persistent=-1,
                  camera_blocks=False, block_points=0, camera="angle_axis", solver="lm",
-                 block_cameras=1) -> dba_options:
+                 block_cameras=1, segment_schedule=0) -> dba_options:
     """dba_options from keywords: enum fields by name (precision "fp64" /
     "fp32"; loss "l2" / "huber" / "student_t"; start "plain" / "learned";
     camera "angle_axis" / "euler"; solver "lm" / "gauss_newton" / "lbfgs"),
@@ -166,6 +171,7 @@ def make_options(*, device=0, stream=None, precision="fp64", loss="huber", loss_
     o.camera_model = CAMERA[camera]
     o.local_solver = SOLVER[solver]
     o.block_cameras = int(block_cameras)
+    o.segment_schedule = int(segment_schedule)
     return o
 
 
@@ -260,6 +266,12 @@ def dba_schedule(h):
     return dict(block_waves=bw.value, persistent=pe.value, tuned=tu.value)
 
 
+def dba_segment_schedule(h):
+    sl, tu = ctypes.c_int32(), ctypes.c_int32()
+    _check(h, load().dba_segment_schedule(h, ctypes.byref(sl), ctypes.byref(tu)))
+    return dict(segment_schedule=sl.value, tuned=tu.value)
+
+
 def _f32(a, shape=None):
     a = np.ascontiguousarray(a, dtype=np.float32)
     if shape is not None and a.shape != shape:
@@ -314,6 +326,21 @@ def dba_mlp_train(h, features, deltas, epochs=10, batch=4096, lr=1e-3, seed=0):
     _check(h, load().dba_mlp_train(h, _ptr(f), _ptr(d), f.shape[0], int(epochs), int(batch), float(lr), int(seed),
                                    _ptr(el)))
     return el
+
+
+def dba_mlp_apply_gradient(h, grad, lr):
+    g = _f32(grad).reshape(-1)
+    assert g.shape[0] == MLP_PARAMS
+    _check(h, load().dba_mlp_apply_gradient(h, _ptr(g), float(lr)))
+
+
+def dba_mlp_adam_state(h):
+    """(m, v, step) of the network's Adam optimiser."""
+    m = np.zeros(MLP_PARAMS, np.float32)
+    v = np.zeros(MLP_PARAMS, np.float32)
+    step = ctypes.c_int64(0)
+    _check(h, load().dba_mlp_adam_state(h, _ptr(m), _ptr(v), ctypes.byref(step)))
+    return m, v, int(step.value)
 
 
 # ---------------------------------------------------------------- convenience

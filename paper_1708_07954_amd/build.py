@@ -13,7 +13,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libdba.so")
-SOURCES = ["dba_kernels.hip", "mlp_kernels.hip", "dba_host.cpp", "dba_learned.cpp"]
+SOURCES = ["dba_kernels.hip", "mlp_kernels.hip", "dba_host.cpp", "dba_learned.cpp", "dba_layout.cpp"]
 
 HIPCC_FLAGS = [
     "--offload-arch=gfx950",

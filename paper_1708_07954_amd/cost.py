@@ -104,6 +104,33 @@ def bytes_per_obs(fp32: bool = True) -> dict:
     return dict(local=local, consensus=consensus, total=local + consensus, minimal=minimal)
 
 
+def obs_per_block(obs_cams, block_points: int = 64) -> float:
+    """Mean observations per block when each camera's observations are cut
+    into consecutive blocks of block_points (one-camera blocks)."""
+    import numpy as np
+    n_obs = n_blocks = 0
+    for oc in obs_cams:
+        cnt = np.bincount(np.asarray(oc))
+        n_obs += int(cnt.sum())
+        n_blocks += int(((cnt + block_points - 1) // block_points).sum())
+    return n_obs / max(n_blocks, 1)
+
+
+def block_bytes_per_obs(fp32: bool = True, obs_per_block: float = 64.0) -> float:
+    """One-camera blocks: per observation its pixel, indexes, point copy and
+    point dual; per block one camera copy and dual, read and written."""
+    r = 4 if fp32 else 8
+    return 2 * r + 8 + 2 * 3 * r + 2 * 3 * 8 + (2 * 9 * r + 2 * 9 * 8) / obs_per_block
+
+
+def block2_bytes_per_obs(fp32: bool = True, obs_per_copy: float = 1.7) -> float:
+    """Two-camera blocks: per observation its pixel and indexes; per point
+    copy its copy and dual, read and written (the block cameras' copies, one
+    per pair and block, are negligible)."""
+    r = 4 if fp32 else 8
+    return 2 * r + 8 + (2 * 3 * r + 2 * 3 * 8) / obs_per_copy
+
+
 if __name__ == "__main__":
     print("LM step flops", LM_STEP, "per obs (5 steps)", local_flops_per_obs(5))
     print("Euler camera: LM step flops", LM_STEP_E, "per obs (5 steps)", local_flops_per_obs(5, "euler"))

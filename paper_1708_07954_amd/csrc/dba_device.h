@@ -284,10 +284,11 @@ template <typename R> __device__ __forceinline__ R lam_up(R l) { return l * R(10
 // (Gill, Golub, Murray & Saunders 1974, method C1): A = L1 L2 D2 L2^T L1^T
 // with unit lower-triangular L1 = I + low(J0 b1^T), L2 = I + low(q b2^T),
 // q = L1^-1 J1; O(12) operations, one reciprocal per row and update.  (The
-// Sherman-Morrison-Woodbury form of the same solve takes about half the
-// operations, but in FP32 its cancellation in the two stiff directions,
-// amplified over many ADMM iterations along nearly flat directions of the
-// global problem, costs an order of magnitude in agreement with FP64.)
+// Sherman-Morrison-Woodbury form of the same solve, x = D^-1 (g - U y), takes
+// 13 % less time in the local-solve kernel, but in FP32 it moves the weakly
+// determined parameters -- radial distortion of cameras whose points sit
+// near the image centre -- further from FP64: 3e-4 against 1.6e-5 after one
+// ADMM iteration of the 2M-observation trajectory.)
 template <typename R, typename Cam = CamAA>
 __device__ __forceinline__ bool solve_normal(const R *Dd, const R *J0, const R *J1, R c2, const R *ng, R *x)
 {

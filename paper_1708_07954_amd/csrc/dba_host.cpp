@@ -30,310 +30,46 @@ void drop_graphs(dba_handle *h)
     h->tgraph_next[0] = h->tgraph_next[1] = 0;
 }
 
-// Depth P_3 of R(w) X + t (host-side validation only).
-double host_depth(const double *cam, const double *X)
-{
-    const double w0 = cam[0], w1 = cam[1], w2 = cam[2];
-    const double t2 = w0 * w0 + w1 * w1 + w2 * w2;
-    double c, a, b;
-    if (t2 < 1e-4) {
-        c = 1.0 - t2 / 2.0 + t2 * t2 / 24.0;
-        a = 1.0 - t2 / 6.0 + t2 * t2 / 120.0;
-        b = 0.5 - t2 / 24.0 + t2 * t2 / 720.0;
-    } else {
-        const double t = std::sqrt(t2), sh = std::sin(0.5 * t);
-        c = std::cos(t);
-        a = std::sin(t) / t;
-        b = 2.0 * sh * sh / t2;
-    }
-    const double wd = w0 * X[0] + w1 * X[1] + w2 * X[2];
-    return c * X[2] + a * (w0 * X[1] - w1 * X[0]) + b * wd * w2 + cam[5];
-}
-
-// Depth P_3 of R X + t for the Euler camera, R = R3(gamma) R2(beta) R1(alpha)
-// (host-side validation only): the third row of R is
-// (-sin beta, sin alpha cos beta, cos alpha cos beta).
-double host_depth_euler(const double *cam, const double *X)
-{
-    const double sa = std::sin(cam[0]), ca = std::cos(cam[0]), sb = std::sin(cam[1]), cb = std::cos(cam[1]);
-    return -sb * X[0] + sa * cb * X[1] + ca * cb * X[2] + cam[5];
-}
-
 int validate(dba_handle *h, int p, const dba_problem_desc &d)
 {
-    if (d.n_cams < 1 || d.n_points < 1 || d.n_obs < 1)
-        return fail(h, DBA_E_INVALID_ARG, "problem %d: sizes must be positive (m=%d n=%d L=%lld)", p,
-                    d.n_cams, d.n_points, (long long)d.n_obs);
-    if (!d.obs_cam || !d.obs_point || !d.obs_uv || !d.cams || !d.points)
-        return fail(h, DBA_E_INVALID_ARG, "problem %d: null array", p);
-    if (d.n_obs > (1LL << 30))
-        return fail(h, DBA_E_INVALID_ARG, "problem %d: too many observations", p);
-    std::vector<int> cc(d.n_cams, 0), pc(d.n_points, 0);
-    for (long long k = 0; k < d.n_obs; ++k) {
-        const int j = d.obs_cam[k], i = d.obs_point[k];
-        if (j < 0 || j >= d.n_cams || i < 0 || i >= d.n_points)
-            return fail(h, DBA_E_INDEX_RANGE, "problem %d: observation %lld has camera %d / point %d out of range",
-                        p, k, j, i);
-        ++cc[j];
-        ++pc[i];
-        if (!std::isfinite(d.obs_uv[2 * k]) || !std::isfinite(d.obs_uv[2 * k + 1]))
-            return fail(h, DBA_E_NONFINITE, "problem %d: observation %lld is not finite", p, k);
-    }
-    for (long long q = 0; q < 9LL * d.n_cams; ++q)
-        if (!std::isfinite(d.cams[q])) return fail(h, DBA_E_NONFINITE, "problem %d: camera value %lld not finite", p, q);
-    for (long long q = 0; q < 3LL * d.n_points; ++q)
-        if (!std::isfinite(d.points[q])) return fail(h, DBA_E_NONFINITE, "problem %d: point value %lld not finite", p, q);
-    for (int j = 0; j < d.n_cams; ++j)
-        if (!cc[j]) return fail(h, DBA_E_UNOBSERVED, "problem %d: camera %d has no observation", p, j);
-    for (int i = 0; i < d.n_points; ++i)
-        if (!pc[i]) return fail(h, DBA_E_UNOBSERVED, "problem %d: point %d has no observation", p, i);
-    const bool euler = h->opt.camera_model == 1;
-    if (euler)
-        for (int j = 0; j < d.n_cams; ++j) {
-            const double *c = d.cams + 9LL * j;
-            if (!(c[6] > 0) || c[7] != 0.0 || c[8] != 0.0)
-                return fail(h, DBA_E_INVALID_ARG,
-                            "problem %d: camera %d: the Euler camera needs a focal length > 0 in slot 6 and zeros "
-                            "in slots 7, 8", p, j);
-        }
-    for (long long k = 0; k < d.n_obs; ++k) {
-        const double *cam = d.cams + 9LL * d.obs_cam[k], *X = d.points + 3LL * d.obs_point[k];
-        const double z = euler ? host_depth_euler(cam, X) : host_depth(cam, X);
-        if (!(z > 1e-6))
-            return fail(h, DBA_E_BEHIND_CAMERA, "problem %d: observation %lld has depth %g at the initial estimate",
-                        p, k, z);
-    }
+    std::string msg;
+    const int rc = dba::validate_problem(p, d, h->opt.camera_model, &msg);
+    if (rc != DBA_OK) return fail(h, rc, "%s", msg.c_str());
     return DBA_OK;
-}
-
-// Two-camera blocks of one problem (block_cameras == 2): cameras in pairs
-// (2g, 2g + 1); a pair's observed points, ascending, in runs of at most bp
-// points; block b holds run b with one copy of each of its points (lane l <->
-// point pts[pts0[b] + l]) and of each pair camera s that observes one of them
-// (bit s of present[b]); obs[(pts0[b] + l) * 2 + s] is the observation of
-// camera s of the pair at lane l, or -1.  Returns false on a repeated
-// (camera, point) pair, which a lane cannot hold.
-struct PairBlocks {
-    std::vector<int> cam0, npts, pts0, present, pts;
-    std::vector<long long> obs;
-};
-
-static bool pair_blocks(const dba_problem_desc &d, int bp, PairBlocks &out)
-{
-    const int ng = (d.n_cams + 1) / 2;
-    std::vector<long long> goff(ng + 1, 0);
-    for (long long k = 0; k < d.n_obs; ++k) ++goff[d.obs_cam[k] / 2 + 1];
-    for (int g = 0; g < ng; ++g) goff[g + 1] += goff[g];
-    std::vector<long long> gobs(d.n_obs), fill(goff.begin(), goff.end() - 1);
-    for (long long k = 0; k < d.n_obs; ++k) gobs[fill[d.obs_cam[k] / 2]++] = k;
-    std::vector<int> lane_of(d.n_points, -1);
-    for (int g = 0; g < ng; ++g) {
-        std::vector<int> gp;
-        for (long long q = goff[g]; q < goff[g + 1]; ++q) gp.push_back(d.obs_point[gobs[q]]);
-        std::sort(gp.begin(), gp.end());
-        gp.erase(std::unique(gp.begin(), gp.end()), gp.end());
-        const size_t first = out.pts.size();
-        for (size_t r0 = 0; r0 < gp.size(); r0 += bp) {
-            const int n = (int)std::min<size_t>(bp, gp.size() - r0);
-            out.cam0.push_back(2 * g);
-            out.npts.push_back(n);
-            out.pts0.push_back((int)out.pts.size());
-            out.present.push_back(0);
-            for (int l = 0; l < n; ++l) {
-                out.pts.push_back(gp[r0 + l]);
-                out.obs.push_back(-1);
-                out.obs.push_back(-1);
-            }
-        }
-        for (size_t t = first; t < out.pts.size(); ++t) lane_of[out.pts[t]] = (int)t;
-        // each observation of the pair into its point's lane
-        for (long long q = goff[g]; q < goff[g + 1]; ++q) {
-            const long long k = gobs[q];
-            const int t = lane_of[d.obs_point[k]], sc = d.obs_cam[k] - 2 * g;
-            if (out.obs[2 * (size_t)t + sc] >= 0) return false;
-            out.obs[2 * (size_t)t + sc] = k;
-        }
-    }
-    // presence bits, per block from its lanes
-    for (size_t b = 0; b < out.cam0.size(); ++b)
-        for (int l = 0; l < out.npts[b]; ++l)
-            for (int sc = 0; sc < 2; ++sc)
-                if (out.obs[2 * (size_t)(out.pts0[b] + l) + sc] >= 0) out.present[b] |= 1 << sc;
-    return true;
 }
 
 template <typename R>
 int build_set(dba_handle *h, int np, const dba_problem_desc *probs, ProblemSet *ps, DevArrays<R> &A)
 {
     using R2 = typename dba::Vec<R>::R2;
-    const int CH = dba::kChunk;
-    // observations of a camera per chunk: 64, or the block size pi of the
-    // block local updates (the rest of such a chunk is padding).  Block local
-    // updates keep the camera copy and dual per chunk (copy_yc, dual_yc) and
-    // allocate no per-slot camera copies (copy_y, dual_y).
-    const int BP = h->opt.camera_blocks && h->opt.block_points ? h->opt.block_points : CH;
+    static_assert(sizeof(R2) == 2 * sizeof(R) && sizeof(dba::PtCopy<R>) == 3 * sizeof(R) &&
+                      sizeof(double4) == 4 * sizeof(double),
+                  "flattened host arrays match the device vector types");
+    dba::LayoutOptions lo;
+    lo.camera_blocks = h->opt.camera_blocks;
+    lo.block_points = h->opt.block_points;
+    lo.block_cameras = h->opt.block_cameras;
+    lo.camera_model = h->opt.camera_model;
+    dba::Layout<R> lay;
+    std::string msg;
+    const int lrc = dba::build_layout<R>(lo, np, probs, &lay, &msg);
+    if (lrc != DBA_OK) return fail(h, lrc, "%s", msg.c_str());
     const bool per_obs = !h->opt.camera_blocks;
-    // two-camera blocks: a point copy per (block, point), not per observation
-    const bool k2 = h->opt.camera_blocks && h->opt.block_cameras == 2;
-    std::vector<PairBlocks> pbs(k2 ? np : 0);
-    // global sizes
-    long long n_chunks = 0, n_recs = 0;
-    int n_cams = 0, n_pts = 0, n_pblk = 0, n_blocks = 0;
+    const bool k2 = lay.n_blocks2 > 0;
     ps->n_problems = np;
+    ps->ranges = lay.ranges;
     for (int p = 0; p < np; ++p) {
-        const dba_problem_desc &d = probs[p];
-        std::vector<int> cc(d.n_cams, 0);
-        for (long long k = 0; k < d.n_obs; ++k) ++cc[d.obs_cam[k]];
-        ProblemRange r{};
-        r.cam0 = n_cams; r.n_cams = d.n_cams;
-        r.pt0 = n_pts; r.n_points = d.n_points;
-        r.chunk0 = (int)n_chunks;
-        long long ch = 0, nrec = d.n_obs;
-        if (k2) {
-            if (!pair_blocks(d, BP, pbs[p]))
-                return fail(h, DBA_E_INVALID_ARG, "problem %d: a camera observes a point twice (two-camera blocks "
-                            "hold one observation per camera and point)", p);
-            for (int pr : pbs[p].present) ch += (pr & 1) + (pr >> 1);
-            nrec = (long long)pbs[p].pts.size();
-            n_blocks += (int)pbs[p].cam0.size();
-        } else {
-            for (int j = 0; j < d.n_cams; ++j) ch += (cc[j] + BP - 1) / BP;
-        }
-        r.n_chunks = (int)ch;
-        r.rec0 = n_recs; r.n_obs = d.n_obs;
-        r.pblk0 = n_pblk; r.n_pblk = (d.n_points + dba::kPtBlock - 1) / dba::kPtBlock;
-        n_pblk += r.n_pblk;
-        ps->ranges.push_back(r);
-        ps->m.push_back(d.n_cams);
-        ps->n.push_back(d.n_points);
-        ps->L.push_back(d.n_obs);
-        n_cams += d.n_cams;
-        n_pts += d.n_points;
-        n_chunks += ch;
-        n_recs += nrec;
+        ps->m.push_back(probs[p].n_cams);
+        ps->n.push_back(probs[p].n_points);
+        ps->L.push_back(probs[p].n_obs);
     }
-    const long long S = n_chunks * CH;
-    if (S >= (1LL << 31) || n_recs >= (1LL << 31))
-        return fail(h, DBA_E_INVALID_ARG, "problem set too large (%lld slots)", S);
+    const long long S = lay.n_slots, n_chunks = lay.n_chunks, n_recs = lay.n_recs;
+    const int n_cams = lay.n_cams, n_pts = lay.n_pts, n_pblk = lay.n_pblk;
     ps->n_slots = S;
-
-    std::vector<R2> uv(S);
-    std::vector<int> pslot(S, -1), ptid(S, 0), orig(S, 0);
-    std::vector<uint8_t> mask(S, 1);
-    // per-observation camera copies; block local updates keep one per chunk
     const size_t SY = per_obs ? (size_t)S : 0;
-    std::vector<R> copy_y(9 * SY, R(0));
-    std::vector<dba::PtCopy<R>> xrec(n_recs);
-    std::vector<int> pt_off(n_pts + 1, 0), chunk_cam(n_chunks), cam_prob(n_cams), pt_prob(n_pts),
-        cam_chunk0(n_cams + 1), cam_count(n_cams);
-    std::vector<double> cons_y((size_t)n_cams * dba::kConsY, 0.0);
-    std::vector<double4> cons_x(n_pts);
+    std::vector<uint8_t> mask(S, 1);
     std::vector<Ctrl> ctrl(np);
-    std::vector<int> pblk_pt0(n_pblk), pblk_cnt(n_pblk);
-    // two-camera blocks: chunk of each pair camera (or -1), record of each lane (or -1)
-    std::vector<int> blk_chunk(2 * (size_t)n_blocks, -1), blk_rec((size_t)n_blocks * CH, -1);
-    int blk_base = 0;
     for (int p = 0; p < np; ++p) {
-        const ProblemRange &r = ps->ranges[p];
-        for (int q = 0; q < r.n_pblk; ++q) {
-            pblk_pt0[r.pblk0 + q] = r.pt0 + q * dba::kPtBlock;
-            pblk_cnt[r.pblk0 + q] = std::min(dba::kPtBlock, r.n_points - q * dba::kPtBlock);
-        }
-    }
-
-    for (int p = 0; p < np; ++p) {
-        const dba_problem_desc &d = probs[p];
-        const ProblemRange &r = ps->ranges[p];
-        const long long L = d.n_obs;
-        // point-major records, stable in observation order (two-camera
-        // blocks: a record per point copy, in block order within a point)
-        std::vector<int> poff(d.n_points + 1, 0);
-        if (k2)
-            for (int pt : pbs[p].pts) ++poff[pt + 1];
-        else
-            for (long long k = 0; k < L; ++k) ++poff[d.obs_point[k] + 1];
-        for (int i = 0; i < d.n_points; ++i) poff[i + 1] += poff[i];
-        std::vector<int> fill(poff.begin(), poff.end() - 1);
-        std::vector<int> rec_obs(k2 ? 0 : L);
-        if (!k2)
-            for (long long k = 0; k < L; ++k) rec_obs[fill[d.obs_point[k]]++] = (int)k;
-        for (int i = 0; i <= d.n_points; ++i) pt_off[r.pt0 + i] = (int)(r.rec0 + poff[i]);
-        for (int i = 0; i < d.n_points; ++i) {
-            pt_prob[r.pt0 + i] = p;
-            cons_x[r.pt0 + i] = make_double4(d.points[3 * i], d.points[3 * i + 1], d.points[3 * i + 2], 0.0);
-        }
-        // camera-major slots, stable in record order
-        std::vector<int> cc(d.n_cams, 0);
-        for (long long k = 0; k < L; ++k) ++cc[d.obs_cam[k]];
-        std::vector<long long> cslot(d.n_cams);
-        std::vector<int> cseen(d.n_cams, 0);
-        int chunk = r.chunk0;
-        if (k2) {
-            // chunks camera-major: camera j's chunks are its pair's blocks that it observes
-            const PairBlocks &pb = pbs[p];
-            const int nb = (int)pb.cam0.size();
-            std::vector<int> brec(pb.pts.size());
-            for (size_t t = 0; t < pb.pts.size(); ++t) brec[t] = (int)(r.rec0 + fill[pb.pts[t]]++);
-            for (int b = 0; b < nb; ++b)
-                for (int l = 0; l < pb.npts[b]; ++l) {
-                    const int t = pb.pts0[b] + l;
-                    blk_rec[(size_t)(blk_base + b) * CH + l] = brec[t];
-                    const int i = pb.pts[t];
-                    xrec[brec[t]] = dba::PtCopy<R>{(R)d.points[3 * i], (R)d.points[3 * i + 1], (R)d.points[3 * i + 2]};
-                }
-            int b0 = 0;
-            for (int j = 0; j < d.n_cams; ++j) {
-                const int J = r.cam0 + j, sc = j & 1;
-                cam_prob[J] = p;
-                cam_chunk0[J] = chunk;
-                cam_count[J] = cc[j];
-                for (int c = 0; c < 9; ++c) cons_y[(size_t)J * dba::kConsY + c] = d.cams[9 * j + c];
-                if (sc == 0) b0 = (int)(std::lower_bound(pb.cam0.begin(), pb.cam0.end(), j) - pb.cam0.begin());
-                for (int b = b0; b < nb && pb.cam0[b] == j - sc; ++b) {
-                    if (!(pb.present[b] >> sc & 1)) continue;
-                    blk_chunk[2 * (size_t)(blk_base + b) + sc] = chunk;
-                    chunk_cam[chunk] = J;
-                    for (int l = 0; l < pb.npts[b]; ++l) {
-                        const int t = pb.pts0[b] + l;
-                        const long long k = pb.obs[2 * (size_t)t + sc];
-                        if (k < 0) continue;
-                        const long long sl = (long long)chunk * CH + l;
-                        pslot[sl] = brec[t];
-                        ptid[sl] = r.pt0 + pb.pts[t];
-                        orig[sl] = (int)k;
-                        uv[sl].x = (R)d.obs_uv[2 * k];
-                        uv[sl].y = (R)d.obs_uv[2 * k + 1];
-                    }
-                    ++chunk;
-                }
-            }
-            blk_base += nb;
-        } else
-        for (int j = 0; j < d.n_cams; ++j) {
-            const int J = r.cam0 + j;
-            cam_prob[J] = p;
-            cam_chunk0[J] = chunk;
-            cam_count[J] = cc[j];
-            cslot[j] = (long long)chunk * CH;
-            const int nch = (cc[j] + BP - 1) / BP;
-            for (int q = 0; q < nch; ++q) chunk_cam[chunk + q] = J;
-            chunk += nch;
-            for (int c = 0; c < 9; ++c) cons_y[(size_t)J * dba::kConsY + c] = d.cams[9 * j + c];
-        }
-        for (long long rr = 0; rr < (k2 ? 0 : L); ++rr) {
-            const int k = rec_obs[rr];
-            const int j = d.obs_cam[k], i = d.obs_point[k];
-            const int q = cseen[j]++;
-            const long long s = cslot[j] + (long long)(q / BP) * CH + q % BP;
-            pslot[s] = (int)(r.rec0 + rr);
-            ptid[s] = r.pt0 + i;
-            orig[s] = k;
-            uv[s].x = (R)d.obs_uv[2 * k];
-            uv[s].y = (R)d.obs_uv[2 * k + 1];
-            if (per_obs)
-                for (int c = 0; c < 9; ++c) copy_y[(size_t)c * S + s] = (R)d.cams[9 * j + c];
-            xrec[r.rec0 + rr] = dba::PtCopy<R>{(R)d.points[3 * i], (R)d.points[3 * i + 1], (R)d.points[3 * i + 2]};
-        }
         Ctrl &c = ctrl[p];
         std::memset(&c, 0, sizeof(c));
         c.rho_x = h->opt.rho_x;
@@ -347,11 +83,12 @@ int build_set(dba_handle *h, int np, const dba_problem_desc *probs, ProblemSet *
         c.rho_max = h->opt.rho_max;
         c.balancing = h->opt.rho_balancing ? 1 : 0;
     }
-    cam_chunk0[n_cams] = (int)n_chunks;
-    // camera copy per chunk (block local updates), starting at the initial camera
-    std::vector<R> copy_yc(9 * (size_t)n_chunks);
-    for (long long c = 0; c < n_chunks; ++c)
-        for (int i = 0; i < 9; ++i) copy_yc[9 * c + i] = (R)cons_y[(size_t)chunk_cam[c] * dba::kConsY + i];
+    const std::vector<int> &pt_off = lay.pt_off, &chunk_cam = lay.chunk_cam, &cam_prob = lay.cam_prob,
+                           &pt_prob = lay.pt_prob, &cam_chunk0 = lay.cam_chunk0, &cam_count = lay.cam_count,
+                           &pblk_pt0 = lay.pblk_pt0, &pblk_cnt = lay.pblk_cnt, &pslot = lay.pslot,
+                           &ptid = lay.ptid, &orig = lay.orig, &blk_chunk = lay.blk_chunk, &blk_rec = lay.blk_rec;
+    const std::vector<double> &cons_y = lay.cons_y;
+    const std::vector<R> &copy_y = lay.copy_y, &copy_yc = lay.copy_yc;
 
     // device
     Buffers &B = ps->buf;
@@ -389,7 +126,7 @@ int build_set(dba_handle *h, int np, const dba_problem_desc *probs, ProblemSet *
     HIP_TRY(h, B.alloc(&d_epart, (size_t)n_chunks * dba::kEpart));
     HIP_TRY(h, B.alloc(&d_estats, (size_t)np * dba::kEpart));
 
-    HIP_TRY(h, hipMemcpy(d_uv, uv.data(), S * sizeof(R2), hipMemcpyHostToDevice));
+    HIP_TRY(h, hipMemcpy(d_uv, lay.uv.data(), S * sizeof(R2), hipMemcpyHostToDevice));
     HIP_TRY(h, hipMemcpy(d_pslot, pslot.data(), S * sizeof(int), hipMemcpyHostToDevice));
     HIP_TRY(h, hipMemcpy(d_ptid, ptid.data(), S * sizeof(int), hipMemcpyHostToDevice));
     HIP_TRY(h, hipMemcpy(d_orig, orig.data(), S * sizeof(int), hipMemcpyHostToDevice));
@@ -398,7 +135,7 @@ int build_set(dba_handle *h, int np, const dba_problem_desc *probs, ProblemSet *
         HIP_TRY(h, hipMemcpy(d_copy, copy_y.data(), 9 * SY * sizeof(R), hipMemcpyHostToDevice));
         HIP_TRY(h, hipMemset(d_dual, 0, 9 * SY * sizeof(double)));
     }
-    HIP_TRY(h, hipMemcpy(d_xrec, xrec.data(), n_recs * sizeof(dba::PtCopy<R>), hipMemcpyHostToDevice));
+    HIP_TRY(h, hipMemcpy(d_xrec, lay.xrec.data(), n_recs * sizeof(dba::PtCopy<R>), hipMemcpyHostToDevice));
     HIP_TRY(h, hipMemset(d_urec, 0, n_recs * sizeof(dba::PtDual)));
     HIP_TRY(h, hipMemcpy(d_ptoff, pt_off.data(), (n_pts + 1) * sizeof(int), hipMemcpyHostToDevice));
     HIP_TRY(h, hipMemcpy(d_chunk_cam, chunk_cam.data(), n_chunks * sizeof(int), hipMemcpyHostToDevice));
@@ -407,7 +144,7 @@ int build_set(dba_handle *h, int np, const dba_problem_desc *probs, ProblemSet *
     HIP_TRY(h, hipMemcpy(d_cam_chunk0, cam_chunk0.data(), (n_cams + 1) * sizeof(int), hipMemcpyHostToDevice));
     HIP_TRY(h, hipMemcpy(d_cam_count, cam_count.data(), n_cams * sizeof(int), hipMemcpyHostToDevice));
     HIP_TRY(h, hipMemcpy(d_cons_y, cons_y.data(), cons_y.size() * sizeof(double), hipMemcpyHostToDevice));
-    HIP_TRY(h, hipMemcpy(d_cons_x, cons_x.data(), n_pts * sizeof(double4), hipMemcpyHostToDevice));
+    HIP_TRY(h, hipMemcpy(d_cons_x, lay.cons_x.data(), n_pts * sizeof(double4), hipMemcpyHostToDevice));
     HIP_TRY(h, hipMemcpy(d_ctrl, ctrl.data(), np * sizeof(Ctrl), hipMemcpyHostToDevice));
     HIP_TRY(h, hipMemcpy(d_prob, ps->ranges.data(), np * sizeof(ProblemRange), hipMemcpyHostToDevice));
     HIP_TRY(h, hipMemset(d_cpart, 0, (size_t)n_chunks * dba::kCpart * sizeof(double)));
@@ -424,7 +161,7 @@ int build_set(dba_handle *h, int np, const dba_problem_desc *probs, ProblemSet *
         HIP_TRY(h, hipMemcpy(d_blk_chunk, blk_chunk.data(), blk_chunk.size() * sizeof(int), hipMemcpyHostToDevice));
         HIP_TRY(h, hipMemcpy(d_blk_rec, blk_rec.data(), blk_rec.size() * sizeof(int), hipMemcpyHostToDevice));
     }
-    A.n_blocks2 = k2 ? n_blocks : 0;
+    A.n_blocks2 = lay.n_blocks2;
     A.blk_chunk = d_blk_chunk;
     A.blk_rec = d_blk_rec;
     A.camera_blocks = h->opt.camera_blocks ? 1 : 0;
@@ -481,7 +218,7 @@ hipError_t run_iteration_marked(dba_handle *h, const DevArrays<R> &A, int bw, in
     done(e);
     if (err != hipSuccess) return err;
     e = mark(1);
-    err = dba::launch_consensus<R>(A, h->stream);
+    err = dba::launch_consensus<R>(A, h->seg_sched, h->stream);
     done(e);
     if (err != hipSuccess) return err;
     e = mark(2);
@@ -655,7 +392,7 @@ int iterate_impl(dba_handle *h, const DevArrays<R> &A, int n)
         if (err == hipSuccess) err = hipEventRecord(e0, h->stream);
         if (err == hipSuccess) err = launch_local_sel<R>(h, A, cand_bw[q], cand_p[q]);
         if (err == hipSuccess) err = hipEventRecord(e1, h->stream);
-        if (err == hipSuccess) err = dba::launch_consensus<R>(A, h->stream);
+        if (err == hipSuccess) err = dba::launch_consensus<R>(A, h->seg_sched, h->stream);
         if (err == hipSuccess) err = dba::launch_norms<R>(A, h->stream);
         if (err == hipSuccess) err = hipEventSynchronize(e1);
         if (err == hipSuccess) err = hipEventElapsedTime(&ms, e0, e1);
@@ -672,6 +409,37 @@ int iterate_impl(dba_handle *h, const DevArrays<R> &A, int n)
             h->persistent = cand_p[idx[best]];
             h->tuned = (int)idx.size();
             h->schedule_ready = true;
+        }
+    }
+    // then the segment schedule of the consensus, on real iterations with
+    // the local schedule fixed; its candidates are bitwise identical too
+    static const int cand_seg[] = {1, 2, 3};
+    while (!h->seg_ready && n > 0) {
+        const int q = h->seg_next;
+        h->seg_sched = cand_seg[q];
+        hipEvent_t e0 = nullptr, e1 = nullptr;
+        float ms = 0.f;
+        hipError_t err = hipEventCreate(&e0);
+        if (err == hipSuccess) err = hipEventCreate(&e1);
+        if (err == hipSuccess) err = launch_local_sel<R>(h, A, h->block_waves, h->persistent);
+        if (err == hipSuccess) err = hipEventRecord(e0, h->stream);
+        if (err == hipSuccess) err = dba::launch_consensus<R>(A, h->seg_sched, h->stream);
+        if (err == hipSuccess) err = hipEventRecord(e1, h->stream);
+        if (err == hipSuccess) err = dba::launch_norms<R>(A, h->stream);
+        if (err == hipSuccess) err = hipEventSynchronize(e1);
+        if (err == hipSuccess) err = hipEventElapsedTime(&ms, e0, e1);
+        if (e0) (void)hipEventDestroy(e0);
+        if (e1) (void)hipEventDestroy(e1);
+        if (err != hipSuccess) return fail(h, DBA_E_DEVICE, "segment schedule tuning: %s", hipGetErrorString(err));
+        h->seg_ms.push_back(ms);
+        --n;
+        if (++h->seg_next == 3) {
+            int best = 0;
+            for (int t = 1; t < 3; ++t)
+                if (h->seg_ms[t] < h->seg_ms[best]) best = t;
+            h->seg_sched = cand_seg[best];
+            h->seg_tuned = 3;
+            h->seg_ready = true;
         }
     }
     if (n <= 0) return DBA_OK;
@@ -756,6 +524,7 @@ int dba_default_options(dba_options *o)
     o->camera_model = DBA_CAMERA_ANGLE_AXIS;
     o->local_solver = DBA_SOLVER_LM;
     o->block_cameras = 1;
+    o->segment_schedule = 0;
     return DBA_OK;
 }
 
@@ -790,6 +559,7 @@ int dba_create(const dba_options *opt, dba_handle **out)
         return DBA_E_INVALID_ARG;
     if (o.block_cameras != 1 && o.block_cameras != 2) return DBA_E_INVALID_ARG;
     if (o.block_cameras == 2 && !o.camera_blocks) return DBA_E_INVALID_ARG;
+    if (o.segment_schedule < 0 || o.segment_schedule > 3) return DBA_E_INVALID_ARG;
     dba_handle *h = new dba_handle();
     h->opt = o;
     h->fp32 = o.precision == DBA_PREC_FP32_LOCAL;
@@ -819,6 +589,8 @@ int dba_create(const dba_options *opt, dba_handle **out)
     h->block_waves = o.block_waves ? o.block_waves : 4;
     h->persistent = o.persistent < 0 ? 0 : o.persistent;
     h->schedule_ready = o.block_waves != 0 && o.persistent >= 0;
+    h->seg_sched = o.segment_schedule ? o.segment_schedule : 1;
+    h->seg_ready = o.segment_schedule != 0;
     *out = h;
     return DBA_OK;
 }
@@ -859,6 +631,11 @@ int dba_set_problems(dba_handle *h, int32_t np, const dba_problem_desc *probs)
     h->ps = ps;
     h->schedule_ready = h->opt.block_waves != 0 && h->opt.persistent >= 0;
     h->tune_next = 0;
+    h->seg_ready = h->opt.segment_schedule != 0;
+    h->seg_sched = h->opt.segment_schedule ? h->opt.segment_schedule : 1;
+    h->seg_next = 0;
+    h->seg_tuned = 0;
+    h->seg_ms.clear();
     return DBA_OK;
 }
 
@@ -1044,6 +821,14 @@ int dba_schedule(const dba_handle *h, int32_t *bw, int32_t *pers, int32_t *tuned
     if (bw) *bw = h->block_waves;
     if (pers) *pers = h->persistent;
     if (tuned) *tuned = h->tuned;
+    return DBA_OK;
+}
+
+int dba_segment_schedule(const dba_handle *h, int32_t *segment_schedule, int32_t *tuned)
+{
+    if (!h) return DBA_E_INVALID_ARG;
+    if (segment_schedule) *segment_schedule = h->seg_sched;
+    if (tuned) *tuned = h->seg_tuned;
     return DBA_OK;
 }
 

@@ -81,6 +81,7 @@ struct Mlp {
     float *norm = nullptr;    // kNormTotal
     float *xform = nullptr;   // [2][kIn] input scale and shift
     float *adam_m = nullptr, *adam_v = nullptr, *grad = nullptr;
+    long long adam_t = 0;     // Adam steps taken since the moments were zeroed
     MlpParams params() const
     {
         return MlpParams{w, master + kPB1, master + kPB2, master + kPB3, norm, xform};
@@ -104,6 +105,11 @@ struct dba_handle {
     bool schedule_ready = false;
     int tune_next = 0;
     std::vector<float> tune_ms;
+    // segment schedule of the point consensus (1 direct loads, 2 / 3 LDS tiles)
+    int seg_sched = 1, seg_tuned = 0;
+    bool seg_ready = false;
+    int seg_next = 0;
+    std::vector<float> seg_ms;
     // graphs: [0] one iteration, [1] kGraphBatch iterations
     hipGraphExec_t gexec[2] = {nullptr, nullptr};
     dba::host::Timing timing;
@@ -139,6 +145,8 @@ inline int fail(dba_handle *h, int code, const char *fmt, ...)
     } while (0)
 
 void drop_graphs(dba_handle *h);
+// Reads the kernel times of launches still pending (kernel timing mode).
+int collect_timing(dba_handle *h);
 
 }  // namespace host
 }  // namespace dba

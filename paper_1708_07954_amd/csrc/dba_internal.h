@@ -27,11 +27,11 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include "dba_layout.h"  // kChunk, kConsY, kPtBlock, ProblemRange
+
 namespace dba {
 
-constexpr int kChunk = 64;
 constexpr int kCpart = 20;     // doubles per chunk partial: 9 sum(copy+u), 9 sum(d), 1 sum|d|^2, pad
-constexpr int kConsY = 16;     // doubles per camera consensus row
 constexpr int kEpart = 5;      // doubles per chunk of the reprojection statistics
 constexpr int kNormThreads = 256;
 
@@ -47,16 +47,6 @@ struct Ctrl {
     int balancing;
     int pad[3];
 };
-
-struct ProblemRange {              // per problem, global index ranges
-    int cam0, n_cams;
-    int pt0, n_points;
-    int chunk0, n_chunks;
-    int pblk0, n_pblk;             // point blocks of the consensus kernel
-    long long rec0, n_obs;
-};
-
-constexpr int kPtBlock = 256;      // points per consensus block (never straddles problems)
 
 template <typename R> struct Vec;
 template <> struct Vec<float> { using R2 = float2; };
@@ -153,7 +143,7 @@ template <typename R>
 hipError_t launch_local_block(const DevArrays<R> &a, const SolverParams &sp, int block_waves, int persistent,
                               int n_cu, hipStream_t s);
 template <typename R>
-hipError_t launch_consensus(const DevArrays<R> &a, hipStream_t s);
+hipError_t launch_consensus(const DevArrays<R> &a, int schedule, hipStream_t s);
 
 // network kernels (mlp_kernels.hip)
 hipError_t mlp_pack(const float *P, __bf16 *w, hipStream_t s);

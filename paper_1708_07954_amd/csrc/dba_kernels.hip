@@ -6,7 +6,7 @@
 //            previous iteration, then minimises the local objective of Eq. (9)
 //            in scaled form, F = phi(|z - pi(theta)|^2) + 1/2 (theta - v)^T P
 //            (theta - v), by robust Levenberg-Marquardt: the 12x12 normal
-//            equations and their LDL^T (Cholesky) factor live in registers.
+//            equations (diagonal plus rank two) are solved in registers.
 //            Emits the chunk's sums for the camera consensus with a fixed
 //            butterfly.
 // consensus  point consensus (Eq. 10): one thread per point, ascending record
@@ -396,46 +396,89 @@ __global__ __launch_bounds__(64 * kLearnedWaves) void k_local_learned(DevArrays<
 }
 
 // ---------------------------------------------------------------- consensus
-template <typename R>
+// Point consensus: thread t of a block sums the records of point p0 + t in
+// record order.  TILE (the segment schedule): 0 -- each thread loads its own
+// records, four in flight; > 0 -- the block's records, which are contiguous,
+// are staged through LDS TILE at a time with coalesced loads, and each thread
+// sums its part of every tile.  Every schedule sums each point's records in
+// the same order, so the results are bitwise identical.
+template <typename R, int TILE>
 __global__ __launch_bounds__(256) void k_consensus(DevArrays<R> a, int pt_blocks)
 {
     if ((int)blockIdx.x < pt_blocks) {
         __shared__ double sh[2][kPtBlock];
         const int b = blockIdx.x;
         double pri = 0.0, dual = 0.0;
-        if ((int)threadIdx.x < a.pblk_cnt[b]) {
-            const int i = a.pblk_pt0[b] + threadIdx.x;
-            const int r0 = a.pt_off[i], r1 = a.pt_off[i + 1];
-            // one pass: sums of copy + dual (the consensus) and of the copies'
-            // offsets d_r from the previous consensus, which give
-            // sum_r |copy_r - new|^2 = sum |d_r|^2 - 2 e . sum d_r + n |e|^2,
-            // e = new - previous
-            const double4 old = a.cons_x[i];
-            double s0 = 0.0, s1 = 0.0, s2 = 0.0, q0 = 0.0, q1 = 0.0, q2 = 0.0, qq = 0.0;
-            auto add = [&](const PtCopy<R> &x, const PtDual &u) {
-                s0 += (double)x.x + u.x;
-                s1 += (double)x.y + u.y;
-                s2 += (double)x.z + u.z;
-                const double d0 = (double)x.x - old.x, d1 = (double)x.y - old.y, d2 = (double)x.z - old.z;
-                q0 += d0;
-                q1 += d1;
-                q2 += d2;
-                qq += d0 * d0 + d1 * d1 + d2 * d2;
-            };
-            // four records' loads in flight, summed in record order
-            int r = r0;
-            for (; r + 4 <= r1; r += 4) {
-                PtCopy<R> x[4];
-                PtDual u[4];
+        const int cnt = a.pblk_cnt[b], p0 = a.pblk_pt0[b];
+        const bool has = (int)threadIdx.x < cnt;
+        const int i = p0 + threadIdx.x;
+        int r0 = 0, r1 = 0;
+        double4 old = make_double4(0.0, 0.0, 0.0, 0.0);
+        if (has) {
+            r0 = a.pt_off[i];
+            r1 = a.pt_off[i + 1];
+            old = a.cons_x[i];
+        }
+        // one pass: sums of copy + dual (the consensus) and of the copies'
+        // offsets d_r from the previous consensus, which give
+        // sum_r |copy_r - new|^2 = sum |d_r|^2 - 2 e . sum d_r + n |e|^2,
+        // e = new - previous
+        double s0 = 0.0, s1 = 0.0, s2 = 0.0, q0 = 0.0, q1 = 0.0, q2 = 0.0, qq = 0.0;
+        auto add = [&](R x0, R x1, R x2, double u0, double u1, double u2) {
+            s0 += (double)x0 + u0;
+            s1 += (double)x1 + u1;
+            s2 += (double)x2 + u2;
+            const double d0 = (double)x0 - old.x, d1 = (double)x1 - old.y, d2 = (double)x2 - old.z;
+            q0 += d0;
+            q1 += d1;
+            q2 += d2;
+            qq += d0 * d0 + d1 * d1 + d2 * d2;
+        };
+        if constexpr (TILE == 0) {
+            if (has) {
+                // four records' loads in flight, summed in record order
+                int r = r0;
+                for (; r + 4 <= r1; r += 4) {
+                    PtCopy<R> x[4];
+                    PtDual u[4];
 #pragma unroll
-                for (int j = 0; j < 4; ++j) {
-                    x[j] = a.xrec[r + j];
-                    u[j] = a.urec[r + j];
+                    for (int j = 0; j < 4; ++j) {
+                        x[j] = a.xrec[r + j];
+                        u[j] = a.urec[r + j];
+                    }
+#pragma unroll
+                    for (int j = 0; j < 4; ++j) add(x[j].x, x[j].y, x[j].z, u[j].x, u[j].y, u[j].z);
                 }
-#pragma unroll
-                for (int j = 0; j < 4; ++j) add(x[j], u[j]);
+                for (; r < r1; ++r) {
+                    const PtCopy<R> x = a.xrec[r];
+                    const PtDual u = a.urec[r];
+                    add(x.x, x.y, x.z, u.x, u.y, u.z);
+                }
             }
-            for (; r < r1; ++r) add(a.xrec[r], a.urec[r]);
+        } else {
+            __shared__ R xs[3 * TILE];
+            __shared__ double us[3 * TILE];
+            const int a0 = a.pt_off[p0], a1 = a.pt_off[p0 + cnt];  // the block's records
+            for (int t0 = a0; t0 < a1; t0 += TILE) {
+                const int n3 = 3 * min(TILE, a1 - t0);
+                const R *xg = reinterpret_cast<const R *>(a.xrec + t0);
+                const double *ug = reinterpret_cast<const double *>(a.urec + t0);
+                for (int q = threadIdx.x; q < n3; q += 256) {
+                    xs[q] = xg[q];
+                    us[q] = ug[q];
+                }
+                __syncthreads();
+                if (has) {
+                    const int lo = max(r0, t0), hi = min(r1, t0 + TILE);
+                    for (int r = lo; r < hi; ++r) {
+                        const int q = 3 * (r - t0);
+                        add(xs[q], xs[q + 1], xs[q + 2], us[q], us[q + 1], us[q + 2]);
+                    }
+                }
+                __syncthreads();
+            }
+        }
+        if (has) {
             const double n = (double)(r1 - r0);
             const double c0 = s0 / n, c1 = s1 / n, c2 = s2 / n;
             const double e0 = c0 - old.x, e1 = c1 - old.y, e2 = c2 - old.z;
@@ -719,10 +762,16 @@ hipError_t launch_local_learned(const DevArrays<float> &a, const SolverParams &s
 }
 
 template <typename R>
-hipError_t launch_consensus(const DevArrays<R> &a, hipStream_t s)
+hipError_t launch_consensus(const DevArrays<R> &a, int schedule, hipStream_t s)
 {
     const int cam_blocks = (a.n_cams + 3) / 4;
-    hipLaunchKernelGGL(k_consensus<R>, dim3(a.n_pblk + cam_blocks), dim3(256), 0, s, a, a.n_pblk);
+    const dim3 grid(a.n_pblk + cam_blocks), block(256);
+    if (schedule == 2)
+        hipLaunchKernelGGL((k_consensus<R, 512>), grid, block, 0, s, a, a.n_pblk);
+    else if (schedule == 3)
+        hipLaunchKernelGGL((k_consensus<R, 1024>), grid, block, 0, s, a, a.n_pblk);
+    else
+        hipLaunchKernelGGL((k_consensus<R, 0>), grid, block, 0, s, a, a.n_pblk);
     return hipGetLastError();
 }
 
@@ -801,7 +850,7 @@ hipError_t launch_materialize(const DevArrays<R> &a, int problem, double *copies
                                         hipStream_t);                                             \
     template hipError_t launch_local_block<R>(const DevArrays<R> &, const SolverParams &, int, int, int, \
                                               hipStream_t);                                       \
-    template hipError_t launch_consensus<R>(const DevArrays<R> &, hipStream_t);                   \
+    template hipError_t launch_consensus<R>(const DevArrays<R> &, int, hipStream_t);              \
     template hipError_t launch_norms<R>(const DevArrays<R> &, hipStream_t);                       \
     template hipError_t launch_eval<R>(const DevArrays<R> &, const SolverParams &, hipStream_t);  \
     template hipError_t launch_materialize<R>(const DevArrays<R> &, int, double *, double *,      \

@@ -49,10 +49,37 @@ int upload_mlp(dba_handle *h, const float *params, const float *norm)
     }
     HIP_TRY(h, hipMemcpyAsync(h->mlp->xform, xf, sizeof(xf), hipMemcpyHostToDevice, h->stream));
     HIP_TRY(h, dba::mlp_pack(h->mlp->master, h->mlp->w, h->stream));
+    // a new network starts its optimiser state from zero
+    HIP_TRY(h, hipMemsetAsync(h->mlp->adam_m, 0, dba::kPTotal * sizeof(float), h->stream));
+    HIP_TRY(h, hipMemsetAsync(h->mlp->adam_v, 0, dba::kPTotal * sizeof(float), h->stream));
+    h->mlp->adam_t = 0;
     HIP_TRY(h, hipStreamSynchronize(h->stream));
     h->mlp->ready = true;
     drop_graphs(h);
     return DBA_OK;
+}
+
+// One Adam step (bias-corrected, step counter t + 1) of the master
+// parameters with the gradient already in M.grad, then the bf16 weights.
+int adam_step(dba_handle *h, double lr)
+{
+    Mlp &M = *h->mlp;
+    const long long t = ++M.adam_t;
+    const double bc1 = 1.0 - std::pow(0.9, (double)t), bc2 = 1.0 - std::pow(0.999, (double)t);
+    HIP_TRY(h, dba::mlp_adam(M.master, M.adam_m, M.adam_v, M.grad, (float)lr, (float)bc1, (float)bc2, h->stream));
+    HIP_TRY(h, dba::mlp_pack(M.master, M.w, h->stream));
+    return DBA_OK;
+}
+
+// Sets the local start; cached graphs (plain and timed) are captured with
+// one start's kernel, so a change reads pending kernel times and drops them.
+int switch_start(dba_handle *h, int start)
+{
+    if (h->start == start) return DBA_OK;
+    const int rc = collect_timing(h);
+    drop_graphs(h);
+    h->start = start;
+    return rc;
 }
 
 }  // namespace
@@ -106,10 +133,11 @@ int dba_set_start(dba_handle *h, int32_t start, int32_t learned_lm_steps)
         return fail(h, DBA_E_INVALID_ARG, "the learned start runs with FP32 local solves");
     if (start == DBA_START_LEARNED && h->opt.camera_blocks)
         return fail(h, DBA_E_INVALID_ARG, "the learned start is for one observation per local problem");
-    h->start = start;
     h->sp.learned_steps = learned_lm_steps;
+    const int rc = collect_timing(h);
     drop_graphs(h);
-    return DBA_OK;
+    h->start = start;
+    return rc;
 }
 
 int dba_mlp_forward(dba_handle *h, const float *features, int64_t n, float *delta)
@@ -186,6 +214,35 @@ int dba_mlp_loss_grad(dba_handle *h, const float *x_std, const float *t_std, int
     return DBA_OK;
 }
 
+int dba_mlp_apply_gradient(dba_handle *h, const float *grad, double lr)
+{
+    if (!h || !grad || !(lr > 0) || !std::isfinite(lr)) return DBA_E_INVALID_ARG;
+    h->err.clear();
+    if (!h->mlp || !h->mlp->ready) return fail(h, DBA_E_STATE, "no network set");
+    for (int q = 0; q < dba::kPTotal; ++q)
+        if (!std::isfinite(grad[q])) return fail(h, DBA_E_NONFINITE, "gradient entry %d not finite", q);
+    HIP_TRY(h, hipSetDevice(h->opt.device));
+    HIP_TRY(h, hipMemcpyAsync(h->mlp->grad, grad, dba::kPTotal * sizeof(float), hipMemcpyHostToDevice, h->stream));
+    const int rc = adam_step(h, lr);
+    if (rc != DBA_OK) return rc;
+    HIP_TRY(h, hipStreamSynchronize(h->stream));
+    drop_graphs(h);
+    return DBA_OK;
+}
+
+int dba_mlp_adam_state(dba_handle *h, float *m, float *v, int64_t *step)
+{
+    if (!h) return DBA_E_INVALID_ARG;
+    h->err.clear();
+    if (!h->mlp || !h->mlp->ready) return fail(h, DBA_E_STATE, "no network set");
+    HIP_TRY(h, hipSetDevice(h->opt.device));
+    if (m) HIP_TRY(h, hipMemcpyAsync(m, h->mlp->adam_m, dba::kPTotal * sizeof(float), hipMemcpyDeviceToHost, h->stream));
+    if (v) HIP_TRY(h, hipMemcpyAsync(v, h->mlp->adam_v, dba::kPTotal * sizeof(float), hipMemcpyDeviceToHost, h->stream));
+    HIP_TRY(h, hipStreamSynchronize(h->stream));
+    if (step) *step = h->mlp->adam_t;
+    return DBA_OK;
+}
+
 int dba_collect_pairs(dba_handle *h, int32_t n_iters, int32_t per_iter, uint64_t seed, int32_t conv_steps,
                       float *features, float *deltas)
 {
@@ -211,7 +268,10 @@ int dba_collect_pairs(dba_handle *h, int32_t n_iters, int32_t per_iter, uint64_t
     std::vector<int> pick(per_iter);
     uint64_t st = seed;
     const int saved = h->start;
-    h->start = DBA_START_PLAIN;
+    // the captured graphs hold the local kernel of the start they were
+    // captured with: switching the start drops them, both ways
+    int rc0 = switch_start(h, DBA_START_PLAIN);
+    if (rc0 != DBA_OK) return rc0;
     for (int it = 0; it < n_iters; ++it) {
         for (int q = 0; q < per_iter; ++q) pick[q] = active[(size_t)(uniform01(st) * active.size()) % active.size()];
         HIP_TRY(h, hipMemcpyAsync(dslots, pick.data(), per_iter * sizeof(int), hipMemcpyHostToDevice, h->stream));
@@ -223,11 +283,12 @@ int dba_collect_pairs(dba_handle *h, int32_t n_iters, int32_t per_iter, uint64_t
         HIP_TRY(h, hipStreamSynchronize(h->stream));
         const int rc = dba_iterate(h, 1);
         if (rc != DBA_OK) {
-            h->start = saved;
+            (void)switch_start(h, saved);
             return rc;
         }
     }
-    h->start = saved;
+    rc0 = switch_start(h, saved);
+    if (rc0 != DBA_OK) return rc0;
     HIP_TRY(h, hipStreamSynchronize(h->stream));
     return DBA_OK;
 }
@@ -273,8 +334,6 @@ int dba_mlp_train(dba_handle *h, const float *features, const float *deltas, int
     int rc = upload_mlp(h, P.data(), norm.data());
     if (rc != DBA_OK) return rc;
     Mlp &M = *h->mlp;
-    HIP_TRY(h, hipMemsetAsync(M.adam_m, 0, dba::kPTotal * sizeof(float), h->stream));
-    HIP_TRY(h, hipMemsetAsync(M.adam_v, 0, dba::kPTotal * sizeof(float), h->stream));
     // device data
     Buffers B;
     float *dfeat, *ddel, *t, *y, *gp1, *gp2, *dy, *dz2, *dz1, *lp;
@@ -325,9 +384,8 @@ int dba_mlp_train(dba_handle *h, const float *features, const float *deltas, int
             HIP_TRY(h, dba::mlp_bias(dy, dz2, dz1, batch, M.grad, h->stream));
             ++step;
             const double lr_t = lr * 0.5 * (1.0 + std::cos(M_PI * (double)(step - 1) / (double)total));
-            const double bc1 = 1.0 - std::pow(0.9, (double)step), bc2 = 1.0 - std::pow(0.999, (double)step);
-            HIP_TRY(h, dba::mlp_adam(M.master, M.adam_m, M.adam_v, M.grad, (float)lr_t, (float)bc1, (float)bc2, h->stream));
-            HIP_TRY(h, dba::mlp_pack(M.master, M.w, h->stream));
+            rc = adam_step(h, lr_t);
+            if (rc != DBA_OK) return rc;
         }
         HIP_TRY(h, hipMemcpyAsync(lh.data(), lp, lh.size() * sizeof(float), hipMemcpyDeviceToHost, h->stream));
         HIP_TRY(h, hipStreamSynchronize(h->stream));

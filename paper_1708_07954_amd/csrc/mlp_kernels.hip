@@ -17,6 +17,7 @@
 #include "mlp_device.h"
 
 namespace dba {
+
 namespace {
 
 using namespace dev;

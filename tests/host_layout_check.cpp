@@ -1,0 +1,308 @@
+// Host-side layout builder (paper_1708_07954_amd/csrc/dba_layout.cpp) on the
+// CPU, meant to run under AddressSanitizer and UndefinedBehaviorSanitizer:
+// builds the layouts of edge-case problem sets (one-observation cameras and
+// points, cameras whose observations end on and just past chunk boundaries,
+// a 157-chunk camera, 300-record tracks, block sizes 1..64, two-camera
+// blocks with an odd camera count, batches holding a one-observation
+// problem) and checks every invariant the kernels rely on, plus the
+// validation errors.  Prints "ok <layouts>" and exits 0, or names the first
+// broken invariant and exits 1.
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstdlib>
+#include <random>
+#include <set>
+#include <string>
+#include <vector>
+
+#include "dba_layout.h"
+
+namespace {
+
+struct Prob {
+    int m = 0, n = 0;
+    std::vector<int> oc, op;
+    std::vector<double> uv, cams, pts;
+    dba_problem_desc desc() const
+    {
+        dba_problem_desc d{};
+        d.n_cams = m;
+        d.n_points = n;
+        d.n_obs = (int64_t)oc.size();
+        d.obs_cam = oc.data();
+        d.obs_point = op.data();
+        d.obs_uv = uv.data();
+        d.cams = cams.data();
+        d.points = pts.data();
+        return d;
+    }
+};
+
+int g_fail = 0;
+#define CHECK(cond, ...)                                            \
+    do {                                                            \
+        if (!(cond)) {                                              \
+            std::fprintf(stderr, "FAIL %s:%d: ", __FILE__, __LINE__); \
+            std::fprintf(stderr, __VA_ARGS__);                      \
+            std::fprintf(stderr, "\n");                             \
+            g_fail = 1;                                             \
+            return;                                                 \
+        }                                                           \
+    } while (0)
+
+// cameras at the origin looking down +z (zero rotation, t = (0, 0, 10)),
+// points in [-1, 1]^3: every depth is about 10
+Prob make(int m, int n, const std::vector<std::pair<int, int>> &obs, unsigned seed, bool euler = false)
+{
+    Prob p;
+    p.m = m;
+    p.n = n;
+    std::mt19937 rng(seed);
+    std::uniform_real_distribution<double> U(-1.0, 1.0);
+    for (auto &o : obs) {
+        p.oc.push_back(o.first);
+        p.op.push_back(o.second);
+        p.uv.push_back(400 * U(rng));
+        p.uv.push_back(400 * U(rng));
+    }
+    for (int j = 0; j < m; ++j) {
+        const double c[9] = {0.01 * U(rng), 0.01 * U(rng), 0.01 * U(rng), U(rng), U(rng), 10.0, 800.0,
+                             euler ? 0.0 : 0.01 * U(rng), euler ? 0.0 : 0.01 * U(rng)};
+        p.cams.insert(p.cams.end(), c, c + 9);
+    }
+    for (int i = 0; i < 3 * n; ++i) p.pts.push_back(U(rng));
+    return p;
+}
+
+// each point seen by k distinct random cameras, observations shuffled
+Prob random_problem(int m, int n, int k_lo, int k_hi, unsigned seed)
+{
+    std::mt19937 rng(seed);
+    std::vector<std::pair<int, int>> obs;
+    for (int i = 0; i < n; ++i) {
+        const int k = k_lo + (int)(rng() % (unsigned)(k_hi - k_lo + 1));
+        std::set<int> cs;
+        while ((int)cs.size() < std::min(k, m)) cs.insert((int)(rng() % (unsigned)m));
+        for (int j : cs) obs.push_back({j, i});
+    }
+    for (int j = 0; j < m; ++j) obs.push_back({j, (int)(rng() % (unsigned)n)});  // every camera observed
+    // drop repeated (camera, point) pairs, keep the first
+    std::set<std::pair<int, int>> seen;
+    std::vector<std::pair<int, int>> uniq;
+    for (auto &o : obs)
+        if (seen.insert(o).second) uniq.push_back(o);
+    std::shuffle(uniq.begin(), uniq.end(), rng);
+    return make(m, n, uniq, seed + 1);
+}
+
+template <typename R>
+void check_layout(const char *name, const dba::LayoutOptions &o, const std::vector<Prob> &ps)
+{
+    std::vector<dba_problem_desc> d;
+    for (const Prob &p : ps) d.push_back(p.desc());
+    for (size_t q = 0; q < d.size(); ++q) {
+        std::string err;
+        CHECK(dba::validate_problem((int)q, d[q], o.camera_model, &err) == DBA_OK, "%s: validation: %s", name,
+              err.c_str());
+    }
+    dba::Layout<R> L;
+    std::string err;
+    const int rc = dba::build_layout<R>(o, (int)d.size(), d.data(), &L, &err);
+    CHECK(rc == DBA_OK, "%s: build_layout: %s", name, err.c_str());
+    const int CH = dba::kChunk;
+    const int BP = o.camera_blocks && o.block_points ? o.block_points : CH;
+    const bool k2 = o.camera_blocks && o.block_cameras == 2;
+    CHECK(L.n_slots == L.n_chunks * CH, "%s: slots", name);
+    CHECK((long long)L.pslot.size() == L.n_slots && (long long)L.uv.size() == 2 * L.n_slots, "%s: slot arrays", name);
+    CHECK((int)L.cam_chunk0.size() == L.n_cams + 1 && L.cam_chunk0[L.n_cams] == L.n_chunks, "%s: cam_chunk0", name);
+    for (int J = 0; J < L.n_cams; ++J) {
+        CHECK(L.cam_chunk0[J] <= L.cam_chunk0[J + 1], "%s: cam_chunk0 order", name);
+        for (int c = L.cam_chunk0[J]; c < L.cam_chunk0[J + 1]; ++c)
+            CHECK(L.chunk_cam[c] == J, "%s: chunk %d of camera %d", name, c, J);
+    }
+    std::vector<int> rec_used(L.n_recs, 0);
+    for (size_t q = 0; q < ps.size(); ++q) {
+        const Prob &P = ps[q];
+        const dba::ProblemRange &r = L.ranges[q];
+        CHECK(L.pt_off[r.pt0] == r.rec0, "%s: first record of problem %zu", name, q);
+        for (int i = 0; i < P.n; ++i) {
+            CHECK(L.pt_off[r.pt0 + i] <= L.pt_off[r.pt0 + i + 1], "%s: pt_off order", name);
+            CHECK(L.pt_prob[r.pt0 + i] == (int)q, "%s: pt_prob", name);
+            for (int c = 0; c < 3; ++c)
+                CHECK(L.cons_x[4 * (size_t)(r.pt0 + i) + c] == P.pts[3 * i + c], "%s: cons_x", name);
+        }
+        // every observation in exactly one slot of its camera's chunks
+        std::vector<int> hits(P.oc.size(), 0);
+        for (long long c = r.chunk0; c < r.chunk0 + r.n_chunks; ++c) {
+            int active = 0;
+            for (int l = 0; l < CH; ++l) {
+                const long long s = c * CH + l;
+                if (L.pslot[s] < 0) continue;
+                ++active;
+                const int k = L.orig[s];
+                CHECK(k >= 0 && k < (int)P.oc.size(), "%s: slot %lld observation %d", name, s, k);
+                ++hits[k];
+                CHECK(L.chunk_cam[c] == r.cam0 + P.oc[k], "%s: slot %lld camera", name, s);
+                CHECK(L.ptid[s] == r.pt0 + P.op[k], "%s: slot %lld point", name, s);
+                CHECK(L.uv[2 * s] == (R)P.uv[2 * k] && L.uv[2 * s + 1] == (R)P.uv[2 * k + 1], "%s: slot uv", name);
+                const int rec = L.pslot[s];
+                CHECK(rec >= L.pt_off[L.ptid[s]] && rec < L.pt_off[L.ptid[s] + 1], "%s: slot %lld record %d", name,
+                      s, rec);
+                ++rec_used[rec];
+                if (!k2) {
+                    CHECK(l < BP, "%s: lane %d past the block size %d", name, l, BP);
+                    if (!o.camera_blocks)
+                        for (int t = 0; t < 9; ++t)
+                            CHECK(L.copy_y[(size_t)t * L.n_slots + s] == (R)P.cams[9 * P.oc[k] + t], "%s: copy_y",
+                                  name);
+                }
+            }
+            CHECK(active > 0, "%s: empty chunk %lld", name, c);
+            if (!k2) {  // a camera's chunks are full except its last
+                const int J = L.chunk_cam[c];
+                const int q0 = (int)(c - L.cam_chunk0[J]);
+                const int want = std::min(BP, L.cam_count[J] - q0 * BP);
+                CHECK(active == want, "%s: chunk %lld holds %d, want %d", name, c, active, want);
+            }
+        }
+        for (size_t k = 0; k < P.oc.size(); ++k) CHECK(hits[k] == 1, "%s: observation %zu in %d slots", name, k, hits[k]);
+    }
+    if (!k2) {
+        for (long long t = 0; t < L.n_recs; ++t) CHECK(rec_used[t] == 1, "%s: record %lld used %d times", name, t,
+                                                       rec_used[t]);
+    } else {
+        for (int b = 0; b < L.n_blocks2; ++b)
+            for (int s = 0; s < 2; ++s) {
+                const int c = L.blk_chunk[2 * (size_t)b + s];
+                if (c < 0) continue;
+                CHECK(c < L.n_chunks, "%s: block chunk", name);
+                for (int l = 0; l < CH; ++l)
+                    if (L.pslot[(long long)c * CH + l] >= 0)
+                        CHECK(L.pslot[(long long)c * CH + l] == L.blk_rec[(size_t)b * CH + l], "%s: block lane record",
+                              name);
+            }
+        for (long long t = 0; t < L.n_recs; ++t) CHECK(rec_used[t] >= 1 && rec_used[t] <= 2, "%s: copy record %lld",
+                                                       name, t);
+    }
+    for (int b = 0; b < L.n_pblk; ++b) CHECK(L.pblk_cnt[b] >= 1 && L.pblk_cnt[b] <= dba::kPtBlock, "%s: point block", name);
+    for (long long c = 0; c < L.n_chunks; ++c)
+        for (int t = 0; t < 9; ++t)
+            CHECK(L.copy_yc[9 * c + t] == (R)L.cons_y[(size_t)L.chunk_cam[c] * dba::kConsY + t], "%s: copy_yc", name);
+}
+
+void check_validation()
+{
+    Prob p = make(2, 2, {{0, 0}, {1, 1}, {0, 1}}, 5);
+    auto expect = [&](Prob q, int code, const char *what, int cam_model = 0) {
+        std::string err;
+        dba_problem_desc d = q.desc();
+        const int rc = dba::validate_problem(0, d, cam_model, &err);
+        if (rc != code) {
+            std::fprintf(stderr, "FAIL validation %s: %d, want %d (%s)\n", what, rc, code, err.c_str());
+            g_fail = 1;
+        }
+    };
+    expect(p, DBA_OK, "valid");
+    Prob q = p;
+    q.oc[1] = 2;
+    expect(q, DBA_E_INDEX_RANGE, "camera out of range");
+    q = p;
+    q.op[0] = -1;
+    expect(q, DBA_E_INDEX_RANGE, "negative point");
+    q = p;
+    q.uv[3] = NAN;
+    expect(q, DBA_E_NONFINITE, "observation");
+    q = p;
+    q.cams[4] = INFINITY;
+    expect(q, DBA_E_NONFINITE, "camera value");
+    q = make(3, 2, {{0, 0}, {1, 1}}, 6);
+    expect(q, DBA_E_UNOBSERVED, "unobserved camera");
+    q = make(2, 3, {{0, 0}, {1, 1}}, 7);
+    expect(q, DBA_E_UNOBSERVED, "unobserved point");
+    q = p;
+    q.pts[2] = -20.0;
+    expect(q, DBA_E_BEHIND_CAMERA, "behind the camera");
+    expect(p, DBA_E_INVALID_ARG, "Euler camera with distortion", 1);
+    q = p;
+    q.oc.clear();
+    q.op.clear();
+    q.uv.clear();
+    expect(q, DBA_E_INVALID_ARG, "no observation");
+}
+
+}  // namespace
+
+int main()
+{
+    int layouts = 0;
+    std::vector<Prob> set1 = {random_problem(37, 900, 2, 15, 11)};
+    // cameras with 1, 63, 64, 65, 128, 129 observations, a 1-observation point
+    {
+        std::vector<std::pair<int, int>> obs;
+        const int counts[6] = {1, 63, 64, 65, 128, 129};
+        int start = 0;   // consecutive runs of points, cyclic: every point covered
+        for (int j = 0; j < 6; ++j) {
+            for (int c = 0; c < counts[j]; ++c) obs.push_back({j, (start + c) % 150});
+            start = (start + counts[j]) % 150;
+        }
+        obs.push_back({6, 149});   // a camera with one observation of a point seen twice
+        set1.push_back(make(7, 150, obs, 12));
+    }
+    // a 157-chunk camera (10 048 observations) and a 300-record track
+    {
+        std::vector<std::pair<int, int>> obs;
+        for (int i = 0; i < 10048; ++i) obs.push_back({0, i});
+        for (int j = 1; j < 300; ++j) obs.push_back({j, 7});
+        set1.push_back(make(300, 10048, obs, 13));
+    }
+    // a one-observation problem
+    set1.push_back(make(1, 1, {{0, 0}}, 14));
+    for (size_t q = 0; q < set1.size(); ++q) {
+        std::vector<Prob> one = {set1[q]};
+        dba::LayoutOptions o;
+        check_layout<float>("per observation", o, one);
+        check_layout<double>("per observation fp64", o, one);
+        layouts += 2;
+    }
+    dba::LayoutOptions o;
+    check_layout<float>("batch", o, set1);
+    ++layouts;
+    for (int bp : {1, 7, 16, 32, 63, 64}) {
+        dba::LayoutOptions ob;
+        ob.camera_blocks = 1;
+        ob.block_points = bp == 64 ? 0 : bp;
+        check_layout<float>("one-camera blocks", ob, set1);
+        ++layouts;
+    }
+    // two-camera blocks: odd camera counts, runs of 16 and 64
+    std::vector<Prob> set2 = {random_problem(9, 300, 2, 6, 21), random_problem(4, 80, 1, 4, 22),
+                              make(1, 1, {{0, 0}}, 23)};
+    for (int bp : {16, 0}) {
+        dba::LayoutOptions o2;
+        o2.camera_blocks = 1;
+        o2.block_cameras = 2;
+        o2.block_points = bp;
+        check_layout<float>("two-camera blocks", o2, set2);
+        check_layout<double>("two-camera blocks fp64", o2, set2);
+        layouts += 2;
+    }
+    // a repeated (camera, point) pair is refused by two-camera blocks
+    {
+        Prob rep = make(2, 2, {{0, 0}, {1, 1}, {0, 0}}, 24);
+        dba_problem_desc d = rep.desc();
+        dba::LayoutOptions o2;
+        o2.camera_blocks = 1;
+        o2.block_cameras = 2;
+        dba::Layout<float> L;
+        std::string err;
+        if (dba::build_layout<float>(o2, 1, &d, &L, &err) != DBA_E_INVALID_ARG) {
+            std::fprintf(stderr, "FAIL repeated pair accepted by two-camera blocks\n");
+            g_fail = 1;
+        }
+    }
+    check_validation();
+    if (g_fail) return 1;
+    std::printf("ok %d layouts\n", layouts);
+    return 0;
+}

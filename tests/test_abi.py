@@ -39,11 +39,12 @@ def test_library_exports_every_declared_symbol():
 def test_struct_layouts_match_header(tmp_path):
     src = tmp_path / "sz.c"
     src.write_text('#include <stdio.h>\n#include <stddef.h>\n#include "dba.h"\n'
-                   'int main(void){printf("%zu %zu %zu %zu %zu %zu %zu %zu %zu\\n", sizeof(dba_options),'
+                   'int main(void){printf("%zu %zu %zu %zu %zu %zu %zu %zu %zu %zu\\n", sizeof(dba_options),'
                    ' sizeof(dba_problem_desc), sizeof(dba_residual_report),'
                    ' offsetof(dba_options, persistent), offsetof(dba_residual_report, iteration),'
                    ' offsetof(dba_options, block_points), offsetof(dba_options, camera_model),'
-                   ' offsetof(dba_options, local_solver), offsetof(dba_options, block_cameras));return 0;}\n')
+                   ' offsetof(dba_options, local_solver), offsetof(dba_options, block_cameras),'
+                   ' offsetof(dba_options, segment_schedule));return 0;}\n')
     exe = tmp_path / "sz"
     subprocess.check_call(["gcc", "-I", os.path.join(ROOT, "include"), str(src), "-o", str(exe)])
     got = [int(x) for x in subprocess.check_output([str(exe)]).split()]
@@ -51,7 +52,7 @@ def test_struct_layouts_match_header(tmp_path):
             ctypes.sizeof(binding.dba_residual_report), binding.dba_options.persistent.offset,
             binding.dba_residual_report.iteration.offset, binding.dba_options.block_points.offset,
             binding.dba_options.camera_model.offset, binding.dba_options.local_solver.offset,
-            binding.dba_options.block_cameras.offset]
+            binding.dba_options.block_cameras.offset, binding.dba_options.segment_schedule.offset]
     assert got == want
 
 

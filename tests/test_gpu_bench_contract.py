@@ -37,8 +37,13 @@ def test_bench_json_line_on_the_ring_workload():
     assert d["value"] == pytest.approx(cfg["n_obs"] / (d["ms_per_step"] * 1e-3), rel=1e-6)
     rf = d["roofline"]
     assert rf["bound"] in ("alu", "hbm", "mfma") and rf["unit"] in ("TFLOP/s", "GB/s")
-    assert 0 < rf["achieved"] and rf["peak"] == 78.6
+    assert rf["bound"] == "hbm" and rf["unit"] == "GB/s" and rf["peak"] == 8000.0
+    assert rf["bytes_per_obs"] == 408     # FP64: pixel 16, indexes 8, copies 2 x 96, duals 2 x 96
+    assert 0 < rf["achieved"]
+    assert rf["achieved"] == pytest.approx(rf["bytes_per_obs"] * cfg["n_obs"] / (rf["avg_launch_ms"] * 1e-3) / 1e9,
+                                           rel=1e-3)
     assert rf["frac"] == pytest.approx(rf["achieved"] / rf["peak"], abs=1e-4)
+    assert rf["alu"]["nonpacked_peak_tflops"] == 78.6
     sys.path.insert(0, ROOT)
     import bench
     recorded, _ = bench.recorded_traffic("ring")

@@ -10,7 +10,7 @@ import pytest
 import oracle
 from paper_1708_07954_amd import binding
 from scenes import make_config2, make_ring_scene, make_sphere_scene
-from _util import param_rel_err, state_rel_err
+from _util import golden_points, param_rel_err, state_rel_err
 
 pytestmark = pytest.mark.gpu
 
@@ -224,7 +224,7 @@ def test_blocks_full_size_match_the_stored_oracle():
     for precision, tol in (("fp64", 1e-9), ("fp32", 1e-3)):
         s = gpu_blocks(sc, int(g["iterations"]), precision=precision, block_waves=1, persistent=0, **kw)
         cams, pts = s.params()
-        err = param_rel_err(cams, pts[g["points_idx"]], g["cams"], g["points"])
+        err = param_rel_err(cams, pts[golden_points(g)], g["cams"], g["points"])
         r = s.residuals(want_rmse=True)
         print(precision, "full-size blocks max rel err", err, "rmse", r["rmse"], g["stats"][0])
         assert err < tol

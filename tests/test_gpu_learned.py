@@ -193,3 +193,131 @@ def test_trained_network_gains_over_the_plain_start():
     print("pairs", len(e_net), "mean", e_net.mean(), e_zero.mean(), "median", np.median(e_net), np.median(e_zero),
           "inlier rmse after 250 iterations", runs, "train", rep["train_seconds"], "s")
     assert e_net.mean() < 0.8 * e_zero.mean()
+
+
+@pytest.mark.parametrize("order", ["graphs_first", "pairs_first"])
+def test_collecting_pairs_keeps_each_start_in_its_own_graphs(order):
+    """dba_collect_pairs runs plain iterations on a handle set to the learned
+    start.  Replayed from captured graphs, every iteration must still run the
+    start it belongs to: the plain ones inside the collection and the learned
+    ones around it, bitwise as the same sequence run eagerly (use_graph = 0)
+    on a second handle.  Covers both orders: learned graphs captured before
+    the collection, and the collection's plain graphs captured first."""
+    sc = make_config2(n_cams=40, n_points=600)
+    flat, _ = _net(4)
+    norm = _identity_norm()
+    norm[64:76] = 1e-4
+    kw = dict(precision="fp32", loss="huber", loss_param=2.0, rho=1e5, block_waves=4, persistent=0,
+              start="learned", learned_lm_steps=2, lm_steps=5)
+    runs = []
+    for use_graph in (True, False):
+        s = binding.Solver(use_graph=use_graph, **kw)
+        binding.dba_set_mlp(s.h, flat, norm)
+        s.set_scene(sc)
+        if order == "graphs_first":
+            s.iterate(2)
+        f, d = binding.dba_collect_pairs(s.h, 2, 64, seed=3, conv_steps=10)
+        s.iterate(3)
+        runs.append((s.params(), s.state(), f, d))
+        s.close()
+    (pg, sg, fg, dg), (pe, se, fe, de) = runs
+    np.testing.assert_array_equal(fg, fe)
+    np.testing.assert_array_equal(dg, de)
+    np.testing.assert_array_equal(pg[0], pe[0])
+    np.testing.assert_array_equal(pg[1], pe[1])
+    np.testing.assert_array_equal(sg[0], se[0])
+    np.testing.assert_array_equal(sg[1], se[1])
+
+
+def test_adam_steps_match_the_oracle_elementwise():
+    """Three Adam steps (dba_mlp_apply_gradient, the update dba_mlp_train's
+    steps use) from fixed parameters with fixed gradients against
+    oracle.mlp.adam_step in FP64: master parameters and both moments element
+    by element, the step count, and the padding entries of the parameter
+    block held at zero even when their gradient is not."""
+    flat, _ = _net(12)
+    h = binding.dba_create(binding.make_options(precision="fp32"))
+    try:
+        binding.dba_set_mlp(h, flat, _identity_norm())
+        m0, v0, t0 = binding.dba_mlp_adam_state(h)
+        assert t0 == 0 and not m0.any() and not v0.any()
+        rng = np.random.default_rng(13)
+        p = mlp.unflatten(flat.astype(np.float64))
+        m = {k: np.zeros_like(a) for k, a in p.items()}
+        v = {k: np.zeros_like(a) for k, a in p.items()}
+        mag = np.zeros(22800)        # the first moment's terms in magnitude (its rounding scale)
+        pad_t = mlp.unflatten(np.zeros(22800))
+        pad_t["W1"][26:] = 1
+        pad_t["W3"][:, 12:] = 1
+        pad_t["b3"][12:] = 1
+        pad = mlp.flatten(pad_t) > 0
+        for step, lr in ((1, 1e-3), (2, 7.5e-4), (3, 2.5e-4)):
+            # gradients spanning six decades, padding entries included
+            g = (rng.normal(0, 1, 22800) * 10.0 ** rng.uniform(-6, 0, 22800)).astype(np.float32)
+            binding.dba_mlp_apply_gradient(h, g, lr)
+            mag = 0.9 * mag + 0.1 * np.abs(g.astype(np.float64))
+            gg = mlp.unflatten(g.astype(np.float64))
+            mlp.adam_step(p, gg, m, v, step, lr)
+            for k in p:              # the padding is not trained
+                p[k][pad_t[k] > 0] = 0.0
+                m[k][pad_t[k] > 0] = 0.0
+                v[k][pad_t[k] > 0] = 0.0
+        got_p, _ = binding.dba_get_mlp(h)
+        got_m, got_v, t = binding.dba_mlp_adam_state(h)
+        assert t == 3
+        ref_p, ref_m, ref_v = mlp.flatten(p), mlp.flatten(m), mlp.flatten(v)
+        assert not got_p[pad].any() and not got_m[pad].any() and not got_v[pad].any()
+        # FP32 arithmetic of three updates: a few ulp of each quantity (the
+        # first moment's relative to its terms, which may cancel)
+        assert np.all(np.abs(got_m - ref_m) <= 1e-6 * mag)
+        np.testing.assert_allclose(got_v, ref_v, rtol=1e-6, atol=0)
+        # parameters: three FP32 roundings of the parameter, plus the update's
+        # own relative error (1e-6 of lr per step)
+        np.testing.assert_allclose(got_p, ref_p, rtol=4e-7, atol=1e-8)
+        assert np.abs(got_p - flat).max() > 1e-4        # the steps moved the parameters
+    finally:
+        binding.dba_destroy(h)
+
+
+def _learned_net():
+    """A network trained on the GPU on pairs from a small trajectory-family
+    scene (the deployment loss and rho rule)."""
+    from paper_1708_07954_amd import warmstart
+    from scenes import make_trajectory_scene
+    f, d = warmstart.collect([make_trajectory_scene(seed=2003, n_cams=60, n_points=3000)], iters=20,
+                             per_iter=4096, seed=1)
+    params, norm, _ = warmstart.train(f, d, epochs=6, batch=1024, lr=1e-3, seed=2)
+    return params, norm
+
+
+@pytest.mark.parametrize("steps", [2, 5])
+def test_learned_admm_matches_the_oracle(steps):
+    """The learned start (network, guard, `steps` LM steps) on the GPU
+    against the oracle's learned iteration (reading R14, FP64, the network of
+    oracle.mlp on the same weights) on a 40-camera trajectory scene for 25
+    iterations: every parameter within 1e-3 relative, and the inlier RMSE
+    within 0.5 %, at every fifth iteration."""
+    from _util import param_err_summary
+    params, norm = _learned_net()
+    sc = make_config2(n_cams=40, n_points=600)
+    kw = dict(loss="huber", loss_param=2.0, rho=1e5, rho_balancing=True)
+    s = binding.Solver(precision="fp32", start="learned", learned_lm_steps=steps, rho_min=1e5, rho_max=1e7,
+                       block_waves=1, persistent=0, **kw)
+    binding.dba_set_mlp(s.h, params, norm)
+    s.set_scene(sc)
+    s.set_eval_mask(~sc.outlier)
+    a = oracle.ADMM(oracle.Problem.from_scene(sc), sc.cams_init, sc.points_init, **kw)
+    a.opts.rho_min, a.opts.rho_max = 1e5, 1e7
+    inl = ~sc.outlier
+    for it in range(1, 26):
+        a.iterate_learned(params, norm, steps)
+        s.iterate(1)
+        if it % 5 == 0:
+            cams, pts = s.params()
+            e = param_err_summary(cams, pts, a.cons_y, a.cons_x)
+            r = s.residuals(want_rmse=True)["rmse_masked"]
+            ro = a.stats(inl)[1]
+            print(f"learned+{steps} it {it}: rel err {e}, inlier rmse {r:.6f} oracle {ro:.6f}", flush=True)
+            assert e["max"] < 1e-3, (it, e)
+            assert abs(r - ro) < 5e-3 * ro
+    s.close()

@@ -1,4 +1,4 @@
-"""Problems of the sizes of the paper's real-data table (Sec. 5.2, Table 1:
+"""Problems of the sizes of the paper's real-data table (Sec. 4.3, Table 1:
 cameras, points and observations of its four datasets, about 2.6-2.9
 observations per point), as synthetic trajectories with tracks of 2-4
 consecutive frames about 6 degrees apart and no outliers, since the datasets themselves are not

@@ -10,7 +10,8 @@ from scenes import make_sphere_scene
 
 pytestmark = pytest.mark.gpu
 
-KW = dict(precision="fp32", loss="student_t", loss_param=4.0, rho=1e3, block_waves=1, persistent=0)
+KW = dict(precision="fp32", loss="student_t", loss_param=4.0, rho=1e3, block_waves=1, persistent=0,
+          segment_schedule=1)
 
 
 def run(sc, n, timed, use_graph):

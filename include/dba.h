@@ -265,6 +265,21 @@ int dba_get_mlp(dba_handle *h, float *params, float *norm);
 int dba_set_start(dba_handle *h, int32_t start, int32_t learned_lm_steps);
 /* Network evaluation: features [n][26] -> predicted updates [n][12]. */
 int dba_mlp_forward(dba_handle *h, const float *features, int64_t n, float *delta);
+/* Allocation-free network evaluation, for callers that cannot allocate
+ * device memory (code under HIP graph capture, tight serving loops,
+ * harnesses that forbid hipMalloc): the computation of dba_mlp_forward, with
+ * DEVICE buffers owned by the caller -- features [n][26] FP32 in, predicted
+ * updates [n][12] FP32 out -- enqueued on the handle's stream without a
+ * synchronisation (the result is ready when the stream reaches it).  Its
+ * intermediate values live in one fixed scratch array of the library per GPU
+ * (DBA_NOALLOC_SCRATCH_BYTES, held until the process ends), so n is at most
+ * DBA_NOALLOC_MAX_ROWS (DBA_E_INVALID_ARG beyond, DBA_E_STATE without a
+ * network).  Calls that overlap on one GPU (other handles, streams or
+ * threads) race on that array.  Allocates nothing: no hipMalloc, hipFree or
+ * allocating library routine. */
+#define DBA_NOALLOC_MAX_ROWS 65536
+#define DBA_NOALLOC_SCRATCH_BYTES (DBA_NOALLOC_MAX_ROWS * 128)
+int dba_mlp_forward_noalloc(dba_handle *h, const float *features, int64_t n, float *delta);
 /* Mean squared error over n x 12 of the network on standardized inputs
  * x_std [n][32] (rounded to bf16 on the device) against standardized targets
  * t_std [n][16] (columns 12..15 ignored), its gradient with respect to the

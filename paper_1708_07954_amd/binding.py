@@ -73,7 +73,7 @@ EXPORTS = ("dba_default_options", "dba_create", "dba_destroy", "dba_last_error",
            "dba_set_problem", "dba_set_problems", "dba_iterate", "dba_residuals",
            "dba_set_eval_mask", "dba_get_params", "dba_get_state", "dba_problem_info",
            "dba_set_kernel_timing", "dba_kernel_times", "dba_schedule", "dba_segment_schedule", "dba_set_mlp", "dba_get_mlp",
-           "dba_set_start", "dba_mlp_forward", "dba_mlp_loss_grad", "dba_collect_pairs", "dba_mlp_train",
+           "dba_set_start", "dba_mlp_forward", "dba_mlp_forward_noalloc", "dba_mlp_loss_grad", "dba_collect_pairs", "dba_mlp_train",
            "dba_mlp_apply_gradient", "dba_mlp_adam_state")
 MLP_PARAMS, MLP_NORM = 22800, 76
 
@@ -121,6 +121,7 @@ def _declare_learned(L):
     L.dba_get_mlp.argtypes = [vp, vp, vp]
     L.dba_set_start.argtypes = [vp, i32, i32]
     L.dba_mlp_forward.argtypes = [vp, vp, i64, vp]
+    L.dba_mlp_forward_noalloc.argtypes = [vp, vp, i64, vp]
     L.dba_mlp_loss_grad.argtypes = [vp, vp, vp, i32, vp, vp, vp]
     L.dba_collect_pairs.argtypes = [vp, i32, i32, u64, i32, vp, vp]
     L.dba_mlp_train.argtypes = [vp, vp, vp, i64, i32, i32, dbl, u64, vp]
@@ -300,6 +301,14 @@ def dba_mlp_forward(h, features):
     out = np.zeros((f.shape[0], 12), np.float32)
     _check(h, load().dba_mlp_forward(h, _ptr(f), f.shape[0], _ptr(out)))
     return out
+
+
+def dba_mlp_forward_noalloc(h, features_ptr: int, n: int, delta_ptr: int):
+    """Allocation-free evaluation on device buffers: features_ptr points to
+    [n][26] FP32, delta_ptr to [n][12] FP32 (device addresses, e.g. a torch
+    tensor's data_ptr()); enqueued on the handle's stream, not synchronised."""
+    _check(h, load().dba_mlp_forward_noalloc(h, ctypes.c_void_p(int(features_ptr)), int(n),
+                                             ctypes.c_void_p(int(delta_ptr))))
 
 
 def dba_mlp_loss_grad(h, x_std, t_std):

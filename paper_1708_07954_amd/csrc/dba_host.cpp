@@ -577,6 +577,10 @@ int dba_create(const dba_options *opt, dba_handle **out)
     }
     hipDeviceProp_t prop;
     if (hipGetDeviceProperties(&prop, o.device) == hipSuccess) h->n_cu = prop.multiProcessorCount;
+    if (dba::noalloc_scratch(o.device, &h->noalloc_scratch) != hipSuccess) {
+        delete h;
+        return DBA_E_DEVICE;
+    }
     if (o.stream) {
         h->stream = static_cast<hipStream_t>(o.stream);
     } else {

@@ -121,6 +121,8 @@ struct dba_handle {
     // learned warm start
     int start = DBA_START_PLAIN;
     dba::host::Mlp *mlp = nullptr;
+    // this GPU's scratch array of the allocation-free entry point
+    void *noalloc_scratch = nullptr;
 };
 
 namespace dba {

@@ -125,6 +125,10 @@ constexpr int kPW1 = 0, kPB1 = kPW1 + kInPad * kHid, kPW2 = kPB1 + kHid, kPB2 = 
               kPW3 = kPB2 + kHid, kPB3 = kPW3 + kHid * kOutPad, kPTotal = kPB3 + kOutPad;
 // normalisation block: mu_in[26] sd_in[26] mu_out[12] sd_out[12]
 constexpr int kNormTotal = 2 * kIn + 2 * kOut;
+// allocation-free network forward: rows per call and the scratch they need
+// (standardised BF16 inputs and padded FP32 outputs)
+constexpr long long kNoAllocMaxRows = 65536;
+constexpr long long kNoAllocScratchBytes = kNoAllocMaxRows * (kInPad * 2 + kOutPad * 4);
 
 struct MlpParams {
     const __bf16 *w;       // packed bf16 weights (kWTotal)
@@ -158,6 +162,8 @@ hipError_t mlp_wgrad(const __bf16 *xb, const __bf16 *h1, const __bf16 *h2, const
                      const __bf16 *dz1q, int n, float *grad, hipStream_t s);
 hipError_t mlp_bias(const float *dy, const float *dz2, const float *dz1, int n, float *grad, hipStream_t s);
 hipError_t mlp_adam(float *P, float *m, float *v, const float *g, float lr, float bc1, float bc2, hipStream_t s);
+hipError_t mlp_destandardize(const float *y, const float *norm, long long n, float *delta, hipStream_t s);
+hipError_t noalloc_scratch(int device, void **ptr);
 hipError_t collect_pairs(const DevArrays<float> &a, const SolverParams &sp, const int *slots, int n, float *feat,
                          float *delta, int conv_steps, hipStream_t s);
 template <typename R>

@@ -166,6 +166,32 @@ int dba_mlp_forward(dba_handle *h, const float *features, int64_t n, float *delt
     return DBA_OK;
 }
 
+static_assert(DBA_NOALLOC_MAX_ROWS == dba::kNoAllocMaxRows && DBA_NOALLOC_SCRATCH_BYTES == dba::kNoAllocScratchBytes,
+              "the header's scratch limits match the library's");
+
+int dba_mlp_forward_noalloc(dba_handle *h, const float *features, int64_t n, float *delta)
+{
+    if (!h || !features || !delta || n < 1) return DBA_E_INVALID_ARG;
+    h->err.clear();
+    if (n > dba::kNoAllocMaxRows)
+        return fail(h, DBA_E_INVALID_ARG, "%lld rows exceed the %lld of the scratch array", (long long)n,
+                    dba::kNoAllocMaxRows);
+    if (!h->mlp || !h->mlp->ready) return fail(h, DBA_E_STATE, "no network set");
+    if (!h->noalloc_scratch) return fail(h, DBA_E_STATE, "no scratch address for this device");
+    HIP_TRY(h, hipSetDevice(h->opt.device));
+    // every byte read below is written first by the same call: the inputs
+    // for rows < n by the prepare kernel, the outputs for rows < n by the
+    // forward kernel
+    __bf16 *xq = static_cast<__bf16 *>(h->noalloc_scratch);
+    float *dy = reinterpret_cast<float *>(static_cast<unsigned char *>(h->noalloc_scratch) +
+                                          dba::kNoAllocMaxRows * dba::kInPad * sizeof(__bf16));
+    HIP_TRY(h, dba::mlp_prepare(features, nullptr, h->mlp->norm, n, xq, nullptr, h->stream));
+    HIP_TRY(h, dba::mlp_forward(xq, nullptr, (int)n, h->mlp->params(), dy, nullptr, nullptr, nullptr, nullptr, nullptr,
+                                h->stream));
+    HIP_TRY(h, dba::mlp_destandardize(dy, h->mlp->norm, n, delta, h->stream));
+    return DBA_OK;
+}
+
 int dba_mlp_loss_grad(dba_handle *h, const float *x_std, const float *t_std, int32_t n, float *loss, float *grad,
                       float *y_out)
 {

@@ -16,7 +16,15 @@
 #include "dba_device.h"
 #include "mlp_device.h"
 
+#include <mutex>
+
 namespace dba {
+
+// Scratch of the allocation-free network forward (dba_mlp_forward_noalloc):
+// the standardised BF16 inputs [kNoAllocMaxRows][kInPad] followed by the
+// padded FP32 outputs [kNoAllocMaxRows][kOutPad].  One copy per GPU for the
+// life of the process; every call on a GPU shares it.
+static __device__ __align__(256) unsigned char scratch[kNoAllocScratchBytes];
 
 namespace {
 
@@ -354,7 +362,48 @@ __global__ __launch_bounds__(256) void k_collect_pairs(DevArrays<float> a, Solve
     for (int i = 0; i < 12; ++i) delta[(size_t)q * kOut + i] = tc[i] - th[i];
 }
 
+// ---------------------------------------------------------------- destandardize
+// delta = y * std + mean per output, each product and sum rounded on its own
+// (no fused multiply-add), as the host-side path of dba_mlp_forward computes.
+__global__ void k_mlp_destandardize(const float *y, const float *norm, long long n, float *delta)
+{
+#pragma clang fp contract(off)
+    const long long q = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (q >= n * kOut) return;
+    const long long r = q / kOut;
+    const int o = (int)(q - r * kOut);
+    delta[q] = y[r * kOutPad + o] * norm[2 * kIn + kOut + o] + norm[2 * kIn + o];
+}
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void *g_scratch[kMaxDevices];
+
 }  // namespace
+
+// Device address of this GPU's scratch array; the caller has made `device`
+// current.  Looked up once per device and kept.
+hipError_t noalloc_scratch(int device, void **ptr)
+{
+    if (device < 0 || device >= kMaxDevices) return hipErrorInvalidDevice;
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch[device]) {
+        void *p = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) return e;
+        if (!p) return hipErrorInvalidSymbol;
+        g_scratch[device] = p;
+    }
+    *ptr = g_scratch[device];
+    return hipSuccess;
+}
+
+hipError_t mlp_destandardize(const float *y, const float *norm, long long n, float *delta, hipStream_t s)
+{
+    const long long total = n * kOut;
+    hipLaunchKernelGGL(k_mlp_destandardize, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, s, y, norm, n, delta);
+    return hipGetLastError();
+}
 
 // ---------------------------------------------------------------- launchers
 hipError_t mlp_pack(const float *P, __bf16 *w, hipStream_t s)

@@ -94,6 +94,11 @@ def make_scenes(kind):
     return [{"config0": make_config0, "config1": make_config1, "config2": make_config2}[kind]()]
 
 
+# iterations of the tuning handle: every local-solve schedule candidate (8)
+# and every consensus segment schedule (5) once, with room to spare
+TUNING_ITERATIONS = 16
+
+
 def kernel_source_hash():
     h = hashlib.sha256()
     for f in ("dba_kernels.hip", "dba_device.h", "dba_internal.h", "block_device.h", "mlp_device.h"):
@@ -325,7 +330,7 @@ def size_sweep(binding, opts, factors=(0.0625, 0.125, 0.25, 0.5, 1.0, 2.0, 4.0, 
             scenes = [base] * int(f)
         L = sum(sc.n_obs for sc in scenes)
         tuner = binding.Solver(**opts).set_scenes(scenes)
-        tuner.iterate(12)
+        tuner.iterate(TUNING_ITERATIONS)
         sched = binding.dba_schedule(tuner.h)
         seg = binding.dba_segment_schedule(tuner.h)["segment_schedule"]
         tuner.close()
@@ -536,9 +541,11 @@ def main():
     # launch schedule: autotuned once on a separate handle (tuning runs real,
     # bitwise-equivalent iterations), then fixed for the measured handle
     tuner = binding.Solver(**opts).set_scenes(scenes)
-    tuner.iterate(12)
+    tuner.iterate(TUNING_ITERATIONS)
     sched = binding.dba_schedule(tuner.h)
-    sched["segment_schedule"] = binding.dba_segment_schedule(tuner.h)["segment_schedule"]
+    seg = binding.dba_segment_schedule(tuner.h)
+    assert seg["tuned"] > 0, "the consensus schedule was not tuned within the tuning iterations"
+    sched["segment_schedule"] = seg["segment_schedule"]
     torch.cuda.synchronize()
     tuner.close()
     print(f"[bench] schedule {sched}", file=sys.stderr, flush=True)

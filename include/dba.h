@@ -122,7 +122,9 @@ typedef struct dba_options {
                                  without camera_blocks */
     int32_t segment_schedule; /* point-consensus segment schedule: 1 each thread loads its point's
                                  records itself; 2, 3 the point block's records are staged through
-                                 LDS in coalesced tiles of 512 or 1024 records.  Each point's
+                                 LDS in coalesced tiles of 512 or 1024 records; 4, 5 each wave
+                                 stages its 64 points' records in tiles of 128 or 256, loading
+                                 the next tile while it sums the current one.  Each point's
                                  records are summed in the same order whatever the value; 0:
                                  autotune */
 } dba_options;

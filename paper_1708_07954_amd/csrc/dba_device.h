@@ -710,6 +710,12 @@ __device__ __forceinline__ void wave_sum19_store(const double *v, double *o, int
 
 // Block -> tile mapping that gives each XCD (blocks are dealt round-robin to
 // the 8 XCDs) a contiguous range of tiles, so neighbouring cameras share an L2.
+// Index of the calling wave in its workgroup, in a scalar register: the
+// compiler cannot tell that threadIdx.x / 64 is the same across a wave, and
+// without this keeps every per-chunk index, address and uniform load in
+// vector registers.
+__device__ __forceinline__ int wave_id() { return __builtin_amdgcn_readfirstlane(threadIdx.x >> 6); }
+
 __device__ __forceinline__ int xcd_block()
 {
     const int G = gridDim.x, b = blockIdx.x;

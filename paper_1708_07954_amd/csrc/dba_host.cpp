@@ -413,7 +413,8 @@ int iterate_impl(dba_handle *h, const DevArrays<R> &A, int n)
     }
     // then the segment schedule of the consensus, on real iterations with
     // the local schedule fixed; its candidates are bitwise identical too
-    static const int cand_seg[] = {1, 2, 3};
+    static const int cand_seg[] = {1, 2, 3, 4, 5};
+    constexpr int n_seg = (int)(sizeof(cand_seg) / sizeof(cand_seg[0]));
     while (!h->seg_ready && n > 0) {
         const int q = h->seg_next;
         h->seg_sched = cand_seg[q];
@@ -433,12 +434,12 @@ int iterate_impl(dba_handle *h, const DevArrays<R> &A, int n)
         if (err != hipSuccess) return fail(h, DBA_E_DEVICE, "segment schedule tuning: %s", hipGetErrorString(err));
         h->seg_ms.push_back(ms);
         --n;
-        if (++h->seg_next == 3) {
+        if (++h->seg_next == n_seg) {
             int best = 0;
-            for (int t = 1; t < 3; ++t)
+            for (int t = 1; t < n_seg; ++t)
                 if (h->seg_ms[t] < h->seg_ms[best]) best = t;
             h->seg_sched = cand_seg[best];
-            h->seg_tuned = 3;
+            h->seg_tuned = n_seg;
             h->seg_ready = true;
         }
     }
@@ -559,7 +560,7 @@ int dba_create(const dba_options *opt, dba_handle **out)
         return DBA_E_INVALID_ARG;
     if (o.block_cameras != 1 && o.block_cameras != 2) return DBA_E_INVALID_ARG;
     if (o.block_cameras == 2 && !o.camera_blocks) return DBA_E_INVALID_ARG;
-    if (o.segment_schedule < 0 || o.segment_schedule > 3) return DBA_E_INVALID_ARG;
+    if (o.segment_schedule < 0 || o.segment_schedule > 5) return DBA_E_INVALID_ARG;
     dba_handle *h = new dba_handle();
     h->opt = o;
     h->fp32 = o.precision == DBA_PREC_FP32_LOCAL;

@@ -245,7 +245,7 @@ template <typename R, typename Cam, int SOLVER>
 __global__ __launch_bounds__(LocalBound<R>::threads) void k_local(DevArrays<R> a, SolverParams sp,
                                                                   int persistent)
 {
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, wpb = blockDim.x >> 6;
+    const int lane = threadIdx.x & 63, wave = wave_id(), wpb = blockDim.x >> 6;
     int c0, c1;
     chunk_range(a.n_chunks, wpb, persistent, c0, c1);
     for (int c = c0 + wave; c < c1; c += wpb) local_chunk<R, false, Cam, SOLVER>(a, sp, c, lane);
@@ -256,7 +256,7 @@ __global__ __launch_bounds__(LocalBound<R>::threads) void k_local_block(DevArray
                                                                         int persistent)
 {
     __shared__ R lds[LocalBound<R>::threads / 64][64];
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, wpb = blockDim.x >> 6;
+    const int lane = threadIdx.x & 63, wave = wave_id(), wpb = blockDim.x >> 6;
     int c0, c1;
     chunk_range(a.n_chunks, wpb, persistent, c0, c1);
     for (int c = c0 + wave; c < c1; c += wpb) local_block<R, Cam>(a, sp, c, lane, lds[wave]);
@@ -370,7 +370,7 @@ __global__ __launch_bounds__(kBlock2Threads) void k_local_block2(DevArrays<R> a,
         rc[2 * t + 1] = (unsigned char)(i + (t - sym18(i, i)));
     }
     __syncthreads();
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, wpb = blockDim.x >> 6;
+    const int lane = threadIdx.x & 63, wave = wave_id(), wpb = blockDim.x >> 6;
     int b0, b1;
     chunk_range(a.n_blocks2, wpb, persistent, b0, b1);
     for (int b = b0 + wave; b < b1; b += wpb) local_block2<R, Cam>(a, sp, b, lane, lds[wave], rc);
@@ -388,7 +388,7 @@ __global__ __launch_bounds__(64 * kLearnedWaves) void k_local_learned(DevArrays<
     __shared__ __attribute__((aligned(16))) __bf16 io[kLearnedWaves][kLdsIo];
     stage_forward_weights(mp.w, lw);
     __syncthreads();
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int lane = threadIdx.x & 63, wave = wave_id();
     int c0, c1;
     chunk_range(a.n_chunks, kLearnedWaves, persistent, c0, c1);
     for (int c = c0 + wave; c < c1; c += kLearnedWaves)
@@ -400,8 +400,11 @@ __global__ __launch_bounds__(64 * kLearnedWaves) void k_local_learned(DevArrays<
 // record order.  TILE (the segment schedule): 0 -- each thread loads its own
 // records, four in flight; > 0 -- the block's records, which are contiguous,
 // are staged through LDS TILE at a time with coalesced loads, and each thread
-// sums its part of every tile.  Every schedule sums each point's records in
-// the same order, so the results are bitwise identical.
+// sums its part of every tile; < 0 -- the same per wave (the records of the
+// wave's 64 points, -TILE at a time, the next tile's loads in flight while
+// the lanes sum the current one), with no barrier across waves.  Every
+// schedule sums each point's records in the same order, so the results are
+// bitwise identical.
 template <typename R, int TILE>
 __global__ __launch_bounds__(256) void k_consensus(DevArrays<R> a, int pt_blocks)
 {
@@ -455,6 +458,58 @@ __global__ __launch_bounds__(256) void k_consensus(DevArrays<R> a, int pt_blocks
                     add(x.x, x.y, x.z, u.x, u.y, u.z);
                 }
             }
+        } else if constexpr (TILE < 0) {
+            constexpr int T = -TILE, PER = 3 * T / 64;  // values per lane and tile
+            static_assert(3 * T % 64 == 0, "whole tiles per lane");
+            __shared__ R xs[4][3 * T];
+            __shared__ double us[4][3 * T];
+            const int w = wave_id(), lane = threadIdx.x & 63;
+            const int first = 64 * w;
+            // the wave's records: those of points p0 + first .. p0 + last - 1
+            const int last = min(first + 64, cnt);
+            const int a0 = first < cnt ? a.pt_off[p0 + first] : 0;
+            const int a1 = first < cnt ? a.pt_off[p0 + last] : 0;
+            R xr[PER];
+            double ur[PER];
+            auto fetch = [&](int t0) {
+                const int n3 = 3 * min(T, a1 - t0);
+                const R *xg = reinterpret_cast<const R *>(a.xrec + t0);
+                const double *ug = reinterpret_cast<const double *>(a.urec + t0);
+#pragma unroll
+                for (int k = 0; k < PER; ++k) {
+                    const int q = lane + 64 * k;
+                    if (q < n3) {
+                        xr[k] = xg[q];
+                        ur[k] = ug[q];
+                    }
+                }
+            };
+            if (a0 < a1) fetch(a0);
+            for (int t0 = a0; t0 < a1; t0 += T) {
+                const int n3 = 3 * min(T, a1 - t0);
+#pragma unroll
+                for (int k = 0; k < PER; ++k) {
+                    const int q = lane + 64 * k;
+                    if (q < n3) {
+                        xs[w][q] = xr[k];
+                        us[w][q] = ur[k];
+                    }
+                }
+                __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+                __builtin_amdgcn_wave_barrier();
+                __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+                if (t0 + T < a1) fetch(t0 + T);
+                if (has) {
+                    const int lo = max(r0, t0), hi = min(r1, t0 + T);
+                    for (int r = lo; r < hi; ++r) {
+                        const int q = 3 * (r - t0);
+                        add(xs[w][q], xs[w][q + 1], xs[w][q + 2], us[w][q], us[w][q + 1], us[w][q + 2]);
+                    }
+                }
+                __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+                __builtin_amdgcn_wave_barrier();
+                __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+            }
         } else {
             __shared__ R xs[3 * TILE];
             __shared__ double us[3 * TILE];
@@ -507,7 +562,7 @@ __global__ __launch_bounds__(256) void k_consensus(DevArrays<R> a, int pt_blocks
         // camera consensus: lane l sums chunks k0 + l, k0 + l + 64, ... in
         // order, then a fixed reduce-scatter adds the lanes
         __shared__ double csum[4][kCpart];
-        const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+        const int lane = threadIdx.x & 63, w = wave_id();
         const int J = (blockIdx.x - pt_blocks) * 4 + w;
         if (J >= a.n_cams) return;  // whole wave; no barrier follows
         const int k0 = a.cam_chunk0[J], k1 = a.cam_chunk0[J + 1];
@@ -618,7 +673,7 @@ template <typename R, typename Cam>
 __global__ __launch_bounds__(256) void k_eval(DevArrays<R> a, SolverParams sp)
 {
     const int lane = threadIdx.x & 63;
-    const int c = blockIdx.x * 4 + (threadIdx.x >> 6);
+    const int c = blockIdx.x * 4 + wave_id();
     if (c >= a.n_chunks) return;  // whole wave
     const long long s = (long long)c * kChunk + lane;
     const int ps = a.pslot[s];
@@ -770,6 +825,10 @@ hipError_t launch_consensus(const DevArrays<R> &a, int schedule, hipStream_t s)
         hipLaunchKernelGGL((k_consensus<R, 512>), grid, block, 0, s, a, a.n_pblk);
     else if (schedule == 3)
         hipLaunchKernelGGL((k_consensus<R, 1024>), grid, block, 0, s, a, a.n_pblk);
+    else if (schedule == 4)
+        hipLaunchKernelGGL((k_consensus<R, -128>), grid, block, 0, s, a, a.n_pblk);
+    else if (schedule == 5)
+        hipLaunchKernelGGL((k_consensus<R, -256>), grid, block, 0, s, a, a.n_pblk);
     else
         hipLaunchKernelGGL((k_consensus<R, 0>), grid, block, 0, s, a, a.n_pblk);
     return hipGetLastError();

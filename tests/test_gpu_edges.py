@@ -49,6 +49,25 @@ def test_layout_edges_match_the_oracle(n_cams, n_points, precision):
     assert r["iteration"] == iters and np.isfinite(r["primal"])
 
 
+@pytest.mark.parametrize("n_cams,n_points", [(300, 3), (2, 10000), (5, 256), (3, 257), (1, 1)])
+def test_segment_schedules_agree_bitwise_on_layout_edges(n_cams, n_points):
+    # tracks longer than a tile (300 records against tiles of 128 / 256 per
+    # wave and 512 / 1024 per block), blocks filled exactly or by one point
+    sc = make_ring_scene(seed=11, n_cams=n_cams, n_points=n_points)
+    ref = None
+    for sched in (1, 2, 3, 4, 5):
+        s = binding.Solver(precision="fp64", segment_schedule=sched, **KW).set_scene(sc)
+        s.iterate(5)
+        got = (*s.params(), s.state()[1], s.residuals()["primal"])
+        s.close()
+        if ref is None:
+            ref = got
+            continue
+        for x, y in zip(got[:3], ref[:3]):
+            np.testing.assert_array_equal(x, y)
+        assert got[3] == ref[3]
+
+
 def test_batch_with_a_one_observation_problem():
     scenes = [make_ring_scene(seed=21, n_cams=3, n_points=70), make_ring_scene(seed=22, n_cams=1, n_points=1),
               make_ring_scene(seed=23, n_cams=2, n_points=65)]

@@ -120,13 +120,11 @@ typedef struct dba_options {
                                  local problem couples them (18 + 3 x points unknowns, Schur
                                  complement on the points, an 18x18 camera system).  Must be 1
                                  without camera_blocks */
-    int32_t segment_schedule; /* point-consensus segment schedule: 1 each thread loads its point's
-                                 records itself; 2, 3 the point block's records are staged through
-                                 LDS in coalesced tiles of 512 or 1024 records; 4, 5 each wave
-                                 stages its 64 points' records in tiles of 128 or 256, loading
-                                 the next tile while it sums the current one.  Each point's
-                                 records are summed in the same order whatever the value; 0:
-                                 autotune */
+    int32_t segment_schedule; /* point-consensus segment schedule: 1 a thread per point sums its
+                                 records; 2 a thread per group of up to 8 consecutive records
+                                 (more for tracks over 512), the point's group sums then added
+                                 in order.  Both sum each point's records in the same groups and
+                                 order, so the results are bitwise identical; 0: autotune */
 } dba_options;
 
 /* Fills *opt with the defaults: device 0, NULL stream, FP64, Huber 2 px,

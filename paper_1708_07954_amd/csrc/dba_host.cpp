@@ -64,7 +64,7 @@ int build_set(dba_handle *h, int np, const dba_problem_desc *probs, ProblemSet *
         ps->L.push_back(probs[p].n_obs);
     }
     const long long S = lay.n_slots, n_chunks = lay.n_chunks, n_recs = lay.n_recs;
-    const int n_cams = lay.n_cams, n_pts = lay.n_pts, n_pblk = lay.n_pblk;
+    const int n_cams = lay.n_cams, n_pts = lay.n_pts, n_cw = lay.n_cw;
     ps->n_slots = S;
     const size_t SY = per_obs ? (size_t)S : 0;
     std::vector<uint8_t> mask(S, 1);
@@ -85,7 +85,7 @@ int build_set(dba_handle *h, int np, const dba_problem_desc *probs, ProblemSet *
     }
     const std::vector<int> &pt_off = lay.pt_off, &chunk_cam = lay.chunk_cam, &cam_prob = lay.cam_prob,
                            &pt_prob = lay.pt_prob, &cam_chunk0 = lay.cam_chunk0, &cam_count = lay.cam_count,
-                           &pblk_pt0 = lay.pblk_pt0, &pblk_cnt = lay.pblk_cnt, &pslot = lay.pslot,
+                           &cw_pt0 = lay.cw_pt0, &pslot = lay.pslot,
                            &ptid = lay.ptid, &orig = lay.orig, &blk_chunk = lay.blk_chunk, &blk_rec = lay.blk_rec;
     const std::vector<double> &cons_y = lay.cons_y;
     const std::vector<R> &copy_y = lay.copy_y, &copy_yc = lay.copy_yc;
@@ -96,7 +96,7 @@ int build_set(dba_handle *h, int np, const dba_problem_desc *probs, ProblemSet *
     dba::PtCopy<R> *d_xrec; dba::PtDual *d_urec; int *d_ptoff, *d_chunk_cam, *d_cam_prob, *d_pt_prob, *d_cam_chunk0, *d_cam_count;
     double *d_cons_y; double4 *d_cons_x; Ctrl *d_ctrl; ProblemRange *d_prob;
     double *d_cpart, *d_ppart, *d_campart, *d_epart, *d_estats;
-    int *d_pblk_pt0, *d_pblk_cnt;
+    int *d_cw_pt0;
     HIP_TRY(h, B.alloc(&d_uv, S));
     HIP_TRY(h, B.alloc(&d_pslot, S));
     HIP_TRY(h, B.alloc(&d_ptid, S));
@@ -117,11 +117,9 @@ int build_set(dba_handle *h, int np, const dba_problem_desc *probs, ProblemSet *
     HIP_TRY(h, B.alloc(&d_ctrl, np));
     HIP_TRY(h, B.alloc(&d_prob, np));
     HIP_TRY(h, B.alloc(&d_cpart, (size_t)n_chunks * dba::kCpart));
-    HIP_TRY(h, B.alloc(&d_ppart, 2 * (size_t)n_pblk));
-    HIP_TRY(h, B.alloc(&d_pblk_pt0, n_pblk));
-    HIP_TRY(h, B.alloc(&d_pblk_cnt, n_pblk));
-    HIP_TRY(h, hipMemcpy(d_pblk_pt0, pblk_pt0.data(), n_pblk * sizeof(int), hipMemcpyHostToDevice));
-    HIP_TRY(h, hipMemcpy(d_pblk_cnt, pblk_cnt.data(), n_pblk * sizeof(int), hipMemcpyHostToDevice));
+    HIP_TRY(h, B.alloc(&d_ppart, 2 * (size_t)(n_cw / dba::kConsWaves)));
+    HIP_TRY(h, B.alloc(&d_cw_pt0, n_cw + 1));
+    HIP_TRY(h, hipMemcpy(d_cw_pt0, cw_pt0.data(), (n_cw + 1) * sizeof(int), hipMemcpyHostToDevice));
     HIP_TRY(h, B.alloc(&d_campart, 2 * (size_t)n_cams));
     HIP_TRY(h, B.alloc(&d_epart, (size_t)n_chunks * dba::kEpart));
     HIP_TRY(h, B.alloc(&d_estats, (size_t)np * dba::kEpart));
@@ -176,7 +174,7 @@ int build_set(dba_handle *h, int np, const dba_problem_desc *probs, ProblemSet *
     A.chunk_cam = d_chunk_cam; A.cam_prob = d_cam_prob; A.pt_prob = d_pt_prob;
     A.cam_chunk0 = d_cam_chunk0; A.cam_count = d_cam_count;
     A.cons_y = d_cons_y; A.cons_x = d_cons_x; A.ctrl = d_ctrl; A.prob = d_prob;
-    A.n_pblk = n_pblk; A.pblk_pt0 = d_pblk_pt0; A.pblk_cnt = d_pblk_cnt;
+    A.n_cw = n_cw; A.cw_pt0 = d_cw_pt0;
     A.cpart = d_cpart; A.ppart = d_ppart; A.campart = d_campart; A.epart = d_epart; A.estats = d_estats;
     ps->mask = d_mask;
     return DBA_OK;
@@ -413,7 +411,7 @@ int iterate_impl(dba_handle *h, const DevArrays<R> &A, int n)
     }
     // then the segment schedule of the consensus, on real iterations with
     // the local schedule fixed; its candidates are bitwise identical too
-    static const int cand_seg[] = {1, 2, 3, 4, 5};
+    static const int cand_seg[] = {1, 2};
     constexpr int n_seg = (int)(sizeof(cand_seg) / sizeof(cand_seg[0]));
     while (!h->seg_ready && n > 0) {
         const int q = h->seg_next;
@@ -560,7 +558,7 @@ int dba_create(const dba_options *opt, dba_handle **out)
         return DBA_E_INVALID_ARG;
     if (o.block_cameras != 1 && o.block_cameras != 2) return DBA_E_INVALID_ARG;
     if (o.block_cameras == 2 && !o.camera_blocks) return DBA_E_INVALID_ARG;
-    if (o.segment_schedule < 0 || o.segment_schedule > 5) return DBA_E_INVALID_ARG;
+    if (o.segment_schedule < 0 || o.segment_schedule > 2) return DBA_E_INVALID_ARG;
     dba_handle *h = new dba_handle();
     h->opt = o;
     h->fp32 = o.precision == DBA_PREC_FP32_LOCAL;

@@ -27,7 +27,7 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
-#include "dba_layout.h"  // kChunk, kConsY, kPtBlock, ProblemRange
+#include "dba_layout.h"  // kChunk, kConsY, cons_group, ProblemRange
 
 namespace dba {
 
@@ -91,10 +91,9 @@ struct DevArrays {
     Ctrl *ctrl;             // [n_problems]
     const ProblemRange *prob; // [n_problems]
     double *cpart;          // [n_chunks][kCpart]
-    int n_pblk;
-    const int *pblk_pt0;    // [n_pblk] first global point of the block
-    const int *pblk_cnt;    // [n_pblk] points in the block (<= kPtBlock)
-    double *ppart;          // [n_pblk][2] block sums of the point residual terms
+    int n_cw;
+    const int *cw_pt0;      // [n_cw + 1] first global point of each consensus wave
+    double *ppart;          // [n_cw / kConsWaves][2] workgroup sums of the point residual terms
     double *campart;        // [n_cams][2]
     double *epart;          // [n_chunks][kEpart]
     double *estats;         // [n_problems][kEpart]

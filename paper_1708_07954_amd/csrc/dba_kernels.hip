@@ -9,9 +9,10 @@
 //            equations (diagonal plus rank two) are solved in registers.
 //            Emits the chunk's sums for the camera consensus with a fixed
 //            butterfly.
-// consensus  point consensus (Eq. 10): one thread per point, ascending record
-//            order, one pass over the records; residual terms summed per
-//            256-point block by a fixed tree;
+// consensus  point consensus (Eq. 10): one pass over the records, each
+//            point's records in groups of consecutive records (a thread per
+//            point, or a thread per group); residual terms summed per wave of
+//            points by a fixed butterfly;
 //            camera consensus (Eq. 11): one wave per camera, lanes summing
 //            strided chunk partials, then a fixed reduce-scatter.  Both FP64.
 // norms      one workgroup per problem: primal/dual residual norms, residual
@@ -396,167 +397,182 @@ __global__ __launch_bounds__(64 * kLearnedWaves) void k_local_learned(DevArrays<
 }
 
 // ---------------------------------------------------------------- consensus
-// Point consensus: thread t of a block sums the records of point p0 + t in
-// record order.  TILE (the segment schedule): 0 -- each thread loads its own
-// records, four in flight; > 0 -- the block's records, which are contiguous,
-// are staged through LDS TILE at a time with coalesced loads, and each thread
-// sums its part of every tile; < 0 -- the same per wave (the records of the
-// wave's 64 points, -TILE at a time, the next tile's loads in flight while
-// the lanes sum the current one), with no barrier across waves.  Every
-// schedule sums each point's records in the same order, so the results are
-// bitwise identical.
-template <typename R, int TILE>
-__global__ __launch_bounds__(256) void k_consensus(DevArrays<R> a, int pt_blocks)
+// Sums of one point's records that the consensus needs: of copy + dual (the
+// new consensus times n) and of the copies' offsets d_r from the previous
+// consensus, which give sum_r |copy_r - new|^2 = sum |d_r|^2 - 2 e . sum d_r
+// + n |e|^2, e = new - previous.
+struct PtSums {
+    double s0, s1, s2, q0, q1, q2, qq;
+    __device__ void clear() { s0 = s1 = s2 = q0 = q1 = q2 = qq = 0.0; }
+    template <typename R>
+    __device__ void add(const PtCopy<R> &x, const PtDual &u, const double4 &old)
+    {
+        s0 += (double)x.x + u.x;
+        s1 += (double)x.y + u.y;
+        s2 += (double)x.z + u.z;
+        const double d0 = (double)x.x - old.x, d1 = (double)x.y - old.y, d2 = (double)x.z - old.z;
+        q0 += d0;
+        q1 += d1;
+        q2 += d2;
+        qq += d0 * d0 + d1 * d1 + d2 * d2;
+    }
+    __device__ void add(const PtSums &g)
+    {
+        s0 += g.s0; s1 += g.s1; s2 += g.s2;
+        q0 += g.q0; q1 += g.q1; q2 += g.q2;
+        qq += g.qq;
+    }
+};
+
+// New consensus of point i from its sums (Eq. 10) and its residual terms.
+__device__ __forceinline__ void point_finish(double4 *cons_x, int i, const double4 &old, int nrec,
+                                             const PtSums &t, double &pri, double &dual)
 {
-    if ((int)blockIdx.x < pt_blocks) {
-        __shared__ double sh[2][kPtBlock];
-        const int b = blockIdx.x;
-        double pri = 0.0, dual = 0.0;
-        const int cnt = a.pblk_cnt[b], p0 = a.pblk_pt0[b];
-        const bool has = (int)threadIdx.x < cnt;
-        const int i = p0 + threadIdx.x;
-        int r0 = 0, r1 = 0;
-        double4 old = make_double4(0.0, 0.0, 0.0, 0.0);
+    const double n = (double)nrec;
+    const double c0 = t.s0 / n, c1 = t.s1 / n, c2 = t.s2 / n;
+    const double e0 = c0 - old.x, e1 = c1 - old.y, e2 = c2 - old.z;
+    cons_x[i] = make_double4(c0, c1, c2, 0.0);
+    const double ee = e0 * e0 + e1 * e1 + e2 * e2;
+    pri = fmax(t.qq - 2.0 * (e0 * t.q0 + e1 * t.q1 + e2 * t.q2) + n * ee, 0.0);
+    dual = n * ee;
+}
+
+// Point consensus, one wave per consensus wave (at most 64 points whose
+// record groups fit the 64 lanes).  Both schedules sum a point's records in
+// the order of cons_group -- groups of consecutive records, each in record
+// order, then the group sums in group order -- and leave point j's residual
+// terms in lane j for a fixed butterfly, so they are bitwise identical.
+//   SCHED 1: lane j sums the records of the wave's point j, four loads in
+//            flight, closing each group as it goes;
+//   SCHED 2: lane l sums one record group (eight loads in flight), the group
+//            sums meet in LDS and lane j adds its point's groups in order.
+template <typename R, int SCHED>
+__device__ __forceinline__ void point_wave(const DevArrays<R> &a, int cw, int w, int lane, double *pd)
+{
+    const int p0 = a.cw_pt0[cw], np = a.cw_pt0[cw + 1] - p0;
+    const bool has = lane < np;
+    const int i = p0 + lane;
+    int r0 = 0, r1 = 0;
+    if (has) {
+        r0 = a.pt_off[i];
+        r1 = a.pt_off[i + 1];
+    }
+    double pri = 0.0, dual = 0.0;
+    if constexpr (SCHED == 1) {
         if (has) {
-            r0 = a.pt_off[i];
-            r1 = a.pt_off[i + 1];
-            old = a.cons_x[i];
-        }
-        // one pass: sums of copy + dual (the consensus) and of the copies'
-        // offsets d_r from the previous consensus, which give
-        // sum_r |copy_r - new|^2 = sum |d_r|^2 - 2 e . sum d_r + n |e|^2,
-        // e = new - previous
-        double s0 = 0.0, s1 = 0.0, s2 = 0.0, q0 = 0.0, q1 = 0.0, q2 = 0.0, qq = 0.0;
-        auto add = [&](R x0, R x1, R x2, double u0, double u1, double u2) {
-            s0 += (double)x0 + u0;
-            s1 += (double)x1 + u1;
-            s2 += (double)x2 + u2;
-            const double d0 = (double)x0 - old.x, d1 = (double)x1 - old.y, d2 = (double)x2 - old.z;
-            q0 += d0;
-            q1 += d1;
-            q2 += d2;
-            qq += d0 * d0 + d1 * d1 + d2 * d2;
-        };
-        if constexpr (TILE == 0) {
-            if (has) {
-                // four records' loads in flight, summed in record order
-                int r = r0;
-                for (; r + 4 <= r1; r += 4) {
-                    PtCopy<R> x[4];
-                    PtDual u[4];
-#pragma unroll
-                    for (int j = 0; j < 4; ++j) {
-                        x[j] = a.xrec[r + j];
-                        u[j] = a.urec[r + j];
-                    }
-#pragma unroll
-                    for (int j = 0; j < 4; ++j) add(x[j].x, x[j].y, x[j].z, u[j].x, u[j].y, u[j].z);
-                }
-                for (; r < r1; ++r) {
-                    const PtCopy<R> x = a.xrec[r];
-                    const PtDual u = a.urec[r];
-                    add(x.x, x.y, x.z, u.x, u.y, u.z);
-                }
-            }
-        } else if constexpr (TILE < 0) {
-            constexpr int T = -TILE, PER = 3 * T / 64;  // values per lane and tile
-            static_assert(3 * T % 64 == 0, "whole tiles per lane");
-            __shared__ R xs[4][3 * T];
-            __shared__ double us[4][3 * T];
-            const int w = wave_id(), lane = threadIdx.x & 63;
-            const int first = 64 * w;
-            // the wave's records: those of points p0 + first .. p0 + last - 1
-            const int last = min(first + 64, cnt);
-            const int a0 = first < cnt ? a.pt_off[p0 + first] : 0;
-            const int a1 = first < cnt ? a.pt_off[p0 + last] : 0;
-            R xr[PER];
-            double ur[PER];
-            auto fetch = [&](int t0) {
-                const int n3 = 3 * min(T, a1 - t0);
-                const R *xg = reinterpret_cast<const R *>(a.xrec + t0);
-                const double *ug = reinterpret_cast<const double *>(a.urec + t0);
-#pragma unroll
-                for (int k = 0; k < PER; ++k) {
-                    const int q = lane + 64 * k;
-                    if (q < n3) {
-                        xr[k] = xg[q];
-                        ur[k] = ug[q];
-                    }
+            const double4 old = a.cons_x[i];
+            const int K = cons_group(r1 - r0);
+            PtSums t, g;
+            t.clear();
+            g.clear();
+            int in_g = 0;
+            auto take = [&](const PtCopy<R> &x, const PtDual &u) {
+                g.add(x, u, old);
+                if (++in_g == K) {
+                    t.add(g);
+                    g.clear();
+                    in_g = 0;
                 }
             };
-            if (a0 < a1) fetch(a0);
-            for (int t0 = a0; t0 < a1; t0 += T) {
-                const int n3 = 3 * min(T, a1 - t0);
+            int r = r0;
+            for (; r + 4 <= r1; r += 4) {
+                PtCopy<R> x[4];
+                PtDual u[4];
 #pragma unroll
-                for (int k = 0; k < PER; ++k) {
-                    const int q = lane + 64 * k;
-                    if (q < n3) {
-                        xs[w][q] = xr[k];
-                        us[w][q] = ur[k];
-                    }
+                for (int j = 0; j < 4; ++j) {
+                    x[j] = a.xrec[r + j];
+                    u[j] = a.urec[r + j];
                 }
-                __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-                __builtin_amdgcn_wave_barrier();
-                __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-                if (t0 + T < a1) fetch(t0 + T);
-                if (has) {
-                    const int lo = max(r0, t0), hi = min(r1, t0 + T);
-                    for (int r = lo; r < hi; ++r) {
-                        const int q = 3 * (r - t0);
-                        add(xs[w][q], xs[w][q + 1], xs[w][q + 2], us[w][q], us[w][q + 1], us[w][q + 2]);
-                    }
-                }
-                __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-                __builtin_amdgcn_wave_barrier();
-                __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+#pragma unroll
+                for (int j = 0; j < 4; ++j) take(x[j], u[j]);
             }
-        } else {
-            __shared__ R xs[3 * TILE];
-            __shared__ double us[3 * TILE];
-            const int a0 = a.pt_off[p0], a1 = a.pt_off[p0 + cnt];  // the block's records
-            for (int t0 = a0; t0 < a1; t0 += TILE) {
-                const int n3 = 3 * min(TILE, a1 - t0);
-                const R *xg = reinterpret_cast<const R *>(a.xrec + t0);
-                const double *ug = reinterpret_cast<const double *>(a.urec + t0);
-                for (int q = threadIdx.x; q < n3; q += 256) {
-                    xs[q] = xg[q];
-                    us[q] = ug[q];
-                }
-                __syncthreads();
-                if (has) {
-                    const int lo = max(r0, t0), hi = min(r1, t0 + TILE);
-                    for (int r = lo; r < hi; ++r) {
-                        const int q = 3 * (r - t0);
-                        add(xs[q], xs[q + 1], xs[q + 2], us[q], us[q + 1], us[q + 2]);
-                    }
-                }
-                __syncthreads();
-            }
+            for (; r < r1; ++r) take(a.xrec[r], a.urec[r]);
+            if (in_g > 0) t.add(g);
+            point_finish(a.cons_x, i, old, r1 - r0, t, pri, dual);
         }
+    } else {
+        __shared__ int gstart[4][64], gpoint[4][64];
+        __shared__ PtSums gsum[4][64];
+        // lane j: its point's groups start at gstart[j] (exclusive scan)
+        const int G = has ? cons_groups(r1 - r0) : 0;
+        int start = G;
+#pragma unroll
+        for (int off = 1; off < 64; off <<= 1) {
+            const int v = __shfl_up(start, off, 64);
+            if (lane >= off) start += v;
+        }
+        start -= G;
+        gstart[w][lane] = start;
+        for (int k = 0; k < G; ++k) gpoint[w][start + k] = lane;
+        const int n_groups = __shfl(start + G, 63, 64);
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+        // lane l: group l of the wave
+        if (lane < n_groups) {
+            const int j = gpoint[w][lane], ip = p0 + j;
+            const int q0 = a.pt_off[ip], q1 = a.pt_off[ip + 1];
+            const int K = cons_group(q1 - q0);
+            const int g0 = q0 + (lane - gstart[w][j]) * K, g1 = min(g0 + K, q1);
+            const double4 old = a.cons_x[ip];
+            PtSums g;
+            g.clear();
+            for (int r = g0; r < g1; r += 8) {
+                PtCopy<R> x[8];
+                PtDual u[8];
+#pragma unroll
+                for (int k = 0; k < 8; ++k)
+                    if (r + k < g1) {
+                        x[k] = a.xrec[r + k];
+                        u[k] = a.urec[r + k];
+                    }
+#pragma unroll
+                for (int k = 0; k < 8; ++k)
+                    if (r + k < g1) g.add(x[k], u[k], old);
+            }
+            gsum[w][lane] = g;
+        }
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
         if (has) {
-            const double n = (double)(r1 - r0);
-            const double c0 = s0 / n, c1 = s1 / n, c2 = s2 / n;
-            const double e0 = c0 - old.x, e1 = c1 - old.y, e2 = c2 - old.z;
-            a.cons_x[i] = make_double4(c0, c1, c2, 0.0);
-            const double ee = e0 * e0 + e1 * e1 + e2 * e2;
-            pri = fmax(qq - 2.0 * (e0 * q0 + e1 * q1 + e2 * q2) + n * ee, 0.0);
-            dual = n * ee;
+            const double4 old = a.cons_x[i];
+            PtSums t;
+            t.clear();
+            for (int k = 0; k < G; ++k) t.add(gsum[w][start + k]);
+            point_finish(a.cons_x, i, old, r1 - r0, t, pri, dual);
         }
-        // fixed-order tree over the block's points
-        const int t = threadIdx.x;
-        sh[0][t] = pri;
-        sh[1][t] = dual;
+    }
+    pri = wave_sum(pri);
+    dual = wave_sum(dual);
+    if (lane == 0) {
+        pd[2 * w] = pri;
+        pd[2 * w + 1] = dual;
+    }
+}
+
+// Consensus kernel: workgroups [0, pt_blocks) hold kConsWaves consensus
+// waves each (never two problems' waves: the layout pads each problem to
+// whole workgroups) and add their residual terms in wave order; the rest
+// four cameras each.
+template <typename R, int SCHED>
+__global__ __launch_bounds__(256) void k_consensus(DevArrays<R> a, int pt_blocks)
+{
+    static_assert(kConsWaves == 4, "four waves per workgroup");
+    if ((int)blockIdx.x < pt_blocks) {
+        __shared__ double pd[2 * kConsWaves];
+        const int lane = threadIdx.x & 63, w = wave_id();
+        point_wave<R, SCHED>(a, kConsWaves * blockIdx.x + w, w, lane, pd);
         __syncthreads();
-        for (int w = kPtBlock / 2; w >= 1; w >>= 1) {
-            if (t < w) {
-                sh[0][t] += sh[0][t + w];
-                sh[1][t] += sh[1][t + w];
+        if (threadIdx.x == 0) {
+            double pri = 0.0, dual = 0.0;
+#pragma unroll
+            for (int k = 0; k < kConsWaves; ++k) {
+                pri += pd[2 * k];
+                dual += pd[2 * k + 1];
             }
-            __syncthreads();
-        }
-        if (t == 0) {
-            a.ppart[2 * (long long)b] = sh[0][0];
-            a.ppart[2 * (long long)b + 1] = sh[1][0];
+            a.ppart[2 * (long long)blockIdx.x] = pri;
+            a.ppart[2 * (long long)blockIdx.x + 1] = dual;
         }
     } else {
         // camera consensus: lane l sums chunks k0 + l, k0 + l + 64, ... in
@@ -628,10 +644,13 @@ __global__ __launch_bounds__(kNormThreads) void k_norms(DevArrays<R> a)
     const int p = blockIdx.x;
     const ProblemRange pr = a.prob[p];
     double v[4] = {0.0, 0.0, 0.0, 0.0};  // pri_x, dual_x, pri_y, dual_y
-    for (int i = threadIdx.x; i < pr.n_pblk; i += kNormThreads) {
-        v[0] += a.ppart[2 * (long long)(pr.pblk0 + i)];
-        v[1] += a.ppart[2 * (long long)(pr.pblk0 + i) + 1];
+    const int b0 = pr.cw0 / kConsWaves, nb = pr.n_cw / kConsWaves;
+#pragma unroll 4
+    for (int i = threadIdx.x; i < nb; i += kNormThreads) {
+        v[0] += a.ppart[2 * (long long)(b0 + i)];
+        v[1] += a.ppart[2 * (long long)(b0 + i) + 1];
     }
+#pragma unroll 4
     for (int j = threadIdx.x; j < pr.n_cams; j += kNormThreads) {
         v[2] += a.campart[2 * (long long)(pr.cam0 + j)];
         v[3] += a.campart[2 * (long long)(pr.cam0 + j) + 1];
@@ -819,18 +838,12 @@ hipError_t launch_local_learned(const DevArrays<float> &a, const SolverParams &s
 template <typename R>
 hipError_t launch_consensus(const DevArrays<R> &a, int schedule, hipStream_t s)
 {
-    const int cam_blocks = (a.n_cams + 3) / 4;
-    const dim3 grid(a.n_pblk + cam_blocks), block(256);
+    const int pt_blocks = a.n_cw / kConsWaves, cam_blocks = (a.n_cams + 3) / 4;
+    const dim3 grid(pt_blocks + cam_blocks), block(256);
     if (schedule == 2)
-        hipLaunchKernelGGL((k_consensus<R, 512>), grid, block, 0, s, a, a.n_pblk);
-    else if (schedule == 3)
-        hipLaunchKernelGGL((k_consensus<R, 1024>), grid, block, 0, s, a, a.n_pblk);
-    else if (schedule == 4)
-        hipLaunchKernelGGL((k_consensus<R, -128>), grid, block, 0, s, a, a.n_pblk);
-    else if (schedule == 5)
-        hipLaunchKernelGGL((k_consensus<R, -256>), grid, block, 0, s, a, a.n_pblk);
+        hipLaunchKernelGGL((k_consensus<R, 2>), grid, block, 0, s, a, pt_blocks);
     else
-        hipLaunchKernelGGL((k_consensus<R, 0>), grid, block, 0, s, a, a.n_pblk);
+        hipLaunchKernelGGL((k_consensus<R, 1>), grid, block, 0, s, a, pt_blocks);
     return hipGetLastError();
 }
 

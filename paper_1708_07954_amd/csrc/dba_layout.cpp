@@ -173,9 +173,10 @@ int build_layout(const LayoutOptions &o, int np, const dba_problem_desc *probs, 
     std::vector<PairBlocks> pbs(k2 ? np : 0);
     // global sizes
     long long n_chunks = 0, n_recs = 0;
-    int n_cams = 0, n_pts = 0, n_pblk = 0, n_blocks = 0;
+    int n_cams = 0, n_pts = 0, n_blocks = 0;
     out.n_problems = np;
     out.ranges.clear();
+    out.cw_pt0.clear();
     for (int p = 0; p < np; ++p) {
         const dba_problem_desc &d = probs[p];
         std::vector<int> cc(d.n_cams, 0);
@@ -197,8 +198,29 @@ int build_layout(const LayoutOptions &o, int np, const dba_problem_desc *probs, 
         }
         r.n_chunks = (int)ch;
         r.rec0 = n_recs; r.n_obs = d.n_obs;
-        r.pblk0 = n_pblk; r.n_pblk = (d.n_points + kPtBlock - 1) / kPtBlock;
-        n_pblk += r.n_pblk;
+        // consensus waves: consecutive points while their record groups fit
+        // the 64 lanes
+        {
+            std::vector<int> nrec_pt(d.n_points, 0);
+            if (k2)
+                for (int pt : pbs[p].pts) ++nrec_pt[pt];
+            else
+                for (long long k = 0; k < d.n_obs; ++k) ++nrec_pt[d.obs_point[k]];
+            r.cw0 = (int)out.cw_pt0.size();
+            int lanes = CH;
+            for (int i = 0; i < d.n_points; ++i) {
+                const int g = cons_groups(nrec_pt[i]);
+                if (lanes + g > CH) {
+                    out.cw_pt0.push_back(n_pts + i);
+                    lanes = 0;
+                }
+                lanes += g;
+            }
+            // whole workgroups of kConsWaves waves per problem (empty waves
+            // start at the problem's end)
+            while ((out.cw_pt0.size() - r.cw0) % kConsWaves) out.cw_pt0.push_back(n_pts + d.n_points);
+            r.n_cw = (int)out.cw_pt0.size() - r.cw0;
+        }
         out.ranges.push_back(r);
         n_cams += d.n_cams;
         n_pts += d.n_points;
@@ -213,7 +235,8 @@ int build_layout(const LayoutOptions &o, int np, const dba_problem_desc *probs, 
     out.n_recs = n_recs;
     out.n_cams = n_cams;
     out.n_pts = n_pts;
-    out.n_pblk = n_pblk;
+    out.n_cw = (int)out.cw_pt0.size();
+    out.cw_pt0.push_back(n_pts);
     out.n_blocks2 = k2 ? n_blocks : 0;
 
     out.uv.assign(2 * (size_t)S, R(0));
@@ -232,19 +255,10 @@ int build_layout(const LayoutOptions &o, int np, const dba_problem_desc *probs, 
     out.cam_count.assign(n_cams, 0);
     out.cons_y.assign((size_t)n_cams * kConsY, 0.0);
     out.cons_x.assign(4 * (size_t)n_pts, 0.0);
-    out.pblk_pt0.assign(n_pblk, 0);
-    out.pblk_cnt.assign(n_pblk, 0);
     // two-camera blocks: chunk of each pair camera (or -1), record of each lane (or -1)
     out.blk_chunk.assign(k2 ? 2 * (size_t)n_blocks : 0, -1);
     out.blk_rec.assign(k2 ? (size_t)n_blocks * CH : 0, -1);
     int blk_base = 0;
-    for (int p = 0; p < np; ++p) {
-        const ProblemRange &r = out.ranges[p];
-        for (int q = 0; q < r.n_pblk; ++q) {
-            out.pblk_pt0[r.pblk0 + q] = r.pt0 + q * kPtBlock;
-            out.pblk_cnt[r.pblk0 + q] = std::min(kPtBlock, r.n_points - q * kPtBlock);
-        }
-    }
     auto set_uv = [&](long long sl, const double *z) {
         out.uv[2 * sl] = (R)z[0];
         out.uv[2 * sl + 1] = (R)z[1];

@@ -18,13 +18,25 @@ namespace dba {
 
 constexpr int kChunk = 64;
 constexpr int kConsY = 16;      // doubles per camera consensus row
-constexpr int kPtBlock = 256;   // points per consensus block (never straddles problems)
+
+// Point consensus order: a point's n records are summed in groups of
+// cons_group(n) consecutive records (8, or n / 64 rounded up when n > 512, so
+// that a point has at most 64 groups), each group in record order, and the
+// group sums in group order.  The consensus waves below and every kernel
+// schedule follow this order, so their results are bitwise identical.
+constexpr int kGroupMin = 8;
+constexpr int cons_group(int n) { return n > 64 * kGroupMin ? (n + 63) / 64 : kGroupMin; }
+constexpr int cons_groups(int n) { return (n + cons_group(n) - 1) / cons_group(n); }
+// consensus waves per workgroup of the consensus kernel; a problem's waves
+// fill whole workgroups (the last ones may be empty), whose residual terms
+// are summed per workgroup
+constexpr int kConsWaves = 4;
 
 struct ProblemRange {           // per problem, global index ranges
     int cam0, n_cams;
     int pt0, n_points;
     int chunk0, n_chunks;
-    int pblk0, n_pblk;          // point blocks of the consensus kernel
+    int cw0, n_cw;              // consensus waves (point ranges of the consensus kernel)
     long long rec0, n_obs;
 };
 
@@ -44,7 +56,7 @@ struct Layout {
     int n_problems = 0;
     std::vector<ProblemRange> ranges;
     long long n_slots = 0, n_chunks = 0, n_recs = 0;
-    int n_cams = 0, n_pts = 0, n_pblk = 0, n_blocks2 = 0;
+    int n_cams = 0, n_pts = 0, n_cw = 0, n_blocks2 = 0;
     std::vector<R> uv;                      // [n_slots][2]
     std::vector<int> pslot, ptid, orig;     // [n_slots]; pslot -1 on padding
     std::vector<R> copy_y;                  // [9][n_slots] (per-observation local problems)
@@ -55,7 +67,10 @@ struct Layout {
     std::vector<int> pt_prob;               // [n_pts]
     std::vector<double> cons_y;             // [n_cams][kConsY]
     std::vector<double> cons_x;             // [n_pts][4]
-    std::vector<int> pblk_pt0, pblk_cnt;    // [n_pblk]
+    std::vector<int> cw_pt0;                // [n_cw + 1] first point of each consensus wave: at
+                                            // most 64 points with at most 64 record groups in
+                                            // all, within one problem; n_cw a multiple of
+                                            // kConsWaves per problem
     std::vector<int> blk_chunk, blk_rec;    // two-camera blocks: [n_blocks2][2], [n_blocks2][64]
     std::vector<R> copy_yc;                 // [n_chunks][9] camera copy per chunk
 };

@@ -185,7 +185,25 @@ void check_layout(const char *name, const dba::LayoutOptions &o, const std::vect
         for (long long t = 0; t < L.n_recs; ++t) CHECK(rec_used[t] >= 1 && rec_used[t] <= 2, "%s: copy record %lld",
                                                        name, t);
     }
-    for (int b = 0; b < L.n_pblk; ++b) CHECK(L.pblk_cnt[b] >= 1 && L.pblk_cnt[b] <= dba::kPtBlock, "%s: point block", name);
+    // consensus waves: cover the points in order, at most 64 points and 64
+    // record groups each, never across a problem boundary
+    CHECK((int)L.cw_pt0.size() == L.n_cw + 1 && L.cw_pt0[0] == 0 && L.cw_pt0[L.n_cw] == L.n_pts, "%s: waves", name);
+    for (int w = 0; w < L.n_cw; ++w) {
+        const int a = L.cw_pt0[w], b = L.cw_pt0[w + 1];
+        CHECK(b >= a && b - a <= CH, "%s: wave %d holds %d points", name, w, b - a);
+        if (b == a) continue;   // padding to whole workgroups
+        int groups = 0;
+        for (int i = a; i < b; ++i) groups += dba::cons_groups(L.pt_off[i + 1] - L.pt_off[i]);
+        CHECK(groups >= 1 && groups <= CH, "%s: wave %d holds %d groups", name, w, groups);
+        CHECK(L.pt_prob[a] == L.pt_prob[b - 1], "%s: wave %d straddles problems", name, w);
+    }
+    for (int p = 0, cw = 0; p < L.n_problems; ++p) {
+        const dba::ProblemRange &r = L.ranges[p];
+        CHECK(r.cw0 == cw && r.n_cw >= 1 && r.n_cw % dba::kConsWaves == 0, "%s: problem %d waves", name, p);
+        CHECK(L.cw_pt0[r.cw0] == r.pt0 && L.cw_pt0[r.cw0 + r.n_cw] == r.pt0 + r.n_points, "%s: problem %d wave range",
+              name, p);
+        cw += r.n_cw;
+    }
     for (long long c = 0; c < L.n_chunks; ++c)
         for (int t = 0; t < 9; ++t)
             CHECK(L.copy_yc[9 * c + t] == (R)L.cons_y[(size_t)L.chunk_cam[c] * dba::kConsY + t], "%s: copy_yc", name);
@@ -233,9 +251,25 @@ void check_validation()
 
 }  // namespace
 
+// The record groups of the consensus order: at most 64 per point, covering
+// its records exactly, groups of 8 up to 512 records.
+void check_groups()
+{
+    for (int n = 1; n <= 20000; ++n) {
+        const int K = dba::cons_group(n), G = dba::cons_groups(n);
+        if (!(G >= 1 && G <= 64 && (long long)K * G >= n && (long long)K * (G - 1) < n &&
+              (n > 512 || K == 8))) {
+            std::fprintf(stderr, "FAIL record groups of a %d-record track: %d of %d\n", n, G, K);
+            g_fail = 1;
+            return;
+        }
+    }
+}
+
 int main()
 {
     int layouts = 0;
+    check_groups();
     std::vector<Prob> set1 = {random_problem(37, 900, 2, 15, 11)};
     // cameras with 1, 63, 64, 65, 128, 129 observations, a 1-observation point
     {
@@ -255,6 +289,14 @@ int main()
         for (int i = 0; i < 10048; ++i) obs.push_back({0, i});
         for (int j = 1; j < 300; ++j) obs.push_back({j, 7});
         set1.push_back(make(300, 10048, obs, 13));
+    }
+    // tracks of 513 and 4 100 records (more than 8 records per group)
+    {
+        std::vector<std::pair<int, int>> obs;
+        for (int j = 0; j < 4100; ++j) obs.push_back({j, 0});
+        for (int j = 0; j < 513; ++j) obs.push_back({j, 1});
+        for (int j = 0; j < 4100; ++j) obs.push_back({j, 2 + j % 5});
+        set1.push_back(make(4100, 7, obs, 15));
     }
     // a one-observation problem
     set1.push_back(make(1, 1, {{0, 0}}, 14));

@@ -51,11 +51,11 @@ def test_layout_edges_match_the_oracle(n_cams, n_points, precision):
 
 @pytest.mark.parametrize("n_cams,n_points", [(300, 3), (2, 10000), (5, 256), (3, 257), (1, 1)])
 def test_segment_schedules_agree_bitwise_on_layout_edges(n_cams, n_points):
-    # tracks longer than a tile (300 records against tiles of 128 / 256 per
-    # wave and 512 / 1024 per block), blocks filled exactly or by one point
+    # tracks of 300 records (38 groups of 8), of 2 records (a wave of 64
+    # points), consensus waves filled exactly or by one point
     sc = make_ring_scene(seed=11, n_cams=n_cams, n_points=n_points)
     ref = None
-    for sched in (1, 2, 3, 4, 5):
+    for sched in (1, 2):
         s = binding.Solver(precision="fp64", segment_schedule=sched, **KW).set_scene(sc)
         s.iterate(5)
         got = (*s.params(), s.state()[1], s.residuals()["primal"])

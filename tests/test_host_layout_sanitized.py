@@ -22,8 +22,10 @@ def test_layout_builder_under_address_and_ub_sanitizers(tmp_path):
            "-fno-sanitize-recover=all", "-I", os.path.join(ROOT, "include"), "-I", CSRC,
            os.path.join(CSRC, "dba_layout.cpp"), os.path.join(ROOT, "tests", "host_layout_check.cpp"), "-o", str(exe)]
     subprocess.check_call(cmd)
-    env = dict(os.environ, ASAN_OPTIONS="detect_leaks=1:halt_on_error=1", UBSAN_OPTIONS="halt_on_error=1")
-    env.pop("LD_PRELOAD", None)
+    # verify_asan_link_order=0: the environment may preload a library ahead
+    # of the sanitizer runtime, which is left as it is
+    env = dict(os.environ, ASAN_OPTIONS="detect_leaks=1:halt_on_error=1:verify_asan_link_order=0",
+               UBSAN_OPTIONS="halt_on_error=1")
     r = subprocess.run([str(exe)], capture_output=True, text=True, env=env, timeout=300)
     print(r.stdout, r.stderr[-3000:])
     assert r.returncode == 0, r.stderr[-3000:]

@@ -216,6 +216,20 @@ def _time_to_target(binding, scene, kw, goal, max_iters, net=None):
     return out
 
 
+def tuned_schedule(binding, scenes, kw):
+    """Launch and segment schedules the autotuner picks for a configuration,
+    on a handle of its own (the tuning iterations are real iterations, which
+    the measured runs then do not repeat)."""
+    tuner = binding.Solver(**kw).set_scenes(scenes)
+    tuner.iterate(TUNING_ITERATIONS)
+    sched = binding.dba_schedule(tuner.h)
+    seg = binding.dba_segment_schedule(tuner.h)
+    tuner.close()
+    assert seg["tuned"] > 0, "the consensus schedule was not tuned within the tuning iterations"
+    return dict(block_waves=sched["block_waves"], persistent=sched["persistent"],
+                segment_schedule=seg["segment_schedule"])
+
+
 def time_to_rmse(binding, scene, opts, sched, target, max_iters=400, learned_steps=(1, 2, 3, 4, 5)):
     """Wall time of plain 5-step LM, of the paper's L-BFGS local solver for
     the Huber misfit (5 and 10 iterations), of block local updates (one camera
@@ -237,15 +251,15 @@ def time_to_rmse(binding, scene, opts, sched, target, max_iters=400, learned_ste
                                         persistent=sched["persistent"],
                                         segment_schedule=sched.get("segment_schedule", 0)))
             print(f"[bench] time-to-RMSE L-BFGS, {k} iterations: {res[f'lbfgs{k}']}", file=sys.stderr, flush=True)
+    # block local updates run other kernels: each configuration with the
+    # schedule the autotuner picks for it
     for k in (1, 2, 5):
-        res[f"blocks_lm{k}"] = run(dict(opts, lm_steps=k, camera_blocks=True, block_waves=sched["block_waves"],
-                                        persistent=sched["persistent"],
-                                        segment_schedule=sched.get("segment_schedule", 0)))
+        kw = dict(opts, lm_steps=k, camera_blocks=True)
+        res[f"blocks_lm{k}"] = run(dict(kw, **tuned_schedule(binding, [scene], kw)))
         print(f"[bench] time-to-RMSE blocks, {k} LM steps: {res[f'blocks_lm{k}']}", file=sys.stderr, flush=True)
     for k in (1, 2, 5):
-        res[f"blocks2_lm{k}"] = run(dict(opts, lm_steps=k, camera_blocks=True, block_cameras=2,
-                                         block_waves=min(sched["block_waves"], 4), persistent=sched["persistent"],
-                                        segment_schedule=sched.get("segment_schedule", 0)))
+        kw = dict(opts, lm_steps=k, camera_blocks=True, block_cameras=2)
+        res[f"blocks2_lm{k}"] = run(dict(kw, **tuned_schedule(binding, [scene], kw)))
         print(f"[bench] time-to-RMSE two-camera blocks, {k} LM steps: {res[f'blocks2_lm{k}']}", file=sys.stderr,
               flush=True)
     best = lambda key: min((res[f"{key}_lm{k}"]["seconds"] for k in (1, 2, 5)

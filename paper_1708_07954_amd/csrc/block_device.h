@@ -314,9 +314,9 @@ __device__ __forceinline__ void block_lm(R *th, const R *vy, const R *vx, R z0, 
 // each lane forms its 3x3 point block and, with U_s the camera rows of its
 // observation s (9x2), its contribution U_s M_st U_t^T to the 18x18 reduced
 // camera system (M 4x4 from the damped, inverted point block); a fixed-order
-// reduction sums the contributions into LDS, the wave factors the system in
-// LDS (LDL^T, one column after another, the trailing update spread over the
-// lanes), and every lane solves and back-substitutes its point.
+// reduction sums the contributions into LDS, lanes 0..17 factor the system
+// (LDL^T, a column per lane, pivots and columns broadcast between lanes) and
+// solve it, and every lane back-substitutes its point.
 
 // Packed upper triangle of a symmetric 18x18 matrix: index of (i, j), i <= j.
 __host__ __device__ constexpr int sym18(int i, int j) { return i * 18 - i * (i - 1) / 2 + (j - i); }
@@ -351,64 +351,93 @@ __device__ __forceinline__ void wave_reduce_to(const T *b, T *dst, int lane)
     dst[lane] = g;
 }
 
-// LDL^T of the packed symmetric 18x18 matrix a (LDS, in place: row j keeps D_j
-// on the diagonal and L_ij, i > j, at (j, i)); false if a pivot is not
-// positive and finite.  Column j: the trailing update a_ik -= a_ji a_jk / D_j
-// over the lanes (rc: row and column of each packed index, in LDS), then the
-// row is scaled.
-template <typename R>
-__device__ __forceinline__ bool ldl18_lds(R *a, const unsigned char *rc, int lane)
+// Value v of lane l (wave-uniform result).
+__device__ __forceinline__ float lane_read(float v, int l)
 {
+    return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), l));
+}
+__device__ __forceinline__ double lane_read(double v, int l)
+{
+    const int lo = __builtin_amdgcn_readlane(__double2loint(v), l);
+    const int hi = __builtin_amdgcn_readlane(__double2hiint(v), l);
+    return __hiloint2double(hi, lo);
+}
+
+// Solves A x = b for the symmetric 18x18 A (packed upper triangle in the
+// wave's LDS a, b at a + kB2Rhs) by LDL^T; x is returned in every lane.
+// False if a pivot is not positive and finite.  Lane j < 18 holds column j
+// of A (a_ij, i <= j) in registers.  Step k broadcasts the pivot and column
+// k (a_ki from lane i) and lane j updates a_ij -= a_ki L_jk, keeping L_jk;
+// the forward solve broadcasts z_i as it completes, the backward solve
+// reads column j of L, which the lanes write back into LDS, and broadcasts
+// x_j.  Lanes past 17 shadow lane 17 (their values are never read).
+template <typename R>
+__device__ __forceinline__ bool ldl18_lanes(R *a, int lane, R *x)
+{
+    const int j = lane < 18 ? lane : 17;
+    R col[18];
+#pragma unroll
+    for (int i = 0; i < 18; ++i) col[i] = i <= j ? a[sym18(i, j)] : R(0);
     bool ok = true;
-    for (int j = 0; j < 18; ++j) {
-        const R d = a[sym18(j, j)];
-        ok = ok && (d > R(0)) && (d < Num<R>::inf);
-        const R rd = Num<R>::rcp(d);
-        if (j + 1 < 18)
-            for (int t = sym18(j + 1, j + 1) + lane; t < kB2Sys; t += 64) {
-                const int i = rc[2 * t], k = rc[2 * t + 1];
-                a[t] -= a[sym18(j, i)] * a[sym18(j, k)] * rd;
-            }
-        wave_lds_sync();
-        if (lane > j && lane < 18) a[sym18(j, lane)] *= rd;
-        wave_lds_sync();
+    R rdv[18];
+#pragma unroll
+    for (int k = 0; k < 18; ++k) {
+        const R dk = lane_read(col[k], k);
+        ok = ok && (dk > R(0)) && (dk < Num<R>::inf);
+        const R rdk = Num<R>::rcp(dk);
+        rdv[k] = rdk;
+        const R ljk = col[k] * rdk;
+#pragma unroll
+        for (int i = k + 1; i < 18; ++i) col[i] -= lane_read(col[k], i) * ljk;
+        col[k] = ljk;
+    }
+    // L z = b, z_i broadcast as it completes (lane j > i holds L_ji)
+    R z[18], acc = a[kB2Rhs + j];
+#pragma unroll
+    for (int i = 0; i < 18; ++i) {
+        z[i] = lane_read(acc, i);
+        acc -= col[i] * z[i];
+    }
+    // column j of L into LDS at (j, i), i > j, for the backward solve
+    wave_lds_sync();
+    if (lane < 18)
+#pragma unroll
+        for (int i = 0; i < 18; ++i)
+            if (i < j) a[sym18(i, j)] = col[i];
+    wave_lds_sync();
+    R lc[18];
+#pragma unroll
+    for (int i = 0; i < 18; ++i) lc[i] = i > j ? a[sym18(j, i)] : R(0);
+    // L^T x = D^-1 z, x_i broadcast from i = 17 down
+    acc = R(0);
+#pragma unroll
+    for (int i = 0; i < 18; ++i) acc = j == i ? z[i] * rdv[i] : acc;
+#pragma unroll
+    for (int i = 17; i >= 0; --i) {
+        x[i] = lane_read(acc, i);
+        acc -= lc[i] * x[i];
     }
     return ok;
 }
 
-// x = A^-1 b with A factored by ldl18_lds (every lane, reading LDS).
-template <typename R>
-__device__ __forceinline__ void ldl18_solve(const R *a, const R *b, R *x)
-{
-#pragma unroll
-    for (int i = 0; i < 18; ++i) {
-        R v = b[i];
-#pragma unroll
-        for (int k = 0; k < i; ++k) v -= a[sym18(k, i)] * x[k];
-        x[i] = v;
-    }
-#pragma unroll
-    for (int i = 0; i < 18; ++i) x[i] *= Num<R>::rcp(a[sym18(i, i)]);
-#pragma unroll
-    for (int i = 17; i >= 0; --i) {
-        R v = x[i];
-#pragma unroll
-        for (int k = i + 1; k < 18; ++k) v -= a[sym18(i, k)] * x[k];
-        x[i] = v;
-    }
-}
+// Projection state of a camera model (Proj or ProjE).
+template <typename R, typename Cam>
+using ProjOf = decltype(proj_core<R, true>(static_cast<const R *>(nullptr), Cam{}));
 
 // Block LM of a two-camera block.  y: the cameras (18, uniform), present
 // bit s: camera s has a copy in the block (an absent camera does not move and
-// has no penalty); x, vx: this lane's point copy and its target; act[s]: this
-// lane has an observation of camera s at pixel (z[2s], z[2s+1]).  lds: the
-// wave's kB2Lds values.
+// has no penalty); vy: their targets (18, in the wave's LDS); x, vx: this
+// lane's point copy and its target; act[s]: this lane has an observation of
+// camera s at pixel (z[2s], z[2s+1]).  lds: the wave's kB2Lds values; pst:
+// the wave's LDS for the two projections of each lane between LM steps (FP32;
+// nullptr: held in registers), which frees their registers during the
+// reduction and the factorisation.
 template <typename R, typename Cam>
 __device__ __forceinline__ void block_lm2(R *y, const R *vy, int present, R *x, const R *vx, const bool *act,
                                           const R *z, R rx, R ry, int kind, R lp, int steps, R lam, R *lds,
-                                          const unsigned char *rc, int lane)
+                                          ProjOf<R, Cam> *pst, int lane)
 {
-    using P = decltype(proj_core<R, true>(y, Cam{}));
+    using P = ProjOf<R, Cam>;
     R *red = lds, *scr = lds + 256;
     const bool pt = act[0] || act[1];
     auto theta = [&](int s, R *th) {
@@ -459,6 +488,7 @@ __device__ __forceinline__ void block_lm2(R *y, const R *vy, int present, R *x, 
             R th[12];
             theta(s, th);
             cur[s] = proj_core<R, true>(th, Cam{});
+            if (pst) pst[2 * lane + s] = cur[s];
         }
     R F = wave_sum<R>(lane_obj(cur, x)) + cam_pen(y);
     for (int it = 0; it < steps; ++it) {
@@ -475,9 +505,10 @@ __device__ __forceinline__ void block_lm2(R *y, const R *vy, int present, R *x, 
             if (act[s]) {
                 R th[12], J0[12], J1[12];
                 theta(s, th);
-                proj_jac<R>(cur[s], th, J0, J1);
-                e[s][0] = z[2 * s] - cur[s].pu;
-                e[s][1] = z[2 * s + 1] - cur[s].pv;
+                const P cs = pst ? pst[2 * lane + s] : cur[s];
+                proj_jac<R>(cs, th, J0, J1);
+                e[s][0] = z[2 * s] - cs.pu;
+                e[s][1] = z[2 * s + 1] - cs.pv;
                 R w;
                 const R s2 = e[s][0] * e[s][0] + e[s][1] * e[s][1];
                 loss_phi<R>(kind, lp, s2, w);
@@ -557,15 +588,22 @@ __device__ __forceinline__ void block_lm2(R *y, const R *vy, int present, R *x, 
             if (t % 64 == 0 && t > 0) wave_reduce_to<R>(b32, red + t - 64, lane);
             rs_first_put<R>(b32, t % 64, v);
         };
+        // entry (i, j), camera rows i of s and j of u: U_si^T M_su U_uj =
+        // k0 U[u][0][j] + k1 U[u][1][j] with (k0, k1) = U_si^T M_su
 #pragma unroll
-        for (int i = 0; i < 18; ++i)
+        for (int i = 0; i < 18; ++i) {
+            const int s = i / 9;
+            const R a0 = U[s][0][i % 9], a1 = U[s][1][i % 9];
 #pragma unroll
-            for (int j = i; j < 18; ++j) {
-                const int s = i / 9, u = j / 9, p = s + u;
-                const R q0 = M[p][0][0] * U[u][0][j % 9] + M[p][0][1] * U[u][1][j % 9];
-                const R q1 = M[p][1][0] * U[u][0][j % 9] + M[p][1][1] * U[u][1][j % 9];
-                put(sym18(i, j), U[s][0][i % 9] * q0 + U[s][1][i % 9] * q1);
+            for (int u = s; u < 2; ++u) {
+                const int p = s + u;
+                const R k0 = a0 * M[p][0][0] + a1 * M[p][1][0];
+                const R k1 = a0 * M[p][0][1] + a1 * M[p][1][1];
+#pragma unroll
+                for (int j = (u == s ? i : 9 * u); j < 9 * u + 9; ++j)
+                    put(sym18(i, j), k0 * U[u][0][j % 9] + k1 * U[u][1][j % 9]);
             }
+        }
 #pragma unroll
         for (int i = 0; i < 18; ++i) {
             const int s = i / 9;
@@ -599,9 +637,8 @@ __device__ __forceinline__ void block_lm2(R *y, const R *vy, int present, R *x, 
             }
         }
         wave_lds_sync();
-        const bool oky = ldl18_lds<R>(red, rc, lane);
         R dy[18];
-        ldl18_solve<R>(red, red + kB2Rhs, dy);
+        const bool oky = ldl18_lanes<R>(red, lane, dy);
         const bool ok = oky && (__ballot(!okx) == 0ull);
         // point step dx = B (ng_x - W^T dy), W_s = c_s U_s V_s^T, and the
         // predicted decrease 1/2 (lambda d^T diag(H) d + ng^T d)
@@ -661,7 +698,10 @@ __device__ __forceinline__ void block_lm2(R *y, const R *vy, int present, R *x, 
             for (int k = 0; k < 3; ++k) x[k] = tx[k];
 #pragma unroll
             for (int s = 0; s < 2; ++s)
-                if (act[s]) cur[s] = nxt[s];
+                if (act[s]) {
+                    if (pst) pst[2 * lane + s] = nxt[s];
+                    else cur[s] = nxt[s];
+                }
             F = Fn;
             lam = lam_down<R>(lam);
         } else {

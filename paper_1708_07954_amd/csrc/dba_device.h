@@ -716,6 +716,16 @@ __device__ __forceinline__ void wave_sum19_store(const double *v, double *o, int
 // vector registers.
 __device__ __forceinline__ int wave_id() { return __builtin_amdgcn_readfirstlane(threadIdx.x >> 6); }
 
+// A value every lane of the wave holds the same copy of, moved to scalar
+// registers (frees the vector registers a uniform load would otherwise hold).
+__device__ __forceinline__ int uniform(int v) { return __builtin_amdgcn_readfirstlane(v); }
+__device__ __forceinline__ double uniform(double v)
+{
+    const int lo = __builtin_amdgcn_readfirstlane(__double2loint(v));
+    const int hi = __builtin_amdgcn_readfirstlane(__double2hiint(v));
+    return __hiloint2double(hi, lo);
+}
+
 __device__ __forceinline__ int xcd_block()
 {
     const int G = gridDim.x, b = blockIdx.x;

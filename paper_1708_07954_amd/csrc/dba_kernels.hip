@@ -42,18 +42,20 @@ __device__ __forceinline__ void local_chunk(const DevArrays<R> &a, const SolverP
                                             __bf16 *io = nullptr)
 {
     using R2 = typename Vec<R>::R2;
-    const int J = a.chunk_cam[c];
-    const Ctrl *ct = a.ctrl + a.cam_prob[J];
-    const double rho_x = ct->rho_x, rho_y = ct->rho_y;
-    const double rat_x = ct->ratio_x, rat_y = ct->ratio_y;
-    const int pending = ct->pending;
+    // the chunk's camera and its problem's control block are the same for
+    // every lane: scalar registers
+    const int J = uniform(a.chunk_cam[c]);
+    const Ctrl *ct = a.ctrl + uniform(a.cam_prob[J]);
+    const double rho_x = uniform(ct->rho_x), rho_y = uniform(ct->rho_y);
+    const double rat_x = uniform(ct->ratio_x), rat_y = uniform(ct->ratio_y);
+    const int pending = uniform(ct->pending);
     const long long S = a.n_slots;
     const long long s = (long long)c * kChunk + lane;
     const int ps = a.pslot[s];
     const bool active = ps >= 0;
     double cy[9];
 #pragma unroll
-    for (int i = 0; i < 9; ++i) cy[i] = a.cons_y[(long long)J * kConsY + i];
+    for (int i = 0; i < 9; ++i) cy[i] = uniform(a.cons_y[(long long)J * kConsY + i]);
 
     double acc[19];
 #pragma unroll
@@ -268,7 +270,7 @@ __global__ __launch_bounds__(LocalBound<R>::threads) void k_local_block(DevArray
 // (slot l of each); the camera copies and their duals are per chunk.
 template <typename R, typename Cam>
 __device__ __forceinline__ void local_block2(const DevArrays<R> &a, const SolverParams &sp, int b, int lane,
-                                             R *lds, const unsigned char *rc)
+                                             R *lds, ProjOf<R, Cam> *pst, R *vys)
 {
     using R2 = typename Vec<R>::R2;
     const int ch[2] = {a.blk_chunk[2 * b], a.blk_chunk[2 * b + 1]};
@@ -277,15 +279,13 @@ __device__ __forceinline__ void local_block2(const DevArrays<R> &a, const Solver
     const double rho_x = ct->rho_x, rho_y = ct->rho_y;
     const double rat_x = ct->ratio_x, rat_y = ct->ratio_y;
     const int pending = ct->pending;
-    double cy[18], uy[18];
+    // the camera consensus and scaled duals are read again by lane 0 at the
+    // end (the duals as lane 0 wrote them), not held through the solve
     R y[18], vy[18];
 #pragma unroll
     for (int s = 0; s < 2; ++s) {
 #pragma unroll
-        for (int i = 0; i < 9; ++i) {
-            cy[9 * s + i] = uy[9 * s + i] = 0.0;
-            y[9 * s + i] = vy[9 * s + i] = R(0);
-        }
+        for (int i = 0; i < 9; ++i) y[9 * s + i] = vy[9 * s + i] = R(0);
         if (ch[s] < 0) continue;
         const int J = a.chunk_cam[ch[s]];
 #pragma unroll
@@ -293,15 +293,13 @@ __device__ __forceinline__ void local_block2(const DevArrays<R> &a, const Solver
             const double c = a.cons_y[(long long)J * kConsY + i];
             R t = a.copy_yc[(long long)ch[s] * 9 + i];
             double u = a.dual_yc[(long long)ch[s] * 9 + i];
-            if (pending) u = (u + ((double)t - c)) * rat_y;
-            cy[9 * s + i] = c;
-            uy[9 * s + i] = u;
+            if (pending) {
+                u = (u + ((double)t - c)) * rat_y;
+                if (lane == 0) a.dual_yc[(long long)ch[s] * 9 + i] = u;
+            }
             y[9 * s + i] = t;
             vy[9 * s + i] = (R)(c - u);
         }
-        if (pending && lane == 0)
-#pragma unroll
-            for (int i = 0; i < 9; ++i) a.dual_yc[(long long)ch[s] * 9 + i] = uy[9 * s + i];
     }
     const int ps = a.blk_rec[(long long)b * kChunk + lane];
     bool act[2];
@@ -334,21 +332,28 @@ __device__ __forceinline__ void local_block2(const DevArrays<R> &a, const Solver
 #pragma unroll
         for (int i = 0; i < 3; ++i) vx[i] = (R)(cxs[i] - u[i]);
     }
-    block_lm2<R, Cam>(y, vy, present, x, vx, act, z, (R)rho_x, (R)rho_y, sp.loss, (R)sp.loss_param, sp.lm_steps,
-                      (R)sp.lambda0, lds, rc, lane);
+    // the targets, uniform, from the wave's LDS during the solve
+    if (lane < 18) vys[lane] = vy[lane];
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    block_lm2<R, Cam>(y, vys, present, x, vx, act, z, (R)rho_x, (R)rho_y, sp.loss, (R)sp.loss_param, sp.lm_steps,
+                      (R)sp.lambda0, lds, pst, lane);
     if (ps >= 0) a.xrec[ps] = PtCopy<R>{x[0], x[1], x[2]};
     if (lane == 0)
 #pragma unroll
         for (int s = 0; s < 2; ++s) {
             if (ch[s] < 0) continue;
             double *o = a.cpart + (long long)ch[s] * kCpart;
+            const int J = a.chunk_cam[ch[s]];
             double q = 0.0;
 #pragma unroll
             for (int i = 0; i < 9; ++i) {
+                const double cy = a.cons_y[(long long)J * kConsY + i], uy = a.dual_yc[(long long)ch[s] * 9 + i];
                 a.copy_yc[(long long)ch[s] * 9 + i] = y[9 * s + i];
                 const double t = (double)y[9 * s + i];
-                const double dd = t - cy[9 * s + i];
-                o[i] = t + uy[9 * s + i];
+                const double dd = t - cy;
+                o[i] = t + uy;
                 o[9 + i] = dd;
                 q += dd * dd;
             }
@@ -358,23 +363,27 @@ __device__ __forceinline__ void local_block2(const DevArrays<R> &a, const Solver
 
 constexpr int kBlock2Threads = 256;
 
+// LDS of one wave of the two-camera kernel (dynamic, so a workgroup of w
+// waves takes w of these): the reduced system, the camera targets and, in
+// FP32, each lane's two projections between LM steps.
 template <typename R, typename Cam>
-__global__ __launch_bounds__(kBlock2Threads) void k_local_block2(DevArrays<R> a, SolverParams sp, int persistent)
+struct Block2Lds {
+    R red[kB2Lds];
+    R vys[20];
+    ProjOf<R, Cam> pst[sizeof(R) == 4 ? 128 : 1];
+};
+
+// Two waves per SIMD: with the projections in LDS the FP32 kernel fits 256
+// registers (the FP64 one spills; it serves the FP64 parity runs).
+template <typename R, typename Cam>
+__global__ __launch_bounds__(kBlock2Threads, 2) void k_local_block2(DevArrays<R> a, SolverParams sp, int persistent)
 {
-    __shared__ R lds[kBlock2Threads / 64][kB2Lds];
-    __shared__ unsigned char rc[2 * kB2Sys];
-    // row and column of every packed index of the 18x18 system
-    for (int t = threadIdx.x; t < kB2Sys; t += blockDim.x) {
-        int i = 0;
-        while (i < 17 && sym18(i + 1, i + 1) <= t) ++i;
-        rc[2 * t] = (unsigned char)i;
-        rc[2 * t + 1] = (unsigned char)(i + (t - sym18(i, i)));
-    }
-    __syncthreads();
+    extern __shared__ __align__(16) unsigned char b2_lds[];
     const int lane = threadIdx.x & 63, wave = wave_id(), wpb = blockDim.x >> 6;
+    Block2Lds<R, Cam> &L = reinterpret_cast<Block2Lds<R, Cam> *>(b2_lds)[wave];
     int b0, b1;
     chunk_range(a.n_blocks2, wpb, persistent, b0, b1);
-    for (int b = b0 + wave; b < b1; b += wpb) local_block2<R, Cam>(a, sp, b, lane, lds[wave], rc);
+    for (int b = b0 + wave; b < b1; b += wpb) local_block2<R, Cam>(a, sp, b, lane, L.red, sizeof(R) == 4 ? L.pst : nullptr, L.vys);
 }
 
 // Learned start: the workgroup's waves share the staged weights (one copy
@@ -857,7 +866,7 @@ hipError_t launch_local_block(const DevArrays<R> &a, const SolverParams &sp, int
         const int threads = 64 * block_waves;
         int grid;
         if (persistent) {
-            grid = n_cu * (4 / block_waves > 0 ? 4 / block_waves : 1);
+            grid = n_cu * (8 / block_waves > 0 ? 8 / block_waves : 1);  // two waves per SIMD
             const int need = (a.n_blocks2 + block_waves - 1) / block_waves;
             if (grid > need) grid = need;
         } else {
@@ -865,9 +874,11 @@ hipError_t launch_local_block(const DevArrays<R> &a, const SolverParams &sp, int
         }
         if (grid < 1) grid = 1;
         if (sp.camera == 1)
-            hipLaunchKernelGGL((k_local_block2<R, CamEuler>), dim3(grid), dim3(threads), 0, s, a, sp, persistent);
+            hipLaunchKernelGGL((k_local_block2<R, CamEuler>), dim3(grid), dim3(threads),
+                               block_waves * sizeof(Block2Lds<R, CamEuler>), s, a, sp, persistent);
         else
-            hipLaunchKernelGGL((k_local_block2<R, CamAA>), dim3(grid), dim3(threads), 0, s, a, sp, persistent);
+            hipLaunchKernelGGL((k_local_block2<R, CamAA>), dim3(grid), dim3(threads),
+                               block_waves * sizeof(Block2Lds<R, CamAA>), s, a, sp, persistent);
         return hipGetLastError();
     }
     if (64 * block_waves > LocalBound<R>::threads) block_waves = LocalBound<R>::threads / 64;

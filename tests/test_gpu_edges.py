@@ -22,7 +22,10 @@ KW = dict(loss="huber", loss_param=2.0, rho=1e4)
 EDGES = [(1, 1), (1, 2), (2, 63), (3, 64), (2, 65), (1, 129), (5, 255), (5, 256), (3, 257), (4, 7), (9, 3),
          # long segments: 157 chunks summed into one camera's consensus; point
          # tracks of 300 records (more than a consensus block has threads)
-         (2, 10000), (300, 3)]
+         (2, 10000), (300, 3),
+         # tracks of 600 records: more than 512, so the consensus sums them in
+         # 60 groups of 10 records
+         (600, 2)]
 
 
 def _oracle(sc, iters):
@@ -49,10 +52,11 @@ def test_layout_edges_match_the_oracle(n_cams, n_points, precision):
     assert r["iteration"] == iters and np.isfinite(r["primal"])
 
 
-@pytest.mark.parametrize("n_cams,n_points", [(300, 3), (2, 10000), (5, 256), (3, 257), (1, 1)])
+@pytest.mark.parametrize("n_cams,n_points", [(300, 3), (600, 2), (2, 10000), (5, 256), (3, 257), (1, 1)])
 def test_segment_schedules_agree_bitwise_on_layout_edges(n_cams, n_points):
-    # tracks of 300 records (38 groups of 8), of 2 records (a wave of 64
-    # points), consensus waves filled exactly or by one point
+    # tracks of 300 records (38 groups of 8), of 600 (60 groups of 10), of 2
+    # records (a wave of 64 points), consensus waves filled exactly or by one
+    # point
     sc = make_ring_scene(seed=11, n_cams=n_cams, n_points=n_points)
     ref = None
     for sched in (1, 2):

@@ -49,13 +49,17 @@ def test_forward_and_gradients_match_oracle():
     scale = np.abs(Y[:, :12]).max()
     err_y = np.abs(y[:, :12] - Y[:, :12]).max() / scale
     print("forward max rel err", err_y)
-    assert err_y < 2e-3
-    assert loss == pytest.approx(mlp.loss(Y, t), rel=2e-3)
+    assert err_y < 1e-3
+    assert loss == pytest.approx(mlp.loss(Y, t), rel=1e-3)
+    # element by element, relative to each parameter block's largest gradient
+    # (both sides round the same activations to BF16; the rest is FP32
+    # against FP64 accumulation)
     gg = mlp.unflatten(grad.astype(np.float64))
     for k in g:
-        e = np.linalg.norm(gg[k] - g[k]) / np.linalg.norm(g[k])
-        print("grad", k, e)
-        assert e < 1e-2, (k, e)
+        e = np.abs(gg[k] - g[k]).max() / np.abs(g[k]).max()
+        print("grad", k, "max element error / max |grad|", e,
+              "norm ratio", np.linalg.norm(gg[k] - g[k]) / np.linalg.norm(g[k]))
+        assert e < 1e-3, (k, e)
     binding.dba_destroy(h)
 
 
@@ -71,7 +75,9 @@ def test_forward_api_standardizes_like_the_oracle():
     nm = norm.astype(np.float64)
     Y, _ = mlp.forward(p, mlp.standardize_input(f.astype(np.float64), nm[:26], nm[26:52]), quantize=True)
     ref = Y[:, :12] * nm[64:76] + nm[52:64]
-    assert np.abs(d - ref).max() < 2e-3 * np.abs(ref - nm[52:64]).max() + 1e-6
+    err = np.abs(d - ref).max() / np.abs(ref - nm[52:64]).max()
+    print("forward through the API, max error / output scale", err)
+    assert err < 1e-3
     binding.dba_destroy(h)
 
 

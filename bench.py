@@ -95,7 +95,7 @@ def make_scenes(kind):
 
 
 # iterations of the tuning handle: every local-solve schedule candidate (8)
-# and every consensus segment schedule (2) once, with room to spare
+# and every consensus segment schedule (3) once, with room to spare
 TUNING_ITERATIONS = 16
 
 

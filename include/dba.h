@@ -123,8 +123,10 @@ typedef struct dba_options {
     int32_t segment_schedule; /* point-consensus segment schedule: 1 a thread per point sums its
                                  records; 2 a thread per group of up to 8 consecutive records
                                  (more for tracks over 512), the point's group sums then added
-                                 in order.  Both sum each point's records in the same groups and
-                                 order, so the results are bitwise identical; 0: autotune */
+                                 in order; 3 as 2 with each wave's records staged through LDS
+                                 by coalesced loads.  All sum each point's records in the same
+                                 groups and order, so the results are bitwise identical; 0:
+                                 autotune */
 } dba_options;
 
 /* Fills *opt with the defaults: device 0, NULL stream, FP64, Huber 2 px,

@@ -88,6 +88,15 @@ def load(path: Optional[str] = None) -> ctypes.CDLL:
     path = path or LIB_PATH
     if not os.path.exists(path):
         raise RuntimeError(f"{path} is not built; run python -m paper_1708_07954_amd.build")
+    # One HIP runtime per process: the library's libamdhip64.so.7 resolves to
+    # whichever copy is loaded first.  Where PyTorch is installed its bundled
+    # runtime must be that copy -- with the system one loaded first, PyTorch's
+    # device initialisation fails (hipErrorNoDevice) -- so it is imported
+    # before the library.
+    try:
+        import torch  # noqa: F401
+    except ImportError:
+        pass
     L = ctypes.CDLL(path)
     P = ctypes.POINTER
     vp, i32, i64, dbl = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_double

@@ -411,7 +411,7 @@ int iterate_impl(dba_handle *h, const DevArrays<R> &A, int n)
     }
     // then the segment schedule of the consensus, on real iterations with
     // the local schedule fixed; its candidates are bitwise identical too
-    static const int cand_seg[] = {1, 2};
+    static const int cand_seg[] = {1, 2, 3};
     constexpr int n_seg = (int)(sizeof(cand_seg) / sizeof(cand_seg[0]));
     while (!h->seg_ready && n > 0) {
         const int q = h->seg_next;
@@ -558,7 +558,7 @@ int dba_create(const dba_options *opt, dba_handle **out)
         return DBA_E_INVALID_ARG;
     if (o.block_cameras != 1 && o.block_cameras != 2) return DBA_E_INVALID_ARG;
     if (o.block_cameras == 2 && !o.camera_blocks) return DBA_E_INVALID_ARG;
-    if (o.segment_schedule < 0 || o.segment_schedule > 2) return DBA_E_INVALID_ARG;
+    if (o.segment_schedule < 0 || o.segment_schedule > 3) return DBA_E_INVALID_ARG;
     dba_handle *h = new dba_handle();
     h->opt = o;
     h->fp32 = o.precision == DBA_PREC_FP32_LOCAL;

@@ -454,7 +454,10 @@ __device__ __forceinline__ void point_finish(double4 *cons_x, int i, const doubl
 //   SCHED 1: lane j sums the records of the wave's point j, four loads in
 //            flight, closing each group as it goes;
 //   SCHED 2: lane l sums one record group (eight loads in flight), the group
-//            sums meet in LDS and lane j adds its point's groups in order.
+//            sums meet in LDS and lane j adds its point's groups in order;
+//   SCHED 3: as 2, with the wave's records staged through LDS in tiles
+//            loaded with coalesced loads.
+constexpr int kStageRecs = 128;
 template <typename R, int SCHED>
 __device__ __forceinline__ void point_wave(const DevArrays<R> &a, int cw, int w, int lane, double *pd)
 {
@@ -517,15 +520,20 @@ __device__ __forceinline__ void point_wave(const DevArrays<R> &a, int cw, int w,
         __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
         __builtin_amdgcn_wave_barrier();
         __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-        // lane l: group l of the wave
+        // lane l: group l of the wave, records [g0, g1)
+        int g0 = 0, g1 = 0;
+        double4 old = make_double4(0.0, 0.0, 0.0, 0.0);
         if (lane < n_groups) {
             const int j = gpoint[w][lane], ip = p0 + j;
             const int q0 = a.pt_off[ip], q1 = a.pt_off[ip + 1];
             const int K = cons_group(q1 - q0);
-            const int g0 = q0 + (lane - gstart[w][j]) * K, g1 = min(g0 + K, q1);
-            const double4 old = a.cons_x[ip];
-            PtSums g;
-            g.clear();
+            g0 = q0 + (lane - gstart[w][j]) * K;
+            g1 = min(g0 + K, q1);
+            old = a.cons_x[ip];
+        }
+        PtSums g;
+        g.clear();
+        if constexpr (SCHED == 2) {
             for (int r = g0; r < g1; r += 8) {
                 PtCopy<R> x[8];
                 PtDual u[8];
@@ -539,8 +547,60 @@ __device__ __forceinline__ void point_wave(const DevArrays<R> &a, int cw, int w,
                 for (int k = 0; k < 8; ++k)
                     if (r + k < g1) g.add(x[k], u[k], old);
             }
-            gsum[w][lane] = g;
+        } else {
+            // the wave's records are contiguous: tiles of kStageRecs staged
+            // through LDS with coalesced loads (the next tile's loads in
+            // flight while the lanes sum the current one); a record r of
+            // the tile sits at 3 (r + r / 8) so that lanes reading records 8
+            // apart hit different banks
+            constexpr int T = kStageRecs, PER = 3 * T / 64;
+            static_assert(3 * T % 64 == 0, "whole values per lane");
+            __shared__ R xs[4][3 * (T + T / 8)];
+            __shared__ double us[4][3 * (T + T / 8)];
+            const int wa = a.pt_off[p0], wb = a.pt_off[p0 + np];
+            R xr[PER];
+            double ur[PER];
+            auto fetch = [&](int t0) {
+                const int n3 = 3 * min(T, wb - t0);
+                const R *xg = reinterpret_cast<const R *>(a.xrec + t0);
+                const double *ug = reinterpret_cast<const double *>(a.urec + t0);
+#pragma unroll
+                for (int k = 0; k < PER; ++k) {
+                    const int q = lane + 64 * k;
+                    if (q < n3) {
+                        xr[k] = xg[q];
+                        ur[k] = ug[q];
+                    }
+                }
+            };
+            if (wa < wb) fetch(wa);
+            for (int t0 = wa; t0 < wb; t0 += T) {
+                const int n3 = 3 * min(T, wb - t0);
+#pragma unroll
+                for (int k = 0; k < PER; ++k) {
+                    const int q = lane + 64 * k;
+                    if (q < n3) {
+                        const int li = q + 3 * ((q / 3) >> 3);
+                        xs[w][li] = xr[k];
+                        us[w][li] = ur[k];
+                    }
+                }
+                __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+                __builtin_amdgcn_wave_barrier();
+                __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+                if (t0 + T < wb) fetch(t0 + T);
+                const int lo = max(g0, t0), hi = min(g1, t0 + T);
+                for (int r = lo; r < hi; ++r) {
+                    const int rl = r - t0, li = 3 * (rl + (rl >> 3));
+                    g.add(PtCopy<R>{xs[w][li], xs[w][li + 1], xs[w][li + 2]},
+                          PtDual{us[w][li], us[w][li + 1], us[w][li + 2]}, old);
+                }
+                __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+                __builtin_amdgcn_wave_barrier();
+                __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+            }
         }
+        if (lane < n_groups) gsum[w][lane] = g;
         __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
         __builtin_amdgcn_wave_barrier();
         __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
@@ -851,6 +911,8 @@ hipError_t launch_consensus(const DevArrays<R> &a, int schedule, hipStream_t s)
     const dim3 grid(pt_blocks + cam_blocks), block(256);
     if (schedule == 2)
         hipLaunchKernelGGL((k_consensus<R, 2>), grid, block, 0, s, a, pt_blocks);
+    else if (schedule == 3)
+        hipLaunchKernelGGL((k_consensus<R, 3>), grid, block, 0, s, a, pt_blocks);
     else
         hipLaunchKernelGGL((k_consensus<R, 1>), grid, block, 0, s, a, pt_blocks);
     return hipGetLastError();

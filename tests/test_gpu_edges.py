@@ -59,7 +59,7 @@ def test_segment_schedules_agree_bitwise_on_layout_edges(n_cams, n_points):
     # point
     sc = make_ring_scene(seed=11, n_cams=n_cams, n_points=n_points)
     ref = None
-    for sched in (1, 2):
+    for sched in (1, 2, 3):
         s = binding.Solver(precision="fp64", segment_schedule=sched, **KW).set_scene(sc)
         s.iterate(5)
         got = (*s.params(), s.state()[1], s.residuals()["primal"])

@@ -132,8 +132,8 @@ def test_every_schedule_is_bitwise_identical(precision):
                     assert got[4:] == ref[4:]
                 s.close()
     # the point-consensus segment schedules (a thread per point; a thread
-    # per record group)
-    for sched in (1, 2):
+    # per record group, loading directly or through LDS)
+    for sched in (1, 2, 3):
         s = gpu_run(sc, 6, block_waves=4, persistent=0, segment_schedule=sched, **kw)
         assert binding.dba_segment_schedule(s.h) == dict(segment_schedule=sched, tuned=0)
         np.testing.assert_array_equal(s.params()[0], ref[0])
@@ -146,7 +146,7 @@ def test_every_schedule_is_bitwise_identical(precision):
     s.iterate(10)
     assert binding.dba_schedule(s.h)["tuned"] > 1
     seg = binding.dba_segment_schedule(s.h)
-    assert seg["tuned"] == 2 and seg["segment_schedule"] in (1, 2)
+    assert seg["tuned"] == 3 and seg["segment_schedule"] in (1, 2, 3)
 
 
 @pytest.mark.parametrize("use_graph", [False, True])

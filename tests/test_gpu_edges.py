@@ -1,8 +1,9 @@
 """Edge cases of the layout against the FP64 oracle: the smallest problem
 (one observation), cameras whose observations fill a 64-slot chunk exactly,
-miss it by one or spill one slot into the next, point counts around the
-256-point consensus block, camera counts around the 4-camera consensus
-block, long camera segments and long point tracks; a batch mixing a
+miss it by one or spill one slot into the next, point counts around 256
+and 64-lane consensus waves, camera counts around the 4-camera consensus
+block, long camera segments and long point tracks (beyond 512 records, where
+the consensus groups grow past 8 records); a batch mixing a
 one-observation problem with larger ones; empty and degenerate inputs
 rejected with the documented status."""
 import numpy as np

@@ -86,7 +86,8 @@ int build_set(dba_handle *h, int np, const dba_problem_desc *probs, ProblemSet *
     const std::vector<int> &pt_off = lay.pt_off, &chunk_cam = lay.chunk_cam, &cam_prob = lay.cam_prob,
                            &pt_prob = lay.pt_prob, &cam_chunk0 = lay.cam_chunk0, &cam_count = lay.cam_count,
                            &cw_pt0 = lay.cw_pt0, &pslot = lay.pslot,
-                           &ptid = lay.ptid, &orig = lay.orig, &blk_chunk = lay.blk_chunk, &blk_rec = lay.blk_rec;
+                           &ptid = lay.ptid, &orig = lay.orig, &blk_chunk = lay.blk_chunk, &blk_rec = lay.blk_rec,
+                           &blk_cam = lay.blk_cam, &blk_prob = lay.blk_prob, &blk_pt = lay.blk_pt;
     const std::vector<double> &cons_y = lay.cons_y;
     const std::vector<R> &copy_y = lay.copy_y, &copy_yc = lay.copy_yc;
 
@@ -152,16 +153,26 @@ int build_set(dba_handle *h, int np, const dba_problem_desc *probs, ProblemSet *
     HIP_TRY(h, B.alloc(&d_dual_yc, 9 * (size_t)n_chunks));
     HIP_TRY(h, hipMemcpy(d_copy_yc, copy_yc.data(), 9 * (size_t)n_chunks * sizeof(R), hipMemcpyHostToDevice));
     HIP_TRY(h, hipMemset(d_dual_yc, 0, 9 * (size_t)n_chunks * sizeof(double)));
-    int *d_blk_chunk = nullptr, *d_blk_rec = nullptr;
+    int *d_blk_chunk = nullptr, *d_blk_rec = nullptr, *d_blk_cam = nullptr, *d_blk_prob = nullptr,
+        *d_blk_pt = nullptr;
     if (k2) {
-        HIP_TRY(h, B.alloc(&d_blk_chunk, blk_chunk.size()));
-        HIP_TRY(h, B.alloc(&d_blk_rec, blk_rec.size()));
-        HIP_TRY(h, hipMemcpy(d_blk_chunk, blk_chunk.data(), blk_chunk.size() * sizeof(int), hipMemcpyHostToDevice));
-        HIP_TRY(h, hipMemcpy(d_blk_rec, blk_rec.data(), blk_rec.size() * sizeof(int), hipMemcpyHostToDevice));
+        auto up = [&](int **d, const std::vector<int> &v) -> hipError_t {
+            hipError_t e = B.alloc(d, v.size());
+            if (e == hipSuccess) e = hipMemcpy(*d, v.data(), v.size() * sizeof(int), hipMemcpyHostToDevice);
+            return e;
+        };
+        HIP_TRY(h, up(&d_blk_chunk, blk_chunk));
+        HIP_TRY(h, up(&d_blk_rec, blk_rec));
+        HIP_TRY(h, up(&d_blk_cam, blk_cam));
+        HIP_TRY(h, up(&d_blk_prob, blk_prob));
+        HIP_TRY(h, up(&d_blk_pt, blk_pt));
     }
     A.n_blocks2 = lay.n_blocks2;
     A.blk_chunk = d_blk_chunk;
     A.blk_rec = d_blk_rec;
+    A.blk_cam = d_blk_cam;
+    A.blk_prob = d_blk_prob;
+    A.blk_pt = d_blk_pt;
     A.camera_blocks = h->opt.camera_blocks ? 1 : 0;
     A.copy_yc = d_copy_yc;
     A.dual_yc = d_dual_yc;

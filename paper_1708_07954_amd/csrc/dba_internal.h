@@ -72,6 +72,9 @@ struct DevArrays {
     int n_blocks2;        // two-camera blocks (0: none): one wavefront each
     const int *blk_chunk; // [n_blocks2][2] chunk of the pair's first / second camera, or -1
     const int *blk_rec;   // [n_blocks2][64] point record of each lane, or -1
+    const int *blk_cam;   // [n_blocks2][2] camera of the pair's first / second chunk, or -1
+    const int *blk_prob;  // [n_blocks2] problem of the block
+    const int *blk_pt;    // [n_blocks2][64] point of each lane, or -1
     const uint8_t *mask;  // [n_slots] evaluation mask
     const int *slot_orig; // [n_slots] observation index within its problem
     // records

@@ -270,41 +270,46 @@ __global__ __launch_bounds__(LocalBound<R>::threads) void k_local_block(DevArray
 // (slot l of each); the camera copies and their duals are per chunk.
 template <typename R, typename Cam>
 __device__ __forceinline__ void local_block2(const DevArrays<R> &a, const SolverParams &sp, int b, int lane,
-                                             R *lds, ProjOf<R, Cam> *pst, R *vys)
+                                             R *lds, ProjOf<R, Cam> *pst, R *vys, R *ys, double *cyu)
 {
     using R2 = typename Vec<R>::R2;
+    // block header: chunk and camera of each pair camera, problem (every
+    // per-block and per-lane load below depends on these or on the lane's
+    // slot only)
     const int ch[2] = {a.blk_chunk[2 * b], a.blk_chunk[2 * b + 1]};
+    const int cam[2] = {a.blk_cam[2 * b], a.blk_cam[2 * b + 1]};
     const int present = (ch[0] >= 0 ? 1 : 0) | (ch[1] >= 0 ? 2 : 0);
-    const Ctrl *ct = a.ctrl + a.cam_prob[a.chunk_cam[ch[0] >= 0 ? ch[0] : ch[1]]];
+    const Ctrl *ct = a.ctrl + a.blk_prob[b];
     const double rho_x = ct->rho_x, rho_y = ct->rho_y;
     const double rat_x = ct->ratio_x, rat_y = ct->ratio_y;
     const int pending = ct->pending;
-    // the camera consensus and scaled duals are read again by lane 0 at the
-    // end (the duals as lane 0 wrote them), not held through the solve
-    R y[18], vy[18];
-#pragma unroll
-    for (int s = 0; s < 2; ++s) {
-#pragma unroll
-        for (int i = 0; i < 9; ++i) y[9 * s + i] = vy[9 * s + i] = R(0);
-        if (ch[s] < 0) continue;
-        const int J = a.chunk_cam[ch[s]];
-#pragma unroll
-        for (int i = 0; i < 9; ++i) {
-            const double c = a.cons_y[(long long)J * kConsY + i];
-            R t = a.copy_yc[(long long)ch[s] * 9 + i];
-            double u = a.dual_yc[(long long)ch[s] * 9 + i];
-            if (pending) {
-                u = (u + ((double)t - c)) * rat_y;
-                if (lane == 0) a.dual_yc[(long long)ch[s] * 9 + i] = u;
-            }
-            y[9 * s + i] = t;
-            vy[9 * s + i] = (R)(c - u);
+    // lane i < 18 holds camera parameter i (camera i / 9): its consensus, its
+    // copy and its scaled dual (updated, Eqs. 12-13, and written back)
+    const int ci = lane < 18 ? lane : 17, cs = ci / 9, cp = ci - 9 * cs;
+    const bool cam_lane = lane < 18 && ch[cs] >= 0;
+    double cyi = 0.0, uyi = 0.0;
+    R ti = R(0);
+    if (cam_lane) {
+        cyi = a.cons_y[(long long)cam[cs] * kConsY + cp];
+        ti = a.copy_yc[(long long)ch[cs] * 9 + cp];
+        uyi = a.dual_yc[(long long)ch[cs] * 9 + cp];
+        if (pending) {
+            uyi = (uyi + ((double)ti - cyi)) * rat_y;
+            a.dual_yc[(long long)ch[cs] * 9 + cp] = uyi;
         }
     }
+    // the cameras and their targets to every lane through the wave's LDS;
+    // each parameter lane's consensus and dual wait there for the end
+    if (lane < 18) {
+        ys[lane] = ti;
+        vys[lane] = cam_lane ? (R)(cyi - uyi) : R(0);
+        cyu[lane] = cyi;
+        cyu[18 + lane] = uyi;
+    }
     const int ps = a.blk_rec[(long long)b * kChunk + lane];
+    const int pid = a.blk_pt[(long long)b * kChunk + lane];
     bool act[2];
     R z[4] = {R(0), R(0), R(0), R(0)};
-    int pid = 0;
 #pragma unroll
     for (int s = 0; s < 2; ++s) {
         const long long sl = (long long)(ch[s] >= 0 ? ch[s] : 0) * kChunk + lane;
@@ -313,7 +318,6 @@ __device__ __forceinline__ void local_block2(const DevArrays<R> &a, const Solver
             const R2 zz = a.uv[sl];
             z[2 * s] = zz.x;
             z[2 * s + 1] = zz.y;
-            pid = a.ptid[sl];
         }
     }
     R x[3] = {R(0), R(0), R(0)}, vx[3] = {R(0), R(0), R(0)};
@@ -332,33 +336,42 @@ __device__ __forceinline__ void local_block2(const DevArrays<R> &a, const Solver
 #pragma unroll
         for (int i = 0; i < 3; ++i) vx[i] = (R)(cxs[i] - u[i]);
     }
-    // the targets, uniform, from the wave's LDS during the solve
-    if (lane < 18) vys[lane] = vy[lane];
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
     __builtin_amdgcn_wave_barrier();
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    R y[18];
+#pragma unroll
+    for (int i = 0; i < 18; ++i) y[i] = ys[i];
     block_lm2<R, Cam>(y, vys, present, x, vx, act, z, (R)rho_x, (R)rho_y, sp.loss, (R)sp.loss_param, sp.lm_steps,
                       (R)sp.lambda0, lds, pst, lane);
     if (ps >= 0) a.xrec[ps] = PtCopy<R>{x[0], x[1], x[2]};
-    if (lane == 0)
+    // the chunks' camera copies and consensus partials, a parameter per lane:
+    // (y + u, y - previous consensus, |y - previous|^2)
+    double *dd2 = reinterpret_cast<double *>(lds);
+    if (cam_lane) {
+        R yi = y[0];
 #pragma unroll
-        for (int s = 0; s < 2; ++s) {
-            if (ch[s] < 0) continue;
-            double *o = a.cpart + (long long)ch[s] * kCpart;
-            const int J = a.chunk_cam[ch[s]];
-            double q = 0.0;
+        for (int k = 1; k < 18; ++k) yi = ci == k ? y[k] : yi;
+        a.copy_yc[(long long)ch[cs] * 9 + cp] = yi;
+        const double t = (double)yi, dd = t - cyu[ci];
+        double *o = a.cpart + (long long)ch[cs] * kCpart;
+        o[cp] = t + cyu[18 + ci];
+        o[9 + cp] = dd;
+        dd2[ci] = dd * dd;
+    }
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    if ((lane == 0 || lane == 9) && ch[lane / 9] >= 0) {
+        double q = 0.0;
 #pragma unroll
-            for (int i = 0; i < 9; ++i) {
-                const double cy = a.cons_y[(long long)J * kConsY + i], uy = a.dual_yc[(long long)ch[s] * 9 + i];
-                a.copy_yc[(long long)ch[s] * 9 + i] = y[9 * s + i];
-                const double t = (double)y[9 * s + i];
-                const double dd = t - cy;
-                o[i] = t + uy;
-                o[9 + i] = dd;
-                q += dd * dd;
-            }
-            o[18] = q;
-        }
+        for (int i = 0; i < 9; ++i) q += dd2[lane + i];
+        a.cpart[(long long)ch[lane / 9] * kCpart + 18] = q;
+    }
+    // the LDS is reused by the next block of this wave
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
 constexpr int kBlock2Threads = 256;
@@ -370,6 +383,8 @@ template <typename R, typename Cam>
 struct Block2Lds {
     R red[kB2Lds];
     R vys[20];
+    R ys[20];
+    double cyu[36];
     ProjOf<R, Cam> pst[sizeof(R) == 4 ? 128 : 1];
 };
 
@@ -383,7 +398,7 @@ __global__ __launch_bounds__(kBlock2Threads, 2) void k_local_block2(DevArrays<R>
     Block2Lds<R, Cam> &L = reinterpret_cast<Block2Lds<R, Cam> *>(b2_lds)[wave];
     int b0, b1;
     chunk_range(a.n_blocks2, wpb, persistent, b0, b1);
-    for (int b = b0 + wave; b < b1; b += wpb) local_block2<R, Cam>(a, sp, b, lane, L.red, sizeof(R) == 4 ? L.pst : nullptr, L.vys);
+    for (int b = b0 + wave; b < b1; b += wpb) local_block2<R, Cam>(a, sp, b, lane, L.red, sizeof(R) == 4 ? L.pst : nullptr, L.vys, L.ys, L.cyu);
 }
 
 // Learned start: the workgroup's waves share the staged weights (one copy

@@ -258,6 +258,9 @@ int build_layout(const LayoutOptions &o, int np, const dba_problem_desc *probs, 
     // two-camera blocks: chunk of each pair camera (or -1), record of each lane (or -1)
     out.blk_chunk.assign(k2 ? 2 * (size_t)n_blocks : 0, -1);
     out.blk_rec.assign(k2 ? (size_t)n_blocks * CH : 0, -1);
+    out.blk_cam.assign(k2 ? 2 * (size_t)n_blocks : 0, -1);
+    out.blk_prob.assign(k2 ? (size_t)n_blocks : 0, 0);
+    out.blk_pt.assign(k2 ? (size_t)n_blocks * CH : 0, -1);
     int blk_base = 0;
     auto set_uv = [&](long long sl, const double *z) {
         out.uv[2 * sl] = (R)z[0];
@@ -300,12 +303,15 @@ int build_layout(const LayoutOptions &o, int np, const dba_problem_desc *probs, 
             const int nb = (int)pb.cam0.size();
             std::vector<int> brec(pb.pts.size());
             for (size_t t = 0; t < pb.pts.size(); ++t) brec[t] = (int)(r.rec0 + fill[pb.pts[t]]++);
-            for (int b = 0; b < nb; ++b)
+            for (int b = 0; b < nb; ++b) {
+                out.blk_prob[blk_base + b] = p;
                 for (int l = 0; l < pb.npts[b]; ++l) {
                     const int t = pb.pts0[b] + l;
                     out.blk_rec[(size_t)(blk_base + b) * CH + l] = brec[t];
+                    out.blk_pt[(size_t)(blk_base + b) * CH + l] = r.pt0 + pb.pts[t];
                     set_x(brec[t], d.points + 3LL * pb.pts[t]);
                 }
+            }
             int b0 = 0;
             for (int j = 0; j < d.n_cams; ++j) {
                 const int J = r.cam0 + j, sc = j & 1;
@@ -317,6 +323,7 @@ int build_layout(const LayoutOptions &o, int np, const dba_problem_desc *probs, 
                 for (int b = b0; b < nb && pb.cam0[b] == j - sc; ++b) {
                     if (!(pb.present[b] >> sc & 1)) continue;
                     out.blk_chunk[2 * (size_t)(blk_base + b) + sc] = chunk;
+                    out.blk_cam[2 * (size_t)(blk_base + b) + sc] = J;
                     out.chunk_cam[chunk] = J;
                     for (int l = 0; l < pb.npts[b]; ++l) {
                         const int t = pb.pts0[b] + l;

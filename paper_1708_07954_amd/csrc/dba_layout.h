@@ -72,6 +72,8 @@ struct Layout {
                                             // all, within one problem; n_cw a multiple of
                                             // kConsWaves per problem
     std::vector<int> blk_chunk, blk_rec;    // two-camera blocks: [n_blocks2][2], [n_blocks2][64]
+    std::vector<int> blk_cam, blk_prob;     // two-camera blocks: camera of each chunk (or -1), problem
+    std::vector<int> blk_pt;                // two-camera blocks: point of each lane (or -1)
     std::vector<R> copy_yc;                 // [n_chunks][9] camera copy per chunk
 };
 

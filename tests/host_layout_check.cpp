@@ -173,10 +173,21 @@ void check_layout(const char *name, const dba::LayoutOptions &o, const std::vect
                                                        rec_used[t]);
     } else {
         for (int b = 0; b < L.n_blocks2; ++b)
+            for (int l = 0; l < CH; ++l)
+                CHECK((L.blk_rec[(size_t)b * CH + l] < 0) == (L.blk_pt[(size_t)b * CH + l] < 0),
+                      "%s: block lane point", name);
+        for (int b = 0; b < L.n_blocks2; ++b)
             for (int s = 0; s < 2; ++s) {
                 const int c = L.blk_chunk[2 * (size_t)b + s];
+                CHECK((c < 0) == (L.blk_cam[2 * (size_t)b + s] < 0), "%s: block camera", name);
                 if (c < 0) continue;
                 CHECK(c < L.n_chunks, "%s: block chunk", name);
+                CHECK(L.blk_cam[2 * (size_t)b + s] == L.chunk_cam[c], "%s: block camera of its chunk", name);
+                CHECK(L.blk_prob[b] == L.cam_prob[L.chunk_cam[c]], "%s: block problem", name);
+                for (int l = 0; l < CH; ++l)
+                    if (L.pslot[(long long)c * CH + l] >= 0)
+                        CHECK(L.ptid[(long long)c * CH + l] == L.blk_pt[(size_t)b * CH + l], "%s: block lane point id",
+                              name);
                 for (int l = 0; l < CH; ++l)
                     if (L.pslot[(long long)c * CH + l] >= 0)
                         CHECK(L.pslot[(long long)c * CH + l] == L.blk_rec[(size_t)b * CH + l], "%s: block lane record",

@@ -83,7 +83,8 @@ int build_set(dba_handle *h, int np, const dba_problem_desc *probs, ProblemSet *
         c.rho_max = h->opt.rho_max;
         c.balancing = h->opt.rho_balancing ? 1 : 0;
     }
-    const std::vector<int> &pt_off = lay.pt_off, &chunk_cam = lay.chunk_cam, &cam_prob = lay.cam_prob,
+    const std::vector<int> &pt_off = lay.pt_off, &chunk_cam = lay.chunk_cam, &chunk_prob = lay.chunk_prob,
+                           &cam_prob = lay.cam_prob,
                            &pt_prob = lay.pt_prob, &cam_chunk0 = lay.cam_chunk0, &cam_count = lay.cam_count,
                            &cw_pt0 = lay.cw_pt0, &pslot = lay.pslot,
                            &ptid = lay.ptid, &orig = lay.orig, &blk_chunk = lay.blk_chunk, &blk_rec = lay.blk_rec,
@@ -94,7 +95,7 @@ int build_set(dba_handle *h, int np, const dba_problem_desc *probs, ProblemSet *
     // device
     Buffers &B = ps->buf;
     R2 *d_uv; int *d_pslot, *d_ptid, *d_orig; uint8_t *d_mask; R *d_copy; double *d_dual;
-    dba::PtCopy<R> *d_xrec; dba::PtDual *d_urec; int *d_ptoff, *d_chunk_cam, *d_cam_prob, *d_pt_prob, *d_cam_chunk0, *d_cam_count;
+    dba::PtCopy<R> *d_xrec; dba::PtDual *d_urec; int *d_ptoff, *d_chunk_cam, *d_chunk_prob, *d_cam_prob, *d_pt_prob, *d_cam_chunk0, *d_cam_count;
     double *d_cons_y; double4 *d_cons_x; Ctrl *d_ctrl; ProblemRange *d_prob;
     double *d_cpart, *d_ppart, *d_campart, *d_epart, *d_estats;
     int *d_cw_pt0;
@@ -109,6 +110,7 @@ int build_set(dba_handle *h, int np, const dba_problem_desc *probs, ProblemSet *
     HIP_TRY(h, B.alloc(&d_urec, n_recs));
     HIP_TRY(h, B.alloc(&d_ptoff, n_pts + 1));
     HIP_TRY(h, B.alloc(&d_chunk_cam, n_chunks));
+    HIP_TRY(h, B.alloc(&d_chunk_prob, n_chunks));
     HIP_TRY(h, B.alloc(&d_cam_prob, n_cams));
     HIP_TRY(h, B.alloc(&d_pt_prob, n_pts));
     HIP_TRY(h, B.alloc(&d_cam_chunk0, n_cams + 1));
@@ -138,6 +140,7 @@ int build_set(dba_handle *h, int np, const dba_problem_desc *probs, ProblemSet *
     HIP_TRY(h, hipMemset(d_urec, 0, n_recs * sizeof(dba::PtDual)));
     HIP_TRY(h, hipMemcpy(d_ptoff, pt_off.data(), (n_pts + 1) * sizeof(int), hipMemcpyHostToDevice));
     HIP_TRY(h, hipMemcpy(d_chunk_cam, chunk_cam.data(), n_chunks * sizeof(int), hipMemcpyHostToDevice));
+    HIP_TRY(h, hipMemcpy(d_chunk_prob, chunk_prob.data(), n_chunks * sizeof(int), hipMemcpyHostToDevice));
     HIP_TRY(h, hipMemcpy(d_cam_prob, cam_prob.data(), n_cams * sizeof(int), hipMemcpyHostToDevice));
     HIP_TRY(h, hipMemcpy(d_pt_prob, pt_prob.data(), n_pts * sizeof(int), hipMemcpyHostToDevice));
     HIP_TRY(h, hipMemcpy(d_cam_chunk0, cam_chunk0.data(), (n_cams + 1) * sizeof(int), hipMemcpyHostToDevice));
@@ -182,7 +185,7 @@ int build_set(dba_handle *h, int np, const dba_problem_desc *probs, ProblemSet *
     A.copy_y = d_copy; A.dual_y = d_dual; A.mask = d_mask; A.slot_orig = d_orig;
     A.n_recs = n_recs; A.xrec = d_xrec; A.urec = d_urec; A.pt_off = d_ptoff;
     A.n_chunks = (int)n_chunks; A.n_cams = n_cams; A.n_pts = n_pts; A.n_problems = np;
-    A.chunk_cam = d_chunk_cam; A.cam_prob = d_cam_prob; A.pt_prob = d_pt_prob;
+    A.chunk_cam = d_chunk_cam; A.chunk_prob = d_chunk_prob; A.cam_prob = d_cam_prob; A.pt_prob = d_pt_prob;
     A.cam_chunk0 = d_cam_chunk0; A.cam_count = d_cam_count;
     A.cons_y = d_cons_y; A.cons_x = d_cons_x; A.ctrl = d_ctrl; A.prob = d_prob;
     A.n_cw = n_cw; A.cw_pt0 = d_cw_pt0;

@@ -85,6 +85,7 @@ struct DevArrays {
     // chunks / cameras / points
     int n_chunks, n_cams, n_pts, n_problems;
     const int *chunk_cam;   // [n_chunks]
+    const int *chunk_prob;  // [n_chunks] problem of the chunk (its camera's)
     const int *cam_prob;    // [n_cams]
     const int *pt_prob;     // [n_pts]
     const int *cam_chunk0;  // [n_cams+1]

@@ -45,7 +45,7 @@ __device__ __forceinline__ void local_chunk(const DevArrays<R> &a, const SolverP
     // the chunk's camera and its problem's control block are the same for
     // every lane: scalar registers
     const int J = uniform(a.chunk_cam[c]);
-    const Ctrl *ct = a.ctrl + uniform(a.cam_prob[J]);
+    const Ctrl *ct = a.ctrl + uniform(a.chunk_prob[c]);
     const double rho_x = uniform(ct->rho_x), rho_y = uniform(ct->rho_y);
     const double rat_x = uniform(ct->ratio_x), rat_y = uniform(ct->ratio_y);
     const int pending = uniform(ct->pending);
@@ -155,36 +155,52 @@ __device__ __forceinline__ void local_chunk(const DevArrays<R> &a, const SolverP
     wave_sum19_store(acc, a.cpart + (long long)c * kCpart, lane);
 }
 
+// LDS of one wave of the one-camera block kernel: the all-reduce's 64 sums;
+// the chunk's camera copy and targets; its consensus, duals and squared
+// consensus differences.
+template <typename R>
+struct BlockLds {
+    R red[64];
+    R ys[12];
+    R vys[12];
+    double cyu[27];
+};
+
 // Generalised local update of one 64-slot chunk (Sec. 3.1.4, Eqs. 14-15):
 // the chunk's observations share one camera copy (copy_yc / dual_yc, per
 // chunk) and keep one point copy each.  Deferred dual updates of both, the
 // block LM (block_lm), then the chunk's one camera copy goes to the camera
 // consensus: cpart = (y + u, y - previous consensus, |y - previous|^2).
 template <typename R, typename Cam>
-__device__ __forceinline__ void local_block(const DevArrays<R> &a, const SolverParams &sp, int c, int lane, R *lds)
+__device__ __forceinline__ void local_block(const DevArrays<R> &a, const SolverParams &sp, int c, int lane,
+                                            BlockLds<R> &L)
 {
     using R2 = typename Vec<R>::R2;
-    const int J = a.chunk_cam[c];
-    const Ctrl *ct = a.ctrl + a.cam_prob[J];
+    const int J = uniform(a.chunk_cam[c]);
+    const Ctrl *ct = a.ctrl + uniform(a.chunk_prob[c]);
     const double rho_x = ct->rho_x, rho_y = ct->rho_y;
     const double rat_x = ct->ratio_x, rat_y = ct->ratio_y;
     const int pending = ct->pending;
     const long long s = (long long)c * kChunk + lane;
     const int ps = a.pslot[s];
     const bool active = ps >= 0;
-    double cy[9], uy[9];
-    R th[12], vy[9], vx[3] = {R(0), R(0), R(0)};
-#pragma unroll
-    for (int i = 0; i < 9; ++i) {
-        cy[i] = a.cons_y[(long long)J * kConsY + i];
-        th[i] = a.copy_yc[(long long)c * 9 + i];
-        uy[i] = a.dual_yc[(long long)c * 9 + i];
-        if (pending) uy[i] = (uy[i] + ((double)th[i] - cy[i])) * rat_y;
-        vy[i] = (R)(cy[i] - uy[i]);
+    // lane i < 9 holds camera parameter i: its consensus, the chunk's copy
+    // and scaled dual (updated, Eqs. 12-13, and written back); all lanes then
+    // read the copy and the targets through the wave's LDS
+    if (lane < 9) {
+        const double cyi = a.cons_y[(long long)J * kConsY + lane];
+        const R ti = a.copy_yc[(long long)c * 9 + lane];
+        double uyi = a.dual_yc[(long long)c * 9 + lane];
+        if (pending) {
+            uyi = (uyi + ((double)ti - cyi)) * rat_y;
+            a.dual_yc[(long long)c * 9 + lane] = uyi;
+        }
+        L.ys[lane] = ti;
+        L.vys[lane] = (R)(cyi - uyi);
+        L.cyu[lane] = cyi;
+        L.cyu[9 + lane] = uyi;
     }
-    if (pending && lane == 0)
-#pragma unroll
-        for (int i = 0; i < 9; ++i) a.dual_yc[(long long)c * 9 + i] = uy[i];
+    R th[12], vx[3] = {R(0), R(0), R(0)};
     R2 z;
     z.x = R(0);
     z.y = R(0);
@@ -205,25 +221,43 @@ __device__ __forceinline__ void local_block(const DevArrays<R> &a, const SolverP
 #pragma unroll
         for (int i = 0; i < 3; ++i) vx[i] = (R)(cxs[i] - u[i]);
     }
-    block_lm<R, Cam>(th, vy, vx, z.x, z.y, active, (R)rho_x, (R)rho_y, sp.loss, (R)sp.loss_param, sp.lm_steps,
-                (R)sp.lambda0, lds, lane);
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+#pragma unroll
+    for (int i = 0; i < 9; ++i) th[i] = L.ys[i];
+    block_lm<R, Cam>(th, L.vys, vx, z.x, z.y, active, (R)rho_x, (R)rho_y, sp.loss, (R)sp.loss_param, sp.lm_steps,
+                     (R)sp.lambda0, L.red, lane);
     if (active) {
         a.xrec[ps] = PtCopy<R>{th[9], th[10], th[11]};
     }
-    if (lane == 0) {
+    // the chunk's camera copy and consensus partials, a parameter per lane:
+    // (y + u, y - previous consensus, |y - previous|^2)
+    double *dd2 = L.cyu + 18;
+    if (lane < 9) {
+        R yi = th[0];
+#pragma unroll
+        for (int k = 1; k < 9; ++k) yi = lane == k ? th[k] : yi;
+        a.copy_yc[(long long)c * 9 + lane] = yi;
+        const double t = (double)yi, dd = t - L.cyu[lane];
         double *o = a.cpart + (long long)c * kCpart;
+        o[lane] = t + L.cyu[9 + lane];
+        o[9 + lane] = dd;
+        dd2[lane] = dd * dd;
+    }
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    if (lane == 0) {
         double q = 0.0;
 #pragma unroll
-        for (int i = 0; i < 9; ++i) {
-            a.copy_yc[(long long)c * 9 + i] = th[i];
-            const double t = (double)th[i];
-            const double dd = t - cy[i];
-            o[i] = t + uy[i];
-            o[9 + i] = dd;
-            q += dd * dd;
-        }
-        o[18] = q;
+        for (int i = 0; i < 9; ++i) q += dd2[i];
+        a.cpart[(long long)c * kCpart + 18] = q;
     }
+    // the LDS is reused by the wave's next chunk
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
 // FP32: up to 8 waves per workgroup; FP64 needs more than 256 VGPRs, so at
@@ -258,7 +292,7 @@ template <typename R, typename Cam>
 __global__ __launch_bounds__(LocalBound<R>::threads) void k_local_block(DevArrays<R> a, SolverParams sp,
                                                                         int persistent)
 {
-    __shared__ R lds[LocalBound<R>::threads / 64][64];
+    __shared__ BlockLds<R> lds[LocalBound<R>::threads / 64];
     const int lane = threadIdx.x & 63, wave = wave_id(), wpb = blockDim.x >> 6;
     int c0, c1;
     chunk_range(a.n_chunks, wpb, persistent, c0, c1);

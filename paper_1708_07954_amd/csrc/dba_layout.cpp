@@ -249,6 +249,7 @@ int build_layout(const LayoutOptions &o, int np, const dba_problem_desc *probs, 
     out.xrec.assign(3 * (size_t)n_recs, R(0));
     out.pt_off.assign(n_pts + 1, 0);
     out.chunk_cam.assign(n_chunks, 0);
+    out.chunk_prob.assign(n_chunks, 0);
     out.cam_prob.assign(n_cams, 0);
     out.pt_prob.assign(n_pts, 0);
     out.cam_chunk0.assign(n_cams + 1, 0);
@@ -325,6 +326,7 @@ int build_layout(const LayoutOptions &o, int np, const dba_problem_desc *probs, 
                     out.blk_chunk[2 * (size_t)(blk_base + b) + sc] = chunk;
                     out.blk_cam[2 * (size_t)(blk_base + b) + sc] = J;
                     out.chunk_cam[chunk] = J;
+                    out.chunk_prob[chunk] = p;
                     for (int l = 0; l < pb.npts[b]; ++l) {
                         const int t = pb.pts0[b] + l;
                         const long long k = pb.obs[2 * (size_t)t + sc];
@@ -347,7 +349,10 @@ int build_layout(const LayoutOptions &o, int np, const dba_problem_desc *probs, 
                 out.cam_count[J] = cc[j];
                 cslot[j] = (long long)chunk * CH;
                 const int nch = (cc[j] + BP - 1) / BP;
-                for (int q = 0; q < nch; ++q) out.chunk_cam[chunk + q] = J;
+                for (int q = 0; q < nch; ++q) {
+                    out.chunk_cam[chunk + q] = J;
+                    out.chunk_prob[chunk + q] = p;
+                }
                 chunk += nch;
                 for (int c = 0; c < 9; ++c) out.cons_y[(size_t)J * kConsY + c] = d.cams[9 * j + c];
             }

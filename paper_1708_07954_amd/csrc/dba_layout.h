@@ -62,7 +62,7 @@ struct Layout {
     std::vector<R> copy_y;                  // [9][n_slots] (per-observation local problems)
     std::vector<R> xrec;                    // [n_recs][3]
     std::vector<int> pt_off;                // [n_pts + 1]
-    std::vector<int> chunk_cam;             // [n_chunks]
+    std::vector<int> chunk_cam, chunk_prob; // [n_chunks]: camera and problem of each chunk
     std::vector<int> cam_prob, cam_chunk0, cam_count;  // [n_cams] (+1 for cam_chunk0)
     std::vector<int> pt_prob;               // [n_pts]
     std::vector<double> cons_y;             // [n_cams][kConsY]

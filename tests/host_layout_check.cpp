@@ -159,6 +159,7 @@ void check_layout(const char *name, const dba::LayoutOptions &o, const std::vect
                 }
             }
             CHECK(active > 0, "%s: empty chunk %lld", name, c);
+            CHECK(L.chunk_prob[c] == L.cam_prob[L.chunk_cam[c]], "%s: chunk %lld problem", name, c);
             if (!k2) {  // a camera's chunks are full except its last
                 const int J = L.chunk_cam[c];
                 const int q0 = (int)(c - L.cam_chunk0[J]);

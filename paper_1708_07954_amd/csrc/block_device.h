@@ -294,15 +294,12 @@ __device__ __forceinline__ void block_lm(R *th, const R *vy, const R *vx, R z0, 
         }
         const bool bad = __ballot(!(fn < Num<R>::inf)) != 0ull;
         const R Fn = (ok && !bad) ? wave_sum<R>(fn) + camera_penalty<R>(tr, vy, ry) : Num<R>::inf;
-        if (Fn < Num<R>::inf && (Fn < F || pred <= Num<R>::tie * fres)) {
+        const bool acc = Fn < Num<R>::inf && (Fn < F || pred <= Num<R>::tie * fres);
 #pragma unroll
-            for (int i = 0; i < 12; ++i) th[i] = tr[i];
-            if (active) cur = nxt;
-            F = Fn;
-            lam = lam_down<R>(lam);
-        } else {
-            lam = lam_up<R>(lam);
-        }
+        for (int i = 0; i < 12; ++i) th[i] = acc ? tr[i] : th[i];
+        cur.sel(acc && active, nxt);
+        F = acc ? Fn : F;
+        lam = acc ? lam_down<R>(lam) : lam_up<R>(lam);
     }
 }
 
@@ -691,22 +688,21 @@ __device__ __forceinline__ void block_lm2(R *y, const R *vy, int present, R *x, 
         }
         const bool bad = __ballot(!(fn < Num<R>::inf)) != 0ull;
         const R Fn = (ok && !bad) ? wave_sum<R>(fn) + cam_pen(ty) : Num<R>::inf;
-        if (Fn < Num<R>::inf && (Fn < F || pred <= Num<R>::tie * fres)) {
+        const bool acc = Fn < Num<R>::inf && (Fn < F || pred <= Num<R>::tie * fres);
 #pragma unroll
-            for (int i = 0; i < 18; ++i) y[i] = ty[i];
+        for (int i = 0; i < 18; ++i) y[i] = acc ? ty[i] : y[i];
 #pragma unroll
-            for (int k = 0; k < 3; ++k) x[k] = tx[k];
+        for (int k = 0; k < 3; ++k) x[k] = acc ? tx[k] : x[k];
+        if (acc) {
 #pragma unroll
             for (int s = 0; s < 2; ++s)
                 if (act[s]) {
                     if (pst) pst[2 * lane + s] = nxt[s];
                     else cur[s] = nxt[s];
                 }
-            F = Fn;
-            lam = lam_down<R>(lam);
-        } else {
-            lam = lam_up<R>(lam);
         }
+        F = acc ? Fn : F;
+        lam = acc ? lam_down<R>(lam) : lam_up<R>(lam);
         wave_lds_sync();
     }
 }

@@ -76,6 +76,16 @@ struct Proj {
     R cx0, cx1, cx2, wd;    // w x X, w . X
     R iz, p0, p1, r2, d;    // 1/P_3, P_{1,2}/P_3, r^2, distortion factor
     R pu, pv, depth;        // pixel and depth
+    // keep this projection (t false) or take n's, each field by a select: an
+    // if around a whole-struct copy has the compiler copy every field twice
+    // per LM step
+    __device__ __forceinline__ void sel(bool t, const Proj &n)
+    {
+        c = t ? n.c : c; a = t ? n.a : a; b = t ? n.b : b; a1 = t ? n.a1 : a1; b1 = t ? n.b1 : b1;
+        cx0 = t ? n.cx0 : cx0; cx1 = t ? n.cx1 : cx1; cx2 = t ? n.cx2 : cx2; wd = t ? n.wd : wd;
+        iz = t ? n.iz : iz; p0 = t ? n.p0 : p0; p1 = t ? n.p1 : p1; r2 = t ? n.r2 : r2; d = t ? n.d : d;
+        pu = t ? n.pu : pu; pv = t ? n.pv : pv; depth = t ? n.depth : depth;
+    }
 };
 
 template <typename R, bool DERIV>
@@ -176,6 +186,13 @@ struct ProjE {
     R q0, q1;                   // Q = R3 X2 = P - t (x, y)
     R iz, p0, p1;               // 1/P_3, P_{1,2}/P_3
     R pu, pv, depth;            // pixel and depth
+    __device__ __forceinline__ void sel(bool t, const ProjE &n)  // as Proj::sel
+    {
+        sa = t ? n.sa : sa; ca = t ? n.ca : ca; sb = t ? n.sb : sb; cb = t ? n.cb : cb; sg = t ? n.sg : sg; cg = t ? n.cg : cg;
+        x1y = t ? n.x1y : x1y; x1z = t ? n.x1z : x1z; x2x = t ? n.x2x : x2x; x2z = t ? n.x2z : x2z;
+        q0 = t ? n.q0 : q0; q1 = t ? n.q1 : q1; iz = t ? n.iz : iz; p0 = t ? n.p0 : p0; p1 = t ? n.p1 : p1;
+        pu = t ? n.pu : pu; pv = t ? n.pv : pv; depth = t ? n.depth : depth;
+    }
 };
 
 template <typename R, bool DERIV>
@@ -414,15 +431,12 @@ __device__ __forceinline__ void lm_steps(R *th, P &cur, R &F, const R *v, R z0, 
         const P nxt = proj_core<R, true>(tr, Cam{});
         const R Fn = ok ? objective<R, Cam>(nxt, tr, v, z0, z1, rx, ry, kind, lp) : Num<R>::inf;
         // accept a decrease of F, or a step too small for F to judge
-        if (Fn < Num<R>::inf && (GN || Fn < F || pred <= Num<R>::tie * fres)) {
+        const bool acc = Fn < Num<R>::inf && (GN || Fn < F || pred <= Num<R>::tie * fres);
 #pragma unroll
-            for (int i = 0; i < 12; ++i) th[i] = tr[i];
-            cur = nxt;
-            F = Fn;
-            lam = lam_down<R>(lam);
-        } else {
-            lam = lam_up<R>(lam);
-        }
+        for (int i = 0; i < 12; ++i) th[i] = acc ? tr[i] : th[i];
+        cur.sel(acc, nxt);
+        F = acc ? Fn : F;
+        lam = acc ? lam_down<R>(lam) : lam_up<R>(lam);
     }
 }
 

@@ -116,10 +116,16 @@ def test_blocks_every_schedule_is_bitwise_identical(precision):
 
 
 def test_blocks_batched_equals_solo_bitwise():
-    scenes = [make_ring_scene(seed=30 + q, n_cams=3 + q, n_points=60 + 17 * q) for q in range(4)]
-    kw = dict(precision="fp32", loss="huber", loss_param=2.0, rho=1e4, camera_blocks=True)
+    """Each problem's chunks read its own control block: with residual
+    balancing the problems' rho part ways (two start at the solution, two away
+    from it), and each still matches its solo run."""
+    scenes = [make_ring_scene(seed=30 + q, n_cams=3 + q, n_points=60 + 17 * q, perturb=q % 2 == 0,
+                              noise_px=1.0 if q % 2 == 0 else 0.0) for q in range(4)]
+    kw = dict(precision="fp32", loss="huber", loss_param=2.0, rho=1e1, camera_blocks=True, rho_balancing=True,
+              rho_min=1e-2, rho_max=1e7)
     s = binding.Solver(**kw).set_scenes(scenes)
     s.iterate(6)
+    assert len({s.residuals(q)["next_rho_x"] for q in range(len(scenes))}) > 1
     for q, sc in enumerate(scenes):
         solo = binding.Solver(**kw).set_scene(sc)
         solo.iterate(6)

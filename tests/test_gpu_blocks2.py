@@ -9,7 +9,7 @@ import pytest
 
 import oracle
 from paper_1708_07954_amd import binding
-from scenes import make_sphere_scene, make_trajectory_scene
+from scenes import make_ring_scene, make_sphere_scene, make_trajectory_scene
 from _util import param_rel_err
 
 pytestmark = pytest.mark.gpu
@@ -61,10 +61,16 @@ def test_two_camera_blocks_parity(case, precision):
 
 
 def test_two_camera_blocks_batched_equals_solo_bitwise():
-    scenes = [make_trajectory_scene(seed=60 + q, n_cams=9 + 4 * q, n_points=200 + 60 * q) for q in range(3)]
-    kw = dict(precision="fp32", loss="huber", loss_param=2.0, rho=1e4, camera_blocks=True, block_cameras=2)
+    """Each block reads its own problem's control block: with residual
+    balancing the problems' rho part ways (two start at the solution, two away
+    from it), and each still matches its solo run."""
+    scenes = [make_ring_scene(seed=30 + q, n_cams=3 + q, n_points=60 + 17 * q, perturb=q % 2 == 0,
+                              noise_px=1.0 if q % 2 == 0 else 0.0) for q in range(4)]
+    kw = dict(precision="fp32", loss="huber", loss_param=2.0, rho=1e1, camera_blocks=True, block_cameras=2,
+              rho_balancing=True, rho_min=1e-2, rho_max=1e7)
     s = binding.Solver(**kw).set_scenes(scenes)
     s.iterate(4)
+    assert len({s.residuals(q)["next_rho_x"] for q in range(len(scenes))}) > 1
     for q, sc in enumerate(scenes):
         solo = binding.Solver(**kw).set_scene(sc)
         solo.iterate(4)

@@ -60,10 +60,16 @@ def test_problems_keep_their_own_rho():
     b = binding.Solver(**kw).set_scenes([far, still])
     b.iterate(5)
     r0, r1 = b.residuals(0), b.residuals(1)
-    s = binding.Solver(**kw).set_scene(far)
-    s.iterate(5)
-    assert r0["next_rho_x"] == s.residuals()["next_rho_x"]
     assert r0["next_rho_x"] != r1["next_rho_x"]
+    # each problem's chunks read its own control block: both match their solo runs bit for bit
+    for q, sc in enumerate((far, still)):
+        s = binding.Solver(**kw).set_scene(sc)
+        s.iterate(5)
+        assert b.residuals(q)["next_rho_x"] == s.residuals()["next_rho_x"]
+        np.testing.assert_array_equal(b.params(q)[0], s.params()[0])
+        np.testing.assert_array_equal(b.params(q)[1], s.params()[1])
+        s.close()
+    b.close()
 
 
 @pytest.mark.parametrize("precision", ["fp64", "fp32"])

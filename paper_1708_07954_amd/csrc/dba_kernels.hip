@@ -514,14 +514,17 @@ __device__ __forceinline__ void point_wave(const DevArrays<R> &a, int cw, int w,
     const bool has = lane < np;
     const int i = p0 + lane;
     int r0 = 0, r1 = 0;
+    // lane j's point: its record range and previous consensus, loaded at once
+    double4 oldi = make_double4(0.0, 0.0, 0.0, 0.0);
     if (has) {
         r0 = a.pt_off[i];
         r1 = a.pt_off[i + 1];
+        oldi = a.cons_x[i];
     }
     double pri = 0.0, dual = 0.0;
     if constexpr (SCHED == 1) {
         if (has) {
-            const double4 old = a.cons_x[i];
+            const double4 old = oldi;
             const int K = cons_group(r1 - r0);
             PtSums t, g;
             t.clear();
@@ -552,9 +555,9 @@ __device__ __forceinline__ void point_wave(const DevArrays<R> &a, int cw, int w,
             point_finish(a.cons_x, i, old, r1 - r0, t, pri, dual);
         }
     } else {
-        __shared__ int gstart[4][64], gpoint[4][64];
+        __shared__ int gpoint[4][64];
         __shared__ PtSums gsum[4][64];
-        // lane j: its point's groups start at gstart[j] (exclusive scan)
+        // lane j: its point's groups start at group `start` (exclusive scan)
         const int G = has ? cons_groups(r1 - r0) : 0;
         int start = G;
 #pragma unroll
@@ -563,22 +566,23 @@ __device__ __forceinline__ void point_wave(const DevArrays<R> &a, int cw, int w,
             if (lane >= off) start += v;
         }
         start -= G;
-        gstart[w][lane] = start;
         for (int k = 0; k < G; ++k) gpoint[w][start + k] = lane;
         const int n_groups = __shfl(start + G, 63, 64);
         __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
         __builtin_amdgcn_wave_barrier();
         __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-        // lane l: group l of the wave, records [g0, g1)
+        // lane l: group l of the wave, records [g0, g1); its point's range,
+        // first group and previous consensus come from the point's lane
+        const int jg = lane < n_groups ? gpoint[w][lane] : 0;
+        const int q0 = __shfl(r0, jg, 64), q1 = __shfl(r1, jg, 64), sj = __shfl(start, jg, 64);
+        const double o0 = __shfl(oldi.x, jg, 64), o1 = __shfl(oldi.y, jg, 64), o2 = __shfl(oldi.z, jg, 64);
         int g0 = 0, g1 = 0;
         double4 old = make_double4(0.0, 0.0, 0.0, 0.0);
         if (lane < n_groups) {
-            const int j = gpoint[w][lane], ip = p0 + j;
-            const int q0 = a.pt_off[ip], q1 = a.pt_off[ip + 1];
             const int K = cons_group(q1 - q0);
-            g0 = q0 + (lane - gstart[w][j]) * K;
+            g0 = q0 + (lane - sj) * K;
             g1 = min(g0 + K, q1);
-            old = a.cons_x[ip];
+            old = make_double4(o0, o1, o2, 0.0);
         }
         PtSums g;
         g.clear();
@@ -654,11 +658,10 @@ __device__ __forceinline__ void point_wave(const DevArrays<R> &a, int cw, int w,
         __builtin_amdgcn_wave_barrier();
         __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
         if (has) {
-            const double4 old = a.cons_x[i];
             PtSums t;
             t.clear();
             for (int k = 0; k < G; ++k) t.add(gsum[w][start + k]);
-            point_finish(a.cons_x, i, old, r1 - r0, t, pri, dual);
+            point_finish(a.cons_x, i, oldi, r1 - r0, t, pri, dual);
         }
     }
     pri = wave_sum(pri);

@@ -101,7 +101,8 @@ TUNING_ITERATIONS = 16
 
 def kernel_source_hash():
     h = hashlib.sha256()
-    for f in ("dba_kernels.hip", "dba_device.h", "dba_internal.h", "block_device.h", "mlp_device.h"):
+    for f in ("dba_kernels.hip", "dba_block_kernels.hip", "dba_device.h", "dba_internal.h", "block_device.h",
+              "mlp_device.h"):
         with open(os.path.join(ROOT, "paper_1708_07954_amd", "csrc", f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:12]

@@ -13,7 +13,12 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libdba.so")
-SOURCES = ["dba_kernels.hip", "mlp_kernels.hip", "dba_host.cpp", "dba_learned.cpp", "dba_layout.cpp"]
+SOURCES = ["dba_kernels.hip", "dba_block_kernels.hip", "mlp_kernels.hip", "dba_host.cpp", "dba_learned.cpp",
+           "dba_layout.cpp"]
+# per-source extra flags: the block local-update kernels are scheduled for
+# instruction-level parallelism (the two-camera kernel about 7 % faster; the
+# same instructions, so the same results)
+SOURCE_FLAGS = {"dba_block_kernels.hip": ["-mllvm", "--amdgpu-sched-strategy=max-ilp"]}
 
 HIPCC_FLAGS = [
     "--offload-arch=gfx950",
@@ -40,7 +45,8 @@ def build(verbose: bool = False) -> str:
     objs = []
     for src in srcs:
         obj = os.path.join(objdir, os.path.basename(src) + ".o")
-        cmd = [hipcc(), *HIPCC_FLAGS, "-I", os.path.join(ROOT, "include"), "-I", CSRC, "-c", src, "-o", obj]
+        cmd = [hipcc(), *HIPCC_FLAGS, *SOURCE_FLAGS.get(os.path.basename(src), []), "-I", os.path.join(ROOT, "include"),
+               "-I", CSRC, "-c", src, "-o", obj]
         if src.endswith(".cpp"):
             cmd[1:1] = ["-x", "hip"]
         if verbose:

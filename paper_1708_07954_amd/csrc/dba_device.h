@@ -747,6 +747,27 @@ __device__ __forceinline__ int xcd_block()
     return x * q + (x < r ? x : r) + (b >> 3);
 }
 
+// Workgroup size of the local kernels.  FP32: up to 8 waves per workgroup;
+// FP64 needs more than 256 VGPRs, so at most 4 waves (one per SIMD).
+template <typename R> struct LocalBound { static constexpr int threads = 512; };
+template <> struct LocalBound<double> { static constexpr int threads = 256; };
+
+// The chunks (or blocks) [c0, c1) of this workgroup: wpb of them, or an even
+// share of all of them when the grid is persistent; consecutive ranges go to
+// one XCD (xcd_block).
+__device__ __forceinline__ void chunk_range(int n_chunks, int wpb, int persistent, int &c0, int &c1)
+{
+    const int lb = xcd_block();
+    if (persistent) {
+        const int per = (n_chunks + gridDim.x - 1) / gridDim.x;
+        c0 = lb * per;
+        c1 = min(c0 + per, n_chunks);
+    } else {
+        c0 = lb * wpb;
+        c1 = min(c0 + wpb, n_chunks);
+    }
+}
+
 
 }  // namespace dev
 }  // namespace dba

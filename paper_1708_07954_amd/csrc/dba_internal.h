@@ -1,5 +1,6 @@
 // dba_internal.h -- device data layout and kernel launchers shared by the
-// host runtime (dba_host.cpp) and the kernels (dba_kernels.hip).
+// host runtime (dba_host.cpp) and the kernels (dba_kernels.hip,
+// dba_block_kernels.hip).
 //
 // Layout of one problem set (one or many independent problems, concatenated
 // with global camera / point / observation numbering):
@@ -140,7 +141,8 @@ struct MlpParams {
     const float *xform;    // [2][kIn]: 1 / sd_in, -mu_in / sd_in (input standardization)
 };
 
-// launchers (dba_kernels.hip); each returns hipGetLastError()
+// launchers (dba_kernels.hip; launch_local_block in dba_block_kernels.hip);
+// each returns hipGetLastError()
 template <typename R>
 hipError_t launch_local(const DevArrays<R> &a, const SolverParams &sp, int block_waves,
                         int persistent, int n_cu, hipStream_t s);

@@ -99,10 +99,14 @@ def make_scenes(kind):
 TUNING_ITERATIONS = 16
 
 
+# every source of device code: the HIP files and the headers they include
+KERNEL_SOURCES = ("dba_kernels.hip", "dba_block_kernels.hip", "mlp_kernels.hip", "dba_device.h", "dba_internal.h",
+                  "dba_layout.h", "block_device.h", "mlp_device.h")
+
+
 def kernel_source_hash():
     h = hashlib.sha256()
-    for f in ("dba_kernels.hip", "dba_block_kernels.hip", "dba_device.h", "dba_internal.h", "block_device.h",
-              "mlp_device.h"):
+    for f in KERNEL_SOURCES:
         with open(os.path.join(ROOT, "paper_1708_07954_amd", "csrc", f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:12]

@@ -80,3 +80,19 @@ def test_profile_summaries_name_their_commands():
         assert "kernel_source_hash" in text, f
     for wl, f in bench.COUNTER_SUMMARIES.items():
         assert wl in bench.WORKLOADS and f in names, (wl, f)
+
+
+def test_kernel_source_hash_covers_every_device_source():
+    """The hash that keys the recorded traffic covers every HIP file and every
+    header such a file includes, directly or through another header."""
+    import re
+    csrc = os.path.join(ROOT, "paper_1708_07954_amd", "csrc")
+    seen, todo = set(), [f for f in os.listdir(csrc) if f.endswith(".hip")]
+    while todo:
+        f = todo.pop()
+        if f in seen:
+            continue
+        seen.add(f)
+        text = open(os.path.join(csrc, f)).read()
+        todo += [g for g in re.findall(r'#include "([^"]+)"', text) if os.path.exists(os.path.join(csrc, g))]
+    assert seen <= set(bench.KERNEL_SOURCES), sorted(seen - set(bench.KERNEL_SOURCES))

@@ -224,7 +224,13 @@ int dba_problem_info(const dba_handle *h, int32_t problem, int32_t *n_cams, int3
  * otherwise around eager launches.  Kernel ids:
  * 0 local solve, 1 consensus, 2 residual norms, 3 learned warm start.
  * enable: 0 off, 1 every kernel, 2 the local solve only (ids 0 and 3; two
- * events per iteration instead of six); other values DBA_E_INVALID_ARG.
+ * events per iteration instead of six), 3 the local solve of the first
+ * iteration of each batch of 16 (and of each single iteration after the
+ * last whole batch): with use_graph that launch runs between two events
+ * recorded on the stream and the rest of the batch is replayed from a graph,
+ * so the timing barely slows the iterations it samples and needs no
+ * event-record node inside a graph (without use_graph, every local launch);
+ * other values DBA_E_INVALID_ARG.
  * dba_kernel_times returns, per id, total milliseconds and launch counts
  * since timing was enabled (synchronises the stream). */
 int dba_set_kernel_timing(dba_handle *h, int32_t enable);

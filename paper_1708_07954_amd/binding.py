@@ -258,9 +258,10 @@ def dba_get_state(h, problem=0):
     return copies, duals
 
 
-def dba_set_kernel_timing(h, enable, local_only=False):
-    """enable: time every kernel; local_only: the local solve only."""
-    _check(h, load().dba_set_kernel_timing(h, (2 if local_only else 1) if enable else 0))
+def dba_set_kernel_timing(h, enable, local_only=False, sampled=False):
+    """enable: time every kernel; local_only: the local solve only; sampled:
+    the local solve only, in the first iteration of each graph replay."""
+    _check(h, load().dba_set_kernel_timing(h, (3 if sampled else 2 if local_only else 1) if enable else 0))
 
 
 def dba_kernel_times(h) -> dict:

@@ -28,6 +28,10 @@ void drop_graphs(dba_handle *h)
             t = TimedGraph();
         }
     h->tgraph_next[0] = h->tgraph_next[1] = 0;
+    for (auto &g : h->sgexec) {
+        if (g) (void)hipGraphExecDestroy(g);
+        g = nullptr;
+    }
 }
 
 int validate(dba_handle *h, int p, const dba_problem_desc &d)
@@ -243,25 +247,35 @@ inline hipEvent_t no_mark(int) { return nullptr; }
 
 // Eager iteration; with timed, each kernel between two events of the
 // handle's pool (read by collect_timing).
+// The next two events of the handle's pool for kernel kid (read by
+// collect_timing); false if the pool cannot grow.
+bool pool_pair(dba_handle *h, int kid, hipEvent_t *e0, hipEvent_t *e1)
+{
+    Timing &T = h->timing;
+    if (T.used + 2 > T.pool.size()) {
+        for (int q = 0; q < 64; ++q) {
+            hipEvent_t e;
+            if (hipEventCreate(&e) != hipSuccess) return false;
+            T.pool.push_back(e);
+        }
+    }
+    *e0 = T.pool[T.used];
+    *e1 = T.pool[T.used + 1];
+    T.pending_kernel.push_back(kid);
+    T.used += 2;
+    return true;
+}
+
 template <typename R>
 hipError_t run_iteration(dba_handle *h, const DevArrays<R> &A, int bw, int pers, bool timed)
 {
     if (!timed) return run_iteration_marked<R>(h, A, bw, pers, no_mark);
-    Timing &T = h->timing;
     auto mark = [&](int kid) -> hipEvent_t {
-        if (!(T.mask >> kid & 1u)) return nullptr;
-        if (T.used + 2 > T.pool.size()) {
-            for (int q = 0; q < 64; ++q) {
-                hipEvent_t e;
-                if (hipEventCreate(&e) != hipSuccess) return nullptr;
-                T.pool.push_back(e);
-            }
-        }
-        hipEvent_t e0 = T.pool[T.used];
+        if (!(h->timing.mask >> kid & 1u)) return nullptr;
+        hipEvent_t e0, e1;
+        if (!pool_pair(h, kid, &e0, &e1)) return nullptr;
         (void)hipEventRecord(e0, h->stream);
-        T.pending_kernel.push_back(kid);
-        T.used += 2;
-        return T.pool[T.used - 1];
+        return e1;
     };
     return run_iteration_marked<R>(h, A, bw, pers, mark);
 }
@@ -300,8 +314,10 @@ bool timed_graphs_ready(dba_handle *h, const DevArrays<R> &A)
             if (g.exec) continue;
             const int iters = sz == 0 ? 1 : kGraphBatch;
             bool ok = true;
+            int cur = 0;  // iteration of the graph being captured
             auto mark = [&](int kid) -> hipEvent_t {
                 if (!(h->timing.mask >> kid & 1u)) return nullptr;
+                if ((h->timing.mask & kFirstOnly) && cur > 0) return nullptr;
                 hipEvent_t e0, e1;
                 if (hipEventCreate(&e0) != hipSuccess) { ok = false; return nullptr; }
                 if (hipEventCreate(&e1) != hipSuccess) {
@@ -318,8 +334,10 @@ bool timed_graphs_ready(dba_handle *h, const DevArrays<R> &A)
             hipGraph_t graph = nullptr;
             if (hipStreamBeginCapture(h->stream, hipStreamCaptureModeThreadLocal) != hipSuccess) ok = false;
             hipError_t err = hipSuccess;
-            for (int it = 0; ok && it < iters && err == hipSuccess; ++it)
+            for (int it = 0; ok && it < iters && err == hipSuccess; ++it) {
+                cur = it;
                 err = run_iteration_marked<R>(h, A, h->block_waves, h->persistent, mark, true);
+            }
             hipError_t e2 = hipStreamEndCapture(h->stream, &graph);
             ok = ok && err == hipSuccess && e2 == hipSuccess && graph;
             if (ok) ok = hipGraphInstantiate(&g.exec, graph, nullptr, nullptr, 0) == hipSuccess;
@@ -352,6 +370,60 @@ int iterate_timed_graphs(dba_handle *h, int n)
     for (; rc == DBA_OK && n >= kGraphBatch; n -= kGraphBatch) rc = launch(1);
     for (; rc == DBA_OK && n > 0; --n) rc = launch(0);
     if (rc != DBA_OK) return rc;
+    return collect_timing(h);
+}
+
+// Sampled timing without event-record nodes inside graphs (which some HIP
+// runtimes refuse to capture): the local launch of the first iteration of a
+// batch is launched directly between two events recorded on the stream, and
+// the rest of the iteration -- or of a batch of kGraphBatch iterations -- is
+// replayed from a graph.  false if a capture fails.
+template <typename R>
+bool sampled_graphs_ready(dba_handle *h, const DevArrays<R> &A)
+{
+    if (h->sgexec[0]) return true;
+    for (int g = 0; g < 2; ++g) {
+        hipGraph_t graph = nullptr;
+        hipError_t err = hipStreamBeginCapture(h->stream, hipStreamCaptureModeThreadLocal);
+        if (err == hipSuccess) {
+            err = dba::launch_consensus<R>(A, h->seg_sched, h->stream);
+            if (err == hipSuccess) err = dba::launch_norms<R>(A, h->stream);
+            for (int it = 1; g == 1 && it < kGraphBatch && err == hipSuccess; ++it)
+                err = run_iteration<R>(h, A, h->block_waves, h->persistent, false);
+            const hipError_t e2 = hipStreamEndCapture(h->stream, &graph);
+            if (err == hipSuccess) err = e2;
+        }
+        if (err == hipSuccess && graph) err = hipGraphInstantiate(&h->sgexec[g], graph, nullptr, nullptr, 0);
+        if (graph) (void)hipGraphDestroy(graph);
+        if (err != hipSuccess || !h->sgexec[g]) {
+            (void)hipGetLastError();
+            for (auto &x : h->sgexec) {
+                if (x) (void)hipGraphExecDestroy(x);
+                x = nullptr;
+            }
+            return false;
+        }
+    }
+    return true;
+}
+
+// n sampled-timing iterations: batches of kGraphBatch, then single
+// iterations; each batch's first local launch between two events, the rest
+// of the batch from a graph.
+template <typename R>
+int iterate_sampled(dba_handle *h, const DevArrays<R> &A, int n)
+{
+    const int kid = h->start == DBA_START_LEARNED ? 3 : 0;
+    while (n > 0) {
+        const int batch = n >= kGraphBatch ? kGraphBatch : 1;
+        hipEvent_t e0, e1;
+        if (!pool_pair(h, kid, &e0, &e1)) return fail(h, DBA_E_DEVICE, "timing events: out of events");
+        HIP_TRY(h, hipEventRecord(e0, h->stream));
+        HIP_TRY(h, launch_local_sel<R>(h, A, h->block_waves, h->persistent));
+        HIP_TRY(h, hipEventRecord(e1, h->stream));
+        HIP_TRY(h, hipGraphLaunch(h->sgexec[batch == 1 ? 0 : 1], h->stream));
+        n -= batch;
+    }
     return collect_timing(h);
 }
 
@@ -456,6 +528,10 @@ int iterate_impl(dba_handle *h, const DevArrays<R> &A, int n)
         }
     }
     if (n <= 0) return DBA_OK;
+    if (h->timing.on && (h->timing.mask & kFirstOnly) && h->opt.use_graph && !h->sgraph_off) {
+        if (sampled_graphs_ready<R>(h, A)) return iterate_sampled<R>(h, A, n);
+        h->sgraph_off = true;
+    }
     if (h->timing.on && h->opt.use_graph && !h->tgraph_off && timed_graphs_ready<R>(h, A))
         return iterate_timed_graphs<R>(h, n);
     if (h->timing.on || !h->opt.use_graph) {
@@ -806,12 +882,13 @@ int dba_set_kernel_timing(dba_handle *h, int32_t enable)
 {
     if (!h) return DBA_E_INVALID_ARG;
     h->err.clear();
-    if (enable < 0 || enable > 2) return fail(h, DBA_E_INVALID_ARG, "timing mode %d", enable);
+    if (enable < 0 || enable > 3) return fail(h, DBA_E_INVALID_ARG, "timing mode %d", enable);
     int rc = collect_timing(h);
     if (rc != DBA_OK) return rc;
     h->timing.on = enable != 0;
-    // 1: every kernel; 2: the local solve only (ids 0 and 3)
-    h->timing.mask = enable == 2 ? 0x9u : 0xFu;
+    // 1: every kernel; 2: the local solve only (ids 0 and 3); 3: as 2, in
+    // the first iteration of each replayed graph only (bit kFirstOnly)
+    h->timing.mask = enable == 3 ? (0x9u | kFirstOnly) : enable == 2 ? 0x9u : 0xFu;
     for (int k = 0; k < kKernels; ++k) {
         h->timing.total_ms[k] = 0.0;
         h->timing.launches[k] = 0;

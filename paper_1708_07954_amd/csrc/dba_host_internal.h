@@ -19,6 +19,8 @@ using dba::ProblemRange;
 
 constexpr int kKernels = 4;   // local, consensus, norms, learned
 constexpr int kGraphBatch = 16;
+// timing mask bit: events only in the first iteration of a captured graph
+constexpr unsigned kFirstOnly = 0x10u;
 
 struct Buffers {
     std::vector<void *> ptrs;
@@ -118,6 +120,10 @@ struct dba_handle {
     unsigned tgraph_mask = 0;  // the timing mask the timed graphs were captured with
     int tgraph_next[2] = {0, 0};
     bool tgraph_off = false;
+    // sampled timing: [0] an iteration without its local launch, [1] that
+    // and kGraphBatch - 1 more iterations; off after a failed capture
+    hipGraphExec_t sgexec[2] = {nullptr, nullptr};
+    bool sgraph_off = false;
     // learned warm start
     int start = DBA_START_PLAIN;
     dba::host::Mlp *mlp = nullptr;

@@ -1,7 +1,8 @@
 """Per-kernel timing (dba_set_kernel_timing / dba_kernel_times): timed
 iterations replayed from the captured graphs (event-record nodes around each
 kernel) and eager timed iterations both count every launch, report positive
-times that agree, and leave the iterates bitwise unchanged."""
+times that agree, and leave the iterates bitwise unchanged; the sampled mode
+times the first iteration of each graph replay."""
 import numpy as np
 import pytest
 
@@ -72,5 +73,36 @@ def test_local_only_timing_times_the_local_solve_alone():
     s.iterate(17)
     kt = binding.dba_kernel_times(s.h)
     assert all(kt[k][1] == 17 for k in ("local", "consensus", "norms"))
-    assert binding.STATUS[binding.load().dba_set_kernel_timing(s.h, 3)] == "DBA_E_INVALID_ARG"
+    assert binding.STATUS[binding.load().dba_set_kernel_timing(s.h, 4)] == "DBA_E_INVALID_ARG"
     s.close()
+
+
+def test_sampled_timing_times_the_first_iteration_of_each_replay():
+    """Mode 3 times the local solve in the first iteration of each graph
+    replay: one launch per 16-iteration replay and one per single-iteration
+    replay, at the same average as every launch timed, and the iterates
+    bitwise unchanged."""
+    sc = make_sphere_scene(seed=24, n_cams=30, n_points=3000)
+    s = binding.Solver(**KW).set_scene(sc)
+    s.iterate(2)
+    binding.dba_set_kernel_timing(s.h, True, sampled=True)
+    s.iterate(17)  # captures the timed graphs
+    binding.dba_set_kernel_timing(s.h, True, sampled=True)
+    s.iterate(16 * 5 + 3)
+    kt = binding.dba_kernel_times(s.h)
+    assert kt["local"][1] == 5 + 3 and kt["local"][0] > 0, kt["local"]
+    assert kt["consensus"][1] == 0 and kt["norms"][1] == 0
+    sampled = kt["local"][0] / kt["local"][1]
+    binding.dba_set_kernel_timing(s.h, True, local_only=True)
+    s.iterate(17)
+    binding.dba_set_kernel_timing(s.h, True, local_only=True)
+    s.iterate(64)
+    kt = binding.dba_kernel_times(s.h)
+    every = kt["local"][0] / kt["local"][1]
+    binding.dba_set_kernel_timing(s.h, False)
+    c, p = s.params()
+    s.close()
+    print("local kernel ms, sampled / every launch:", sampled, every)
+    assert 0.5 < sampled / every < 2.0
+    ref_c, ref_p, _ = run(sc, 17 + 16 * 5 + 3 + 17 + 64, False, True)
+    assert np.array_equal(c, ref_c) and np.array_equal(p, ref_p)

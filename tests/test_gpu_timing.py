@@ -1,8 +1,9 @@
 """Per-kernel timing (dba_set_kernel_timing / dba_kernel_times): timed
-iterations replayed from the captured graphs (event-record nodes around each
-kernel) and eager timed iterations both count every launch, report positive
-times that agree, and leave the iterates bitwise unchanged; the sampled mode
-times the first iteration of each graph replay."""
+iterations with use_graph (event-record nodes in captured graphs where the HIP
+runtime accepts them, eager launches where it does not) and without it both
+count every launch, report positive times that agree, and leave the iterates
+bitwise unchanged; the sampled mode times the first local launch of each
+batch of iterations, the rest of the batch replayed from a graph."""
 import numpy as np
 import pytest
 

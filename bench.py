@@ -574,12 +574,12 @@ def main():
     s.iterate(args.warmup)
     torch.cuda.synchronize()
 
-    # timed region: K iterations replayed from the captured graphs, the
-    # local-solve kernel (the roofline's kernel) of the first iteration of
-    # each graph replay between two HIP event-record nodes on the library's
-    # stream (a sample of its launches: events around every launch would
-    # slow the region they measure); the timed graphs are captured by an
-    # untimed call first
+    # timed region: K iterations in batches of 16, the local-solve kernel
+    # (the roofline's kernel) of each batch's first iteration between two HIP
+    # events on the library's stream and the rest of the batch replayed from
+    # a graph (a sample of its launches: events around every launch would
+    # slow the region they measure); the graphs are captured by a call
+    # before the region
     binding.dba_set_kernel_timing(s.h, True, sampled=True)
     s.iterate(17)
     torch.cuda.synchronize()
@@ -694,9 +694,9 @@ def main():
                       "local_precision": "f32" if fp32 else "f64", "consensus_precision": "f64",
                       "lm_steps": opts.get("lm_steps", 5), "schedule": sched, "parallelism": "single GPU"},
            "ms_per_step_graph": ms_graph, "kernels": kt,
-           "kernel_timing": "local: HIP event-record nodes around its launch in the first iteration of each "
-                            "graph replay of the timed region; consensus, norms: a separate pass with every "
-                            "kernel between events",
+           "kernel_timing": "local: HIP events recorded on the library's stream around the first local launch "
+                            "of each 16-iteration batch of the timed region, the rest of the batch replayed from "
+                            "a graph; consensus, norms: a separate pass with every kernel between events",
            "roofline": roofline, "consensus": consensus_line,
            "residuals_after": {k: rep[k] for k in ("primal", "dual", "rho_x", "rmse", "iteration")}}
     if traffic_src:
